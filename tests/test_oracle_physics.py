@@ -1,0 +1,326 @@
+"""Oracle pinned against what the physics and the mathematics fix.
+
+* lossless energy identity of leap-frog (PEC box, no PML, no source);
+* discrete Gauss law: div(eps E) is invariant without sources;
+* coaxial TEM standing wave: exact discrete eigenmode with the Yee
+  dispersion relation sin(w dt/2) = (dt/dz) sin(kappa dz/2);
+* PEC annular-cavity TM resonances at the Bessel cross-product zeros,
+  converging at second order under grid refinement;
+* n-fold symmetry: an n-wedge run tiled with exp(i m l tau) equals the
+  full-circle run;
+* adjoint gradient vs FP64 central finite differences; one broadband adjoint
+  run equals the sum of single-frequency runs;
+* late-time stability of the regularised r-PML, PML reflection bound, and a
+  Courant-violating negative control;
+* the pulse deposits no charge and its DFT equals the analytic spectrum.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+from scipy.special import jv, yv
+
+E_COMPS = ("Er", "Ephi", "Ez")
+H_COMPS = ("Hr", "Hphi", "Hz")
+
+
+def _volumes(z):
+    """Plain cell volumes of each component sample ([nr] radial factor)."""
+    ri = z.r_in + np.arange(z.nr) * z.dr
+    rh = ri + 0.5 * z.dr
+    v = z.dr * z.dphi * z.dz
+    return {"Er": rh * v, "Ephi": ri * v, "Ez": ri * v, "Hr": ri * v, "Hphi": rh * v, "Hz": rh * v}
+
+
+def _random_fields(z, rng):
+    f = {c: rng.standard_normal(z.shape) + 1j * rng.standard_normal(z.shape) for c in E_COMPS + H_COMPS}
+    f["Er"][0] = 0
+    f["Ephi"][0] = 0
+    f["Ephi"][:, 0] = 0
+    f["Ez"][:, 0] = 0
+    f["Hr"][:, 0] = 0
+    f["Hz"][0] = 0
+    for c in f:
+        z.set_field(c, f[c])
+    return f
+
+
+def test_energy_identity_pec(oracle_mod):
+    rng = np.random.default_rng(0)
+    z = oracle_mod.OracleZone(r_in=15.0, nr=10, nphi=8, nz=9, n_fold=9, m=1, dr=1.0, dz=0.8)
+    eps = (1 + 5 * rng.random(z.shape)).astype(np.float32)
+    z.set_eps(eps)
+    _random_fields(z, rng)
+    V = _volumes(z)
+    energies = []
+    for _ in range(20):
+        E = {c: z.get_field(c) for c in E_COMPS}
+        Hm = {c: z.get_field(c) for c in H_COMPS}
+        z.run(1, reset=False)
+        Hp = {c: z.get_field(c) for c in H_COMPS}
+        en = 0.5 * sum(np.sum(eps * V[c][None, :, None] * np.abs(E[c]) ** 2) for c in E_COMPS)
+        en += 0.5 * sum(np.sum(V[c][None, :, None] * np.real(Hm[c] * np.conj(Hp[c]))) for c in H_COMPS)
+        energies.append(en)
+        z.run(100, reset=False)
+    energies = np.array(energies)
+    assert np.abs(energies - energies[0]).max() < 1e-12 * energies[0]
+
+
+def _div_d(z, eps, E, m):
+    """Flux of eps E out of the dual cell of every interior node."""
+    ri = z.r_in + np.arange(z.nr) * z.dr
+    rh = ri + 0.5 * z.dr
+    Dr, Dp, Dz = (eps * E[c] for c in E_COMPS)
+    ph = np.exp(-1j * m * z.tau)
+    Dp_jm = np.concatenate([ph * Dp[:, :, -1:], Dp[:, :, :-1]], axis=2)
+    div = np.zeros(z.shape, complex)
+    div[:, 1:] += (rh[1:, None] * Dr[:, 1:] - rh[:-1, None] * Dr[:, :-1]) * z.dphi * z.dz
+    div += (Dp - Dp_jm) * z.dr * z.dz
+    div[1:] += (Dz[1:] - Dz[:-1]) * (ri[:, None] * z.dr * z.dphi)
+    return div[1:, 1:]
+
+
+def test_gauss_law(oracle_mod):
+    rng = np.random.default_rng(1)
+    z = oracle_mod.OracleZone(r_in=10.0, nr=9, nphi=7, nz=8, n_fold=5, m=2)
+    eps = (1 + 3 * rng.random(z.shape)).astype(np.float32)
+    z.set_eps(eps)
+    _random_fields(z, rng)
+    d0 = _div_d(z, eps, {c: z.get_field(c) for c in E_COMPS}, 2)
+    z.run(500, reset=False)
+    d1 = _div_d(z, eps, {c: z.get_field(c) for c in E_COMPS}, 2)
+    assert np.abs(d0).max() > 1.0
+    assert np.abs(d1 - d0).max() < 1e-12 * np.abs(d0).max()
+
+
+@pytest.mark.parametrize("q", [1, 3])
+def test_coax_tem_discrete_dispersion(oracle_mod, q):
+    z = oracle_mod.OracleZone(r_in=30.0, nr=12, nphi=4, nz=20, n_fold=40, m=0, dr=1.0, dz=1.0)
+    dz, dt = z.dz, z.dt
+    kap = q * np.pi / (z.nz * dz)
+    w = 2 / dt * np.arcsin(dt / dz * np.sin(kap * dz / 2))
+    rh = z.r_in + (np.arange(z.nr) + 0.5) * z.dr
+    k = np.arange(z.nz)
+    e = (np.sin(kap * k * dz)[:, None] / rh[None, :])[:, :, None] * np.ones(z.nphi)
+    h = (np.cos(kap * (k + 0.5) * dz)[:, None] / rh[None, :])[:, :, None] * np.ones(z.nphi)
+    z.set_field("Er", e)
+    z.set_field("Hphi", np.sin(w * dt / 2) * h)
+    N = 777
+    z.run(N, reset=False)
+    assert np.abs(z.get_field("Er") - np.cos(w * N * dt) * e).max() < 1e-12
+    assert np.abs(z.get_field("Hphi") + np.sin(w * (N - 0.5) * dt) * h).max() < 1e-12
+    assert np.abs(z.get_field("Ez")).max() < 1e-13
+
+
+def _pencil_freqs(x, dt, nmodes):
+    """Matrix-pencil estimate of the angular frequencies in a time series."""
+    N = x.size
+    L = N // 2
+    Y = np.array([x[i:i + L + 1] for i in range(N - L)])
+    U, s, Vh = np.linalg.svd(Y, full_matrices=False)
+    V = Vh[:nmodes].conj().T
+    V0, V1 = V[:-1], V[1:]
+    zeig = np.linalg.eigvals(np.linalg.pinv(V0) @ V1)
+    return np.abs(np.angle(zeig)) / dt
+
+
+def _tm_root(nu, a, b, guess):
+    f = lambda k: jv(nu, k * a) * yv(nu, k * b) - jv(nu, k * b) * yv(nu, k * a)
+    ks = np.linspace(0.5 * guess, 1.5 * guess, 400)
+    vals = f(ks)
+    roots = [brentq(f, ks[j], ks[j + 1]) for j in range(len(ks) - 1) if np.sign(vals[j]) != np.sign(vals[j + 1])]
+    return min(roots, key=lambda r: abs(r - guess))
+
+
+def test_annular_cavity_bessel_resonance(oracle_mod):
+    """Lowest TM (E_z) resonance of a PEC annular wedge (z-invariant, one
+    cell in z) with Bloch order nu = m = 1: J_1(ka) Y_1(kb) = J_1(kb) Y_1(ka)."""
+    a, width, n = 20.0, 8.0, 8
+    k_exact = _tm_root(1, a, a + width, np.pi / width)
+    errs = []
+    for res in (1, 2, 4):
+        dr = 1.0 / res
+        nr, nphi = int(width * res), 8 * res
+        z = oracle_mod.OracleZone(r_in=a, nr=nr, nphi=nphi, nz=1, n_fold=n, m=1, dr=dr, dz=dr)
+        ri = a + np.arange(nr) * dr
+        prof = np.sin(np.pi * (ri - a) / width)
+        phi = np.arange(nphi) * z.dphi
+        z.set_field("Ez", (prof[:, None] * np.exp(1j * phi)[None, :])[None])
+        T = 4000
+        x = np.empty(T, complex)
+        probe = (0, nr // 3, 1)
+        for t in range(T):
+            z.run(1, reset=False)
+            x[t] = z.get_field("Ez")[probe]
+        wd = _pencil_freqs(x, z.dt, 6)
+        lam = 2 / z.dt * np.sin(wd * z.dt / 2)      # remove the leap-frog time error
+        errs.append(np.min(np.abs(lam - k_exact)) / k_exact)
+    errs = np.array(errs)
+    assert errs[0] < 1e-2
+    order = np.log2(errs[:-1] / errs[1:])
+    assert np.all(order > 1.8), (errs, order)
+
+
+def test_nfold_tiling(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(2)
+    n, nphi = 4, 6
+    kw = dict(r_in=20.0, nr=14, nz=16, m=1, pml=(3, 3, 3, 3), k_mon=12)
+    zw = O.OracleZone(nphi=nphi, n_fold=n, **kw)
+    zf = O.OracleZone(nphi=nphi * n, n_fold=1, **kw)
+    eps = (1 + 4 * rng.random(zw.shape)).astype(np.float32)
+    zw.set_eps(eps)
+    zf.set_eps(np.tile(eps, (1, 1, n)))
+    T = 400
+    g, _ = O.pulse(T, zw.dt, 0.3, 6.0)
+    ow = zw.run(T, patterns=zw.preset_pattern()[None], profiles=g[None], k_src=4, omegas=[0.3])
+    of = zf.run(T, patterns=zf.preset_pattern()[None], profiles=g[None], k_src=4, omegas=[0.3])
+    tau = 2 * np.pi / n
+    for c in E_COMPS + H_COMPS:
+        fw, ff = zw.get_field(c), zf.get_field(c)
+        tiled = np.concatenate([fw * np.exp(1j * l * tau) for l in range(n)], axis=2)
+        assert np.abs(tiled - ff).max() < 1e-11 * np.abs(ff).max()
+    tiled = np.concatenate([ow["plane"] * np.exp(1j * l * tau) for l in range(n)], axis=3)
+    assert np.abs(tiled - of["plane"]).max() < 1e-11 * np.abs(of["plane"]).max()
+
+
+def _grad_zone(O, rng, omegas=(0.3, 0.36)):
+    z = O.OracleZone(r_in=14.0, nr=12, nphi=6, nz=14, n_fold=8, m=1, pml=(3, 3, 3, 3),
+                     k_mon=10, design=(5, 8))
+    eps = np.ones(z.shape, np.float32)
+    eps[:5] = 2.1
+    z.set_eps(eps)
+    rho = rng.random((3, 12, 6))
+    z.set_design(rho, fp64=True)
+    return z, rho
+
+
+def _objective(wts, plane):
+    s = np.einsum("kaij,kaij->k", wts, plane)
+    return np.sum(np.abs(s) ** 2), np.conj(s)[:, None, None, None] * wts
+
+
+def test_adjoint_gradient_vs_central_fd(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    z, rho = _grad_zone(O, rng)
+    T, omegas = 5000, np.array([0.3, 0.36])
+    wts = rng.standard_normal((2, 2, 12, 6)) + 1j * rng.standard_normal((2, 2, 12, 6))
+    fwd = z.forward(T, omegas, omega_c=0.33, width=8.0, k_src=3, volume=True)
+    _, g = _objective(wts, fwd["plane"])
+    grad = z.adjoint_grad(g)
+    h = 1e-3
+    pix = [(0, 5, 2), (1, 6, 0), (2, 4, 5), (1, 1, 3), (0, 10, 1)]   # last two inside the r-PML
+
+    def central(a, b, c, hh):
+        vals = []
+        for s in (+1, -1):
+            r2 = rho.copy()
+            r2[a, b, c] += s * hh
+            z.set_design(r2, fp64=True)
+            out = z.run(T, patterns=z.preset_pattern()[None],
+                        profiles=O.pulse(T, z.dt, 0.33, 8.0)[0][None], k_src=3, omegas=omegas)
+            vals.append(_objective(wts, out["plane"])[0])
+        return (vals[0] - vals[1]) / (2 * hh)
+
+    for (a, b, c) in pix:
+        # Richardson: removes the O(h^2) term of the central difference
+        fd = (4 * central(a, b, c, h / 2) - central(a, b, c, h)) / 3
+        assert abs(fd - grad[a, b, c]) < 1e-7 * np.abs(grad).max(), (a, b, c, fd, grad[a, b, c])
+    z.set_design(rho, fp64=True)
+
+
+def test_broadband_adjoint_equals_single_frequency_runs(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(6)
+    omegas = np.array([0.28, 0.33, 0.39])
+    wts = rng.standard_normal((3, 2, 12, 6)) + 1j * rng.standard_normal((3, 2, 12, 6))
+    z, _ = _grad_zone(O, rng)
+    T = 5000
+    fwd = z.forward(T, omegas, omega_c=0.33, width=8.0, k_src=3, volume=True)
+    _, g = _objective(wts, fwd["plane"])
+    broad = z.adjoint_grad(g)
+    total = np.zeros_like(broad)
+    for k in range(3):
+        z.forward(T, omegas[k:k + 1], omega_c=0.33, width=8.0, k_src=3, volume=True)
+        total += z.adjoint_grad(g[k:k + 1])
+    assert np.linalg.norm(broad - total) < 1e-9 * np.linalg.norm(total)
+
+
+def test_late_time_stability_regularised_r_pml(oracle_mod):
+    """Random fields in a zone with all four layers: nothing may grow over
+    1e5 steps (the unregularised inner layer grows by ~1e10 per 4000 steps)."""
+    rng = np.random.default_rng(7)
+    z = oracle_mod.OracleZone(r_in=16.0, nr=16, nphi=6, nz=16, n_fold=8, m=1, pml=(4, 4, 4, 4))
+    f = {c: np.zeros(z.shape, complex) for c in E_COMPS + H_COMPS}
+    for c in f:
+        f[c][5:11, 5:11] = rng.standard_normal((6, 6, 6)) + 1j * rng.standard_normal((6, 6, 6))
+        z.set_field(c, f[c])
+    peaks = []
+    for _ in range(10):
+        z.run(10000, reset=False)
+        peaks.append(max(np.abs(z.get_field(c)).max() for c in E_COMPS))
+    assert max(peaks[1:]) <= 1.01 * peaks[0], peaks
+    assert peaks[-1] <= 1.001 * peaks[-2], peaks
+
+
+def test_courant_violation_negative_control(oracle_mod):
+    rng = np.random.default_rng(8)
+    z = oracle_mod.OracleZone(r_in=50.0, nr=8, nphi=8, nz=8, n_fold=40, m=1, courant=0.7)
+    _random_fields(z, rng)
+    z.run(400, reset=False)
+    assert max(np.abs(z.get_field(c)).max() for c in E_COMPS) > 1e6
+
+
+@pytest.mark.slow
+def test_r_pml_reflection_bound(oracle_mod):
+    """Inward and outward radial waves: the field near each r-layer equals a
+    reference whose layer is 80 cells further away, up to the reflection."""
+    O = oracle_mod
+    T, ext = 300, 80
+
+    def zone(r_in, nr):
+        return O.OracleZone(r_in=r_in, nr=nr, nphi=64, nz=40, n_fold=16, m=1, pml=(8, 8, 8, 8), k_mon=20)
+
+    for side, bound in (("in", 1e-3), ("out", 1e-4)):
+        zt = zone(200.0, 60)
+        zr = zone(200.0 - ext, 60 + ext) if side == "in" else zone(200.0, 60 + ext)
+        off = ext if side == "in" else 0
+        pat = np.zeros((2, 60, 64), complex)
+        ph = np.exp(1j * np.arange(64) * zt.dphi)
+        pat[0, 26:34], pat[1, 26:34] = ph, 1j * ph
+        patr = np.zeros((2, zr.nr, 64), complex)
+        patr[:, off:off + 60] = pat
+        g, _ = O.pulse(T, zt.dt, 2 * np.pi / 20, 10.0)
+        err = mx = 0.0
+        for n in range(0, T, 20):
+            zt.run(20, patterns=pat[None], profiles=g[None, n:n + 20], k_src=20, reset=(n == 0), n_start=n)
+            zr.run(20, patterns=patr[None], profiles=g[None, n:n + 20], k_src=20, reset=(n == 0), n_start=n)
+            a, b = zt.get_field("Ez")[:, 8:52], zr.get_field("Ez")[:, off + 8:off + 52]
+            err, mx = max(err, np.abs(a - b).max()), max(mx, np.abs(b).max())
+        assert err / mx < bound, (side, err / mx)
+
+
+def test_pulse_zero_charge_and_spectrum(oracle_mod):
+    O = oracle_mod
+    dt, wc, w = 0.5, 2 * np.pi / 20, 20.0
+    T = 3000
+    g, n0 = O.pulse(T, dt, wc, w)
+    assert n0 == 240
+    assert abs(g.sum()) < 1e-13
+    th = (np.arange(T) + 0.5) * dt
+    t0 = (n0 + 0.5) * dt
+    for om in (0.25, wc, 0.4):
+        num = dt * np.sum(g * np.exp(1j * om * th))
+        # sin(wc t) = (e^{i wc t} - e^{-i wc t}) / 2i times the Gaussian transform
+        ana = (w * np.sqrt(2 * np.pi) / 2j) * (np.exp(-w * w * (om + wc) ** 2 / 2)
+                                               - np.exp(-w * w * (om - wc) ** 2 / 2)) * np.exp(1j * om * t0)
+        assert abs(num - ana) < 1e-7 * abs(ana) + 1e-12
+
+
+def test_design_interpolation_eq6(oracle_mod):
+    z = oracle_mod.OracleZone(r_in=20.0, nr=4, nphi=4, nz=6, n_fold=16, m=1, design=(2, 4),
+                              eps_bg=1.0, eps_hi=6.25)
+    rho = np.linspace(0, 1, 32).reshape(2, 4, 4)
+    z.set_design(rho)
+    assert np.allclose(z.eps[2:4], 1.0 + 5.25 * rho, atol=1e-6)
+    assert np.all(z.eps[:2] == 1.0) and np.all(z.eps[4:] == 1.0)
