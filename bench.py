@@ -1,0 +1,187 @@
+"""Benchmark of the ZDA zone hot path on one MI355X.
+
+A step is one leap-frog time step of the whole forward hot path over the
+production zone (n = 512 wedge, 512 x 1024 x 400 cells): the H half-step, the
+E half-step with the soft source sheet and the 3-frequency exit-plane DFT.
+K timed steps run inside one zda_fdtd_run after W warm-up steps; the value is
+cell-updates per second.  The dominant kernel's roofline uses its algorithmic
+bytes per launch over its average duration, both measured live with HIP
+events on the run's stream; the FP64 oracle is timed on the host cores on a
+few steps of the same zone.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cyl-FDTD Gcell-updates/s, % HBM roofline; design iters/s plain vs surrogate"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_hash():
+    src = os.path.join(ROOT, "paper_2501_07979_amd", "csrc", "zda_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(wl, K):
+    """Bytes each update kernel must move per launch (one time step).
+
+    H kernel: read E (3 x 8 B), read+write H (6 x 8 B) = 72 B/cell; r-layer
+    cells +88 B (four stretch auxiliaries read+written, the H_phi integral
+    read+written, the E_phi integral read); z-layer cells +32 B.
+    E kernel: read H, read+write E, read dt/eps = 76 B/cell; r-layer +88 B,
+    z-layer +32 B; exit-plane cells +K x 2 x 16 B (DFT read+write); source
+    plane cells +2 x 8 B (pattern).
+    Fused minimum (every field read and written once, dt/eps once): 100 B/cell
+    + both kernels' layer and DFT terms."""
+    cells = wl.cells
+    plane = wl.nr * wl.nphi
+    r_cells = (wl.pml[0] + wl.pml[1]) * wl.nphi * wl.nz
+    z_cells = (wl.pml[2] + wl.pml[3]) * plane
+    h = 72 * cells + 88 * r_cells + 32 * z_cells
+    e = 76 * cells + 88 * r_cells + 32 * z_cells + K * 2 * 16 * plane + 16 * plane
+    fused = 100 * cells + 176 * r_cells + 64 * z_cells + K * 2 * 16 * plane + 16 * plane
+    return h, e, fused
+
+
+def load_traffic(wl_name):
+    """HBM traffic of the E kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "e_step_kernel_%s_pmc.json" % wl_name)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_sha") != kernel_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(wl, budget_s=12.0, max_steps=12):
+    """The FP64 oracle on the same zone for a few steps (whole zone, full
+    source and DFT work), timed after one untimed step."""
+    from oracle import oracle
+    eps = wl.eps()
+    oz = oracle.OracleZone(**wl.desc_kwargs(), eps=eps)
+    del eps
+    g, n0 = oracle.pulse(max_steps + 1, oz.dt, wl.omega_c, wl.width)
+    pat = oz.preset_pattern()[None]
+    om = np.array(wl.omegas)
+    oz.run(1, patterns=pat, profiles=g[None, :1], k_src=wl.k_src, omegas=om)
+    steps, t0 = 0, time.perf_counter()
+    while steps < max_steps and time.perf_counter() - t0 < budget_s:
+        oz.run(1, patterns=pat, profiles=g[None, steps + 1:steps + 2], k_src=wl.k_src, omegas=om, reset=False,
+               n_start=steps + 1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(wl.cells * steps / dt / 1e9, 5), "unit": "Gcell-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d time steps of the full %s zone (FP64, whole-zone H+E updates, source, 3-frequency "
+                      "exit-plane DFT), after one untimed step, %.1f s" % (steps, wl.name, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 4 GiB device copy (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs one zone on one GPU; --gpus %d is not supported "
+              "(zones shard one per GPU, see the design notes)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2501_07979_amd import zda
+    from paper_2501_07979_amd.workloads import WORKLOADS
+
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]()
+    K = len(wl.omegas)
+    print("bench: building %s (%d cells)" % (wl.name, wl.cells), file=sys.stderr, flush=True)
+    eps = torch.from_numpy(wl.eps()).cuda()
+    zone = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+    del eps
+    run_kw = dict(k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    print("bench: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+    zone.run(args.warmup, wl.omegas, **run_kw)
+    torch.cuda.synchronize()
+    print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    zone.run(args.steps, wl.omegas, timing=True, **run_kw)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    tm = zone.last_timing()
+    # sanity: the run produced finite monitors
+    plane = zone.dft(zda.MON_PLANE)
+    assert torch.isfinite(torch.view_as_real(plane)).all().item()
+    zone.close()
+
+    gcells = wl.cells * args.steps / (ms / 1e3) / 1e9
+    hb, eb, fused = algorithmic_bytes(wl, K)
+    e_avg = tm.e_ms / tm.e_launches
+    h_avg = tm.h_ms / tm.h_launches
+    achieved = eb / (e_avg / 1e3) / 1e9
+    traffic = load_traffic(wl.name)
+    out = {
+        "metric": METRIC,
+        "value": round(gcells, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "cells": wl.cells,
+            "zone": {"n_fold": wl.n_fold, "m": wl.m, "nr": wl.nr, "nphi": wl.nphi, "nz": wl.nz,
+                     "r_in": wl.r_in, "pml": list(wl.pml)},
+            "frequencies": K,
+            "run_steps_of_full_job": wl.steps,
+            "h_kernel_ms": round(h_avg, 5),
+            "e_kernel_ms": round(e_avg, 5),
+            "wall_s": round(wall, 3),
+            "fused_min_bytes_per_cell_update": round(fused / wl.cells, 2),
+            "fused_min_roofline_frac": round(gcells * 1e9 * (fused / wl.cells) / (HBM_PEAK_GBS * 1e9), 4),
+        },
+        "roofline": {"bound": "hbm", "kernel": "e_step_kernel", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": eb},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * zda.h -- C ABI of the MI355X (gfx950) library for one zone of zoned discrete
+ * axisymmetry (ZDA), arXiv 2501.07979: the cylindrical (r, phi, z) Yee FDTD
+ * of one annular-sector zone with n-fold Bloch periodicity in phi, CPML in r
+ * and z, a soft pulsed current source, on-the-fly multi-frequency DFT
+ * monitors, and the adjoint run with the permittivity-gradient overlap.
+ *
+ * Conventions shared by every call
+ *  - Units eps0 = mu0 = c = 1, mu = 1.  Cell (i, j, k): i radial in [0, nr),
+ *    j azimuthal in [0, nphi), k axial in [0, nz).  r_p = r_in + p dr,
+ *    dphi = 2 pi / (n_fold nphi), dt = courant * min(dr, dz).
+ *  - Every 3-D array is [nz][nr][nphi] (phi fastest), row-major, FP32.
+ *    Complex arrays are interleaved (re, im) pairs of float.
+ *  - Component samples sit on the staggered Yee grid: E_r (i+1/2, j, k),
+ *    E_phi (i, j+1/2, k), E_z (i, j, k+1/2), H_r (i, j+1/2, k+1/2),
+ *    H_phi (i+1/2, j, k+1/2), H_z (i+1/2, j+1/2, k).  The stored field is the
+ *    physical Bloch field; crossing the wedge boundary multiplies by
+ *    exp(+-i m 2 pi / n_fold) (eq. 1-2 of the paper).
+ *  - Pointers flagged *_on_device are HIP device pointers on the zone's
+ *    device, otherwise host pointers.  Input buffers are copied; the caller
+ *    keeps ownership of everything it passes.  The zone owns all its device
+ *    memory and frees it in zda_zone_destroy.
+ *  - Calls that take a `stream` (a hipStream_t, NULL = default stream) are
+ *    asynchronous on it unless they read into host memory.  Calls on one
+ *    zone must not overlap; different zones are independent.
+ *  - Every call returns a zda_status; no exception or abort crosses the ABI.
+ *    zda_last_error() gives a message for the last failure on the calling
+ *    thread.
+ */
+#ifndef ZDA_H
+#define ZDA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ZDA_OK = 0,
+    ZDA_ERR_ARG = 1,          /* bad sizes, indices, NULL pointer, buffer too small */
+    ZDA_ERR_CFL = 2,          /* Courant number at or above the stability bound */
+    ZDA_ERR_UNSUPPORTED = 3,  /* r_in <= 0 (axis zone) or an unsupported preset */
+    ZDA_ERR_OOM = 4,          /* device allocation failed */
+    ZDA_ERR_STATE = 5,        /* call out of order (e.g. gradient without forward volume DFT) */
+    ZDA_ERR_HIP = 6,          /* a HIP runtime call failed */
+    ZDA_ERR_DIVERGED = 7      /* non-finite or exploding fields found by the watchdog */
+} zda_status;
+
+#define ZDA_MAX_FREQ 8        /* frequencies per run (K) */
+
+/*
+ * Zone description (a zone is radii, wedge angle 2 pi / n, height, grid steps
+ * and an eps map: Fig. 2 caption and the section on the cylindrical solver).
+ * pml_* widths are cells (0 = bare PEC wall on that face).  pml_sigma_max
+ * <= 0 selects 0.8 (order + 1) / step; pml_alpha is the constant CFS shift.
+ * The inner r-layer is the regularised one (radius stretched with |Sigma|).
+ * k_mon: exit-plane monitor index in [1, nz).  Design layer k in
+ * [design_k0, design_k1) over all i, j; eq. (6) maps rho to
+ * eps = eps_bg + rho (eps_hi - eps_bg).
+ */
+typedef struct {
+    double r_in;            /* inner radius (> 0), length units */
+    int nr, nphi, nz;       /* cells */
+    int n_fold;             /* wedge angle tau = 2 pi / n_fold */
+    int m;                  /* Bloch angular momentum of the forward run */
+    double dr, dz;          /* grid steps */
+    double courant;         /* dt = courant * min(dr, dz) */
+    int pml_r_in, pml_r_out, pml_z_lo, pml_z_hi;
+    double pml_order, pml_sigma_max_r, pml_sigma_max_z, pml_alpha;
+    int k_mon;
+    int design_k0, design_k1;
+    double eps_bg, eps_hi;
+} zda_zone_desc;
+
+typedef struct zda_zone zda_zone;
+
+/* Fill *d with defaults (PML 8 cells everywhere, order 3, alpha 0.05,
+ * courant 0.5, eps_bg 1, eps_hi 6.25); sizes are left zero. */
+void zda_zone_desc_default(zda_zone_desc *d);
+
+/*
+ * Create a zone on the current HIP device.  eps: nz*nr*nphi FP32 [k][i][j]
+ * (may be NULL: eps = 1).  Errors: ZDA_ERR_ARG (sizes < 1, n_fold < 1, PML
+ * wider than half the extent, k_mon or design layer out of range),
+ * ZDA_ERR_CFL (courant * min(dr,dz) * sqrt(1/dr^2 + 1/(r_in dphi)^2 + 1/dz^2)
+ * >= 1), ZDA_ERR_UNSUPPORTED (r_in <= 0), ZDA_ERR_OOM.
+ */
+zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_device,
+                           zda_zone **out);
+
+/* NULL-safe; waits for the zone's work to finish. */
+void zda_zone_destroy(zda_zone *z);
+
+/* Replace the permittivity (nz*nr*nphi FP32).  Synchronous. */
+zda_status zda_zone_set_eps(zda_zone *z, const float *eps, int on_device);
+
+/* eq. (6) inside the design layer: rho is (design_k1-design_k0)*nr*nphi FP32
+ * in [0, 1] (values are not clamped).  Synchronous. */
+zda_status zda_zone_set_design(zda_zone *z, const float *rho, int on_device);
+
+/* Source presets (the normally incident plane wave decomposes into m = +-1,
+ * section "Results and Discussion"). */
+typedef enum {
+    ZDA_SRC_PLANE_CIRC = 0,   /* J_r = -g e^{i m phi_j}/dz, J_phi = -i sgn(m) g e^{i m phi_{j+1/2}}/dz; |m| = 1 */
+    ZDA_SRC_RADIAL = 1,       /* J_r = -g / dz; m = 0 */
+    ZDA_SRC_CUSTOM = 2        /* n_profiles patterns, each [2][nr][nphi] complex (J_r, J_phi) */
+} zda_src_kind;
+
+/*
+ * Soft current sheet on plane k_src (in [1, nz)):
+ * J^{n+1/2}(x) = sum_p pattern_p(x) profile_p(n).  For presets the profile
+ * is the pulse g(t) = sin(omega_c (t - t0)) exp(-(t - t0)^2 / (2 width^2)),
+ * t = (n + 1/2) dt, t0 = (n0 + 1/2) dt, n0 < 0 selects round(6 width / dt),
+ * g = 0 for n > 2 n0.  CUSTOM: patterns (device or host, per
+ * patterns_on_device) and profiles (host, complex [n_profiles][nsteps],
+ * interleaved doubles); at most ZDA_MAX_FREQ profiles.
+ */
+typedef struct {
+    int kind;                 /* zda_src_kind */
+    int k_src;
+    double omega_c, width;
+    int n0;
+    int n_profiles;           /* CUSTOM only */
+    const float *patterns;    /* CUSTOM only */
+    int patterns_on_device;
+    const double *profiles;   /* CUSTOM only, host */
+} zda_source;
+
+/* dft_flags */
+#define ZDA_DFT_PLANE   1     /* exit plane k_mon: E_r, E_phi */
+#define ZDA_DFT_VOLUME  2     /* design layer: E_r, E_phi, E_z (needed by zda_adjoint_grad) */
+#define ZDA_RUN_CONTINUE 4    /* keep fields/aux/DFTs from the previous call (no reset) */
+#define ZDA_RUN_TIMING   8    /* bracket every update kernel with HIP events (zda_zone_last_timing) */
+
+/*
+ * Time-step nsteps leap-frog steps (H half-step then E half-step with the
+ * source) and accumulate Ehat(w_k) = dt sum_{n=1..T} E^n e^{i w_k n dt} for
+ * K <= ZDA_MAX_FREQ angular frequencies omega[] (host).  Resets fields,
+ * auxiliaries and DFTs first unless ZDA_RUN_CONTINUE.  Asynchronous on
+ * `stream`.  Errors: ZDA_ERR_ARG, ZDA_ERR_HIP.
+ */
+zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const double *omega, int K,
+                        int dft_flags, void *stream);
+
+/* monitor ids */
+#define ZDA_MON_PLANE  0      /* layout [K][2][nr][nphi] complex (E_r, E_phi at k_mon) */
+#define ZDA_MON_VOLUME 1      /* layout [K][3][design_k1-design_k0][nr][nphi] complex */
+#define ZDA_MON_ADJOINT_VOLUME 2  /* same layout, the adjoint run's volume DFT */
+
+/*
+ * Copy a DFT monitor into out (out_floats floats available; interleaved
+ * complex on the native staggered points).  Synchronises if out is host
+ * memory.  ZDA_ERR_ARG if out is too small, ZDA_ERR_STATE if the monitor was
+ * not accumulated by the last run.
+ */
+zda_status zda_dft_fields(zda_zone *z, int monitor, float *out, size_t out_floats, int out_on_device);
+
+/*
+ * Adjoint gradient (hybrid time/frequency adjoint with broadband adjoint
+ * sources, section on the cylindrical solver; eq. 6).  dF_dE: the
+ * Wirtinger derivative dF/dEhat of a real objective with respect to the last
+ * forward run's exit-plane DFT, [K][2][nr][nphi] complex.  Runs the adjoint
+ * (Bloch order -m, same eps and PML, current W^{-1} dF/dEhat_k / (i wt_k) on
+ * plane k_mon with time profiles mixing K pulses so that each frequency sees
+ * exactly its own pattern), accumulates its design-volume DFT and writes
+ * grad_rho[(design_k1-design_k0)*nr*nphi] = dF/drho =
+ * (eps_hi - eps_bg) sum_k sum_alpha 2 Re[wt_k^2 W Xhat Ehat].  adj_width <= 0
+ * reuses the forward pulse width (and n0).  Requires a forward run with
+ * ZDA_DFT_VOLUME (ZDA_ERR_STATE otherwise).  Synchronises if grad_rho is
+ * host memory.
+ */
+zda_status zda_adjoint_grad(zda_zone *z, const float *dF_dE, int dF_on_device, float *grad_rho,
+                            int grad_on_device, double adj_width, void *stream);
+
+/* Raw field access (testing and checkpoints).  comp: 0..5 = E_r, E_phi, E_z,
+ * H_r, H_phi, H_z; buffer nz*nr*nphi complex.  Writing E_phi also seeds the
+ * r-layer's integrated-field auxiliary as the first step expects.
+ * Synchronous. */
+zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_device);
+zda_status zda_zone_write_field(zda_zone *z, int comp, const float *in, int in_on_device);
+
+typedef struct {
+    size_t cells;             /* nr*nphi*nz */
+    size_t device_bytes;      /* owned device memory */
+    double dt;
+    double cfl;               /* courant * min(dr,dz) * sqrt(...) (< 1 when stable) */
+    int launch_chunks;        /* z chunks of the update kernels */
+} zda_zone_info;
+
+zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);
+
+/* Per-kernel device time of the last zda_fdtd_run made with ZDA_RUN_TIMING
+ * (HIP events on the run's stream around each launch).  Synchronises. */
+typedef struct {
+    int h_launches, e_launches;
+    double h_ms, e_ms;        /* summed kernel durations */
+} zda_timing;
+
+zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
+
+const char *zda_status_str(int status);
+const char *zda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZDA_H */

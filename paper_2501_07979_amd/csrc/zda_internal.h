@@ -1,0 +1,74 @@
+// zda_internal.h -- device-side parameter blocks shared by the gfx950 kernels
+// and the host runtime of the ZDA zone library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/zda.h"
+
+namespace zda {
+
+// Per-radial-row constants (index i, FP32, computed in FP64 on the host).
+// "int" = at r_i, "half" = at r_{i+1/2}.
+struct RowCoef {
+    float inv_rdphi_int, inv_rdphi_half;   // 1/(r dphi)
+    float inv_2r_int, inv_2r_half;         // 1/(2 r)
+    // divide-by-stretch recursions y = g1 x - g2 u, u <- c u + dt y
+    float g1_s_int, g2_s_int, g1_s_half, g2_s_half;   // radial lengths l = dr (1 + sigma F)
+    float g1_t_int, g2_t_int, g1_t_half, g2_t_half;   // radius ratio R / r = 1 + (Sigma/r) F
+    float hz_c1, hz_c0;                    // Sigma_{i+1}/(r_{i+1/2} dr), Sigma_i/(r_{i+1/2} dr)
+    float ez_c1, ez_c0;                    // Sigma_{i+1/2}/(r_i dr), Sigma_{i-1/2}/(r_i dr)
+};
+
+struct ZCoef {
+    float g1_int, g2_int, g1_half, g2_half;   // axial lengths dz (1 + sigma_z F)
+};
+
+// Arguments of the update kernels (passed by value).
+struct StepArgs {
+    int nr, nphi, nz;
+    int pr0, pr1, pz0, pz1;        // layer widths
+    int dR, dZ;                    // slab thicknesses
+    float dt, inv_dr, inv_dz;
+    float cr, cz;                  // exp(-alpha dt)
+    float2 seam_p, seam_m;         // exp(+i m tau), exp(-i m tau)
+    // fields [nz][nr][nphi]
+    float2 *Er, *Ep, *Ez, *Hr, *Hp, *Hz;
+    const float *ceps;             // dt/eps per cell
+    float2 *auxR;                  // [10][nz][dR][nphi]
+    float2 *auxZ;                  // [4][dZ][nr][nphi]
+    const RowCoef *rows;           // [nr]
+    const ZCoef *zrows;            // [nz]
+    // source
+    int k_src, n_prof;
+    const float2 *pattern;         // [P][2][nr][nphi]
+    const float2 *profile;         // [T][P]
+    // DFT
+    int K;
+    const float2 *twiddle;         // [T][K]: dt e^{i w_k (n+1) dt}
+    int k_mon;
+    float2 *dft_plane;             // [K][2][nr][nphi] or null
+    int k0, k1;
+    float2 *dft_vol;               // [K][3][k1-k0][nr][nphi] or null
+    int kchunk;                    // planes per z-chunk
+};
+
+enum { AUX_HR_T, AUX_HP_S, AUX_HZ_S, AUX_HZ_T, AUX_V_HP,
+       AUX_ER_T, AUX_EP_S, AUX_EZ_S, AUX_EZ_T, AUX_U_EP, N_AUX_R };
+enum { ZAUX_HR, ZAUX_HP, ZAUX_ER, ZAUX_EP, N_AUX_Z };
+
+void launch_h_step(const StepArgs &a, int n, hipStream_t s);
+void launch_e_step(const StepArgs &a, int n, hipStream_t s);
+void launch_fill(float2 *p, size_t n, hipStream_t s);
+void launch_design_dt(float *ceps, const float *rho, size_t n, double eps_bg, double eps_hi, double dt,
+                      hipStream_t s);
+void launch_inv_eps(float *ceps, const float *eps, size_t n, double dt, hipStream_t s);
+void launch_seed_u(float2 *aux_u, const float2 *Ep, int nr, int nphi, int nz, int pr0, int pr1, float dt,
+                   hipStream_t s);
+void launch_adjoint_pattern(float2 *pat, const float2 *dFdE, const float2 *fac, int K, int nr, int nphi,
+                            hipStream_t s);
+void launch_overlap(float *grad, const float2 *fwd, const float2 *adj, const float2 *wr, const float2 *wz,
+                    int K, int nd, int nr, int nphi, float scale, hipStream_t s);
+void launch_nonfinite(const float2 *p, size_t n, int *flag, hipStream_t s);
+
+}  // namespace zda

@@ -1,0 +1,383 @@
+// zda_kernels.hip -- gfx950 kernels of the ZDA zone library.
+//
+// The H and E half-steps of the cylindrical Yee leap-frog (eq. 3-5 of arXiv
+// 2501.07979, section on the cylindrical solver) for one n-fold Bloch wedge.
+// Each thread owns one (i, j) column and marches through a chunk of z-planes,
+// keeping the column's previous/next plane in registers; phi is the fastest
+// index so a 64-lane wavefront reads 64 consecutive complex samples (512 B)
+// per access.  The E half-step fuses the soft source sheet and the exit-plane
+// and design-volume DFT accumulation, so the fields are read once per step.
+//
+// PML: complex stretch of radial lengths (1 + sigma F), radii (1 + Sigma/r F)
+// and axial lengths; each stretched term x is divided by its stretch with one
+// auxiliary recursion y = g1 x - g2 u, u <- c u + dt y (F is the causal
+// one-pole filter dt / (1 - c e^{i w dt})).
+#include "zda_internal.h"
+
+namespace zda {
+
+namespace {
+
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 c_fma(float2 acc, float2 a, float2 b)   // acc + a*b
+{
+    return make_float2(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 zero2() { return make_float2(0.f, 0.f); }
+
+// y = x / (1 + s F) with the auxiliary u = F y
+__device__ __forceinline__ float2 div_stretch(float2 x, float2 *aux, float g1, float g2, float c, float dt)
+{
+    float2 u = *aux;
+    float2 y = make_float2(g1 * x.x - g2 * u.x, g1 * x.y - g2 * u.y);
+    *aux = make_float2(c * u.x + dt * y.x, c * u.y + dt * y.y);
+    return y;
+}
+
+__device__ __forceinline__ int slab_row(int q, int n, int d0, int d1)
+{
+    if (q < d0) return q;
+    if (q >= n - d1) return d0 + (q - (n - d1));
+    return -1;
+}
+
+constexpr int BX = 64;   // one wavefront along phi
+constexpr int BY = 4;    // radial rows per block
+
+// H^{n+1/2} = H^{n-1/2} - dt curlE(E^n); also advances V = F H_phi in the r-layer.
+__global__ __launch_bounds__(BX * BY) void h_step_kernel(StepArgs a, int n)
+{
+    const int j = blockIdx.x * BX + threadIdx.x;
+    const int i = blockIdx.y * BY + threadIdx.y;
+    if (j >= a.nphi || i >= a.nr) return;
+    const int kb = blockIdx.z * a.kchunk;
+    const int ke = min(kb + a.kchunk, a.nz);
+    const int nphi = a.nphi, nr = a.nr, nz = a.nz;
+    const size_t plane = (size_t)nr * nphi;
+    const int ir = slab_row(i, nr, a.pr0, a.pr1);
+    const int ir1 = (i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
+    const RowCoef rc = a.rows[i];
+    const int jp = (j + 1 < nphi) ? j + 1 : 0;
+    const bool wrap = (j + 1 >= nphi);
+    const size_t slabR = (size_t)nz * a.dR * nphi;
+    const size_t slabZ = (size_t)a.dZ * plane;
+    const float dt = a.dt;
+
+    size_t c = ((size_t)kb * nr + i) * nphi + j;
+    float2 er = a.Er[c], ep = a.Ep[c];
+    for (int k = kb; k < ke; ++k, c += plane) {
+        const size_t row = c - j;
+        const float2 ez = a.Ez[c];
+        float2 er_kp = zero2(), ep_kp = zero2();
+        if (k + 1 < nz) { er_kp = a.Er[c + plane]; ep_kp = a.Ep[c + plane]; }
+        float2 ez_jp = a.Ez[row + jp], er_jp = a.Er[row + jp];
+        if (wrap) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+        float2 ez_ip = zero2(), ep_ip = zero2();
+        if (i + 1 < nr) { ez_ip = a.Ez[c + nphi]; ep_ip = a.Ep[c + nphi]; }
+        const int kz = slab_row(k, nz, a.pz0, a.pz1);
+        const size_t sr = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi + j : 0;
+        const size_t sz = kz >= 0 ? ((size_t)kz * nr + i) * nphi + j : 0;
+        const ZCoef zc = a.zrows[k];
+
+        // H_r at (i, j+1/2, k+1/2)
+        if (i > 0) {
+            float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
+            float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
+            if (ir >= 0) t1 = div_stretch(t1, a.auxR + AUX_HR_T * slabR + sr, rc.g1_t_int, rc.g2_t_int, a.cr, dt);
+            if (kz >= 0) t2 = div_stretch(t2, a.auxZ + ZAUX_HR * slabZ + sz, zc.g1_half, zc.g2_half, a.cz, dt);
+            float2 h = a.Hr[c];
+            a.Hr[c] = make_float2(h.x - dt * (t1.x - t2.x), h.y - dt * (t1.y - t2.y));
+        }
+        // H_phi at (i+1/2, j, k+1/2)
+        {
+            float2 t1 = c_scale(c_sub(er_kp, er), a.inv_dz);
+            float2 t2 = c_scale(c_sub(ez_ip, ez), a.inv_dr);
+            if (kz >= 0) t1 = div_stretch(t1, a.auxZ + ZAUX_HP * slabZ + sz, zc.g1_half, zc.g2_half, a.cz, dt);
+            if (ir >= 0) t2 = div_stretch(t2, a.auxR + AUX_HP_S * slabR + sr, rc.g1_s_half, rc.g2_s_half, a.cr, dt);
+            float2 h = a.Hp[c];
+            h = make_float2(h.x - dt * (t1.x - t2.x), h.y - dt * (t1.y - t2.y));
+            a.Hp[c] = h;
+            if (ir >= 0) {
+                float2 *v = a.auxR + AUX_V_HP * slabR + sr;
+                float2 vv = *v;
+                *v = make_float2(a.cr * vv.x + dt * h.x, a.cr * vv.y + dt * h.y);
+            }
+        }
+        // H_z at (i+1/2, j+1/2, k)
+        if (k > 0) {
+            float2 t = c_add(c_scale(c_sub(ep_ip, ep), a.inv_dr), c_scale(c_add(ep_ip, ep), rc.inv_2r_half));
+            if (ir >= 0) {
+                const float2 *U = a.auxR + AUX_U_EP * slabR;
+                float2 u0 = U[sr];
+                float2 u1 = ir1 >= 0 ? U[((size_t)k * a.dR + ir1) * nphi + j] : zero2();
+                t = c_add(t, c_sub(c_scale(u1, rc.hz_c1), c_scale(u0, rc.hz_c0)));
+                t = div_stretch(t, a.auxR + AUX_HZ_S * slabR + sr, rc.g1_s_half, rc.g2_s_half, a.cr, dt);
+            }
+            t = c_sub(t, c_scale(c_sub(er_jp, er), rc.inv_rdphi_half));
+            if (ir >= 0) t = div_stretch(t, a.auxR + AUX_HZ_T * slabR + sr, rc.g1_t_half, rc.g2_t_half, a.cr, dt);
+            float2 h = a.Hz[c];
+            a.Hz[c] = make_float2(h.x - dt * t.x, h.y - dt * t.y);
+        }
+        er = er_kp;
+        ep = ep_kp;
+    }
+}
+
+// E^{n+1} = E^n + (dt/eps)(curlH(H^{n+1/2}) - J^{n+1/2}); source sheet, DFT
+// accumulation and U = F E_phi in the r-layer fused.
+__global__ __launch_bounds__(BX * BY) void e_step_kernel(StepArgs a, int n)
+{
+    const int j = blockIdx.x * BX + threadIdx.x;
+    const int i = blockIdx.y * BY + threadIdx.y;
+    if (j >= a.nphi || i >= a.nr) return;
+    const int kb = blockIdx.z * a.kchunk;
+    const int ke = min(kb + a.kchunk, a.nz);
+    const int nphi = a.nphi, nr = a.nr, nz = a.nz;
+    const size_t plane = (size_t)nr * nphi;
+    const int ir = slab_row(i, nr, a.pr0, a.pr1);
+    const int irm = (i > 0) ? slab_row(i - 1, nr, a.pr0, a.pr1) : -1;
+    const RowCoef rc = a.rows[i];
+    const int jm = (j > 0) ? j - 1 : nphi - 1;
+    const bool wrap = (j == 0);
+    const size_t slabR = (size_t)nz * a.dR * nphi;
+    const size_t slabZ = (size_t)a.dZ * plane;
+    const float dt = a.dt;
+    const int nd = a.k1 - a.k0;
+
+    size_t c = ((size_t)kb * nr + i) * nphi + j;
+    float2 hp_km = zero2(), hr_km = zero2();
+    if (kb > 0) { hp_km = a.Hp[c - plane]; hr_km = a.Hr[c - plane]; }
+    for (int k = kb; k < ke; ++k, c += plane) {
+        const size_t row = c - j;
+        const float2 hr = a.Hr[c], hp = a.Hp[c], hz = a.Hz[c];
+        float2 hz_jm = a.Hz[row + jm], hr_jm = a.Hr[row + jm];
+        if (wrap) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+        float2 hz_im = zero2(), hp_im = zero2();
+        if (i > 0) { hz_im = a.Hz[c - nphi]; hp_im = a.Hp[c - nphi]; }
+        const float ce = a.ceps[c];
+        const int kz = slab_row(k, nz, a.pz0, a.pz1);
+        const size_t sr = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi + j : 0;
+        const size_t sz = kz >= 0 ? ((size_t)kz * nr + i) * nphi + j : 0;
+        const ZCoef zc = a.zrows[k];
+        float2 jr = zero2(), jp = zero2();
+        if (k == a.k_src) {
+            for (int p = 0; p < a.n_prof; ++p) {
+                const float2 g = a.profile[(size_t)n * a.n_prof + p];
+                const float2 *pat = a.pattern + (size_t)p * 2 * plane + (size_t)i * nphi + j;
+                jr = c_fma(jr, pat[0], g);
+                jp = c_fma(jp, pat[plane], g);
+            }
+        }
+        float2 er = a.Er[c], ep = a.Ep[c], ez = a.Ez[c];
+        // E_r at (i+1/2, j, k)
+        if (k > 0) {
+            float2 t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
+            float2 t2 = c_scale(c_sub(hp, hp_km), a.inv_dz);
+            if (ir >= 0) t1 = div_stretch(t1, a.auxR + AUX_ER_T * slabR + sr, rc.g1_t_half, rc.g2_t_half, a.cr, dt);
+            if (kz >= 0) t2 = div_stretch(t2, a.auxZ + ZAUX_ER * slabZ + sz, zc.g1_int, zc.g2_int, a.cz, dt);
+            er = make_float2(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
+            a.Er[c] = er;
+        }
+        // E_phi at (i, j+1/2, k)
+        if (k > 0 && i > 0) {
+            float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
+            float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
+            if (kz >= 0) t1 = div_stretch(t1, a.auxZ + ZAUX_EP * slabZ + sz, zc.g1_int, zc.g2_int, a.cz, dt);
+            if (ir >= 0) t2 = div_stretch(t2, a.auxR + AUX_EP_S * slabR + sr, rc.g1_s_int, rc.g2_s_int, a.cr, dt);
+            ep = make_float2(ep.x + ce * (t1.x - t2.x - jp.x), ep.y + ce * (t1.y - t2.y - jp.y));
+            a.Ep[c] = ep;
+            if (ir >= 0) {
+                float2 *u = a.auxR + AUX_U_EP * slabR + sr;
+                float2 uu = *u;
+                *u = make_float2(a.cr * uu.x + dt * ep.x, a.cr * uu.y + dt * ep.y);
+            }
+        }
+        // E_z at (i, j, k+1/2)
+        if (i > 0) {
+            float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
+            if (ir >= 0) {
+                const float2 *V = a.auxR + AUX_V_HP * slabR;
+                float2 v1 = V[sr];
+                float2 v0 = irm >= 0 ? V[((size_t)k * a.dR + irm) * nphi + j] : zero2();
+                t = c_add(t, c_sub(c_scale(v1, rc.ez_c1), c_scale(v0, rc.ez_c0)));
+                t = div_stretch(t, a.auxR + AUX_EZ_S * slabR + sr, rc.g1_s_int, rc.g2_s_int, a.cr, dt);
+            }
+            t = c_sub(t, c_scale(c_sub(hr, hr_jm), rc.inv_rdphi_int));
+            if (ir >= 0) t = div_stretch(t, a.auxR + AUX_EZ_T * slabR + sr, rc.g1_t_int, rc.g2_t_int, a.cr, dt);
+            ez = make_float2(ez.x + ce * t.x, ez.y + ce * t.y);
+            a.Ez[c] = ez;
+        }
+        // DFT monitors: Ehat += dt e^{i w (n+1) dt} E^{n+1}
+        if (a.dft_plane && k == a.k_mon) {
+            for (int f = 0; f < a.K; ++f) {
+                const float2 tw = a.twiddle[(size_t)n * a.K + f];
+                float2 *o = a.dft_plane + (size_t)f * 2 * plane + (size_t)i * nphi + j;
+                o[0] = c_fma(o[0], tw, er);
+                o[plane] = c_fma(o[plane], tw, ep);
+            }
+        }
+        if (a.dft_vol && k >= a.k0 && k < a.k1) {
+            const size_t vs = (size_t)nd * plane;
+            for (int f = 0; f < a.K; ++f) {
+                const float2 tw = a.twiddle[(size_t)n * a.K + f];
+                float2 *o = a.dft_vol + (size_t)f * 3 * vs + (size_t)(k - a.k0) * plane + (size_t)i * nphi + j;
+                o[0] = c_fma(o[0], tw, er);
+                o[vs] = c_fma(o[vs], tw, ep);
+                o[2 * vs] = c_fma(o[2 * vs], tw, ez);
+            }
+        }
+        hp_km = hp;
+        hr_km = hr;
+    }
+}
+
+__global__ void fill_kernel(float2 *p, size_t n)
+{
+    size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; q < n; q += stride) p[q] = zero2();
+}
+
+__global__ void inv_eps_kernel(float *ceps, const float *eps, size_t n, double dt)
+{
+    size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) ceps[q] = (float)(dt / (double)eps[q]);
+}
+
+// eq. (6): eps = eps_bg + rho (eps_hi - eps_bg), rounded to FP32, then dt/eps
+__global__ void design_kernel(float *ceps, const float *rho, size_t n, double eps_bg, double eps_hi, double dt)
+{
+    size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) {
+        float e = (float)(eps_bg + (double)rho[q] * (eps_hi - eps_bg));
+        ceps[q] = (float)(dt / (double)e);
+    }
+}
+
+__global__ void seed_u_kernel(float2 *U, const float2 *Ep, int nr, int nphi, int nz, int pr0, int pr1, float dt)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int k = blockIdx.z;
+    if (j >= nphi) return;
+    const int ir = slab_row(i, nr, pr0, pr1);
+    if (ir < 0) return;
+    const int dR = pr0 + pr1;
+    float2 e = Ep[((size_t)k * nr + i) * nphi + j];
+    U[((size_t)k * dR + ir) * nphi + j] = make_float2(dt * e.x, dt * e.y);
+}
+
+__global__ void adjoint_pattern_kernel(float2 *pat, const float2 *g, const float2 *fac, int K, int nr, int nphi)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int ka = blockIdx.z;            // frequency * 2 + component
+    if (j >= nphi) return;
+    const size_t q = ((size_t)ka * nr + i) * nphi + j;
+    pat[q] = c_mul(g[q], fac[(size_t)ka * nr + i]);
+}
+
+// grad = scale * sum_k sum_a Re[wr(k,a,i) wz(k,a,kd) X E]; fixed summation order
+__global__ void overlap_kernel(float *grad, const float2 *fwd, const float2 *adj, const float2 *wr,
+                               const float2 *wz, int K, int nd, int nr, int nphi, float scale)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int kd = blockIdx.z;
+    if (j >= nphi) return;
+    const size_t plane = (size_t)nr * nphi;
+    const size_t vs = (size_t)nd * plane;
+    const size_t off = (size_t)kd * plane + (size_t)i * nphi + j;
+    float acc = 0.f;
+    for (int f = 0; f < K; ++f)
+        for (int a = 0; a < 3; ++a) {
+            const size_t q = ((size_t)f * 3 + a) * vs + off;
+            const float2 w = c_mul(wr[((size_t)f * 3 + a) * nr + i], wz[((size_t)f * 3 + a) * nd + kd]);
+            const float2 p = c_mul(adj[q], fwd[q]);
+            acc += w.x * p.x - w.y * p.y;
+        }
+    grad[off] = scale * acc;
+}
+
+__global__ void nonfinite_kernel(const float2 *p, size_t n, int *flag)
+{
+    size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; q < n; q += stride) {
+        float2 v = p[q];
+        if (!isfinite(v.x) || !isfinite(v.y)) *flag = 1;
+    }
+}
+
+}  // namespace
+
+void launch_h_step(const StepArgs &a, int n, hipStream_t s)
+{
+    dim3 block(BX, BY, 1);
+    dim3 grid((a.nphi + BX - 1) / BX, (a.nr + BY - 1) / BY, (a.nz + a.kchunk - 1) / a.kchunk);
+    hipLaunchKernelGGL(h_step_kernel, grid, block, 0, s, a, n);
+}
+
+void launch_e_step(const StepArgs &a, int n, hipStream_t s)
+{
+    dim3 block(BX, BY, 1);
+    dim3 grid((a.nphi + BX - 1) / BX, (a.nr + BY - 1) / BY, (a.nz + a.kchunk - 1) / a.kchunk);
+    hipLaunchKernelGGL(e_step_kernel, grid, block, 0, s, a, n);
+}
+
+void launch_fill(float2 *p, size_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+}
+
+void launch_inv_eps(float *ceps, const float *eps, size_t n, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(inv_eps_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ceps, eps, n, dt);
+}
+
+void launch_design_dt(float *ceps, const float *rho, size_t n, double eps_bg, double eps_hi, double dt,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(design_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ceps, rho, n, eps_bg,
+                       eps_hi, dt);
+}
+
+void launch_seed_u(float2 *U, const float2 *Ep, int nr, int nphi, int nz, int pr0, int pr1, float dt,
+                   hipStream_t s)
+{
+    hipLaunchKernelGGL(seed_u_kernel, dim3((nphi + 63) / 64, nr, nz), dim3(64), 0, s, U, Ep, nr, nphi, nz, pr0,
+                       pr1, dt);
+}
+
+void launch_adjoint_pattern(float2 *pat, const float2 *g, const float2 *fac, int K, int nr, int nphi,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(adjoint_pattern_kernel, dim3((nphi + 63) / 64, nr, 2 * K), dim3(64), 0, s, pat, g, fac, K,
+                       nr, nphi);
+}
+
+void launch_overlap(float *grad, const float2 *fwd, const float2 *adj, const float2 *wr, const float2 *wz,
+                    int K, int nd, int nr, int nphi, float scale, hipStream_t s)
+{
+    hipLaunchKernelGGL(overlap_kernel, dim3((nphi + 63) / 64, nr, nd), dim3(64), 0, s, grad, fwd, adj, wr, wz, K,
+                       nd, nr, nphi, scale);
+}
+
+void launch_nonfinite(const float2 *p, size_t n, int *flag, hipStream_t s)
+{
+    if (n == 0) return;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, flag);
+}
+
+}  // namespace zda

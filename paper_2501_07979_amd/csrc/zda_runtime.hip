@@ -1,0 +1,778 @@
+// zda_runtime.hip -- host runtime of the ZDA zone library: the C ABI of
+// include/zda.h.  Zone setup (FP64 precompute of the per-row metric and PML
+// constants, device allocation), the time loop, the broadband adjoint source
+// and the gradient overlap (arXiv 2501.07979, section on the cylindrical
+// solver and eq. 6).  All per-cell work runs in zda_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "zda_internal.h"
+
+using cd = std::complex<double>;
+using namespace zda;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+zda_status fail(zda_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(ZDA_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// graded conductivity at coordinate p (cell units) on an axis of n cells
+double grade(double p, int n, int d0, int d1, double order, double smax)
+{
+    double rho = 0.0;
+    if (d0 > 0 && p < d0) rho = (d0 - p) / d0;
+    else if (d1 > 0 && p > n - d1) rho = (p - (n - d1)) / d1;
+    return rho > 0.0 ? smax * std::pow(rho, order) : 0.0;
+}
+
+}  // namespace
+
+struct zda_zone {
+    zda_zone_desc d;
+    int device = 0;
+    double dt = 0, dphi = 0, tau = 0, cfl = 0;
+    size_t ncell = 0, plane = 0;
+    int dR = 0, dZ = 0, nd = 0, kchunk = 1;
+    // FP64 layer constants: [0] integer points, [1] half points
+    std::vector<double> sig_r[2], Sig_r[2], sgt_r[2], sig_z[2];
+    double cr = 1, cz = 1;
+    // device memory
+    float2 *F[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    float *ceps = nullptr;
+    float2 *auxR = nullptr, *auxZ = nullptr;
+    RowCoef *rows = nullptr;
+    ZCoef *zrows = nullptr;
+    float2 *dft_plane = nullptr, *dft_vol = nullptr, *dft_vol_adj = nullptr;
+    float2 *pattern = nullptr, *profile = nullptr, *twiddle = nullptr, *scratch = nullptr;
+    size_t cap_pattern = 0, cap_profile = 0, cap_twiddle = 0, cap_scratch = 0;
+    int *flag = nullptr;
+    size_t bytes = 0;
+    // host staging (kept until the next call)
+    std::vector<float2> st_pat, st_prof, st_tw, st_misc;
+    // state of the last forward run
+    int n_done = 0;
+    int last_K = 0;
+    double last_omega[ZDA_MAX_FREQ] = {0};
+    int last_T = 0;
+    double last_width = 0;
+    int last_n0 = -1;
+    bool have_plane = false, have_vol = false, have_vol_adj = false;
+    // per-launch timing events of the last timed run
+    std::vector<hipEvent_t> ev;
+    int timed_steps = 0;
+};
+
+namespace {
+
+template <typename T>
+zda_status dev_alloc(zda_zone *z, T **p, size_t count)
+{
+    if (count == 0) { *p = nullptr; return ZDA_OK; }
+    void *q = nullptr;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ZDA_ERR_OOM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    *p = (T *)q;
+    z->bytes += count * sizeof(T);
+    return ZDA_OK;
+}
+
+template <typename T>
+zda_status ensure(zda_zone *z, T **p, size_t *cap, size_t count)
+{
+    if (count <= *cap) return ZDA_OK;
+    if (*p) { (void)hipFree(*p); z->bytes -= *cap * sizeof(T); *p = nullptr; *cap = 0; }
+    zda_status st = dev_alloc(z, p, count);
+    if (st == ZDA_OK) *cap = count;
+    return st;
+}
+
+void free_all(zda_zone *z)
+{
+    for (auto e : z->ev) (void)hipEventDestroy(e);
+    z->ev.clear();
+    for (auto &f : z->F) if (f) (void)hipFree(f);
+    void *ptrs[] = {z->ceps, z->auxR, z->auxZ, z->rows, z->zrows, z->dft_plane, z->dft_vol, z->dft_vol_adj,
+                    z->pattern, z->profile, z->twiddle, z->scratch, z->flag};
+    for (void *p : ptrs) if (p) (void)hipFree(p);
+}
+
+// s(w) = 1 + sigma F(w), F = dt / (1 - c e^{i w dt})
+cd stretch(double sigma, double c, double w, double dt)
+{
+    cd F = dt / (1.0 - c * std::exp(cd(0.0, w * dt)));
+    return 1.0 + sigma * F;
+}
+
+// Layer constants and per-row coefficients (the PML contract of the design
+// notes): radial lengths dr (1 + sigma F), radii R = r + Sigma F with Sigma
+// accumulated outwards in the outer layer and (regularised, |Sigma|) inwards
+// in the inner layer, axial lengths dz (1 + sigma_z F).
+void setup_layers(zda_zone *z, std::vector<RowCoef> &rows, std::vector<ZCoef> &zr)
+{
+    const zda_zone_desc &d = z->d;
+    const int nr = d.nr, nz = d.nz, d0 = d.pml_r_in, d1 = d.pml_r_out;
+    const double smr = d.pml_sigma_max_r > 0 ? d.pml_sigma_max_r : 0.8 * (d.pml_order + 1.0) / d.dr;
+    const double smz = d.pml_sigma_max_z > 0 ? d.pml_sigma_max_z : 0.8 * (d.pml_order + 1.0) / d.dz;
+    for (int h = 0; h < 2; ++h) {
+        z->sig_r[h].assign(nr + 1, 0.0);
+        z->Sig_r[h].assign(nr + 1, 0.0);
+        z->sgt_r[h].assign(nr + 1, 0.0);
+        z->sig_z[h].assign(nz + 1, 0.0);
+        for (int i = 0; i <= nr; ++i) z->sig_r[h][i] = grade(i + 0.5 * h, nr, d0, d1, d.pml_order, smr);
+        for (int k = 0; k <= nz; ++k)
+            z->sig_z[h][k] = grade(k + 0.5 * h, nz, d.pml_z_lo, d.pml_z_hi, d.pml_order, smz);
+    }
+    // Sigma on the lattice of integer and half points: each step of half a
+    // cell adds dr * sigma at the point in between.
+    if (d1 > 0) {
+        for (int i = nr - d1 + 1; i <= nr; ++i) z->Sig_r[0][i] = z->Sig_r[0][i - 1] + d.dr * z->sig_r[1][i - 1];
+        for (int i = nr - d1; i <= nr; ++i)
+            z->Sig_r[1][i] = (i > 0 ? z->Sig_r[1][i - 1] : 0.0) + d.dr * z->sig_r[0][i];
+    }
+    if (d0 > 0) {
+        for (int i = d0 - 1; i >= 0; --i) z->Sig_r[0][i] = z->Sig_r[0][i + 1] + d.dr * z->sig_r[1][i];
+        for (int i = d0 - 1; i >= 0; --i) z->Sig_r[1][i] = z->Sig_r[1][i + 1] + d.dr * z->sig_r[0][i + 1];
+    }
+    double worst = 0.0;
+    for (int h = 0; h < 2; ++h)
+        for (int i = 0; i <= nr; ++i) {
+            const double r = d.r_in + (i + 0.5 * h) * d.dr;
+            z->sgt_r[h][i] = z->Sig_r[h][i] / r;
+            worst = std::max(worst, -z->sgt_r[h][i]);
+        }
+    const double dt = z->dt;
+    z->cr = std::exp(-(d.pml_alpha + 2.0 * worst) * dt);
+    z->cz = std::exp(-d.pml_alpha * dt);
+    auto g1 = [&](double s) { return (float)(1.0 / (1.0 + s * dt)); };
+    auto g2 = [&](double s, double c) { return (float)(s * c / (1.0 + s * dt)); };
+    rows.resize(nr);
+    for (int i = 0; i < nr; ++i) {
+        const double ri = d.r_in + i * d.dr, rh = ri + 0.5 * d.dr;
+        RowCoef &rc = rows[i];
+        rc.inv_rdphi_int = (float)(1.0 / (ri * z->dphi));
+        rc.inv_rdphi_half = (float)(1.0 / (rh * z->dphi));
+        rc.inv_2r_int = (float)(0.5 / ri);
+        rc.inv_2r_half = (float)(0.5 / rh);
+        rc.g1_s_int = g1(z->sig_r[0][i]);
+        rc.g2_s_int = g2(z->sig_r[0][i], z->cr);
+        rc.g1_s_half = g1(z->sig_r[1][i]);
+        rc.g2_s_half = g2(z->sig_r[1][i], z->cr);
+        rc.g1_t_int = g1(z->sgt_r[0][i]);
+        rc.g2_t_int = g2(z->sgt_r[0][i], z->cr);
+        rc.g1_t_half = g1(z->sgt_r[1][i]);
+        rc.g2_t_half = g2(z->sgt_r[1][i], z->cr);
+        rc.hz_c1 = (float)((i + 1 < nr ? z->Sig_r[0][i + 1] : 0.0) / (rh * d.dr));
+        rc.hz_c0 = (float)(z->Sig_r[0][i] / (rh * d.dr));
+        rc.ez_c1 = (float)(z->Sig_r[1][i] / (ri * d.dr));
+        rc.ez_c0 = (float)((i > 0 ? z->Sig_r[1][i - 1] : 0.0) / (ri * d.dr));
+    }
+    zr.resize(nz);
+    for (int k = 0; k < nz; ++k) {
+        zr[k].g1_int = g1(z->sig_z[0][k]);
+        zr[k].g2_int = g2(z->sig_z[0][k], z->cz);
+        zr[k].g1_half = g1(z->sig_z[1][k]);
+        zr[k].g2_half = g2(z->sig_z[1][k], z->cz);
+    }
+}
+
+StepArgs step_args(zda_zone *z, int m)
+{
+    StepArgs a{};
+    const zda_zone_desc &d = z->d;
+    a.nr = d.nr; a.nphi = d.nphi; a.nz = d.nz;
+    a.pr0 = d.pml_r_in; a.pr1 = d.pml_r_out; a.pz0 = d.pml_z_lo; a.pz1 = d.pml_z_hi;
+    a.dR = z->dR; a.dZ = z->dZ;
+    a.dt = (float)z->dt;
+    a.inv_dr = (float)(1.0 / d.dr);
+    a.inv_dz = (float)(1.0 / d.dz);
+    a.cr = (float)z->cr; a.cz = (float)z->cz;
+    const double ph = m * z->tau;
+    a.seam_p = make_float2((float)std::cos(ph), (float)std::sin(ph));
+    a.seam_m = make_float2((float)std::cos(ph), (float)-std::sin(ph));
+    a.Er = z->F[0]; a.Ep = z->F[1]; a.Ez = z->F[2]; a.Hr = z->F[3]; a.Hp = z->F[4]; a.Hz = z->F[5];
+    a.ceps = z->ceps;
+    a.auxR = z->auxR; a.auxZ = z->auxZ;
+    a.rows = z->rows; a.zrows = z->zrows;
+    a.k_mon = d.k_mon;
+    a.k0 = d.design_k0; a.k1 = d.design_k1;
+    a.kchunk = z->kchunk;
+    return a;
+}
+
+zda_status reset_state(zda_zone *z, hipStream_t s)
+{
+    for (auto f : z->F) launch_fill(f, z->ncell, s);
+    if (z->auxR) launch_fill(z->auxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, s);
+    if (z->auxZ) launch_fill(z->auxZ, (size_t)N_AUX_Z * z->dZ * z->plane, s);
+    HIP_TRY(hipGetLastError());
+    z->n_done = 0;
+    return ZDA_OK;
+}
+
+// The pulse of the source presets and of the adjoint mixing (window [0, 2 n0]).
+double pulse_at(long n, double dt, double wc, double w, int n0)
+{
+    if (n < 0 || n > 2L * n0) return 0.0;
+    const double t = (double)(n - n0) * dt;
+    return std::sin(wc * t) * std::exp(-t * t / (2.0 * w * w));
+}
+
+int default_n0(double w, double dt) { return (int)std::lround(6.0 * w / dt); }
+
+// Core time loop: P source patterns already on the device in z->pattern,
+// host complex profiles prof[p*nsteps + n], K frequencies.
+zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *prof, const double *omega, int K,
+                    float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, bool timing = false)
+{
+    const size_t T = (size_t)std::max(nsteps, 1);
+    zda_status st;
+    if ((st = ensure(z, &z->profile, &z->cap_profile, T * std::max(P, 1))) != ZDA_OK) return st;
+    if ((st = ensure(z, &z->twiddle, &z->cap_twiddle, T * std::max(K, 1))) != ZDA_OK) return st;
+    if (reset) {
+        if ((st = reset_state(z, s)) != ZDA_OK) return st;
+        if (dft_plane) launch_fill(dft_plane, (size_t)K * 2 * z->plane, s);
+        if (dft_vol) launch_fill(dft_vol, (size_t)K * 3 * z->nd * z->plane, s);
+    }
+    z->st_prof.assign(T * std::max(P, 1), make_float2(0.f, 0.f));
+    for (int n = 0; n < nsteps; ++n)
+        for (int p = 0; p < P; ++p) {
+            const cd g = prof[(size_t)p * nsteps + n];
+            z->st_prof[(size_t)n * P + p] = make_float2((float)g.real(), (float)g.imag());
+        }
+    z->st_tw.assign(T * std::max(K, 1), make_float2(0.f, 0.f));
+    for (int n = 0; n < nsteps; ++n)
+        for (int k = 0; k < K; ++k) {
+            const double N = (double)(z->n_done + n + 1);
+            const cd tw = z->dt * std::exp(cd(0.0, omega[k] * N * z->dt));
+            z->st_tw[(size_t)n * K + k] = make_float2((float)tw.real(), (float)tw.imag());
+        }
+    HIP_TRY(hipMemcpyAsync(z->profile, z->st_prof.data(), z->st_prof.size() * sizeof(float2),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(z->twiddle, z->st_tw.data(), z->st_tw.size() * sizeof(float2),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    StepArgs a = step_args(z, m);
+    a.k_src = k_src;
+    a.n_prof = P;
+    a.pattern = z->pattern;
+    a.profile = z->profile;
+    a.K = K;
+    a.twiddle = z->twiddle;
+    a.dft_plane = dft_plane;
+    a.dft_vol = dft_vol;
+    z->timed_steps = 0;
+    if (timing) {
+        const size_t need = 4 * (size_t)nsteps;
+        while (z->ev.size() < need) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            z->ev.push_back(e);
+        }
+        for (int n = 0; n < nsteps; ++n) {
+            HIP_TRY(hipEventRecord(z->ev[4 * n], s));
+            launch_h_step(a, n, s);
+            HIP_TRY(hipEventRecord(z->ev[4 * n + 1], s));
+            HIP_TRY(hipEventRecord(z->ev[4 * n + 2], s));
+            launch_e_step(a, n, s);
+            HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
+        }
+        z->timed_steps = nsteps;
+    } else {
+        for (int n = 0; n < nsteps; ++n) {
+            launch_h_step(a, n, s);
+            launch_e_step(a, n, s);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    z->n_done += nsteps;
+    return ZDA_OK;
+}
+
+// Gauss-Jordan inverse of a small complex matrix (row-major, n x n).
+bool invert(std::vector<cd> &A, int n)
+{
+    std::vector<cd> inv(n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::abs(A[r * n + c]) > std::abs(A[piv * n + c])) piv = r;
+        if (std::abs(A[piv * n + c]) == 0.0) return false;
+        for (int q = 0; q < n; ++q) { std::swap(A[c * n + q], A[piv * n + q]); std::swap(inv[c * n + q], inv[piv * n + q]); }
+        const cd p = A[c * n + c];
+        for (int q = 0; q < n; ++q) { A[c * n + q] /= p; inv[c * n + q] /= p; }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const cd f = A[r * n + c];
+            for (int q = 0; q < n; ++q) { A[r * n + q] -= f * A[c * n + q]; inv[r * n + q] -= f * inv[c * n + q]; }
+        }
+    }
+    A = inv;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void zda_zone_desc_default(zda_zone_desc *d)
+{
+    if (!d) return;
+    std::memset(d, 0, sizeof *d);
+    d->n_fold = 1;
+    d->dr = d->dz = 1.0;
+    d->courant = 0.5;
+    d->pml_r_in = d->pml_r_out = d->pml_z_lo = d->pml_z_hi = 8;
+    d->pml_order = 3.0;
+    d->pml_alpha = 0.05;
+    d->eps_bg = 1.0;
+    d->eps_hi = 6.25;
+}
+
+zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_device, zda_zone **out)
+{
+    if (!d || !out) return fail(ZDA_ERR_ARG, "NULL descriptor or output");
+    *out = nullptr;
+    if (d->nr < 1 || d->nphi < 1 || d->nz < 2 || d->n_fold < 1)
+        return fail(ZDA_ERR_ARG, "sizes must be >= 1 (nz >= 2) and n_fold >= 1");
+    if (!(d->dr > 0) || !(d->dz > 0) || !(d->courant > 0)) return fail(ZDA_ERR_ARG, "dr, dz, courant must be > 0");
+    if (!(d->r_in > 0)) return fail(ZDA_ERR_UNSUPPORTED, "r_in must be > 0 (the axis zone is not supported)");
+    if (d->pml_r_in < 0 || d->pml_r_out < 0 || d->pml_z_lo < 0 || d->pml_z_hi < 0 ||
+        2 * d->pml_r_in > d->nr || 2 * d->pml_r_out > d->nr || 2 * d->pml_z_lo > d->nz || 2 * d->pml_z_hi > d->nz)
+        return fail(ZDA_ERR_ARG, "PML widths must be in [0, extent/2]");
+    if (d->k_mon < 1 || d->k_mon >= d->nz) return fail(ZDA_ERR_ARG, "k_mon must be in [1, nz)");
+    if (!(d->design_k0 == 0 && d->design_k1 == 0) &&
+        (d->design_k0 < 0 || d->design_k1 > d->nz || d->design_k0 >= d->design_k1))
+        return fail(ZDA_ERR_ARG, "design layer must satisfy 0 <= k0 < k1 <= nz");
+    if (!(d->pml_order > 0) || d->pml_alpha < 0) return fail(ZDA_ERR_ARG, "bad PML profile");
+    const double dphi = 2.0 * M_PI / ((double)d->n_fold * d->nphi);
+    const double dt = d->courant * std::min(d->dr, d->dz);
+    const double cfl = dt * std::sqrt(1.0 / (d->dr * d->dr) + 1.0 / std::pow(d->r_in * dphi, 2) + 1.0 / (d->dz * d->dz));
+    if (cfl >= 1.0) return fail(ZDA_ERR_CFL, "Courant number %.4f >= 1 (dt sqrt(1/dr^2+1/(r_in dphi)^2+1/dz^2))", cfl);
+
+    zda_zone *z = new (std::nothrow) zda_zone();
+    if (!z) return fail(ZDA_ERR_OOM, "host allocation failed");
+    z->d = *d;
+    if (hipGetDevice(&z->device) != hipSuccess) { delete z; return fail(ZDA_ERR_HIP, "no HIP device"); }
+    z->dphi = dphi;
+    z->tau = 2.0 * M_PI / d->n_fold;
+    z->dt = dt;
+    z->cfl = cfl;
+    z->plane = (size_t)d->nr * d->nphi;
+    z->ncell = z->plane * d->nz;
+    z->dR = d->pml_r_in + d->pml_r_out;
+    z->dZ = d->pml_z_lo + d->pml_z_hi;
+    z->nd = d->design_k1 - d->design_k0;
+    // z-chunks: enough wavefronts to fill 256 CUs, chunks of at least 8 planes
+    {
+        const long waves = (long)((d->nphi + 63) / 64) * d->nr;
+        long chunks = (8192 + waves - 1) / waves;
+        chunks = std::max(1L, std::min(chunks, (long)std::max(1, d->nz / 8)));
+        z->kchunk = (int)((d->nz + chunks - 1) / chunks);
+    }
+    std::vector<RowCoef> rows;
+    std::vector<ZCoef> zr;
+    setup_layers(z, rows, zr);
+
+    zda_status st = ZDA_OK;
+    for (auto &f : z->F) if (st == ZDA_OK) st = dev_alloc(z, &f, z->ncell);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->ceps, z->ncell);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->auxR, (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->auxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->rows, (size_t)d->nr);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->zrows, (size_t)d->nz);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->flag, 1);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->dft_plane, (size_t)ZDA_MAX_FREQ * 2 * z->plane);
+    if (st != ZDA_OK) { free_all(z); delete z; return st; }
+    if (hipMemcpy(z->rows, rows.data(), rows.size() * sizeof(RowCoef), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(z->zrows, zr.data(), zr.size() * sizeof(ZCoef), hipMemcpyHostToDevice) != hipSuccess) {
+        free_all(z); delete z;
+        return fail(ZDA_ERR_HIP, "upload of coefficient rows failed");
+    }
+    // a new zone starts from zero fields, auxiliaries and monitors
+    if ((st = reset_state(z, nullptr)) != ZDA_OK) { free_all(z); delete z; return st; }
+    launch_fill(z->dft_plane, (size_t)ZDA_MAX_FREQ * 2 * z->plane, nullptr);
+    if (hipDeviceSynchronize() != hipSuccess) { free_all(z); delete z; return fail(ZDA_ERR_HIP, "zone reset failed"); }
+    *out = z;
+    if ((st = zda_zone_set_eps(z, eps, eps_on_device)) != ZDA_OK) { zda_zone_destroy(z); *out = nullptr; return st; }
+    return ZDA_OK;
+}
+
+void zda_zone_destroy(zda_zone *z)
+{
+    if (!z) return;
+    DeviceGuard g(z->device);
+    (void)hipDeviceSynchronize();
+    free_all(z);
+    delete z;
+}
+
+zda_status zda_zone_set_eps(zda_zone *z, const float *eps, int on_device)
+{
+    if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
+    DeviceGuard g(z->device);
+    if (!eps) {
+        std::vector<float> one(z->ncell, (float)z->dt);
+        HIP_TRY(hipMemcpy(z->ceps, one.data(), z->ncell * sizeof(float), hipMemcpyHostToDevice));
+        return ZDA_OK;
+    }
+    const float *src = eps;
+    float *tmp = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc((void **)&tmp, z->ncell * sizeof(float)));
+        if (hipMemcpy(tmp, eps, z->ncell * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(tmp);
+            return fail(ZDA_ERR_HIP, "eps upload failed");
+        }
+        src = tmp;
+    }
+    launch_inv_eps(z->ceps, src, z->ncell, z->dt, nullptr);
+    hipError_t e = hipDeviceSynchronize();
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(ZDA_ERR_HIP, "eps kernel: %s", hipGetErrorString(e));
+    return ZDA_OK;
+}
+
+zda_status zda_zone_set_design(zda_zone *z, const float *rho, int on_device)
+{
+    if (!z || !rho) return fail(ZDA_ERR_ARG, "NULL argument");
+    if (z->nd <= 0) return fail(ZDA_ERR_STATE, "zone has no design layer");
+    DeviceGuard g(z->device);
+    const size_t n = (size_t)z->nd * z->plane;
+    const float *src = rho;
+    float *tmp = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc((void **)&tmp, n * sizeof(float)));
+        if (hipMemcpy(tmp, rho, n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(tmp);
+            return fail(ZDA_ERR_HIP, "rho upload failed");
+        }
+        src = tmp;
+    }
+    launch_design_dt(z->ceps + (size_t)z->d.design_k0 * z->plane, src, n, z->d.eps_bg, z->d.eps_hi, z->dt, nullptr);
+    hipError_t e = hipDeviceSynchronize();
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(ZDA_ERR_HIP, "design kernel: %s", hipGetErrorString(e));
+    return ZDA_OK;
+}
+
+zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const double *omega, int K, int dft_flags,
+                        void *stream)
+{
+    if (!z || !s) return fail(ZDA_ERR_ARG, "NULL zone or source");
+    if (nsteps < 0) return fail(ZDA_ERR_ARG, "nsteps must be >= 0");
+    if (K < 0 || K > ZDA_MAX_FREQ || (K > 0 && !omega)) return fail(ZDA_ERR_ARG, "K must be in [0, %d]", ZDA_MAX_FREQ);
+    if ((dft_flags & ~(ZDA_DFT_PLANE | ZDA_DFT_VOLUME | ZDA_RUN_CONTINUE | ZDA_RUN_TIMING)) != 0)
+        return fail(ZDA_ERR_ARG, "bad dft_flags");
+    if ((dft_flags & ZDA_DFT_VOLUME) && z->nd <= 0) return fail(ZDA_ERR_STATE, "zone has no design layer");
+    const zda_zone_desc &d = z->d;
+    if (s->k_src < 1 || s->k_src >= d.nz) return fail(ZDA_ERR_ARG, "k_src must be in [1, nz)");
+    DeviceGuard g(z->device);
+    hipStream_t hs = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(hs));   // staging buffers of the previous call are free
+    const bool reset = !(dft_flags & ZDA_RUN_CONTINUE);
+    if (reset) z->n_done = 0;
+    int P = 1;
+    std::vector<cd> prof;
+    double width = 0.0;
+    int n0 = -1;
+    zda_status st;
+    if (s->kind == ZDA_SRC_PLANE_CIRC || s->kind == ZDA_SRC_RADIAL) {
+        if (s->kind == ZDA_SRC_PLANE_CIRC && std::abs(d.m) != 1) return fail(ZDA_ERR_UNSUPPORTED, "PLANE_CIRC needs |m| = 1");
+        if (s->kind == ZDA_SRC_RADIAL && d.m != 0) return fail(ZDA_ERR_UNSUPPORTED, "RADIAL needs m = 0");
+        if (!(s->width > 0)) return fail(ZDA_ERR_ARG, "pulse width must be > 0");
+        width = s->width;
+        n0 = s->n0 >= 0 ? s->n0 : default_n0(width, z->dt);
+        if ((st = ensure(z, &z->pattern, &z->cap_pattern, 2 * z->plane)) != ZDA_OK) return st;
+        z->st_pat.assign(2 * z->plane, make_float2(0.f, 0.f));
+        const double sgn = d.m > 0 ? 1.0 : (d.m < 0 ? -1.0 : 0.0);
+        for (int i = 0; i < d.nr; ++i)
+            for (int j = 0; j < d.nphi; ++j) {
+                cd jr, jp;
+                if (s->kind == ZDA_SRC_PLANE_CIRC) {
+                    jr = -std::exp(cd(0.0, d.m * j * z->dphi)) / d.dz;
+                    jp = cd(0.0, -sgn) * std::exp(cd(0.0, d.m * (j + 0.5) * z->dphi)) / d.dz;
+                } else {
+                    jr = -1.0 / d.dz;
+                    jp = 0.0;
+                }
+                z->st_pat[(size_t)i * d.nphi + j] = make_float2((float)jr.real(), (float)jr.imag());
+                z->st_pat[z->plane + (size_t)i * d.nphi + j] = make_float2((float)jp.real(), (float)jp.imag());
+            }
+        HIP_TRY(hipMemcpyAsync(z->pattern, z->st_pat.data(), 2 * z->plane * sizeof(float2), hipMemcpyHostToDevice, hs));
+        prof.resize(nsteps);
+        for (int n = 0; n < nsteps; ++n) prof[n] = pulse_at(z->n_done + n, z->dt, s->omega_c, width, n0);
+    } else if (s->kind == ZDA_SRC_CUSTOM) {
+        P = s->n_profiles;
+        if (P < 1 || P > ZDA_MAX_FREQ || !s->patterns || !s->profiles)
+            return fail(ZDA_ERR_ARG, "CUSTOM needs 1..%d patterns and profiles", ZDA_MAX_FREQ);
+        if ((st = ensure(z, &z->pattern, &z->cap_pattern, (size_t)P * 2 * z->plane)) != ZDA_OK) return st;
+        HIP_TRY(hipMemcpyAsync(z->pattern, s->patterns, (size_t)P * 2 * z->plane * sizeof(float2),
+                               s->patterns_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
+        prof.resize((size_t)P * nsteps);
+        for (size_t q = 0; q < prof.size(); ++q) prof[q] = cd(s->profiles[2 * q], s->profiles[2 * q + 1]);
+    } else {
+        return fail(ZDA_ERR_ARG, "unknown source kind %d", s->kind);
+    }
+    float2 *dplane = (dft_flags & ZDA_DFT_PLANE) && K > 0 ? z->dft_plane : nullptr;
+    float2 *dvol = nullptr;
+    if ((dft_flags & ZDA_DFT_VOLUME) && K > 0) {
+        if (!z->dft_vol) {
+            if ((st = dev_alloc(z, &z->dft_vol, (size_t)ZDA_MAX_FREQ * 3 * z->nd * z->plane)) != ZDA_OK) return st;
+            launch_fill(z->dft_vol, (size_t)ZDA_MAX_FREQ * 3 * z->nd * z->plane, hs);
+        }
+        dvol = z->dft_vol;
+    }
+    if ((st = run_loop(z, d.m, nsteps, s->k_src, P, prof.data(), omega, K, dplane, dvol, reset, hs,
+                       (dft_flags & ZDA_RUN_TIMING) != 0)) != ZDA_OK)
+        return st;
+    if (reset) {
+        z->last_K = K;
+        for (int k = 0; k < K; ++k) z->last_omega[k] = omega[k];
+        z->last_T = nsteps;
+        z->have_plane = dplane != nullptr;
+        z->have_vol = dvol != nullptr;
+    } else {
+        z->last_T += nsteps;
+    }
+    z->last_width = width;
+    z->last_n0 = n0;
+    z->have_vol_adj = false;
+    return ZDA_OK;
+}
+
+zda_status zda_dft_fields(zda_zone *z, int monitor, float *out, size_t out_floats, int out_on_device)
+{
+    if (!z || !out) return fail(ZDA_ERR_ARG, "NULL argument");
+    DeviceGuard g(z->device);
+    const float2 *src = nullptr;
+    size_t n = 0;
+    if (monitor == ZDA_MON_PLANE) {
+        if (!z->have_plane) return fail(ZDA_ERR_STATE, "no plane DFT in the last run");
+        src = z->dft_plane;
+        n = (size_t)z->last_K * 2 * z->plane;
+    } else if (monitor == ZDA_MON_VOLUME || monitor == ZDA_MON_ADJOINT_VOLUME) {
+        const bool adj = monitor == ZDA_MON_ADJOINT_VOLUME;
+        if (!(adj ? z->have_vol_adj : z->have_vol)) return fail(ZDA_ERR_STATE, "volume DFT not available");
+        src = adj ? z->dft_vol_adj : z->dft_vol;
+        n = (size_t)z->last_K * 3 * z->nd * z->plane;
+    } else {
+        return fail(ZDA_ERR_ARG, "unknown monitor %d", monitor);
+    }
+    if (out_floats < 2 * n) return fail(ZDA_ERR_ARG, "output holds %zu floats, %zu needed", out_floats, 2 * n);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemset(z->flag, 0, sizeof(int)));
+    launch_nonfinite(src, n, z->flag, nullptr);
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, z->flag, sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(out, src, n * sizeof(float2), out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    if (flag) return fail(ZDA_ERR_DIVERGED, "non-finite values in the DFT monitor (the run diverged)");
+    return ZDA_OK;
+}
+
+zda_status zda_adjoint_grad(zda_zone *z, const float *dF_dE, int dF_on_device, float *grad_rho, int grad_on_device,
+                            double adj_width, void *stream)
+{
+    if (!z || !dF_dE || !grad_rho) return fail(ZDA_ERR_ARG, "NULL argument");
+    if (!z->have_vol || z->last_K < 1) return fail(ZDA_ERR_STATE, "needs a forward run with ZDA_DFT_VOLUME");
+    const zda_zone_desc &d = z->d;
+    const int K = z->last_K, T = z->last_T, km = d.k_mon, nd = z->nd;
+    double width = adj_width > 0 ? adj_width : z->last_width;
+    if (!(width > 0)) return fail(ZDA_ERR_ARG, "adjoint pulse width unknown (custom forward source): pass adj_width");
+    const int n0 = (adj_width > 0 || z->last_n0 < 0) ? default_n0(width, z->dt) : z->last_n0;
+    DeviceGuard g(z->device);
+    hipStream_t hs = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(hs));
+    zda_status st;
+    const size_t npl = (size_t)K * 2 * z->plane;
+    const size_t nfac = (size_t)K * 2 * d.nr, nwr = (size_t)K * 3 * d.nr, nwz = (size_t)K * 3 * nd;
+    if ((st = ensure(z, &z->scratch, &z->cap_scratch, npl + nfac + nwr + nwz)) != ZDA_OK) return st;
+    if ((st = ensure(z, &z->pattern, &z->cap_pattern, npl)) != ZDA_OK) return st;
+    if (!z->dft_vol_adj && (st = dev_alloc(z, &z->dft_vol_adj, (size_t)ZDA_MAX_FREQ * 3 * nd * z->plane)) != ZDA_OK)
+        return st;
+    float2 *g_dev = z->scratch, *fac_dev = g_dev + npl, *wr_dev = fac_dev + nfac, *wz_dev = wr_dev + nwr;
+    HIP_TRY(hipMemcpyAsync(g_dev, dF_dE, npl * sizeof(float2),
+                           dF_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
+    // stretched volume W = R l_r l_z dphi and leap-frog frequency wt
+    auto wt = [&](double w) { return 2.0 / z->dt * std::sin(w * z->dt / 2.0); };
+    auto w_r = [&](int comp, int i, double w) {   // comp 0 = E_r (half point), 1, 2 = E_phi, E_z (integer)
+        const int h = comp == 0 ? 1 : 0;
+        const double r = d.r_in + (i + 0.5 * h) * d.dr;
+        return r * stretch(z->sgt_r[h][i], z->cr, w, z->dt) * stretch(z->sig_r[h][i], z->cr, w, z->dt) * d.dr *
+               z->dphi * d.dz;
+    };
+    auto w_z = [&](int comp, int k, double w) {
+        const int h = comp == 2 ? 1 : 0;
+        return stretch(z->sig_z[h][k], z->cz, w, z->dt);
+    };
+    z->st_misc.assign(nfac + nwr + nwz, make_float2(0.f, 0.f));
+    for (int k = 0; k < K; ++k) {
+        const double w = z->last_omega[k];
+        for (int a = 0; a < 2; ++a)
+            for (int i = 0; i < d.nr; ++i) {
+                const cd f = 1.0 / (w_r(a, i, w) * w_z(a, km, w) * cd(0.0, wt(w)));
+                z->st_misc[((size_t)k * 2 + a) * d.nr + i] = make_float2((float)f.real(), (float)f.imag());
+            }
+        for (int a = 0; a < 3; ++a) {
+            for (int i = 0; i < d.nr; ++i) {
+                const cd v = wt(w) * wt(w) * w_r(a, i, w);
+                z->st_misc[nfac + ((size_t)k * 3 + a) * d.nr + i] = make_float2((float)v.real(), (float)v.imag());
+            }
+            for (int kd = 0; kd < nd; ++kd) {
+                const cd v = w_z(a, d.design_k0 + kd, w);
+                z->st_misc[nfac + nwr + ((size_t)k * 3 + a) * nd + kd] = make_float2((float)v.real(), (float)v.imag());
+            }
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(fac_dev, z->st_misc.data(), (nfac + nwr + nwz) * sizeof(float2), hipMemcpyHostToDevice, hs));
+    launch_adjoint_pattern(z->pattern, g_dev, fac_dev, K, d.nr, d.nphi, hs);
+    // broadband profiles: pulses p_l centred on w_l, mixed by P^{-1}, P_kl = phat_l(w_k)
+    std::vector<double> p((size_t)K * T);
+    for (int l = 0; l < K; ++l)
+        for (int n = 0; n < T; ++n) p[(size_t)l * T + n] = pulse_at(n, z->dt, z->last_omega[l], width, n0);
+    std::vector<cd> Pm((size_t)K * K);
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            cd acc = 0.0;
+            for (int n = 0; n < T; ++n)
+                acc += p[(size_t)l * T + n] * std::exp(cd(0.0, z->last_omega[k] * (n + 0.5) * z->dt));
+            Pm[(size_t)k * K + l] = z->dt * acc;
+        }
+    if (!invert(Pm, K)) return fail(ZDA_ERR_ARG, "adjoint pulse spectra are singular at the chosen frequencies");
+    std::vector<cd> q((size_t)K * T, 0.0);
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            const cd c = Pm[(size_t)l * K + k];
+            for (int n = 0; n < T; ++n) q[(size_t)k * T + n] += c * p[(size_t)l * T + n];
+        }
+    if ((st = run_loop(z, -d.m, T, km, K, q.data(), z->last_omega, K, nullptr, z->dft_vol_adj, true, hs)) != ZDA_OK)
+        return st;
+    z->have_vol_adj = true;
+    float *gdst = grad_rho;
+    float *gtmp = nullptr;
+    if (!grad_on_device) {
+        HIP_TRY(hipMalloc((void **)&gtmp, (size_t)nd * z->plane * sizeof(float)));
+        gdst = gtmp;
+    }
+    launch_overlap(gdst, z->dft_vol, z->dft_vol_adj, wr_dev, wz_dev, K, nd, d.nr, d.nphi,
+                   (float)(2.0 * (d.eps_hi - d.eps_bg)), hs);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && gtmp) {
+        e = hipMemcpyAsync(grad_rho, gtmp, (size_t)nd * z->plane * sizeof(float), hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    }
+    if (gtmp) (void)hipFree(gtmp);
+    if (e != hipSuccess) return fail(ZDA_ERR_HIP, "overlap: %s", hipGetErrorString(e));
+    return ZDA_OK;
+}
+
+zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_device)
+{
+    if (!z || !out || comp < 0 || comp > 5) return fail(ZDA_ERR_ARG, "bad argument");
+    DeviceGuard g(z->device);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(out, z->F[comp], z->ncell * sizeof(float2),
+                      out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return ZDA_OK;
+}
+
+zda_status zda_zone_write_field(zda_zone *z, int comp, const float *in, int in_on_device)
+{
+    if (!z || !in || comp < 0 || comp > 5) return fail(ZDA_ERR_ARG, "bad argument");
+    DeviceGuard g(z->device);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(z->F[comp], in, z->ncell * sizeof(float2),
+                      in_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    if (comp == 1 && z->dR > 0) {
+        launch_seed_u(z->auxR + (size_t)AUX_U_EP * z->d.nz * z->dR * z->d.nphi, z->F[1], z->d.nr, z->d.nphi,
+                      z->d.nz, z->d.pml_r_in, z->d.pml_r_out, (float)z->dt, nullptr);
+        HIP_TRY(hipDeviceSynchronize());
+    }
+    return ZDA_OK;
+}
+
+zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info)
+{
+    if (!z || !info) return fail(ZDA_ERR_ARG, "NULL argument");
+    info->cells = z->ncell;
+    info->device_bytes = z->bytes;
+    info->dt = z->dt;
+    info->cfl = z->cfl;
+    info->launch_chunks = (z->d.nz + z->kchunk - 1) / z->kchunk;
+    return ZDA_OK;
+}
+
+zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t)
+{
+    if (!z || !t) return fail(ZDA_ERR_ARG, "NULL argument");
+    DeviceGuard g(z->device);
+    std::memset(t, 0, sizeof *t);
+    if (z->timed_steps == 0) return fail(ZDA_ERR_STATE, "the last run was not timed");
+    HIP_TRY(hipEventSynchronize(z->ev[4 * (size_t)z->timed_steps - 1]));
+    for (int n = 0; n < z->timed_steps; ++n) {
+        float a = 0.f, b = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, z->ev[4 * n], z->ev[4 * n + 1]));
+        HIP_TRY(hipEventElapsedTime(&b, z->ev[4 * n + 2], z->ev[4 * n + 3]));
+        t->h_ms += a;
+        t->e_ms += b;
+    }
+    t->h_launches = t->e_launches = z->timed_steps;
+    return ZDA_OK;
+}
+
+const char *zda_status_str(int status)
+{
+    switch (status) {
+    case ZDA_OK: return "ok";
+    case ZDA_ERR_ARG: return "invalid argument";
+    case ZDA_ERR_CFL: return "Courant condition violated";
+    case ZDA_ERR_UNSUPPORTED: return "unsupported configuration";
+    case ZDA_ERR_OOM: return "out of device memory";
+    case ZDA_ERR_STATE: return "call out of order";
+    case ZDA_ERR_HIP: return "HIP runtime error";
+    case ZDA_ERR_DIVERGED: return "simulation diverged";
+    default: return "unknown status";
+    }
+}
+
+const char *zda_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

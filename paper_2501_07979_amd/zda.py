@@ -1,0 +1,257 @@
+"""ctypes binding of libzda.so (include/zda.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; torch is used for
+device buffers and the current stream.  Importing this module loads the
+library (which needs no GPU to load); any call that touches the GPU raises
+if the library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libzda.so")
+
+ZDA_OK, ZDA_ERR_ARG, ZDA_ERR_CFL, ZDA_ERR_UNSUPPORTED, ZDA_ERR_OOM, ZDA_ERR_STATE, ZDA_ERR_HIP, ZDA_ERR_DIVERGED = range(8)
+ZDA_MAX_FREQ = 8
+SRC_PLANE_CIRC, SRC_RADIAL, SRC_CUSTOM = 0, 1, 2
+DFT_PLANE, DFT_VOLUME, RUN_CONTINUE, RUN_TIMING = 1, 2, 4, 8
+MON_PLANE, MON_VOLUME, MON_ADJOINT_VOLUME = 0, 1, 2
+COMP = {"Er": 0, "Ephi": 1, "Ez": 2, "Hr": 3, "Hphi": 4, "Hz": 5}
+
+EXPORTS = ["zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_zone_set_eps",
+           "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields", "zda_adjoint_grad",
+           "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_last_timing",
+           "zda_status_str", "zda_last_error"]
+
+
+class ZoneDesc(ctypes.Structure):
+    _fields_ = [("r_in", ctypes.c_double), ("nr", ctypes.c_int), ("nphi", ctypes.c_int), ("nz", ctypes.c_int),
+                ("n_fold", ctypes.c_int), ("m", ctypes.c_int), ("dr", ctypes.c_double), ("dz", ctypes.c_double),
+                ("courant", ctypes.c_double), ("pml_r_in", ctypes.c_int), ("pml_r_out", ctypes.c_int),
+                ("pml_z_lo", ctypes.c_int), ("pml_z_hi", ctypes.c_int), ("pml_order", ctypes.c_double),
+                ("pml_sigma_max_r", ctypes.c_double), ("pml_sigma_max_z", ctypes.c_double),
+                ("pml_alpha", ctypes.c_double), ("k_mon", ctypes.c_int), ("design_k0", ctypes.c_int),
+                ("design_k1", ctypes.c_int), ("eps_bg", ctypes.c_double), ("eps_hi", ctypes.c_double)]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("k_src", ctypes.c_int), ("omega_c", ctypes.c_double),
+                ("width", ctypes.c_double), ("n0", ctypes.c_int), ("n_profiles", ctypes.c_int),
+                ("patterns", ctypes.c_void_p), ("patterns_on_device", ctypes.c_int),
+                ("profiles", ctypes.c_void_p)]
+
+
+class ZoneInfo(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t), ("dt", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("launch_chunks", ctypes.c_int)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("h_launches", ctypes.c_int), ("e_launches", ctypes.c_int), ("h_ms", ctypes.c_double),
+                ("e_ms", ctypes.c_double)]
+
+
+class ZdaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (_status_name(status), status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libzda.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libzda.so is not built (run __graft_entry__.build() or paper_2501_07979_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.zda_zone_desc_default.argtypes = [ctypes.POINTER(ZoneDesc)]
+    lib.zda_zone_desc_default.restype = None
+    lib.zda_zone_create.argtypes = [ctypes.POINTER(ZoneDesc), P, I, ctypes.POINTER(P)]
+    lib.zda_zone_destroy.argtypes = [P]
+    lib.zda_zone_destroy.restype = None
+    lib.zda_zone_set_eps.argtypes = [P, P, I]
+    lib.zda_zone_set_design.argtypes = [P, P, I]
+    lib.zda_fdtd_run.argtypes = [P, ctypes.POINTER(Source), I, P, I, I, P]
+    lib.zda_dft_fields.argtypes = [P, I, P, ctypes.c_size_t, I]
+    lib.zda_adjoint_grad.argtypes = [P, P, I, P, I, D, P]
+    lib.zda_zone_read_field.argtypes = [P, I, P, I]
+    lib.zda_zone_write_field.argtypes = [P, I, P, I]
+    lib.zda_zone_get_info.argtypes = [P, ctypes.POINTER(ZoneInfo)]
+    lib.zda_zone_last_timing.argtypes = [P, ctypes.POINTER(Timing)]
+    lib.zda_status_str.argtypes = [I]
+    lib.zda_status_str.restype = ctypes.c_char_p
+    lib.zda_last_error.argtypes = []
+    lib.zda_last_error.restype = ctypes.c_char_p
+    for name in ("zda_zone_create", "zda_zone_set_eps", "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields",
+                 "zda_adjoint_grad", "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info",
+                 "zda_zone_last_timing"):
+        getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _status_name(st):
+    return load().zda_status_str(st).decode() if _lib is not None else str(st)
+
+
+def _check(st):
+    if st != ZDA_OK:
+        raise ZdaError(st, load().zda_last_error().decode())
+
+
+def default_desc(**kw) -> ZoneDesc:
+    d = ZoneDesc()
+    load().zda_zone_desc_default(ctypes.byref(d))
+    for k, v in kw.items():
+        if k == "pml":
+            d.pml_r_in, d.pml_r_out, d.pml_z_lo, d.pml_z_hi = v
+        elif k == "design":
+            d.design_k0, d.design_k1 = v
+        else:
+            setattr(d, k, v)
+    return d
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the ZDA library needs a HIP GPU (no CPU fallback)")
+    return torch
+
+
+def _stream_ptr(torch, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Zone:
+    """One ZDA zone on the current GPU (owns its device memory)."""
+
+    def __init__(self, desc: ZoneDesc, eps=None):
+        torch = _torch()
+        self.desc = desc
+        self.shape = (desc.nz, desc.nr, desc.nphi)
+        lib = load()
+        h = ctypes.c_void_p()
+        ptr, on_dev, keep = self._in_ptr(torch, eps, torch.float32)
+        _check(lib.zda_zone_create(ctypes.byref(desc), ptr, on_dev, ctypes.byref(h)))
+        self._h = h
+        del keep
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().zda_zone_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _in_ptr(torch, x, dtype):
+        """(pointer, on_device, keep-alive) of an input array or tensor."""
+        if x is None:
+            return None, 0, None
+        if isinstance(x, torch.Tensor):
+            t = x.detach().to(dtype).contiguous()
+            return ctypes.c_void_p(t.data_ptr()), int(t.is_cuda), t
+        a = np.ascontiguousarray(np.asarray(x), dtype=np.float32 if dtype == torch.float32 else None)
+        return ctypes.c_void_p(a.ctypes.data), 0, a
+
+    def info(self) -> ZoneInfo:
+        inf = ZoneInfo()
+        _check(load().zda_zone_get_info(self._h, ctypes.byref(inf)))
+        return inf
+
+    @property
+    def dt(self):
+        return self.info().dt
+
+    def set_eps(self, eps):
+        torch = _torch()
+        ptr, dev, keep = self._in_ptr(torch, eps, torch.float32)
+        _check(load().zda_zone_set_eps(self._h, ptr, dev))
+
+    def set_design(self, rho):
+        torch = _torch()
+        ptr, dev, keep = self._in_ptr(torch, rho, torch.float32)
+        _check(load().zda_zone_set_design(self._h, ptr, dev))
+
+    def run(self, nsteps, omegas=(), *, kind=SRC_PLANE_CIRC, k_src=1, omega_c=0.0, width=1.0, n0=-1,
+            patterns=None, profiles=None, plane=True, volume=False, cont=False, timing=False, stream=None):
+        """Time-step (asynchronous on the current torch stream)."""
+        torch = _torch()
+        s = Source()
+        s.kind, s.k_src, s.omega_c, s.width, s.n0 = kind, k_src, omega_c, width, n0
+        keep = []
+        if kind == SRC_CUSTOM:
+            pat = patterns
+            if isinstance(pat, torch.Tensor):
+                pt = torch.view_as_real(pat.to(torch.complex64).contiguous()).contiguous()
+                s.patterns, s.patterns_on_device = pt.data_ptr(), int(pt.is_cuda)
+            else:
+                pt = np.ascontiguousarray(np.asarray(pat, np.complex64))
+                s.patterns, s.patterns_on_device = pt.ctypes.data, 0
+            pr = np.ascontiguousarray(np.asarray(profiles, np.complex128))
+            s.n_profiles = pr.shape[0]
+            s.profiles = pr.ctypes.data
+            keep += [pt, pr]
+        om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, np.float64)))
+        flags = (DFT_PLANE if plane else 0) | (DFT_VOLUME if volume else 0) | (RUN_CONTINUE if cont else 0) | \
+            (RUN_TIMING if timing else 0)
+        _check(load().zda_fdtd_run(self._h, ctypes.byref(s), int(nsteps), ctypes.c_void_p(om.ctypes.data),
+                                   int(om.size), flags, _stream_ptr(torch, stream)))
+        self._K = int(om.size)
+
+    def last_timing(self) -> Timing:
+        t = Timing()
+        _check(load().zda_zone_last_timing(self._h, ctypes.byref(t)))
+        return t
+
+    def dft(self, monitor=MON_PLANE, K=None):
+        """Monitor as a complex64 CUDA tensor ([K][2][nr][nphi] or [K][3][nd][nr][nphi])."""
+        torch = _torch()
+        K = self._K if K is None else K
+        d = self.desc
+        if monitor == MON_PLANE:
+            shape = (K, 2, d.nr, d.nphi)
+        else:
+            shape = (K, 3, d.design_k1 - d.design_k0, d.nr, d.nphi)
+        out = torch.empty(shape, dtype=torch.complex64, device="cuda")
+        _check(load().zda_dft_fields(self._h, monitor, ctypes.c_void_p(out.data_ptr()), 2 * out.numel(), 1))
+        return out
+
+    def adjoint_grad(self, dF_dE, adj_width=0.0, stream=None):
+        torch = _torch()
+        g = dF_dE.to(torch.complex64).contiguous() if isinstance(dF_dE, torch.Tensor) else \
+            torch.as_tensor(np.asarray(dF_dE, np.complex64)).cuda()
+        g = torch.view_as_real(g).contiguous()
+        d = self.desc
+        out = torch.empty((d.design_k1 - d.design_k0, d.nr, d.nphi), dtype=torch.float32, device="cuda")
+        _check(load().zda_adjoint_grad(self._h, ctypes.c_void_p(g.data_ptr()), 1, ctypes.c_void_p(out.data_ptr()),
+                                       1, float(adj_width), _stream_ptr(torch, stream)))
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def read_field(self, name):
+        torch = _torch()
+        out = torch.empty(self.shape, dtype=torch.complex64, device="cuda")
+        _check(load().zda_zone_read_field(self._h, COMP[name], ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def write_field(self, name, value):
+        torch = _torch()
+        t = value if isinstance(value, torch.Tensor) else torch.as_tensor(np.asarray(value, np.complex64))
+        t = t.to(device="cuda", dtype=torch.complex64).contiguous()
+        _check(load().zda_zone_write_field(self._h, COMP[name], ctypes.c_void_p(t.data_ptr()), 1))

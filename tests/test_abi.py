@@ -1,0 +1,86 @@
+"""The C-ABI library loads on a machine without a GPU, exports every symbol
+include/zda.h declares, and rejects bad descriptors before touching a device
+(argument validation precedes every HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "zda.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(zda_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2501_07979_amd import zda
+    return zda.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("zda_zone_create", "zda_fdtd_run", "zda_dft_fields", "zda_adjoint_grad", "zda_zone_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2501_07979_amd import zda
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(zda.EXPORTS) == _declared()
+
+
+def test_status_strings(lib):
+    assert lib.zda_status_str(0) == b"ok"
+    assert lib.zda_status_str(2) == b"Courant condition violated"
+    assert lib.zda_status_str(99) == b"unknown status"
+
+
+def _create(lib, **kw):
+    from paper_2501_07979_amd import zda
+    d = zda.default_desc(**kw)
+    h = ctypes.c_void_p()
+    st = lib.zda_zone_create(ctypes.byref(d), None, 0, ctypes.byref(h))
+    return st, lib.zda_last_error().decode()
+
+
+def test_descriptor_validation_without_gpu(lib):
+    from paper_2501_07979_amd import zda
+    base = dict(r_in=200.0, nr=64, nphi=64, nz=96, n_fold=16, m=1, k_mon=80, design=(30, 40))
+    st, msg = _create(lib, **dict(base, courant=0.9))
+    assert st == zda.ZDA_ERR_CFL and "Courant" in msg
+    # the literal gradient-zone geometry (r_in = 200 with 512 phi cells) is not stable at Courant 0.5
+    st, _ = _create(lib, **dict(base, nphi=512))
+    assert st == zda.ZDA_ERR_CFL
+    assert _create(lib, **dict(base, r_in=0.0))[0] == zda.ZDA_ERR_UNSUPPORTED
+    assert _create(lib, **dict(base, nr=0))[0] == zda.ZDA_ERR_ARG
+    assert _create(lib, **dict(base, k_mon=96))[0] == zda.ZDA_ERR_ARG
+    assert _create(lib, **dict(base, pml=(40, 8, 8, 8)))[0] == zda.ZDA_ERR_ARG
+    assert _create(lib, **dict(base, design=(50, 40)))[0] == zda.ZDA_ERR_ARG
+    st = lib.zda_zone_create(None, None, 0, None)
+    assert st == zda.ZDA_ERR_ARG
+
+
+def test_null_safety(lib):
+    from paper_2501_07979_amd import zda
+    lib.zda_zone_destroy(None)
+    assert lib.zda_fdtd_run(None, None, 1, None, 0, 0, None) == zda.ZDA_ERR_ARG
+    assert lib.zda_dft_fields(None, 0, None, 0, 0) == zda.ZDA_ERR_ARG
+    assert lib.zda_adjoint_grad(None, None, 0, None, 0, 0.0, None) == zda.ZDA_ERR_ARG
+
+
+def test_workloads_are_cfl_stable():
+    import numpy as np
+    from paper_2501_07979_amd.workloads import WORKLOADS
+    for name, f in WORKLOADS.items():
+        w = f()
+        dphi = 2 * np.pi / (w.n_fold * w.nphi)
+        dt = w.courant * min(w.dr, w.dz)
+        cfl = dt * np.sqrt(1 / w.dr ** 2 + 1 / (w.r_in * dphi) ** 2 + 1 / w.dz ** 2)
+        assert cfl < 1, name
+        assert abs(w.r_in * dphi - 1.2272) < 1e-3, name

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Tolerances: exit-plane DFT relative L2 <= 1e-5 (FP32
+fields vs FP64), adjoint gradient relative L2 <= 1e-4."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-parity]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def zda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_07979_amd import zda as Z
+    Z.load()
+    return Z
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _zone_pair(zda, oracle_mod, wl, eps):
+    g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+    o = oracle_mod.OracleZone(**wl.desc_kwargs(), eps=eps)
+    return g, o
+
+
+def test_c1_parity_exit_plane_dft(zda, oracle_mod):
+    from paper_2501_07979_amd.workloads import c1
+    wl = c1()
+    _say("c1 full parity", wl.name, wl.steps)
+    eps = wl.eps()
+    g, o = _zone_pair(zda, oracle_mod, wl, eps)
+    g.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+    gpu = g.dft(zda.MON_PLANE).cpu().numpy()
+    ref = o.forward(wl.steps, np.array(wl.omegas), omega_c=wl.omega_c, width=wl.width, k_src=wl.k_src)["plane"]
+    err = _rel(gpu, ref)
+    _say("c1 exit-plane DFT rel L2 = %.3e" % err)
+    assert err <= 1e-5
+    # the fields themselves after 1000 steps
+    for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz"):
+        e = _rel(g.read_field(c).cpu().numpy(), o.get_field(c))
+        assert e <= 1e-4, (c, e)
+
+
+@pytest.mark.parametrize("case", ["ragged_m1", "ragged_m0", "ragged_mneg", "no_pml"])
+def test_ragged_shapes_all_fields(zda, oracle_mod, case):
+    """Shapes that are not multiples of the tile (nphi 70, nr 37) with uneven
+    PML widths and several z-chunks; every field and the DFTs compared."""
+    from paper_2501_07979_amd.workloads import Workload
+    m = {"ragged_m1": 1, "ragged_m0": 0, "ragged_mneg": -1, "no_pml": 1}[case]
+    pml = (0, 0, 0, 0) if case == "no_pml" else (5, 6, 4, 7)
+    wl = Workload(case, r_in=90.0, nr=37, nphi=70, nz=50, n_fold=7, m=m, dz=0.9, pml=pml, k_src=9, k_mon=40,
+                  design=(12, 17), k_sub=12, steps=300, omegas=(0.28, 0.33), omega_c=0.31, width=7.0, seed=5)
+    rng = np.random.default_rng(21)
+    eps = (1.0 + 4.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
+    _say("ragged", case)
+    g, o = _zone_pair(zda, oracle_mod, wl, eps)
+    kind = zda.SRC_RADIAL if m == 0 else zda.SRC_PLANE_CIRC
+    g.run(wl.steps, wl.omegas, kind=kind, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width, volume=True)
+    ref = o.forward(wl.steps, np.array(wl.omegas), omega_c=wl.omega_c, width=wl.width, k_src=wl.k_src,
+                    kind="radial" if m == 0 else "plane_circ", volume=True)
+    for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz"):
+        e = _rel(g.read_field(c).cpu().numpy(), o.get_field(c))
+        assert e <= 2e-5, (case, c, e)
+    assert _rel(g.dft(zda.MON_PLANE).cpu().numpy(), ref["plane"]) <= 1e-5
+    assert _rel(g.dft(zda.MON_VOLUME).cpu().numpy(), ref["vol"]) <= 1e-5
+
+
+def test_random_state_steps_with_pml(zda, oracle_mod):
+    """Arbitrary initial fields (written through the ABI) stepped without
+    reset: every update term, PML auxiliary and the seam act from step 1."""
+    from paper_2501_07979_amd.workloads import Workload
+    wl = Workload("random_state", r_in=60.0, nr=29, nphi=64, nz=33, n_fold=6, m=2, pml=(6, 5, 5, 6), k_src=3,
+                  k_mon=20, design=(10, 12), steps=40)
+    rng = np.random.default_rng(22)
+    eps = (1.0 + 3.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
+    g, o = _zone_pair(zda, oracle_mod, wl, eps)
+    _say("random state")
+    for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz"):
+        f = (rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)).astype(np.complex64)
+        if c == "Er":
+            f[0] = 0
+        if c == "Ephi":
+            f[0] = 0
+            f[:, 0] = 0
+        if c == "Ez":
+            f[:, 0] = 0
+        if c == "Hr":
+            f[:, 0] = 0
+        if c == "Hz":
+            f[0] = 0
+        g.write_field(c, f)
+        o.set_field(c, f.astype(np.complex128))
+    zero = np.zeros((1, 2, wl.nr, wl.nphi), np.complex64)
+    g.run(wl.steps, (), kind=zda.SRC_CUSTOM, k_src=wl.k_src, patterns=zero, profiles=np.zeros((1, wl.steps)),
+          plane=False, cont=True)
+    o.run(wl.steps, m=wl.m, reset=False)
+    for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz"):
+        e = _rel(g.read_field(c).cpu().numpy(), o.get_field(c))
+        assert e <= 1e-5, (c, e)
+
+
+def test_custom_source_profiles(zda, oracle_mod):
+    """Several complex patterns with complex time profiles (the adjoint's
+    source form) match the oracle."""
+    from paper_2501_07979_amd.workloads import Workload
+    wl = Workload("custom_src", r_in=100.0, nr=30, nphi=64, nz=40, n_fold=8, m=1, pml=(5, 5, 5, 5), k_src=12,
+                  k_mon=30, design=(15, 20), steps=250, omegas=(0.3, 0.35, 0.4))
+    rng = np.random.default_rng(23)
+    eps = (1.0 + 2.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
+    g, o = _zone_pair(zda, oracle_mod, wl, eps)
+    P = 3
+    pat = (rng.standard_normal((P, 2, wl.nr, wl.nphi)) + 1j * rng.standard_normal((P, 2, wl.nr, wl.nphi)))
+    prof = rng.standard_normal((P, wl.steps)) + 1j * rng.standard_normal((P, wl.steps))
+    prof[:, 60:] = 0
+    _say("custom source")
+    g.run(wl.steps, wl.omegas, kind=zda.SRC_CUSTOM, k_src=wl.k_src, patterns=pat.astype(np.complex64),
+          profiles=prof)
+    pat32 = pat.astype(np.complex64).astype(np.complex128)
+    ref = o.run(wl.steps, patterns=pat32, profiles=prof, k_src=wl.k_src, omegas=wl.omegas)
+    assert _rel(g.dft(zda.MON_PLANE).cpu().numpy(), ref["plane"]) <= 1e-5
+
+
+def _objective(wts, plane):
+    s = np.einsum("kaij,kaij->k", wts, plane)
+    return np.sum(np.abs(s) ** 2), np.conj(s)[:, None, None, None] * wts
+
+
+def test_gradient_parity_small_copy(zda, oracle_mod):
+    """Adjoint gradient over the design layer of the gradient zone's small
+    copy (64 x 64 x 96, three frequencies) against the oracle's gradient."""
+    from paper_2501_07979_amd.workloads import c3_small
+    wl = c3_small()
+    rho = wl.rho()
+    eps = wl.eps(rho)
+    g, o = _zone_pair(zda, oracle_mod, wl, eps)
+    om = np.array(wl.omegas)
+    _say("gradient small copy forward", wl.name, wl.steps)
+    g.run(wl.steps, om, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width, volume=True)
+    fwd = o.forward(wl.steps, om, omega_c=wl.omega_c, width=wl.width, k_src=wl.k_src, volume=True)
+    gp = g.dft(zda.MON_PLANE).cpu().numpy()
+    assert _rel(gp, fwd["plane"]) <= 1e-5
+    assert _rel(g.dft(zda.MON_VOLUME).cpu().numpy(), fwd["vol"]) <= 1e-5
+    rng = np.random.default_rng(31)
+    wts = (rng.standard_normal((3, 2, wl.nr, wl.nphi)) + 1j * rng.standard_normal((3, 2, wl.nr, wl.nphi)))
+    _, dF = _objective(wts, fwd["plane"])
+    _say("gradient small copy adjoint")
+    grad_gpu = g.adjoint_grad(dF.astype(np.complex64)).cpu().numpy()
+    grad_ref = o.adjoint_grad(dF.astype(np.complex64).astype(np.complex128))
+    err = _rel(grad_gpu, grad_ref)
+    _say("gradient rel L2 = %.3e" % err)
+    assert err <= 1e-4
+    assert np.isfinite(g.dft(zda.MON_ADJOINT_VOLUME).cpu().numpy()).all()
+
+
+def test_error_paths_on_device(zda):
+    from paper_2501_07979_amd.workloads import c1
+    wl = c1()
+    g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    with pytest.raises(zda.ZdaError) as e:
+        g.adjoint_grad(np.zeros((1, 2, wl.nr, wl.nphi), np.complex64))
+    assert e.value.status == zda.ZDA_ERR_STATE
+    with pytest.raises(zda.ZdaError) as e:
+        g.run(10, [0.3], k_src=0, omega_c=0.3, width=5.0)
+    assert e.value.status == zda.ZDA_ERR_ARG
+    with pytest.raises(zda.ZdaError) as e:
+        g.run(10, [0.3] * 9, k_src=5, omega_c=0.3, width=5.0)
+    assert e.value.status == zda.ZDA_ERR_ARG
+    g.close()
+    g.close()
