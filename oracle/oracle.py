@@ -79,6 +79,8 @@ def _load():
         lib.ora_reset.argtypes = [P]
         lib.ora_set_field.argtypes = [P, ctypes.c_int, P]
         lib.ora_get_field.argtypes = [P, ctypes.c_int, P]
+        lib.ora_num_threads.restype = ctypes.c_int
+        lib.ora_num_threads.argtypes = []
         lib.ora_run.restype = ctypes.c_int
         lib.ora_run.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_long,
                                 ctypes.c_int, P, P, ctypes.c_int,
@@ -91,6 +93,10 @@ def _load():
 
 def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def num_threads():
+    return int(_load().ora_num_threads())
 
 
 def pulse(nsteps, dt, omega_c, width, n0=None):

@@ -39,6 +39,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -187,6 +190,16 @@ ora_zone *ora_create(const ora_params *p)
 }
 
 double ora_dt(const ora_zone *z) { return z->dt; }
+
+/* threads the time loop uses */
+int ora_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Layer constants: which = 0 r-integer, 1 r-half, 2 z-integer, 3 z-half.
  * sig, sgt (sigma~ = Sigma/r, zero for z) and the pole c = exp(-alpha dt). */
