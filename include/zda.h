@@ -186,7 +186,15 @@ typedef struct {
     double dt;
     double cfl;               /* courant * min(dr,dz) * sqrt(...) (< 1 when stable) */
     int launch_chunks;        /* z chunks of the update kernels */
+    int kchunk;               /* z-planes marched by one thread */
+    int tile_rows;            /* radial rows per thread block */
 } zda_zone_info;
+
+/* Launch shape of the update kernels: each thread marches kchunk z-planes of
+ * one (r, phi) column; a block covers tile_rows radial rows x 64 phi cells.
+ * Results do not depend on the shape.  ZDA_ERR_ARG for kchunk outside
+ * [1, nz] or tile_rows not in {1, 2, 4, 8, 16}. */
+zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);
 

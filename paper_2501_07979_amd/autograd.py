@@ -1,0 +1,35 @@
+"""Differentiable zone: forward FDTD + DFT monitors as a torch.autograd.Function
+whose backward is the adjoint FDTD run and the permittivity-gradient overlap
+(hybrid time/frequency adjoint, section on the cylindrical solver of arXiv
+2501.07979; eq. 6 for the design interpolation).  No time history is kept:
+the backward needs only the forward design-volume DFT held by the zone.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import zda
+
+
+class ZoneFDTD(torch.autograd.Function):
+    """rho [k1-k0][nr][nphi] (float32, CUDA) -> exit-plane DFT [K][2][nr][nphi]
+    (complex64, CUDA) of one forward run with the preset plane-wave source."""
+
+    @staticmethod
+    def forward(ctx, rho, zone, run_kw):
+        zone.set_design(rho.detach().contiguous())
+        zone.run(volume=True, **run_kw)
+        plane = zone.dft(zda.MON_PLANE)
+        ctx.zone = zone
+        return plane
+
+    @staticmethod
+    def backward(ctx, grad_plane):
+        # torch passes 2 conj(dF/dEhat) for a real loss F; the ABI takes dF/dEhat
+        g = (grad_plane.conj() * 0.5).to(torch.complex64).contiguous()
+        grad_rho = ctx.zone.adjoint_grad(g)
+        return grad_rho, None, None
+
+
+def zone_fdtd(rho, zone, **run_kw):
+    return ZoneFDTD.apply(rho, zone, run_kw)

@@ -51,6 +51,10 @@ struct StepArgs {
     int k0, k1;
     float2 *dft_vol;               // [K][3][k1-k0][nr][nphi] or null
     int kchunk;                    // planes per z-chunk
+    int tile_rows;                 // radial rows per block (1, 2, 4, 8, 16 split; 3, 7, 15 fused)
+    // fused step: fields and auxiliaries read from the set above, written here
+    float2 *oEr, *oEp, *oEz, *oHr, *oHp, *oHz;
+    float2 *oauxR, *oauxZ;
 };
 
 enum { AUX_HR_T, AUX_HP_S, AUX_HZ_S, AUX_HZ_T, AUX_V_HP,
@@ -59,6 +63,7 @@ enum { ZAUX_HR, ZAUX_HP, ZAUX_ER, ZAUX_EP, N_AUX_Z };
 
 void launch_h_step(const StepArgs &a, int n, hipStream_t s);
 void launch_e_step(const StepArgs &a, int n, hipStream_t s);
+void launch_fused_step(const StepArgs &a, int n, hipStream_t s);
 void launch_fill(float2 *p, size_t n, hipStream_t s);
 void launch_design_dt(float *ceps, const float *rho, size_t n, double eps_bg, double eps_hi, double dt,
                       hipStream_t s);

@@ -48,9 +48,9 @@ __device__ __forceinline__ int slab_row(int q, int n, int d0, int d1)
 }
 
 constexpr int BX = 64;   // one wavefront along phi
-constexpr int BY = 4;    // radial rows per block
 
 // H^{n+1/2} = H^{n-1/2} - dt curlE(E^n); also advances V = F H_phi in the r-layer.
+template <int BY>
 __global__ __launch_bounds__(BX * BY) void h_step_kernel(StepArgs a, int n)
 {
     const int j = blockIdx.x * BX + threadIdx.x;
@@ -131,6 +131,7 @@ __global__ __launch_bounds__(BX * BY) void h_step_kernel(StepArgs a, int n)
 
 // E^{n+1} = E^n + (dt/eps)(curlH(H^{n+1/2}) - J^{n+1/2}); source sheet, DFT
 // accumulation and U = F E_phi in the r-layer fused.
+template <int BY>
 __global__ __launch_bounds__(BX * BY) void e_step_kernel(StepArgs a, int n)
 {
     const int j = blockIdx.x * BX + threadIdx.x;
@@ -237,6 +238,231 @@ __global__ __launch_bounds__(BX * BY) void e_step_kernel(StepArgs a, int n)
     }
 }
 
+
+// y = x / (1 + s F) reading the auxiliary from one buffer and, when the
+// caller owns the cell, writing its update to the other
+__device__ __forceinline__ float2 div_stretch2(float2 x, const float2 *src, float2 *dst, bool store, float g1,
+                                               float g2, float c, float dt)
+{
+    float2 u = *src;
+    float2 y = make_float2(g1 * x.x - g2 * u.x, g1 * x.y - g2 * u.y);
+    if (store) *dst = make_float2(c * u.x + dt * y.x, c * u.y + dt * y.y);
+    return y;
+}
+
+// One whole leap-frog step (H half-step, then E half-step with source and
+// DFT) per launch, reading fields and auxiliaries from one buffer set and
+// writing the next time level to the other, so no block ever reads a value
+// another block of the same launch writes.  Block = (TR + 1) wavefronts x 64
+// lanes marching a z-chunk: wave 0 recomputes H on the radial halo row
+// i0 - 1, waves 1..TR own rows i0 .. i0 + TR - 1; lane l sits on phi cell
+// j0 - 1 + l (j0 = 63 blockIdx.x), lane 0 recomputes H on the azimuthal halo
+// column (across the wedge seam for the first tile), lanes 1..63 own.  Each
+// plane's H^{n+1/2} goes through LDS (two buffers, one barrier per plane) to
+// the owners' E half-step.  A chunk starts one plane early to rebuild
+// H^{n+1/2} at k = kb - 1 for the E half-step at kb.
+template <int TR>
+__global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int n)
+{
+    __shared__ float2 sHz[2][TR + 1][64], sHr[2][TR + 1][64], sHp[2][TR + 1][64], sV[2][TR + 1][64];
+    const int lane = threadIdx.x, ww = threadIdx.y;
+    const int nphi = a.nphi, nr = a.nr, nz = a.nz;
+    const size_t plane = (size_t)nr * nphi;
+    const int i0 = blockIdx.y * TR;
+    const int i = ww == 0 ? i0 - 1 : i0 + ww - 1;
+    const int jj = (int)blockIdx.x * 63 - 1 + lane;
+    const bool hval = i >= 0 && i < nr && jj < nphi;
+    const bool seam_lane = jj < 0;
+    const int j = seam_lane ? nphi - 1 : jj;
+    const bool owner = ww >= 1 && lane >= 1 && hval;
+    const int kb = blockIdx.z * a.kchunk;
+    const int ke = min(kb + a.kchunk, nz);
+    const int kstart = kb > 0 ? kb - 1 : kb;
+    const int ir = hval ? slab_row(i, nr, a.pr0, a.pr1) : -1;
+    const int ir1 = (hval && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
+    const RowCoef rc = a.rows[hval ? i : 0];
+    const int jp = (j + 1 < nphi) ? j + 1 : 0;
+    const bool wrap = (j + 1 >= nphi);
+    const size_t slabR = (size_t)nz * a.dR * nphi;
+    const size_t slabZ = (size_t)a.dZ * plane;
+    const float dt = a.dt;
+    const int nd = a.k1 - a.k0;
+
+    size_t c = ((size_t)kstart * nr + (hval ? i : 0)) * nphi + j;
+    float2 er = zero2(), ep = zero2();
+    if (hval) { er = a.Er[c]; ep = a.Ep[c]; }
+    float2 hr_km = zero2(), hp_km = zero2();
+    for (int k = kstart; k < ke; ++k, c += plane) {
+        const bool store = owner && k >= kb;
+        const int kz = slab_row(k, nz, a.pz0, a.pz1);
+        const ZCoef zc = a.zrows[k];
+        float2 hr = zero2(), hp = zero2(), hz = zero2(), v = zero2();
+        float2 ez = zero2(), er_kp = zero2(), ep_kp = zero2();
+        const size_t sr = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi + j : 0;
+        const size_t sz = kz >= 0 ? ((size_t)kz * nr + (hval ? i : 0)) * nphi + j : 0;
+        if (hval) {
+            const size_t row = c - j;
+            ez = a.Ez[c];
+            if (k + 1 < nz) { er_kp = a.Er[c + plane]; ep_kp = a.Ep[c + plane]; }
+            float2 ez_jp = a.Ez[row + jp], er_jp = a.Er[row + jp];
+            if (wrap) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+            float2 ez_ip = zero2(), ep_ip = zero2();
+            if (i + 1 < nr) { ez_ip = a.Ez[c + nphi]; ep_ip = a.Ep[c + nphi]; }
+            hr = a.Hr[c];
+            hp = a.Hp[c];
+            hz = a.Hz[c];
+            // H_r at (i, j+1/2, k+1/2)
+            if (i > 0) {
+                float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
+                float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
+                if (ir >= 0)
+                    t1 = div_stretch2(t1, a.auxR + AUX_HR_T * slabR + sr, a.oauxR + AUX_HR_T * slabR + sr, store,
+                                      rc.g1_t_int, rc.g2_t_int, a.cr, dt);
+                if (kz >= 0)
+                    t2 = div_stretch2(t2, a.auxZ + ZAUX_HR * slabZ + sz, a.oauxZ + ZAUX_HR * slabZ + sz, store,
+                                      zc.g1_half, zc.g2_half, a.cz, dt);
+                hr = make_float2(hr.x - dt * (t1.x - t2.x), hr.y - dt * (t1.y - t2.y));
+            }
+            // H_phi at (i+1/2, j, k+1/2)
+            {
+                float2 t1 = c_scale(c_sub(er_kp, er), a.inv_dz);
+                float2 t2 = c_scale(c_sub(ez_ip, ez), a.inv_dr);
+                if (kz >= 0)
+                    t1 = div_stretch2(t1, a.auxZ + ZAUX_HP * slabZ + sz, a.oauxZ + ZAUX_HP * slabZ + sz, store,
+                                      zc.g1_half, zc.g2_half, a.cz, dt);
+                if (ir >= 0)
+                    t2 = div_stretch2(t2, a.auxR + AUX_HP_S * slabR + sr, a.oauxR + AUX_HP_S * slabR + sr, store,
+                                      rc.g1_s_half, rc.g2_s_half, a.cr, dt);
+                hp = make_float2(hp.x - dt * (t1.x - t2.x), hp.y - dt * (t1.y - t2.y));
+                if (ir >= 0) {
+                    const float2 vo = a.auxR[AUX_V_HP * slabR + sr];
+                    v = make_float2(a.cr * vo.x + dt * hp.x, a.cr * vo.y + dt * hp.y);
+                    if (store) a.oauxR[AUX_V_HP * slabR + sr] = v;
+                }
+            }
+            // H_z at (i+1/2, j+1/2, k)
+            if (k > 0) {
+                float2 t = c_add(c_scale(c_sub(ep_ip, ep), a.inv_dr), c_scale(c_add(ep_ip, ep), rc.inv_2r_half));
+                if (ir >= 0) {
+                    const float2 *U = a.auxR + AUX_U_EP * slabR;
+                    float2 u0 = U[sr];
+                    float2 u1 = ir1 >= 0 ? U[((size_t)k * a.dR + ir1) * nphi + j] : zero2();
+                    t = c_add(t, c_sub(c_scale(u1, rc.hz_c1), c_scale(u0, rc.hz_c0)));
+                    t = div_stretch2(t, a.auxR + AUX_HZ_S * slabR + sr, a.oauxR + AUX_HZ_S * slabR + sr, store,
+                                     rc.g1_s_half, rc.g2_s_half, a.cr, dt);
+                }
+                t = c_sub(t, c_scale(c_sub(er_jp, er), rc.inv_rdphi_half));
+                if (ir >= 0)
+                    t = div_stretch2(t, a.auxR + AUX_HZ_T * slabR + sr, a.oauxR + AUX_HZ_T * slabR + sr, store,
+                                     rc.g1_t_half, rc.g2_t_half, a.cr, dt);
+                hz = make_float2(hz.x - dt * t.x, hz.y - dt * t.y);
+            }
+            if (store) {
+                a.oHr[c] = hr;
+                a.oHp[c] = hp;
+                a.oHz[c] = hz;
+            }
+        }
+        const int buf = k & 1;
+        if (seam_lane) {   // the halo column across the wedge boundary is j = -1
+            sHz[buf][ww][lane] = c_mul(a.seam_m, hz);
+            sHr[buf][ww][lane] = c_mul(a.seam_m, hr);
+            sHp[buf][ww][lane] = c_mul(a.seam_m, hp);
+            sV[buf][ww][lane] = c_mul(a.seam_m, v);
+        } else {
+            sHz[buf][ww][lane] = hz;
+            sHr[buf][ww][lane] = hr;
+            sHp[buf][ww][lane] = hp;
+            sV[buf][ww][lane] = v;
+        }
+        __syncthreads();
+        if (store) {
+            const float2 hz_jm = sHz[buf][ww][lane - 1], hr_jm = sHr[buf][ww][lane - 1];
+            const float2 hz_im = sHz[buf][ww - 1][lane], hp_im = sHp[buf][ww - 1][lane];
+            const float2 v_im = sV[buf][ww - 1][lane];
+            const float ce = a.ceps[c];
+            float2 jr = zero2(), jph = zero2();
+            if (k == a.k_src) {
+                for (int p = 0; p < a.n_prof; ++p) {
+                    const float2 g = a.profile[(size_t)n * a.n_prof + p];
+                    const float2 *pat = a.pattern + (size_t)p * 2 * plane + (size_t)i * nphi + j;
+                    jr = c_fma(jr, pat[0], g);
+                    jph = c_fma(jph, pat[plane], g);
+                }
+            }
+            float2 er_n = er, ep_n = ep, ez_n = ez;
+            // E_r at (i+1/2, j, k)
+            if (k > 0) {
+                float2 t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
+                float2 t2 = c_scale(c_sub(hp, hp_km), a.inv_dz);
+                if (ir >= 0)
+                    t1 = div_stretch2(t1, a.auxR + AUX_ER_T * slabR + sr, a.oauxR + AUX_ER_T * slabR + sr, true,
+                                      rc.g1_t_half, rc.g2_t_half, a.cr, dt);
+                if (kz >= 0)
+                    t2 = div_stretch2(t2, a.auxZ + ZAUX_ER * slabZ + sz, a.oauxZ + ZAUX_ER * slabZ + sz, true,
+                                      zc.g1_int, zc.g2_int, a.cz, dt);
+                er_n = make_float2(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
+            }
+            // E_phi at (i, j+1/2, k)
+            if (k > 0 && i > 0) {
+                float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
+                float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
+                if (kz >= 0)
+                    t1 = div_stretch2(t1, a.auxZ + ZAUX_EP * slabZ + sz, a.oauxZ + ZAUX_EP * slabZ + sz, true,
+                                      zc.g1_int, zc.g2_int, a.cz, dt);
+                if (ir >= 0)
+                    t2 = div_stretch2(t2, a.auxR + AUX_EP_S * slabR + sr, a.oauxR + AUX_EP_S * slabR + sr, true,
+                                      rc.g1_s_int, rc.g2_s_int, a.cr, dt);
+                ep_n = make_float2(ep.x + ce * (t1.x - t2.x - jph.x), ep.y + ce * (t1.y - t2.y - jph.y));
+                if (ir >= 0) {
+                    const float2 uo = a.auxR[AUX_U_EP * slabR + sr];
+                    a.oauxR[AUX_U_EP * slabR + sr] =
+                        make_float2(a.cr * uo.x + dt * ep_n.x, a.cr * uo.y + dt * ep_n.y);
+                }
+            }
+            // E_z at (i, j, k+1/2)
+            if (i > 0) {
+                float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
+                if (ir >= 0) {
+                    t = c_add(t, c_sub(c_scale(v, rc.ez_c1), c_scale(v_im, rc.ez_c0)));
+                    t = div_stretch2(t, a.auxR + AUX_EZ_S * slabR + sr, a.oauxR + AUX_EZ_S * slabR + sr, true,
+                                     rc.g1_s_int, rc.g2_s_int, a.cr, dt);
+                }
+                t = c_sub(t, c_scale(c_sub(hr, hr_jm), rc.inv_rdphi_int));
+                if (ir >= 0)
+                    t = div_stretch2(t, a.auxR + AUX_EZ_T * slabR + sr, a.oauxR + AUX_EZ_T * slabR + sr, true,
+                                     rc.g1_t_int, rc.g2_t_int, a.cr, dt);
+                ez_n = make_float2(ez.x + ce * t.x, ez.y + ce * t.y);
+            }
+            a.oEr[c] = er_n;
+            a.oEp[c] = ep_n;
+            a.oEz[c] = ez_n;
+            if (a.dft_plane && k == a.k_mon) {
+                for (int f = 0; f < a.K; ++f) {
+                    const float2 tw = a.twiddle[(size_t)n * a.K + f];
+                    float2 *o = a.dft_plane + (size_t)f * 2 * plane + (size_t)i * nphi + j;
+                    o[0] = c_fma(o[0], tw, er_n);
+                    o[plane] = c_fma(o[plane], tw, ep_n);
+                }
+            }
+            if (a.dft_vol && k >= a.k0 && k < a.k1) {
+                const size_t vs = (size_t)nd * plane;
+                for (int f = 0; f < a.K; ++f) {
+                    const float2 tw = a.twiddle[(size_t)n * a.K + f];
+                    float2 *o = a.dft_vol + (size_t)f * 3 * vs + (size_t)(k - a.k0) * plane + (size_t)i * nphi + j;
+                    o[0] = c_fma(o[0], tw, er_n);
+                    o[vs] = c_fma(o[vs], tw, ep_n);
+                    o[2 * vs] = c_fma(o[2 * vs], tw, ez_n);
+                }
+            }
+        }
+        hr_km = hr;
+        hp_km = hp;
+        er = er_kp;
+        ep = ep_kp;
+    }
+}
+
 __global__ void fill_kernel(float2 *p, size_t n)
 {
     size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,19 +543,46 @@ __global__ void nonfinite_kernel(const float2 *p, size_t n, int *flag)
 
 }  // namespace
 
-void launch_h_step(const StepArgs &a, int n, hipStream_t s)
+template <int BY>
+void launch_pair(const StepArgs &a, int n, hipStream_t s, bool h)
 {
     dim3 block(BX, BY, 1);
     dim3 grid((a.nphi + BX - 1) / BX, (a.nr + BY - 1) / BY, (a.nz + a.kchunk - 1) / a.kchunk);
-    hipLaunchKernelGGL(h_step_kernel, grid, block, 0, s, a, n);
+    if (h) hipLaunchKernelGGL(h_step_kernel<BY>, grid, block, 0, s, a, n);
+    else hipLaunchKernelGGL(e_step_kernel<BY>, grid, block, 0, s, a, n);
 }
 
-void launch_e_step(const StepArgs &a, int n, hipStream_t s)
+void launch_step(const StepArgs &a, int n, hipStream_t s, bool h)
 {
-    dim3 block(BX, BY, 1);
-    dim3 grid((a.nphi + BX - 1) / BX, (a.nr + BY - 1) / BY, (a.nz + a.kchunk - 1) / a.kchunk);
-    hipLaunchKernelGGL(e_step_kernel, grid, block, 0, s, a, n);
+    switch (a.tile_rows) {
+    case 1: launch_pair<1>(a, n, s, h); break;
+    case 2: launch_pair<2>(a, n, s, h); break;
+    case 8: launch_pair<8>(a, n, s, h); break;
+    case 16: launch_pair<16>(a, n, s, h); break;
+    default: launch_pair<4>(a, n, s, h); break;
+    }
 }
+
+void launch_h_step(const StepArgs &a, int n, hipStream_t s) { launch_step(a, n, s, true); }
+
+template <int TR>
+void launch_fused_tr(const StepArgs &a, int n, hipStream_t s)
+{
+    dim3 block(64, TR + 1, 1);
+    dim3 grid((a.nphi + 62) / 63, (a.nr + TR - 1) / TR, (a.nz + a.kchunk - 1) / a.kchunk);
+    hipLaunchKernelGGL(eh_fused_kernel<TR>, grid, block, 0, s, a, n);
+}
+
+void launch_fused_step(const StepArgs &a, int n, hipStream_t s)
+{
+    switch (a.tile_rows) {
+    case 3: launch_fused_tr<3>(a, n, s); break;
+    case 15: launch_fused_tr<15>(a, n, s); break;
+    default: launch_fused_tr<7>(a, n, s); break;
+    }
+}
+
+void launch_e_step(const StepArgs &a, int n, hipStream_t s) { launch_step(a, n, s, false); }
 
 void launch_fill(float2 *p, size_t n, hipStream_t s)
 {

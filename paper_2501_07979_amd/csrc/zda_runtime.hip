@@ -68,14 +68,19 @@ struct zda_zone {
     int device = 0;
     double dt = 0, dphi = 0, tau = 0, cfl = 0;
     size_t ncell = 0, plane = 0;
-    int dR = 0, dZ = 0, nd = 0, kchunk = 1;
+    int dR = 0, dZ = 0, nd = 0, kchunk = 1, tile_rows = 7;
     // FP64 layer constants: [0] integer points, [1] half points
     std::vector<double> sig_r[2], Sig_r[2], sgt_r[2], sig_z[2];
     double cr = 1, cz = 1;
     // device memory
-    float2 *F[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // two buffer sets of the six fields and the PML auxiliaries: the split
+    // kernels update set `cur` in place, the fused kernel steps cur -> cur^1
+    float2 *F[2][6] = {{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr},
+                       {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}};
     float *ceps = nullptr;
-    float2 *auxR = nullptr, *auxZ = nullptr;
+    float2 *auxR[2] = {nullptr, nullptr}, *auxZ[2] = {nullptr, nullptr};
+    int cur = 0;
+    bool fused = true;
     RowCoef *rows = nullptr;
     ZCoef *zrows = nullptr;
     float2 *dft_plane = nullptr, *dft_vol = nullptr, *dft_vol_adj = nullptr;
@@ -96,6 +101,7 @@ struct zda_zone {
     // per-launch timing events of the last timed run
     std::vector<hipEvent_t> ev;
     int timed_steps = 0;
+    bool timed_fused = false;
 };
 
 namespace {
@@ -128,9 +134,10 @@ void free_all(zda_zone *z)
 {
     for (auto e : z->ev) (void)hipEventDestroy(e);
     z->ev.clear();
-    for (auto &f : z->F) if (f) (void)hipFree(f);
-    void *ptrs[] = {z->ceps, z->auxR, z->auxZ, z->rows, z->zrows, z->dft_plane, z->dft_vol, z->dft_vol_adj,
-                    z->pattern, z->profile, z->twiddle, z->scratch, z->flag};
+    for (auto &set : z->F)
+        for (auto &f : set) if (f) (void)hipFree(f);
+    void *ptrs[] = {z->ceps, z->auxR[0], z->auxZ[0], z->auxR[1], z->auxZ[1], z->rows, z->zrows, z->dft_plane,
+                    z->dft_vol, z->dft_vol_adj, z->pattern, z->profile, z->twiddle, z->scratch, z->flag};
     for (void *p : ptrs) if (p) (void)hipFree(p);
 }
 
@@ -227,21 +234,30 @@ StepArgs step_args(zda_zone *z, int m)
     const double ph = m * z->tau;
     a.seam_p = make_float2((float)std::cos(ph), (float)std::sin(ph));
     a.seam_m = make_float2((float)std::cos(ph), (float)-std::sin(ph));
-    a.Er = z->F[0]; a.Ep = z->F[1]; a.Ez = z->F[2]; a.Hr = z->F[3]; a.Hp = z->F[4]; a.Hz = z->F[5];
+    const int s0 = z->cur, s1 = z->cur ^ 1;
+    a.Er = z->F[s0][0]; a.Ep = z->F[s0][1]; a.Ez = z->F[s0][2];
+    a.Hr = z->F[s0][3]; a.Hp = z->F[s0][4]; a.Hz = z->F[s0][5];
+    a.oEr = z->F[s1][0]; a.oEp = z->F[s1][1]; a.oEz = z->F[s1][2];
+    a.oHr = z->F[s1][3]; a.oHp = z->F[s1][4]; a.oHz = z->F[s1][5];
     a.ceps = z->ceps;
-    a.auxR = z->auxR; a.auxZ = z->auxZ;
+    a.auxR = z->auxR[s0]; a.auxZ = z->auxZ[s0];
+    a.oauxR = z->auxR[s1]; a.oauxZ = z->auxZ[s1];
     a.rows = z->rows; a.zrows = z->zrows;
     a.k_mon = d.k_mon;
     a.k0 = d.design_k0; a.k1 = d.design_k1;
     a.kchunk = z->kchunk;
+    a.tile_rows = z->tile_rows;
     return a;
 }
 
 zda_status reset_state(zda_zone *z, hipStream_t s)
 {
-    for (auto f : z->F) launch_fill(f, z->ncell, s);
-    if (z->auxR) launch_fill(z->auxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, s);
-    if (z->auxZ) launch_fill(z->auxZ, (size_t)N_AUX_Z * z->dZ * z->plane, s);
+    for (int b = 0; b < 2; ++b) {
+        for (auto f : z->F[b]) if (f) launch_fill(f, z->ncell, s);
+        if (z->auxR[b]) launch_fill(z->auxR[b], (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, s);
+        if (z->auxZ[b]) launch_fill(z->auxZ[b], (size_t)N_AUX_Z * z->dZ * z->plane, s);
+    }
+    z->cur = 0;
     HIP_TRY(hipGetLastError());
     z->n_done = 0;
     return ZDA_OK;
@@ -289,15 +305,32 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     HIP_TRY(hipMemcpyAsync(z->twiddle, z->st_tw.data(), z->st_tw.size() * sizeof(float2),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
-    StepArgs a = step_args(z, m);
-    a.k_src = k_src;
-    a.n_prof = P;
-    a.pattern = z->pattern;
-    a.profile = z->profile;
-    a.K = K;
-    a.twiddle = z->twiddle;
-    a.dft_plane = dft_plane;
-    a.dft_vol = dft_vol;
+    // argument blocks for the two buffer parities of the fused step
+    const int ab_base = z->cur;
+    StepArgs ab[2];
+    for (int b = 0; b < 2; ++b) {
+        ab[b] = step_args(z, m);
+        ab[b].k_src = k_src;
+        ab[b].n_prof = P;
+        ab[b].pattern = z->pattern;
+        ab[b].profile = z->profile;
+        ab[b].K = K;
+        ab[b].twiddle = z->twiddle;
+        ab[b].dft_plane = dft_plane;
+        ab[b].dft_vol = dft_vol;
+        z->cur ^= 1;
+    }
+    const StepArgs &a = ab[0];
+    const bool fused = z->fused;
+    auto step = [&](int n) {
+        if (fused) {
+            launch_fused_step(ab[z->cur ^ ab_base], n, s);
+            z->cur ^= 1;
+        } else {
+            launch_h_step(a, n, s);
+            launch_e_step(a, n, s);
+        }
+    };
     z->timed_steps = 0;
     if (timing) {
         const size_t need = 4 * (size_t)nsteps;
@@ -307,19 +340,23 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
             z->ev.push_back(e);
         }
         for (int n = 0; n < nsteps; ++n) {
-            HIP_TRY(hipEventRecord(z->ev[4 * n], s));
-            launch_h_step(a, n, s);
-            HIP_TRY(hipEventRecord(z->ev[4 * n + 1], s));
-            HIP_TRY(hipEventRecord(z->ev[4 * n + 2], s));
-            launch_e_step(a, n, s);
-            HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
+            if (fused) {
+                HIP_TRY(hipEventRecord(z->ev[4 * n + 2], s));
+                step(n);
+                HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
+            } else {
+                HIP_TRY(hipEventRecord(z->ev[4 * n], s));
+                launch_h_step(a, n, s);
+                HIP_TRY(hipEventRecord(z->ev[4 * n + 1], s));
+                HIP_TRY(hipEventRecord(z->ev[4 * n + 2], s));
+                launch_e_step(a, n, s);
+                HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
+            }
         }
         z->timed_steps = nsteps;
+        z->timed_fused = fused;
     } else {
-        for (int n = 0; n < nsteps; ++n) {
-            launch_h_step(a, n, s);
-            launch_e_step(a, n, s);
-        }
+        for (int n = 0; n < nsteps; ++n) step(n);
     }
     HIP_TRY(hipGetLastError());
     z->n_done += nsteps;
@@ -401,10 +438,12 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     z->dR = d->pml_r_in + d->pml_r_out;
     z->dZ = d->pml_z_lo + d->pml_z_hi;
     z->nd = d->design_k1 - d->design_k0;
-    // z-chunks: enough wavefronts to fill 256 CUs, chunks of at least 8 planes
+    // default launch shape: fused step, 7 owned rows per block, z-chunks
+    // short enough for ~32 wavefronts per CU (256 CUs), at least 8 planes
     {
-        const long waves = (long)((d->nphi + 63) / 64) * d->nr;
-        long chunks = (8192 + waves - 1) / waves;
+        z->tile_rows = 7;
+        const long waves = (long)((d->nphi + 62) / 63) * ((d->nr + 6) / 7) * 8;
+        long chunks = (32768 + waves - 1) / waves;
         chunks = std::max(1L, std::min(chunks, (long)std::max(1, d->nz / 8)));
         z->kchunk = (int)((d->nz + chunks - 1) / chunks);
     }
@@ -413,10 +452,25 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     setup_layers(z, rows, zr);
 
     zda_status st = ZDA_OK;
-    for (auto &f : z->F) if (st == ZDA_OK) st = dev_alloc(z, &f, z->ncell);
+    for (auto &f : z->F[0]) if (st == ZDA_OK) st = dev_alloc(z, &f, z->ncell);
     if (st == ZDA_OK) st = dev_alloc(z, &z->ceps, z->ncell);
-    if (st == ZDA_OK) st = dev_alloc(z, &z->auxR, (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
-    if (st == ZDA_OK) st = dev_alloc(z, &z->auxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->auxR[0], (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->auxZ[0], (size_t)N_AUX_Z * z->dZ * z->plane);
+    // the second buffer set of the fused step; without room for it the zone
+    // keeps the in-place split kernels
+    if (st == ZDA_OK) {
+        zda_status s1 = ZDA_OK;
+        for (auto &f : z->F[1]) if (s1 == ZDA_OK) s1 = dev_alloc(z, &f, z->ncell);
+        if (s1 == ZDA_OK) s1 = dev_alloc(z, &z->auxR[1], (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
+        if (s1 == ZDA_OK) s1 = dev_alloc(z, &z->auxZ[1], (size_t)N_AUX_Z * z->dZ * z->plane);
+        if (s1 != ZDA_OK) {
+            for (auto &f : z->F[1]) if (f) { (void)hipFree(f); z->bytes -= z->ncell * sizeof(float2); f = nullptr; }
+            if (z->auxR[1]) { (void)hipFree(z->auxR[1]); z->auxR[1] = nullptr; }
+            if (z->auxZ[1]) { (void)hipFree(z->auxZ[1]); z->auxZ[1] = nullptr; }
+            z->fused = false;
+            z->tile_rows = 4;
+        }
+    }
     if (st == ZDA_OK) st = dev_alloc(z, &z->rows, (size_t)d->nr);
     if (st == ZDA_OK) st = dev_alloc(z, &z->zrows, (size_t)d->nz);
     if (st == ZDA_OK) st = dev_alloc(z, &z->flag, 1);
@@ -709,7 +763,7 @@ zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_dev
     if (!z || !out || comp < 0 || comp > 5) return fail(ZDA_ERR_ARG, "bad argument");
     DeviceGuard g(z->device);
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(out, z->F[comp], z->ncell * sizeof(float2),
+    HIP_TRY(hipMemcpy(out, z->F[z->cur][comp], z->ncell * sizeof(float2),
                       out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     return ZDA_OK;
 }
@@ -719,13 +773,29 @@ zda_status zda_zone_write_field(zda_zone *z, int comp, const float *in, int in_o
     if (!z || !in || comp < 0 || comp > 5) return fail(ZDA_ERR_ARG, "bad argument");
     DeviceGuard g(z->device);
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(z->F[comp], in, z->ncell * sizeof(float2),
+    HIP_TRY(hipMemcpy(z->F[z->cur][comp], in, z->ncell * sizeof(float2),
                       in_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
     if (comp == 1 && z->dR > 0) {
-        launch_seed_u(z->auxR + (size_t)AUX_U_EP * z->d.nz * z->dR * z->d.nphi, z->F[1], z->d.nr, z->d.nphi,
+        launch_seed_u(z->auxR[z->cur] + (size_t)AUX_U_EP * z->d.nz * z->dR * z->d.nphi, z->F[z->cur][1], z->d.nr,
+                      z->d.nphi,
                       z->d.nz, z->d.pml_r_in, z->d.pml_r_out, (float)z->dt, nullptr);
         HIP_TRY(hipDeviceSynchronize());
     }
+    return ZDA_OK;
+}
+
+zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
+{
+    if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
+    if (kchunk < 1 || kchunk > z->d.nz) return fail(ZDA_ERR_ARG, "kchunk must be in [1, nz]");
+    const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16;
+    const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15;
+    if (!split && !fused) return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16 (split) or 3, 7, 15 (fused)");
+    if (fused && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set for the fused step");
+    if (fused && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set for the fused step");
+    z->kchunk = kchunk;
+    z->tile_rows = tile_rows;
+    z->fused = fused;
     return ZDA_OK;
 }
 
@@ -737,6 +807,8 @@ zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info)
     info->dt = z->dt;
     info->cfl = z->cfl;
     info->launch_chunks = (z->d.nz + z->kchunk - 1) / z->kchunk;
+    info->kchunk = z->kchunk;
+    info->tile_rows = z->tile_rows;
     return ZDA_OK;
 }
 
@@ -749,12 +821,13 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t)
     HIP_TRY(hipEventSynchronize(z->ev[4 * (size_t)z->timed_steps - 1]));
     for (int n = 0; n < z->timed_steps; ++n) {
         float a = 0.f, b = 0.f;
-        HIP_TRY(hipEventElapsedTime(&a, z->ev[4 * n], z->ev[4 * n + 1]));
+        if (!z->timed_fused) HIP_TRY(hipEventElapsedTime(&a, z->ev[4 * n], z->ev[4 * n + 1]));
         HIP_TRY(hipEventElapsedTime(&b, z->ev[4 * n + 2], z->ev[4 * n + 3]));
         t->h_ms += a;
         t->e_ms += b;
     }
-    t->h_launches = t->e_launches = z->timed_steps;
+    t->h_launches = z->timed_fused ? 0 : z->timed_steps;
+    t->e_launches = z->timed_steps;
     return ZDA_OK;
 }
 

@@ -24,7 +24,8 @@ COMP = {"Er": 0, "Ephi": 1, "Ez": 2, "Hr": 3, "Hphi": 4, "Hz": 5}
 
 EXPORTS = ["zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_zone_set_eps",
            "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields", "zda_adjoint_grad",
-           "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_last_timing",
+           "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_set_launch",
+           "zda_zone_last_timing",
            "zda_status_str", "zda_last_error"]
 
 
@@ -47,7 +48,8 @@ class Source(ctypes.Structure):
 
 class ZoneInfo(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t), ("dt", ctypes.c_double),
-                ("cfl", ctypes.c_double), ("launch_chunks", ctypes.c_int)]
+                ("cfl", ctypes.c_double), ("launch_chunks", ctypes.c_int), ("kchunk", ctypes.c_int),
+                ("tile_rows", ctypes.c_int)]
 
 
 class Timing(ctypes.Structure):
@@ -87,13 +89,14 @@ def load():
     lib.zda_zone_write_field.argtypes = [P, I, P, I]
     lib.zda_zone_get_info.argtypes = [P, ctypes.POINTER(ZoneInfo)]
     lib.zda_zone_last_timing.argtypes = [P, ctypes.POINTER(Timing)]
+    lib.zda_zone_set_launch.argtypes = [P, I, I]
     lib.zda_status_str.argtypes = [I]
     lib.zda_status_str.restype = ctypes.c_char_p
     lib.zda_last_error.argtypes = []
     lib.zda_last_error.restype = ctypes.c_char_p
     for name in ("zda_zone_create", "zda_zone_set_eps", "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields",
                  "zda_adjoint_grad", "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info",
-                 "zda_zone_last_timing"):
+                 "zda_zone_last_timing", "zda_zone_set_launch"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -173,6 +176,9 @@ class Zone:
         inf = ZoneInfo()
         _check(load().zda_zone_get_info(self._h, ctypes.byref(inf)))
         return inf
+
+    def set_launch(self, kchunk, tile_rows):
+        _check(load().zda_zone_set_launch(self._h, int(kchunk), int(tile_rows)))
 
     @property
     def dt(self):

@@ -25,18 +25,29 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-def _zone_pair(zda, oracle_mod, wl, eps):
+# launch shapes: (kchunk, tile_rows); tile_rows 3/7/15 select the fused
+# double-buffered step, 1/2/4/8/16 the split in-place H and E kernels;
+# None keeps the zone's default (fused)
+SHAPES = {"default": None, "fused_tr3_kc7": (7, 3), "fused_tr15_kc13": (13, 15), "split_r4_kc7": (7, 4),
+          "split_r1": (0, 1)}
+
+
+def _zone_pair(zda, oracle_mod, wl, eps, shape=None):
     g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+    if shape is not None:
+        kc, tr = shape
+        g.set_launch(kc if kc > 0 else wl.nz, tr)
     o = oracle_mod.OracleZone(**wl.desc_kwargs(), eps=eps)
     return g, o
 
 
-def test_c1_parity_exit_plane_dft(zda, oracle_mod):
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7"])
+def test_c1_parity_exit_plane_dft(zda, oracle_mod, shape):
     from paper_2501_07979_amd.workloads import c1
     wl = c1()
-    _say("c1 full parity", wl.name, wl.steps)
+    _say("c1 full parity", wl.name, wl.steps, shape)
     eps = wl.eps()
-    g, o = _zone_pair(zda, oracle_mod, wl, eps)
+    g, o = _zone_pair(zda, oracle_mod, wl, eps, SHAPES[shape])
     g.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
     gpu = g.dft(zda.MON_PLANE).cpu().numpy()
     ref = o.forward(wl.steps, np.array(wl.omegas), omega_c=wl.omega_c, width=wl.width, k_src=wl.k_src)["plane"]
@@ -49,8 +60,9 @@ def test_c1_parity_exit_plane_dft(zda, oracle_mod):
         assert e <= 1e-4, (c, e)
 
 
+@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "fused_tr15_kc13", "split_r4_kc7"])
 @pytest.mark.parametrize("case", ["ragged_m1", "ragged_m0", "ragged_mneg", "no_pml"])
-def test_ragged_shapes_all_fields(zda, oracle_mod, case):
+def test_ragged_shapes_all_fields(zda, oracle_mod, case, shape):
     """Shapes that are not multiples of the tile (nphi 70, nr 37) with uneven
     PML widths and several z-chunks; every field and the DFTs compared."""
     from paper_2501_07979_amd.workloads import Workload
@@ -60,8 +72,8 @@ def test_ragged_shapes_all_fields(zda, oracle_mod, case):
                   design=(12, 17), k_sub=12, steps=300, omegas=(0.28, 0.33), omega_c=0.31, width=7.0, seed=5)
     rng = np.random.default_rng(21)
     eps = (1.0 + 4.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
-    _say("ragged", case)
-    g, o = _zone_pair(zda, oracle_mod, wl, eps)
+    _say("ragged", case, shape)
+    g, o = _zone_pair(zda, oracle_mod, wl, eps, SHAPES[shape])
     kind = zda.SRC_RADIAL if m == 0 else zda.SRC_PLANE_CIRC
     g.run(wl.steps, wl.omegas, kind=kind, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width, volume=True)
     ref = o.forward(wl.steps, np.array(wl.omegas), omega_c=wl.omega_c, width=wl.width, k_src=wl.k_src,
@@ -73,7 +85,8 @@ def test_ragged_shapes_all_fields(zda, oracle_mod, case):
     assert _rel(g.dft(zda.MON_VOLUME).cpu().numpy(), ref["vol"]) <= 1e-5
 
 
-def test_random_state_steps_with_pml(zda, oracle_mod):
+@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7"])
+def test_random_state_steps_with_pml(zda, oracle_mod, shape):
     """Arbitrary initial fields (written through the ABI) stepped without
     reset: every update term, PML auxiliary and the seam act from step 1."""
     from paper_2501_07979_amd.workloads import Workload
@@ -81,8 +94,8 @@ def test_random_state_steps_with_pml(zda, oracle_mod):
                   k_mon=20, design=(10, 12), steps=40)
     rng = np.random.default_rng(22)
     eps = (1.0 + 3.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
-    g, o = _zone_pair(zda, oracle_mod, wl, eps)
-    _say("random state")
+    g, o = _zone_pair(zda, oracle_mod, wl, eps, SHAPES[shape])
+    _say("random state", shape)
     for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz"):
         f = (rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)).astype(np.complex64)
         if c == "Er":
@@ -133,16 +146,17 @@ def _objective(wts, plane):
     return np.sum(np.abs(s) ** 2), np.conj(s)[:, None, None, None] * wts
 
 
-def test_gradient_parity_small_copy(zda, oracle_mod):
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7"])
+def test_gradient_parity_small_copy(zda, oracle_mod, shape):
     """Adjoint gradient over the design layer of the gradient zone's small
     copy (64 x 64 x 96, three frequencies) against the oracle's gradient."""
     from paper_2501_07979_amd.workloads import c3_small
     wl = c3_small()
     rho = wl.rho()
     eps = wl.eps(rho)
-    g, o = _zone_pair(zda, oracle_mod, wl, eps)
+    g, o = _zone_pair(zda, oracle_mod, wl, eps, SHAPES[shape])
     om = np.array(wl.omegas)
-    _say("gradient small copy forward", wl.name, wl.steps)
+    _say("gradient small copy forward", wl.name, wl.steps, shape)
     g.run(wl.steps, om, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width, volume=True)
     fwd = o.forward(wl.steps, om, omega_c=wl.omega_c, width=wl.width, k_src=wl.k_src, volume=True)
     gp = g.dft(zda.MON_PLANE).cpu().numpy()
@@ -160,6 +174,71 @@ def test_gradient_parity_small_copy(zda, oracle_mod):
     assert np.isfinite(g.dft(zda.MON_ADJOINT_VOLUME).cpu().numpy()).all()
 
 
+def test_production_zone_full_size_steps(zda, oracle_mod):
+    """The production zone (512 x 1024 x 400, n = 512, 12-cell PML, source and
+    3-frequency exit-plane DFT) in the launch shape the benchmark times:
+    random fields everywhere, a few steps, every field and the DFT plane
+    compared with the FP64 oracle on the full zone."""
+    from paper_2501_07979_amd.workloads import c2
+    wl = c2()
+    steps = 3
+    rng = np.random.default_rng(51)
+    eps = wl.eps()
+    _say("production zone: building GPU and oracle zones")
+    g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+    o = oracle_mod.OracleZone(**wl.desc_kwargs(), eps=eps)
+    del eps
+    masks = {"Er": ("k0",), "Ephi": ("k0", "i0"), "Ez": ("i0",), "Hr": ("i0",), "Hphi": (), "Hz": ("k0",)}
+    for c, zero in masks.items():
+        f = rng.standard_normal((wl.nz, wl.nr, 2 * wl.nphi), dtype=np.float32).view(np.complex64)
+        if "k0" in zero:
+            f[0] = 0
+        if "i0" in zero:
+            f[:, 0] = 0
+        g.write_field(c, f)
+        o.set_field(c, f)
+        del f
+    _say("production zone: stepping")
+    g.run(steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width, n0=1, cont=True)
+    g_, n0 = oracle_mod.pulse(steps, o.dt, wl.omega_c, wl.width, 1)
+    assert np.abs(g_).max() > 0
+    ref = o.run(steps, patterns=o.preset_pattern()[None], profiles=g_[None], k_src=wl.k_src,
+                omegas=np.array(wl.omegas), reset=False)
+    _say("production zone: comparing")
+    for c in masks:
+        a = g.read_field(c).cpu().numpy()
+        b = o.get_field(c)
+        e = _rel(a, b)
+        _say("production zone", c, "rel L2 %.2e" % e)
+        assert e <= 1e-5, (c, e)
+        del a, b
+    assert _rel(g.dft(zda.MON_PLANE).cpu().numpy(), ref["plane"]) <= 1e-5
+    g.close()
+
+
+def test_fused_launch_shapes_are_bitwise_identical(zda):
+    """Every cell is computed by the same instruction sequence whatever the
+    tile and chunk shape (halo values are recomputed, not approximated), so
+    the fused step is deterministic across launch shapes."""
+    from paper_2501_07979_amd.workloads import Workload
+    wl = Workload("determinism", r_in=90.0, nr=37, nphi=130, nz=41, n_fold=14, m=1, pml=(5, 6, 4, 7), k_src=9,
+                  k_mon=30, design=(12, 17), k_sub=12, steps=120, omegas=(0.3,), omega_c=0.3, width=6.0)
+    rng = np.random.default_rng(41)
+    eps = (1.0 + 4.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
+    outs = []
+    for kc, tr in [(41, 7), (5, 3), (13, 15), (1, 7)]:
+        _say("determinism", kc, tr)
+        g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+        g.set_launch(kc, tr)
+        g.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+        outs.append([g.read_field(c).cpu().numpy() for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz")] +
+                    [g.dft(zda.MON_PLANE).cpu().numpy()])
+        g.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
 def test_error_paths_on_device(zda):
     from paper_2501_07979_amd.workloads import c1
     wl = c1()
@@ -172,6 +251,9 @@ def test_error_paths_on_device(zda):
     assert e.value.status == zda.ZDA_ERR_ARG
     with pytest.raises(zda.ZdaError) as e:
         g.run(10, [0.3] * 9, k_src=5, omega_c=0.3, width=5.0)
+    assert e.value.status == zda.ZDA_ERR_ARG
+    with pytest.raises(zda.ZdaError) as e:
+        g.set_launch(10, 5)
     assert e.value.status == zda.ZDA_ERR_ARG
     g.close()
     g.close()

@@ -1,0 +1,70 @@
+"""The focal-spot objective: the wedge-weighted projection equals a direct
+first Rayleigh-Sommerfeld quadrature of the Cartesian field over the whole
+ring of n wedge copies (Bloch-tiled), and its gradient convention matches
+torch's complex autograd."""
+import numpy as np
+import torch
+
+from paper_2501_07979_amd import objective
+from paper_2501_07979_amd.workloads import Workload
+
+
+def test_wedge_weights_equal_full_ring_quadrature():
+    rng = np.random.default_rng(3)
+    wl = Workload("obj", r_in=60.0, nr=20, nphi=12, nz=10, n_fold=9, m=1, pml=(3, 4, 2, 2))
+    om = (0.3, 0.41)
+    F = 140.0
+    W = objective.focal_weights(wl, om, F, device="cpu").numpy()
+    Er = rng.standard_normal((2, wl.nr, wl.nphi)) + 1j * rng.standard_normal((2, wl.nr, wl.nphi))
+    Ep = rng.standard_normal((2, wl.nr, wl.nphi)) + 1j * rng.standard_normal((2, wl.nr, wl.nphi))
+    plane = np.stack([Er, Ep], axis=1)
+    a = np.einsum("kaij,kaij->k", W.astype(np.complex128), plane)
+    # direct quadrature over the ring: tile with the Bloch phase of m = 1
+    n, dphi = wl.n_fold, 2 * np.pi / (wl.n_fold * wl.nphi)
+    tau = 2 * np.pi / n
+    ri = wl.r_in + np.arange(wl.nr) * wl.dr
+    rh = ri + 0.5 * wl.dr
+    act = np.zeros(wl.nr)
+    act[wl.pml[0]:wl.nr - wl.pml[1]] = 1
+    for k, w in enumerate(om):
+        ex = ey = 0.0
+        for l in range(n):
+            ph = np.exp(1j * wl.m * l * tau)
+            for (r, comp, off) in ((rh, 0, 0.0), (ri, 1, 0.5)):
+                phi = (np.arange(wl.nphi) + off) * dphi + l * tau
+                R = np.sqrt(r * r + F * F)
+                G = (F / R) * (1j * w - 1 / R) * np.exp(1j * w * R) / R / (2 * np.pi)
+                f = ph * plane[k, comp]
+                # each staggered component contributes its own Cartesian parts
+                if comp == 0:
+                    cx, cy = np.cos(phi), np.sin(phi)
+                else:
+                    cx, cy = -np.sin(phi), np.cos(phi)
+                wq = (act * G * r * wl.dr * dphi)[:, None]
+                ex = ex + np.sum(wq * f * cx[None, :])
+                ey = ey + np.sum(wq * f * cy[None, :])
+        direct = 0.5 * (ex - 1j * ey)
+        assert abs(direct - a[k]) < 1e-6 * abs(a[k])   # weights are complex64
+
+
+def test_objective_gradient_convention():
+    """backward passes conj(grad)/2 as dF/dEhat: check on the objective."""
+    rng = np.random.default_rng(4)
+    wl = Workload("obj", r_in=60.0, nr=10, nphi=8, nz=10, n_fold=9, m=1, pml=(2, 2, 2, 2))
+    W = objective.focal_weights(wl, (0.3,), 100.0, device="cpu").to(torch.complex128)
+    p = torch.tensor(rng.standard_normal((1, 2, 10, 8)) + 1j * rng.standard_normal((1, 2, 10, 8)),
+                     requires_grad=True)
+    F, a = objective.focal_objective(p, W)
+    F.backward()
+    holo = (a.conj()[:, None, None, None] * W).detach()
+    assert torch.allclose(p.grad.conj() * 0.5, holo, rtol=1e-12, atol=1e-14)
+
+
+def test_filter_and_projection_are_differentiable_and_periodic():
+    rho = torch.rand(4, 9, 16, dtype=torch.float64, requires_grad=True)
+    out = objective.tanh_projection(objective.gaussian_filter_phi_periodic(rho, 1.5), 8.0)
+    assert out.shape == rho.shape and float(out.min()) >= 0 and float(out.max()) <= 1
+    shifted = objective.gaussian_filter_phi_periodic(torch.roll(rho, 5, dims=2), 1.5)
+    assert torch.allclose(torch.roll(objective.gaussian_filter_phi_periodic(rho, 1.5), 5, dims=2), shifted)
+    assert torch.autograd.gradcheck(lambda r: objective.tanh_projection(
+        objective.gaussian_filter_phi_periodic(r, 1.0), 4.0).sum(), (rho,))
