@@ -71,6 +71,7 @@ typedef struct {
     int k_mon;
     int design_k0, design_k1;
     double eps_bg, eps_hi;
+    int single_buffer;      /* 1: one field set only (in-place split kernels; half the memory) */
 } zda_zone_desc;
 
 typedef struct zda_zone zda_zone;
@@ -196,6 +197,15 @@ typedef struct {
  * [1, nz] or tile_rows not in {1, 2, 4, 8, 16}. */
 zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 
+/* Launch options of the fused step (results do not depend on them):
+ * ZDA_OPT_XCD_REMAP (default 1) numbers the tiles so that each of the eight
+ * XCDs works on one contiguous range of neighbouring tiles; ZDA_OPT_NT_STORES
+ * (default 0) writes the next buffer set with non-temporal stores.
+ * ZDA_ERR_ARG for an unknown option. */
+#define ZDA_OPT_XCD_REMAP 1
+#define ZDA_OPT_NT_STORES 2
+zda_status zda_zone_set_option(zda_zone *z, int option, int value);
+
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);
 
 /* Per-kernel device time of the last zda_fdtd_run made with ZDA_RUN_TIMING
@@ -206,6 +216,47 @@ typedef struct {
 } zda_timing;
 
 zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
+
+/*
+ * Batches: many zones of uneven size (the lens-scale schedule in which n
+ * grows with radius) stepped together -- one launch per time step (fused
+ * kernels, when every zone has its second buffer set) or two (split), whose
+ * 1-D grid covers the tiles of every zone through a device zone table, with
+ * the time loop captured once into a HIP graph and replayed.  A batch does
+ * not own its zones; they must outlive it and live on one device.
+ */
+typedef struct zda_batch zda_batch;
+
+zda_status zda_batch_create(zda_zone *const *zones, int nzones, zda_batch **out);
+void zda_batch_destroy(zda_batch *b);
+
+/* Forward run of every zone: sources[i] is zone i's source; nsteps, omega[K]
+ * and dft_flags (no ZDA_RUN_TIMING) are shared.  Same results as running the
+ * zones one by one with zda_fdtd_run. */
+zda_status zda_batch_run(zda_batch *b, const zda_source *sources, int nsteps, const double *omega, int K,
+                         int dft_flags, void *stream);
+
+/* Adjoint gradients of every zone in one batched adjoint run; dF_dE[i] and
+ * grad_rho[i] are device pointers with the layouts of zda_adjoint_grad.
+ * Every zone needs a forward run with ZDA_DFT_VOLUME of the same length. */
+zda_status zda_batch_adjoint_grad(zda_batch *b, const float *const *dF_dE, float *const *grad_rho, void *stream);
+
+/* Launch shape shared by the batched kernels (tile_rows as in
+ * zda_zone_set_launch) and per-zone z-chunk depth kchunk[nzones] (NULL keeps
+ * each zone's). */
+zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk);
+
+/* Autotuner: times short probe runs (probe_steps >= 2; the zones' state is
+ * reset) of every kernel family and tile shape, then of z-chunk depths per
+ * size class of zones, keeps the fastest and reports it. */
+typedef struct {
+    int tile_rows;
+    double ms_per_step;
+    int probes;
+} zda_tune_result;
+
+zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe_steps, const double *omega, int K,
+                              void *stream, zda_tune_result *res);
 
 const char *zda_status_str(int status);
 const char *zda_last_error(void);

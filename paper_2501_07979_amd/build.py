@@ -13,6 +13,9 @@ ARCH = os.environ.get("ZDA_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+    # contract a*b+c only inside one source expression, so that every kernel
+    # built from the same update code rounds identically
+    "-ffp-contract=on",
     # no packed FP32 instructions in the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

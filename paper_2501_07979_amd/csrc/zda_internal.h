@@ -55,6 +55,18 @@ struct StepArgs {
     // fused step: fields and auxiliaries read from the set above, written here
     float2 *oEr, *oEp, *oEz, *oHr, *oHp, *oHz;
     float2 *oauxR, *oauxZ;
+    int xcd_remap;                 // fused: contiguous tile ranges per XCD
+    int nt_stores;                 // fused: non-temporal stores of the next buffer set
+};
+
+// Batched launch over many zones: per-zone argument blocks in device memory
+// and the first block index of each zone (prefix sums of tile counts).
+struct BatchArgs {
+    const StepArgs *tab;
+    const unsigned *prefix;
+    int nzones;
+    const int *n_base;             // device step offset added to the launch's step index
+    int xcd_remap;
 };
 
 enum { AUX_HR_T, AUX_HP_S, AUX_HZ_S, AUX_HZ_T, AUX_V_HP,
@@ -65,6 +77,12 @@ void launch_h_step(const StepArgs &a, int n, hipStream_t s);
 void launch_e_step(const StepArgs &a, int n, hipStream_t s);
 void launch_fused_step(const StepArgs &a, int n, hipStream_t s);
 void launch_fill(float2 *p, size_t n, hipStream_t s);
+// tiles of one zone for the split (BY rows) or fused (TR owned rows) kernels
+unsigned tiles_split(const StepArgs &a, int BY);
+unsigned tiles_fused(const StepArgs &a, int TR);
+void launch_batch_step(const BatchArgs &b, unsigned nblocks, int tile_rows, bool fused, int n_rel, hipStream_t s);
+void launch_advance_step(int *n_base, int by, hipStream_t s);
+void launch_set_int(int *p, int v, hipStream_t s);
 void launch_design_dt(float *ceps, const float *rho, size_t n, double eps_bg, double eps_hi, double dt,
                       hipStream_t s);
 void launch_inv_eps(float *ceps, const float *eps, size_t n, double dt, hipStream_t s);

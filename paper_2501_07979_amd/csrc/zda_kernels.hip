@@ -51,12 +51,12 @@ constexpr int BX = 64;   // one wavefront along phi
 
 // H^{n+1/2} = H^{n-1/2} - dt curlE(E^n); also advances V = F H_phi in the r-layer.
 template <int BY>
-__global__ __launch_bounds__(BX * BY) void h_step_kernel(StepArgs a, int n)
+__device__ __forceinline__ void h_step_body(const StepArgs &a, int n, int bx, int by, int bz)
 {
-    const int j = blockIdx.x * BX + threadIdx.x;
-    const int i = blockIdx.y * BY + threadIdx.y;
+    const int j = bx * BX + threadIdx.x;
+    const int i = by * BY + threadIdx.y;
     if (j >= a.nphi || i >= a.nr) return;
-    const int kb = blockIdx.z * a.kchunk;
+    const int kb = bz * a.kchunk;
     const int ke = min(kb + a.kchunk, a.nz);
     const int nphi = a.nphi, nr = a.nr, nz = a.nz;
     const size_t plane = (size_t)nr * nphi;
@@ -132,12 +132,12 @@ __global__ __launch_bounds__(BX * BY) void h_step_kernel(StepArgs a, int n)
 // E^{n+1} = E^n + (dt/eps)(curlH(H^{n+1/2}) - J^{n+1/2}); source sheet, DFT
 // accumulation and U = F E_phi in the r-layer fused.
 template <int BY>
-__global__ __launch_bounds__(BX * BY) void e_step_kernel(StepArgs a, int n)
+__device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, int by, int bz)
 {
-    const int j = blockIdx.x * BX + threadIdx.x;
-    const int i = blockIdx.y * BY + threadIdx.y;
+    const int j = bx * BX + threadIdx.x;
+    const int i = by * BY + threadIdx.y;
     if (j >= a.nphi || i >= a.nr) return;
-    const int kb = blockIdx.z * a.kchunk;
+    const int kb = bz * a.kchunk;
     const int ke = min(kb + a.kchunk, a.nz);
     const int nphi = a.nphi, nr = a.nr, nz = a.nz;
     const size_t plane = (size_t)nr * nphi;
@@ -239,6 +239,18 @@ __global__ __launch_bounds__(BX * BY) void e_step_kernel(StepArgs a, int n)
 }
 
 
+// store of a value no block of this launch reads again (the next buffer set)
+__device__ __forceinline__ void store_out(float2 *p, float2 v, bool nt)
+{
+    if (nt) {
+        unsigned long long bits;
+        __builtin_memcpy(&bits, &v, sizeof bits);
+        __builtin_nontemporal_store(bits, reinterpret_cast<unsigned long long *>(p));
+    } else {
+        *p = v;
+    }
+}
+
 // y = x / (1 + s F) reading the auxiliary from one buffer and, when the
 // caller owns the cell, writing its update to the other
 __device__ __forceinline__ float2 div_stretch2(float2 x, const float2 *src, float2 *dst, bool store, float g1,
@@ -262,22 +274,24 @@ __device__ __forceinline__ float2 div_stretch2(float2 x, const float2 *src, floa
 // the owners' E half-step.  A chunk starts one plane early to rebuild
 // H^{n+1/2} at k = kb - 1 for the E half-step at kb.
 template <int TR>
-__global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int n)
+__device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned p, unsigned gx, unsigned gy)
 {
     __shared__ float2 sHz[2][TR + 1][64], sHr[2][TR + 1][64], sHp[2][TR + 1][64], sV[2][TR + 1][64];
     const int lane = threadIdx.x, ww = threadIdx.y;
     const int nphi = a.nphi, nr = a.nr, nz = a.nz;
     const size_t plane = (size_t)nr * nphi;
-    const int i0 = blockIdx.y * TR;
+    const int bx = (int)(p % gx), by = (int)((p / gx) % gy), bz = (int)(p / (gx * gy));
+    const int i0 = by * TR;
     const int i = ww == 0 ? i0 - 1 : i0 + ww - 1;
-    const int jj = (int)blockIdx.x * 63 - 1 + lane;
+    const int jj = bx * 63 - 1 + lane;
     const bool hval = i >= 0 && i < nr && jj < nphi;
     const bool seam_lane = jj < 0;
     const int j = seam_lane ? nphi - 1 : jj;
     const bool owner = ww >= 1 && lane >= 1 && hval;
-    const int kb = blockIdx.z * a.kchunk;
+    const int kb = bz * a.kchunk;
     const int ke = min(kb + a.kchunk, nz);
     const int kstart = kb > 0 ? kb - 1 : kb;
+    const bool nt = a.nt_stores;
     const int ir = hval ? slab_row(i, nr, a.pr0, a.pr1) : -1;
     const int ir1 = (hval && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
     const RowCoef rc = a.rows[hval ? i : 0];
@@ -358,9 +372,9 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int
                 hz = make_float2(hz.x - dt * t.x, hz.y - dt * t.y);
             }
             if (store) {
-                a.oHr[c] = hr;
-                a.oHp[c] = hp;
-                a.oHz[c] = hz;
+                store_out(a.oHr + c, hr, nt);
+                store_out(a.oHp + c, hp, nt);
+                store_out(a.oHz + c, hz, nt);
             }
         }
         const int buf = k & 1;
@@ -434,9 +448,9 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int
                                      rc.g1_t_int, rc.g2_t_int, a.cr, dt);
                 ez_n = make_float2(ez.x + ce * t.x, ez.y + ce * t.y);
             }
-            a.oEr[c] = er_n;
-            a.oEp[c] = ep_n;
-            a.oEz[c] = ez_n;
+            store_out(a.oEr + c, er_n, nt);
+            store_out(a.oEp + c, ep_n, nt);
+            store_out(a.oEz + c, ez_n, nt);
             if (a.dft_plane && k == a.k_mon) {
                 for (int f = 0; f < a.K; ++f) {
                     const float2 tw = a.twiddle[(size_t)n * a.K + f];
@@ -461,6 +475,93 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int
         er = er_kp;
         ep = ep_kp;
     }
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; renumbering them so that
+// each XCD gets one contiguous range of tiles keeps the halo rows, columns and
+// chunk prologue planes that neighbouring tiles share in the same L2.
+__device__ __forceinline__ unsigned xcd_order(unsigned p, unsigned nblk, int on)
+{
+    if (!on || nblk < 8) return p;
+    const unsigned per = nblk / 8, rem = nblk % 8, x = p % 8, s = p / 8;
+    return x * per + min(x, rem) + s;
+}
+
+template <int BY>
+__global__ __launch_bounds__(BX * BY) void h_step_kernel(StepArgs a, int n)
+{
+    h_step_body<BY>(a, n, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int BY>
+__global__ __launch_bounds__(BX * BY) void e_step_kernel(StepArgs a, int n)
+{
+    e_step_body<BY>(a, n, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int TR>
+__global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int n)
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned nblk = gx * gy * gridDim.z;
+    const unsigned p = xcd_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), nblk, a.xcd_remap);
+    eh_fused_body<TR>(a, n, p, gx, gy);
+}
+
+// Batched launches: one 1-D grid covers the tiles of many zones of uneven
+// size; block b belongs to the zone whose prefix range holds it.
+__device__ __forceinline__ int batch_zone(const unsigned *prefix, int nzones, unsigned b)
+{
+    int lo = 0, hi = nzones - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int BY>
+__global__ __launch_bounds__(BX * BY) void h_step_batch(BatchArgs b, int n_rel)
+{
+    const int zi = batch_zone(b.prefix, b.nzones, blockIdx.x);
+    const StepArgs a = b.tab[zi];
+    const unsigned local = blockIdx.x - b.prefix[zi];
+    const unsigned gx = (a.nphi + BX - 1) / BX, gy = (a.nr + BY - 1) / BY;
+    const int n = n_rel + (b.n_base ? *b.n_base : 0);
+    h_step_body<BY>(a, n, local % gx, (local / gx) % gy, local / (gx * gy));
+}
+
+template <int BY>
+__global__ __launch_bounds__(BX * BY) void e_step_batch(BatchArgs b, int n_rel)
+{
+    const int zi = batch_zone(b.prefix, b.nzones, blockIdx.x);
+    const StepArgs a = b.tab[zi];
+    const unsigned local = blockIdx.x - b.prefix[zi];
+    const unsigned gx = (a.nphi + BX - 1) / BX, gy = (a.nr + BY - 1) / BY;
+    const int n = n_rel + (b.n_base ? *b.n_base : 0);
+    e_step_body<BY>(a, n, local % gx, (local / gx) % gy, local / (gx * gy));
+}
+
+template <int TR>
+__global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_batch(BatchArgs b, int n_rel)
+{
+    const unsigned g = xcd_order(blockIdx.x, gridDim.x, b.xcd_remap);
+    const int zi = batch_zone(b.prefix, b.nzones, g);
+    const StepArgs a = b.tab[zi];
+    const unsigned gx = (a.nphi + 62) / 63, gy = (a.nr + TR - 1) / TR;
+    const int n = n_rel + (b.n_base ? *b.n_base : 0);
+    eh_fused_body<TR>(a, n, g - b.prefix[zi], gx, gy);
+}
+
+__global__ void advance_step_kernel(int *n_base, int by)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *n_base += by;
+}
+
+__global__ void set_int_kernel(int *p, int v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 __global__ void fill_kernel(float2 *p, size_t n)
@@ -583,6 +684,60 @@ void launch_fused_step(const StepArgs &a, int n, hipStream_t s)
 }
 
 void launch_e_step(const StepArgs &a, int n, hipStream_t s) { launch_step(a, n, s, false); }
+
+unsigned tiles_split(const StepArgs &a, int BY)
+{
+    return (unsigned)((a.nphi + BX - 1) / BX) * (unsigned)((a.nr + BY - 1) / BY) *
+           (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
+}
+
+unsigned tiles_fused(const StepArgs &a, int TR)
+{
+    return (unsigned)((a.nphi + 62) / 63) * (unsigned)((a.nr + TR - 1) / TR) *
+           (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
+}
+
+template <int BY>
+void launch_batch_split(const BatchArgs &b, unsigned nblocks, int n_rel, hipStream_t s)
+{
+    hipLaunchKernelGGL(h_step_batch<BY>, dim3(nblocks), dim3(BX, BY), 0, s, b, n_rel);
+    hipLaunchKernelGGL(e_step_batch<BY>, dim3(nblocks), dim3(BX, BY), 0, s, b, n_rel);
+}
+
+template <int TR>
+void launch_batch_fused(const BatchArgs &b, unsigned nblocks, int n_rel, hipStream_t s)
+{
+    hipLaunchKernelGGL(eh_fused_batch<TR>, dim3(nblocks), dim3(64, TR + 1), 0, s, b, n_rel);
+}
+
+void launch_batch_step(const BatchArgs &b, unsigned nblocks, int tile_rows, bool fused, int n_rel, hipStream_t s)
+{
+    if (fused) {
+        switch (tile_rows) {
+        case 3: launch_batch_fused<3>(b, nblocks, n_rel, s); break;
+        case 15: launch_batch_fused<15>(b, nblocks, n_rel, s); break;
+        default: launch_batch_fused<7>(b, nblocks, n_rel, s); break;
+        }
+    } else {
+        switch (tile_rows) {
+        case 1: launch_batch_split<1>(b, nblocks, n_rel, s); break;
+        case 2: launch_batch_split<2>(b, nblocks, n_rel, s); break;
+        case 8: launch_batch_split<8>(b, nblocks, n_rel, s); break;
+        case 16: launch_batch_split<16>(b, nblocks, n_rel, s); break;
+        default: launch_batch_split<4>(b, nblocks, n_rel, s); break;
+        }
+    }
+}
+
+void launch_advance_step(int *n_base, int by, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, s, n_base, by);
+}
+
+void launch_set_int(int *p, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, p, v);
+}
 
 void launch_fill(float2 *p, size_t n, hipStream_t s)
 {

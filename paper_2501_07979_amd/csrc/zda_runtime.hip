@@ -9,6 +9,8 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
+#include <array>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -81,6 +83,7 @@ struct zda_zone {
     float2 *auxR[2] = {nullptr, nullptr}, *auxZ[2] = {nullptr, nullptr};
     int cur = 0;
     bool fused = true;
+    int xcd_remap = 1, nt_stores = 0;
     RowCoef *rows = nullptr;
     ZCoef *zrows = nullptr;
     float2 *dft_plane = nullptr, *dft_vol = nullptr, *dft_vol_adj = nullptr;
@@ -247,6 +250,8 @@ StepArgs step_args(zda_zone *z, int m)
     a.k0 = d.design_k0; a.k1 = d.design_k1;
     a.kchunk = z->kchunk;
     a.tile_rows = z->tile_rows;
+    a.xcd_remap = z->xcd_remap;
+    a.nt_stores = z->nt_stores;
     return a;
 }
 
@@ -275,8 +280,11 @@ int default_n0(double w, double dt) { return (int)std::lround(6.0 * w / dt); }
 
 // Core time loop: P source patterns already on the device in z->pattern,
 // host complex profiles prof[p*nsteps + n], K frequencies.
-zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *prof, const double *omega, int K,
-                    float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, bool timing = false)
+// Upload one run's source profiles and DFT twiddles (after the reset, if
+// asked) and fill the step arguments of the two buffer parities (ab[0] = the
+// zone's current set).
+zda_status prepare_run(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *prof, const double *omega, int K,
+                       float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, StepArgs ab[2])
 {
     const size_t T = (size_t)std::max(nsteps, 1);
     zda_status st;
@@ -305,9 +313,6 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     HIP_TRY(hipMemcpyAsync(z->twiddle, z->st_tw.data(), z->st_tw.size() * sizeof(float2),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
-    // argument blocks for the two buffer parities of the fused step
-    const int ab_base = z->cur;
-    StepArgs ab[2];
     for (int b = 0; b < 2; ++b) {
         ab[b] = step_args(z, m);
         ab[b].k_src = k_src;
@@ -320,6 +325,16 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
         ab[b].dft_vol = dft_vol;
         z->cur ^= 1;
     }
+    return ZDA_OK;
+}
+
+zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *prof, const double *omega, int K,
+                    float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, bool timing = false)
+{
+    StepArgs ab[2];
+    zda_status st = prepare_run(z, m, nsteps, k_src, P, prof, omega, K, dft_plane, dft_vol, reset, s, ab);
+    if (st != ZDA_OK) return st;
+    const int ab_base = z->cur;
     const StepArgs &a = ab[0];
     const bool fused = z->fused;
     auto step = [&](int n) {
@@ -363,6 +378,105 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     return ZDA_OK;
 }
 
+
+// Forward-run setup shared by the single-zone and batched runs: argument
+// checks, source pattern and profiles, DFT buffers.
+struct FwdPlan {
+    int P = 1;
+    std::vector<cd> prof;
+    double width = 0.0;
+    int n0 = -1;
+    float2 *dplane = nullptr, *dvol = nullptr;
+    bool reset = true;
+};
+
+zda_status forward_setup(zda_zone *z, const zda_source *s, int nsteps, const double *omega, int K, int dft_flags,
+                         hipStream_t hs, FwdPlan &plan)
+{
+    if (nsteps < 0) return fail(ZDA_ERR_ARG, "nsteps must be >= 0");
+    if (K < 0 || K > ZDA_MAX_FREQ || (K > 0 && !omega)) return fail(ZDA_ERR_ARG, "K must be in [0, %d]", ZDA_MAX_FREQ);
+    if ((dft_flags & ~(ZDA_DFT_PLANE | ZDA_DFT_VOLUME | ZDA_RUN_CONTINUE | ZDA_RUN_TIMING)) != 0)
+        return fail(ZDA_ERR_ARG, "bad dft_flags");
+    if ((dft_flags & ZDA_DFT_VOLUME) && z->nd <= 0) return fail(ZDA_ERR_STATE, "zone has no design layer");
+    const zda_zone_desc &d = z->d;
+    if (s->k_src < 1 || s->k_src >= d.nz) return fail(ZDA_ERR_ARG, "k_src must be in [1, nz)");
+    HIP_TRY(hipStreamSynchronize(hs));   // staging buffers of the previous call are free
+    plan.reset = !(dft_flags & ZDA_RUN_CONTINUE);
+    if (plan.reset) z->n_done = 0;
+    zda_status st;
+    if (s->kind == ZDA_SRC_PLANE_CIRC || s->kind == ZDA_SRC_RADIAL) {
+        if (s->kind == ZDA_SRC_PLANE_CIRC && std::abs(d.m) != 1) return fail(ZDA_ERR_UNSUPPORTED, "PLANE_CIRC needs |m| = 1");
+        if (s->kind == ZDA_SRC_RADIAL && d.m != 0) return fail(ZDA_ERR_UNSUPPORTED, "RADIAL needs m = 0");
+        if (!(s->width > 0)) return fail(ZDA_ERR_ARG, "pulse width must be > 0");
+        plan.P = 1;
+        plan.width = s->width;
+        plan.n0 = s->n0 >= 0 ? s->n0 : default_n0(plan.width, z->dt);
+        if ((st = ensure(z, &z->pattern, &z->cap_pattern, 2 * z->plane)) != ZDA_OK) return st;
+        z->st_pat.assign(2 * z->plane, make_float2(0.f, 0.f));
+        const double sgn = d.m > 0 ? 1.0 : (d.m < 0 ? -1.0 : 0.0);
+        for (int i = 0; i < d.nr; ++i)
+            for (int j = 0; j < d.nphi; ++j) {
+                cd jr, jp;
+                if (s->kind == ZDA_SRC_PLANE_CIRC) {
+                    jr = -std::exp(cd(0.0, d.m * j * z->dphi)) / d.dz;
+                    jp = cd(0.0, -sgn) * std::exp(cd(0.0, d.m * (j + 0.5) * z->dphi)) / d.dz;
+                } else {
+                    jr = -1.0 / d.dz;
+                    jp = 0.0;
+                }
+                z->st_pat[(size_t)i * d.nphi + j] = make_float2((float)jr.real(), (float)jr.imag());
+                z->st_pat[z->plane + (size_t)i * d.nphi + j] = make_float2((float)jp.real(), (float)jp.imag());
+            }
+        HIP_TRY(hipMemcpyAsync(z->pattern, z->st_pat.data(), 2 * z->plane * sizeof(float2), hipMemcpyHostToDevice, hs));
+        plan.prof.resize(nsteps);
+        for (int n = 0; n < nsteps; ++n) plan.prof[n] = pulse_at(z->n_done + n, z->dt, s->omega_c, plan.width, plan.n0);
+    } else if (s->kind == ZDA_SRC_CUSTOM) {
+        plan.P = s->n_profiles;
+        if (plan.P < 1 || plan.P > ZDA_MAX_FREQ || !s->patterns || !s->profiles)
+            return fail(ZDA_ERR_ARG, "CUSTOM needs 1..%d patterns and profiles", ZDA_MAX_FREQ);
+        if ((st = ensure(z, &z->pattern, &z->cap_pattern, (size_t)plan.P * 2 * z->plane)) != ZDA_OK) return st;
+        HIP_TRY(hipMemcpyAsync(z->pattern, s->patterns, (size_t)plan.P * 2 * z->plane * sizeof(float2),
+                               s->patterns_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
+        plan.prof.resize((size_t)plan.P * nsteps);
+        for (size_t q = 0; q < plan.prof.size(); ++q) plan.prof[q] = cd(s->profiles[2 * q], s->profiles[2 * q + 1]);
+    } else {
+        return fail(ZDA_ERR_ARG, "unknown source kind %d", s->kind);
+    }
+    plan.dplane = (dft_flags & ZDA_DFT_PLANE) && K > 0 ? z->dft_plane : nullptr;
+    plan.dvol = nullptr;
+    if ((dft_flags & ZDA_DFT_VOLUME) && K > 0) {
+        if (!z->dft_vol) {
+            if ((st = dev_alloc(z, &z->dft_vol, (size_t)ZDA_MAX_FREQ * 3 * z->nd * z->plane)) != ZDA_OK) return st;
+            launch_fill(z->dft_vol, (size_t)ZDA_MAX_FREQ * 3 * z->nd * z->plane, hs);
+        }
+        plan.dvol = z->dft_vol;
+    }
+    return ZDA_OK;
+}
+
+void forward_finish(zda_zone *z, const FwdPlan &plan, int nsteps, const double *omega, int K)
+{
+    if (plan.reset) {
+        z->last_K = K;
+        for (int k = 0; k < K; ++k) z->last_omega[k] = omega[k];
+        z->last_T = nsteps;
+        z->have_plane = plan.dplane != nullptr;
+        z->have_vol = plan.dvol != nullptr;
+    } else {
+        // continuing: the monitors keep accumulating from the current state
+        z->last_T += nsteps;
+        if (plan.dplane || plan.dvol) {
+            z->last_K = K;
+            for (int k = 0; k < K; ++k) z->last_omega[k] = omega[k];
+        }
+        if (plan.dplane) z->have_plane = true;
+        if (plan.dvol) z->have_vol = true;
+    }
+    z->last_width = plan.width;
+    z->last_n0 = plan.n0;
+    z->have_vol_adj = false;
+}
+
 // Gauss-Jordan inverse of a small complex matrix (row-major, n x n).
 bool invert(std::vector<cd> &A, int n)
 {
@@ -384,6 +498,120 @@ bool invert(std::vector<cd> &A, int n)
     }
     A = inv;
     return true;
+}
+
+// Adjoint-run setup (a7): the current pattern W^{-1} dF/dEhat_k / (i wt_k)
+// on the monitor plane (built on the GPU) and the broadband time profiles
+// q_k = sum_l (P^{-1})_{lk} p_l; the overlap weights are uploaded for the
+// finish step.
+struct AdjPlan {
+    std::vector<cd> q;
+    int K = 0, T = 0;
+    float2 *wr_dev = nullptr, *wz_dev = nullptr;
+};
+
+zda_status adjoint_setup(zda_zone *z, const float *dF_dE, int dF_on_device, double adj_width, hipStream_t hs,
+                         AdjPlan &plan)
+{
+    if (!z->have_vol || z->last_K < 1) return fail(ZDA_ERR_STATE, "needs a forward run with ZDA_DFT_VOLUME");
+    const zda_zone_desc &d = z->d;
+    const int K = z->last_K, T = z->last_T, km = d.k_mon, nd = z->nd;
+    double width = adj_width > 0 ? adj_width : z->last_width;
+    if (!(width > 0)) return fail(ZDA_ERR_ARG, "adjoint pulse width unknown (custom forward source): pass adj_width");
+    const int n0 = (adj_width > 0 || z->last_n0 < 0) ? default_n0(width, z->dt) : z->last_n0;
+    HIP_TRY(hipStreamSynchronize(hs));
+    zda_status st;
+    const size_t npl = (size_t)K * 2 * z->plane;
+    const size_t nfac = (size_t)K * 2 * d.nr, nwr = (size_t)K * 3 * d.nr, nwz = (size_t)K * 3 * nd;
+    if ((st = ensure(z, &z->scratch, &z->cap_scratch, npl + nfac + nwr + nwz)) != ZDA_OK) return st;
+    if ((st = ensure(z, &z->pattern, &z->cap_pattern, npl)) != ZDA_OK) return st;
+    if (!z->dft_vol_adj && (st = dev_alloc(z, &z->dft_vol_adj, (size_t)ZDA_MAX_FREQ * 3 * nd * z->plane)) != ZDA_OK)
+        return st;
+    float2 *g_dev = z->scratch, *fac_dev = g_dev + npl, *wr_dev = fac_dev + nfac, *wz_dev = wr_dev + nwr;
+    HIP_TRY(hipMemcpyAsync(g_dev, dF_dE, npl * sizeof(float2),
+                           dF_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
+    // stretched volume W = R l_r l_z dphi and leap-frog frequency wt
+    auto wt = [&](double w) { return 2.0 / z->dt * std::sin(w * z->dt / 2.0); };
+    auto w_r = [&](int comp, int i, double w) {   // comp 0 = E_r (half point), 1, 2 = E_phi, E_z (integer)
+        const int h = comp == 0 ? 1 : 0;
+        const double r = d.r_in + (i + 0.5 * h) * d.dr;
+        return r * stretch(z->sgt_r[h][i], z->cr, w, z->dt) * stretch(z->sig_r[h][i], z->cr, w, z->dt) * d.dr *
+               z->dphi * d.dz;
+    };
+    auto w_z = [&](int comp, int k, double w) {
+        const int h = comp == 2 ? 1 : 0;
+        return stretch(z->sig_z[h][k], z->cz, w, z->dt);
+    };
+    z->st_misc.assign(nfac + nwr + nwz, make_float2(0.f, 0.f));
+    for (int k = 0; k < K; ++k) {
+        const double w = z->last_omega[k];
+        for (int a = 0; a < 2; ++a)
+            for (int i = 0; i < d.nr; ++i) {
+                const cd f = 1.0 / (w_r(a, i, w) * w_z(a, km, w) * cd(0.0, wt(w)));
+                z->st_misc[((size_t)k * 2 + a) * d.nr + i] = make_float2((float)f.real(), (float)f.imag());
+            }
+        for (int a = 0; a < 3; ++a) {
+            for (int i = 0; i < d.nr; ++i) {
+                const cd v = wt(w) * wt(w) * w_r(a, i, w);
+                z->st_misc[nfac + ((size_t)k * 3 + a) * d.nr + i] = make_float2((float)v.real(), (float)v.imag());
+            }
+            for (int kd = 0; kd < nd; ++kd) {
+                const cd v = w_z(a, d.design_k0 + kd, w);
+                z->st_misc[nfac + nwr + ((size_t)k * 3 + a) * nd + kd] = make_float2((float)v.real(), (float)v.imag());
+            }
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(fac_dev, z->st_misc.data(), (nfac + nwr + nwz) * sizeof(float2), hipMemcpyHostToDevice, hs));
+    launch_adjoint_pattern(z->pattern, g_dev, fac_dev, K, d.nr, d.nphi, hs);
+    // broadband profiles: pulses p_l centred on w_l, mixed by P^{-1}, P_kl = phat_l(w_k)
+    std::vector<double> p((size_t)K * T);
+    for (int l = 0; l < K; ++l)
+        for (int n = 0; n < T; ++n) p[(size_t)l * T + n] = pulse_at(n, z->dt, z->last_omega[l], width, n0);
+    std::vector<cd> Pm((size_t)K * K);
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            cd acc = 0.0;
+            for (int n = 0; n < T; ++n)
+                acc += p[(size_t)l * T + n] * std::exp(cd(0.0, z->last_omega[k] * (n + 0.5) * z->dt));
+            Pm[(size_t)k * K + l] = z->dt * acc;
+        }
+    if (!invert(Pm, K)) return fail(ZDA_ERR_ARG, "adjoint pulse spectra are singular at the chosen frequencies");
+    std::vector<cd> q((size_t)K * T, 0.0);
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            const cd c = Pm[(size_t)l * K + k];
+            for (int n = 0; n < T; ++n) q[(size_t)k * T + n] += c * p[(size_t)l * T + n];
+        }
+    plan.q.swap(q);
+    plan.K = K;
+    plan.T = T;
+    plan.wr_dev = wr_dev;
+    plan.wz_dev = wz_dev;
+    return ZDA_OK;
+}
+
+// a9: dF/drho = (eps_hi - eps_bg) sum_k sum_alpha 2 Re[wt^2 W Xhat Ehat]
+zda_status adjoint_finish(zda_zone *z, const AdjPlan &plan, float *grad_rho, int grad_on_device, hipStream_t hs)
+{
+    const zda_zone_desc &d = z->d;
+    const int nd = z->nd, K = plan.K;
+    z->have_vol_adj = true;
+    float *gdst = grad_rho;
+    float *gtmp = nullptr;
+    if (!grad_on_device) {
+        HIP_TRY(hipMalloc((void **)&gtmp, (size_t)nd * z->plane * sizeof(float)));
+        gdst = gtmp;
+    }
+    launch_overlap(gdst, z->dft_vol, z->dft_vol_adj, plan.wr_dev, plan.wz_dev, K, nd, d.nr, d.nphi,
+                   (float)(2.0 * (d.eps_hi - d.eps_bg)), hs);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && gtmp) {
+        e = hipMemcpyAsync(grad_rho, gtmp, (size_t)nd * z->plane * sizeof(float), hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    }
+    if (gtmp) (void)hipFree(gtmp);
+    if (e != hipSuccess) return fail(ZDA_ERR_HIP, "overlap: %s", hipGetErrorString(e));
+    return ZDA_OK;
 }
 
 }  // namespace
@@ -456,9 +684,12 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     if (st == ZDA_OK) st = dev_alloc(z, &z->ceps, z->ncell);
     if (st == ZDA_OK) st = dev_alloc(z, &z->auxR[0], (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
     if (st == ZDA_OK) st = dev_alloc(z, &z->auxZ[0], (size_t)N_AUX_Z * z->dZ * z->plane);
-    // the second buffer set of the fused step; without room for it the zone
-    // keeps the in-place split kernels
-    if (st == ZDA_OK) {
+    // the second buffer set of the fused step; without room for it (or when
+    // asked for a single set) the zone keeps the in-place split kernels
+    if (st == ZDA_OK && d->single_buffer) {
+        z->fused = false;
+        z->tile_rows = 4;
+    } else if (st == ZDA_OK) {
         zda_status s1 = ZDA_OK;
         for (auto &f : z->F[1]) if (s1 == ZDA_OK) s1 = dev_alloc(z, &f, z->ncell);
         if (s1 == ZDA_OK) s1 = dev_alloc(z, &z->auxR[1], (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
@@ -552,84 +783,15 @@ zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const doub
                         void *stream)
 {
     if (!z || !s) return fail(ZDA_ERR_ARG, "NULL zone or source");
-    if (nsteps < 0) return fail(ZDA_ERR_ARG, "nsteps must be >= 0");
-    if (K < 0 || K > ZDA_MAX_FREQ || (K > 0 && !omega)) return fail(ZDA_ERR_ARG, "K must be in [0, %d]", ZDA_MAX_FREQ);
-    if ((dft_flags & ~(ZDA_DFT_PLANE | ZDA_DFT_VOLUME | ZDA_RUN_CONTINUE | ZDA_RUN_TIMING)) != 0)
-        return fail(ZDA_ERR_ARG, "bad dft_flags");
-    if ((dft_flags & ZDA_DFT_VOLUME) && z->nd <= 0) return fail(ZDA_ERR_STATE, "zone has no design layer");
-    const zda_zone_desc &d = z->d;
-    if (s->k_src < 1 || s->k_src >= d.nz) return fail(ZDA_ERR_ARG, "k_src must be in [1, nz)");
     DeviceGuard g(z->device);
     hipStream_t hs = (hipStream_t)stream;
-    HIP_TRY(hipStreamSynchronize(hs));   // staging buffers of the previous call are free
-    const bool reset = !(dft_flags & ZDA_RUN_CONTINUE);
-    if (reset) z->n_done = 0;
-    int P = 1;
-    std::vector<cd> prof;
-    double width = 0.0;
-    int n0 = -1;
-    zda_status st;
-    if (s->kind == ZDA_SRC_PLANE_CIRC || s->kind == ZDA_SRC_RADIAL) {
-        if (s->kind == ZDA_SRC_PLANE_CIRC && std::abs(d.m) != 1) return fail(ZDA_ERR_UNSUPPORTED, "PLANE_CIRC needs |m| = 1");
-        if (s->kind == ZDA_SRC_RADIAL && d.m != 0) return fail(ZDA_ERR_UNSUPPORTED, "RADIAL needs m = 0");
-        if (!(s->width > 0)) return fail(ZDA_ERR_ARG, "pulse width must be > 0");
-        width = s->width;
-        n0 = s->n0 >= 0 ? s->n0 : default_n0(width, z->dt);
-        if ((st = ensure(z, &z->pattern, &z->cap_pattern, 2 * z->plane)) != ZDA_OK) return st;
-        z->st_pat.assign(2 * z->plane, make_float2(0.f, 0.f));
-        const double sgn = d.m > 0 ? 1.0 : (d.m < 0 ? -1.0 : 0.0);
-        for (int i = 0; i < d.nr; ++i)
-            for (int j = 0; j < d.nphi; ++j) {
-                cd jr, jp;
-                if (s->kind == ZDA_SRC_PLANE_CIRC) {
-                    jr = -std::exp(cd(0.0, d.m * j * z->dphi)) / d.dz;
-                    jp = cd(0.0, -sgn) * std::exp(cd(0.0, d.m * (j + 0.5) * z->dphi)) / d.dz;
-                } else {
-                    jr = -1.0 / d.dz;
-                    jp = 0.0;
-                }
-                z->st_pat[(size_t)i * d.nphi + j] = make_float2((float)jr.real(), (float)jr.imag());
-                z->st_pat[z->plane + (size_t)i * d.nphi + j] = make_float2((float)jp.real(), (float)jp.imag());
-            }
-        HIP_TRY(hipMemcpyAsync(z->pattern, z->st_pat.data(), 2 * z->plane * sizeof(float2), hipMemcpyHostToDevice, hs));
-        prof.resize(nsteps);
-        for (int n = 0; n < nsteps; ++n) prof[n] = pulse_at(z->n_done + n, z->dt, s->omega_c, width, n0);
-    } else if (s->kind == ZDA_SRC_CUSTOM) {
-        P = s->n_profiles;
-        if (P < 1 || P > ZDA_MAX_FREQ || !s->patterns || !s->profiles)
-            return fail(ZDA_ERR_ARG, "CUSTOM needs 1..%d patterns and profiles", ZDA_MAX_FREQ);
-        if ((st = ensure(z, &z->pattern, &z->cap_pattern, (size_t)P * 2 * z->plane)) != ZDA_OK) return st;
-        HIP_TRY(hipMemcpyAsync(z->pattern, s->patterns, (size_t)P * 2 * z->plane * sizeof(float2),
-                               s->patterns_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
-        prof.resize((size_t)P * nsteps);
-        for (size_t q = 0; q < prof.size(); ++q) prof[q] = cd(s->profiles[2 * q], s->profiles[2 * q + 1]);
-    } else {
-        return fail(ZDA_ERR_ARG, "unknown source kind %d", s->kind);
-    }
-    float2 *dplane = (dft_flags & ZDA_DFT_PLANE) && K > 0 ? z->dft_plane : nullptr;
-    float2 *dvol = nullptr;
-    if ((dft_flags & ZDA_DFT_VOLUME) && K > 0) {
-        if (!z->dft_vol) {
-            if ((st = dev_alloc(z, &z->dft_vol, (size_t)ZDA_MAX_FREQ * 3 * z->nd * z->plane)) != ZDA_OK) return st;
-            launch_fill(z->dft_vol, (size_t)ZDA_MAX_FREQ * 3 * z->nd * z->plane, hs);
-        }
-        dvol = z->dft_vol;
-    }
-    if ((st = run_loop(z, d.m, nsteps, s->k_src, P, prof.data(), omega, K, dplane, dvol, reset, hs,
-                       (dft_flags & ZDA_RUN_TIMING) != 0)) != ZDA_OK)
+    FwdPlan plan;
+    zda_status st = forward_setup(z, s, nsteps, omega, K, dft_flags, hs, plan);
+    if (st != ZDA_OK) return st;
+    if ((st = run_loop(z, z->d.m, nsteps, s->k_src, plan.P, plan.prof.data(), omega, K, plan.dplane, plan.dvol,
+                       plan.reset, hs, (dft_flags & ZDA_RUN_TIMING) != 0)) != ZDA_OK)
         return st;
-    if (reset) {
-        z->last_K = K;
-        for (int k = 0; k < K; ++k) z->last_omega[k] = omega[k];
-        z->last_T = nsteps;
-        z->have_plane = dplane != nullptr;
-        z->have_vol = dvol != nullptr;
-    } else {
-        z->last_T += nsteps;
-    }
-    z->last_width = width;
-    z->last_n0 = n0;
-    z->have_vol_adj = false;
+    forward_finish(z, plan, nsteps, omega, K);
     return ZDA_OK;
 }
 
@@ -666,96 +828,15 @@ zda_status zda_adjoint_grad(zda_zone *z, const float *dF_dE, int dF_on_device, f
                             double adj_width, void *stream)
 {
     if (!z || !dF_dE || !grad_rho) return fail(ZDA_ERR_ARG, "NULL argument");
-    if (!z->have_vol || z->last_K < 1) return fail(ZDA_ERR_STATE, "needs a forward run with ZDA_DFT_VOLUME");
-    const zda_zone_desc &d = z->d;
-    const int K = z->last_K, T = z->last_T, km = d.k_mon, nd = z->nd;
-    double width = adj_width > 0 ? adj_width : z->last_width;
-    if (!(width > 0)) return fail(ZDA_ERR_ARG, "adjoint pulse width unknown (custom forward source): pass adj_width");
-    const int n0 = (adj_width > 0 || z->last_n0 < 0) ? default_n0(width, z->dt) : z->last_n0;
     DeviceGuard g(z->device);
     hipStream_t hs = (hipStream_t)stream;
-    HIP_TRY(hipStreamSynchronize(hs));
-    zda_status st;
-    const size_t npl = (size_t)K * 2 * z->plane;
-    const size_t nfac = (size_t)K * 2 * d.nr, nwr = (size_t)K * 3 * d.nr, nwz = (size_t)K * 3 * nd;
-    if ((st = ensure(z, &z->scratch, &z->cap_scratch, npl + nfac + nwr + nwz)) != ZDA_OK) return st;
-    if ((st = ensure(z, &z->pattern, &z->cap_pattern, npl)) != ZDA_OK) return st;
-    if (!z->dft_vol_adj && (st = dev_alloc(z, &z->dft_vol_adj, (size_t)ZDA_MAX_FREQ * 3 * nd * z->plane)) != ZDA_OK)
+    AdjPlan plan;
+    zda_status st = adjoint_setup(z, dF_dE, dF_on_device, adj_width, hs, plan);
+    if (st != ZDA_OK) return st;
+    if ((st = run_loop(z, -z->d.m, plan.T, z->d.k_mon, plan.K, plan.q.data(), z->last_omega, plan.K, nullptr,
+                       z->dft_vol_adj, true, hs)) != ZDA_OK)
         return st;
-    float2 *g_dev = z->scratch, *fac_dev = g_dev + npl, *wr_dev = fac_dev + nfac, *wz_dev = wr_dev + nwr;
-    HIP_TRY(hipMemcpyAsync(g_dev, dF_dE, npl * sizeof(float2),
-                           dF_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
-    // stretched volume W = R l_r l_z dphi and leap-frog frequency wt
-    auto wt = [&](double w) { return 2.0 / z->dt * std::sin(w * z->dt / 2.0); };
-    auto w_r = [&](int comp, int i, double w) {   // comp 0 = E_r (half point), 1, 2 = E_phi, E_z (integer)
-        const int h = comp == 0 ? 1 : 0;
-        const double r = d.r_in + (i + 0.5 * h) * d.dr;
-        return r * stretch(z->sgt_r[h][i], z->cr, w, z->dt) * stretch(z->sig_r[h][i], z->cr, w, z->dt) * d.dr *
-               z->dphi * d.dz;
-    };
-    auto w_z = [&](int comp, int k, double w) {
-        const int h = comp == 2 ? 1 : 0;
-        return stretch(z->sig_z[h][k], z->cz, w, z->dt);
-    };
-    z->st_misc.assign(nfac + nwr + nwz, make_float2(0.f, 0.f));
-    for (int k = 0; k < K; ++k) {
-        const double w = z->last_omega[k];
-        for (int a = 0; a < 2; ++a)
-            for (int i = 0; i < d.nr; ++i) {
-                const cd f = 1.0 / (w_r(a, i, w) * w_z(a, km, w) * cd(0.0, wt(w)));
-                z->st_misc[((size_t)k * 2 + a) * d.nr + i] = make_float2((float)f.real(), (float)f.imag());
-            }
-        for (int a = 0; a < 3; ++a) {
-            for (int i = 0; i < d.nr; ++i) {
-                const cd v = wt(w) * wt(w) * w_r(a, i, w);
-                z->st_misc[nfac + ((size_t)k * 3 + a) * d.nr + i] = make_float2((float)v.real(), (float)v.imag());
-            }
-            for (int kd = 0; kd < nd; ++kd) {
-                const cd v = w_z(a, d.design_k0 + kd, w);
-                z->st_misc[nfac + nwr + ((size_t)k * 3 + a) * nd + kd] = make_float2((float)v.real(), (float)v.imag());
-            }
-        }
-    }
-    HIP_TRY(hipMemcpyAsync(fac_dev, z->st_misc.data(), (nfac + nwr + nwz) * sizeof(float2), hipMemcpyHostToDevice, hs));
-    launch_adjoint_pattern(z->pattern, g_dev, fac_dev, K, d.nr, d.nphi, hs);
-    // broadband profiles: pulses p_l centred on w_l, mixed by P^{-1}, P_kl = phat_l(w_k)
-    std::vector<double> p((size_t)K * T);
-    for (int l = 0; l < K; ++l)
-        for (int n = 0; n < T; ++n) p[(size_t)l * T + n] = pulse_at(n, z->dt, z->last_omega[l], width, n0);
-    std::vector<cd> Pm((size_t)K * K);
-    for (int k = 0; k < K; ++k)
-        for (int l = 0; l < K; ++l) {
-            cd acc = 0.0;
-            for (int n = 0; n < T; ++n)
-                acc += p[(size_t)l * T + n] * std::exp(cd(0.0, z->last_omega[k] * (n + 0.5) * z->dt));
-            Pm[(size_t)k * K + l] = z->dt * acc;
-        }
-    if (!invert(Pm, K)) return fail(ZDA_ERR_ARG, "adjoint pulse spectra are singular at the chosen frequencies");
-    std::vector<cd> q((size_t)K * T, 0.0);
-    for (int k = 0; k < K; ++k)
-        for (int l = 0; l < K; ++l) {
-            const cd c = Pm[(size_t)l * K + k];
-            for (int n = 0; n < T; ++n) q[(size_t)k * T + n] += c * p[(size_t)l * T + n];
-        }
-    if ((st = run_loop(z, -d.m, T, km, K, q.data(), z->last_omega, K, nullptr, z->dft_vol_adj, true, hs)) != ZDA_OK)
-        return st;
-    z->have_vol_adj = true;
-    float *gdst = grad_rho;
-    float *gtmp = nullptr;
-    if (!grad_on_device) {
-        HIP_TRY(hipMalloc((void **)&gtmp, (size_t)nd * z->plane * sizeof(float)));
-        gdst = gtmp;
-    }
-    launch_overlap(gdst, z->dft_vol, z->dft_vol_adj, wr_dev, wz_dev, K, nd, d.nr, d.nphi,
-                   (float)(2.0 * (d.eps_hi - d.eps_bg)), hs);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && gtmp) {
-        e = hipMemcpyAsync(grad_rho, gtmp, (size_t)nd * z->plane * sizeof(float), hipMemcpyDeviceToHost, hs);
-        if (e == hipSuccess) e = hipStreamSynchronize(hs);
-    }
-    if (gtmp) (void)hipFree(gtmp);
-    if (e != hipSuccess) return fail(ZDA_ERR_HIP, "overlap: %s", hipGetErrorString(e));
-    return ZDA_OK;
+    return adjoint_finish(z, plan, grad_rho, grad_on_device, hs);
 }
 
 zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_device)
@@ -797,6 +878,16 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
     z->tile_rows = tile_rows;
     z->fused = fused;
     return ZDA_OK;
+}
+
+zda_status zda_zone_set_option(zda_zone *z, int option, int value)
+{
+    if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
+    switch (option) {
+    case ZDA_OPT_XCD_REMAP: z->xcd_remap = value ? 1 : 0; return ZDA_OK;
+    case ZDA_OPT_NT_STORES: z->nt_stores = value ? 1 : 0; return ZDA_OK;
+    default: return fail(ZDA_ERR_ARG, "unknown option %d", option);
+    }
 }
 
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info)
@@ -847,5 +938,284 @@ const char *zda_status_str(int status)
 }
 
 const char *zda_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of zones (the lens-scale schedule: many uneven zones stepped in one
+// launch per time step, the time loop replayed from a captured HIP graph).
+
+struct zda_batch {
+    std::vector<zda_zone *> zones;
+    int device = 0;
+    bool fused = false;
+    int tile_rows = 4;
+    StepArgs *tab = nullptr;      // [2][nzones]: both buffer parities
+    unsigned *prefix = nullptr;   // [nzones]: first block of each zone
+    size_t cap = 0;
+    int *n_base = nullptr;        // device step offset advanced inside the graph
+    hipStream_t cap_stream = nullptr;
+    int graph_steps = 32;         // steps per captured graph (even)
+    std::vector<StepArgs> h_tab;
+    std::vector<unsigned> h_prefix;
+};
+
+namespace {
+
+bool zone_has_second_set(const zda_zone *z) { return z->F[1][0] && (z->dR == 0 || z->auxR[1]) && (z->dZ == 0 || z->auxZ[1]); }
+
+// One batched time loop: ab[i][0..1] are zone i's step arguments (prepared).
+zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &ab, int nsteps, hipStream_t s)
+{
+    const int nz = (int)b->zones.size();
+    b->h_tab.resize(2 * (size_t)nz);
+    b->h_prefix.resize(nz);
+    unsigned total = 0;
+    for (int i = 0; i < nz; ++i) {
+        b->h_tab[i] = ab[i][0];
+        b->h_tab[nz + i] = ab[i][1];
+        b->h_prefix[i] = total;
+        total += b->fused ? tiles_fused(ab[i][0], b->tile_rows) : tiles_split(ab[i][0], b->tile_rows);
+    }
+    if ((size_t)nz > b->cap) {
+        if (b->tab) (void)hipFree(b->tab);
+        if (b->prefix) (void)hipFree(b->prefix);
+        b->tab = nullptr;
+        b->prefix = nullptr;
+        HIP_TRY(hipMalloc((void **)&b->tab, 2 * (size_t)nz * sizeof(StepArgs)));
+        HIP_TRY(hipMalloc((void **)&b->prefix, (size_t)nz * sizeof(unsigned)));
+        b->cap = nz;
+    }
+    HIP_TRY(hipMemcpyAsync(b->tab, b->h_tab.data(), b->h_tab.size() * sizeof(StepArgs), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->prefix, b->h_prefix.data(), nz * sizeof(unsigned), hipMemcpyHostToDevice, s));
+    launch_set_int(b->n_base, 0, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    BatchArgs ba[2];
+    for (int p = 0; p < 2; ++p) {
+        ba[p].tab = b->tab + (size_t)p * nz;
+        ba[p].prefix = b->prefix;
+        ba[p].nzones = nz;
+        ba[p].n_base = b->n_base;
+        ba[p].xcd_remap = b->zones[0]->xcd_remap;
+    }
+    const int S = b->graph_steps;
+    const int reps = nsteps >= 2 * S ? nsteps / S : 0;
+    if (reps > 0) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int q = 0; q < S; ++q) launch_batch_step(ba[q & 1], total, b->tile_rows, b->fused, q, b->cap_stream);
+        launch_advance_step(b->n_base, S, b->cap_stream);
+        HIP_TRY(hipStreamEndCapture(b->cap_stream, &graph));
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(ZDA_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        for (int q = 0; q < reps && e == hipSuccess; ++q) e = hipGraphLaunch(exec, s);
+        hipError_t e2 = hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess || e2 != hipSuccess)
+            return fail(ZDA_ERR_HIP, "graph launch: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    const int done = reps * S;
+    for (int q = 0; q < nsteps - done; ++q) launch_batch_step(ba[q & 1], total, b->tile_rows, b->fused, q, s);
+    HIP_TRY(hipGetLastError());
+    for (auto z : b->zones) {
+        z->n_done += nsteps;
+        if (b->fused) z->cur ^= (nsteps & 1);
+    }
+    return ZDA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+zda_status zda_batch_create(zda_zone *const *zones, int nzones, zda_batch **out)
+{
+    if (!zones || nzones < 1 || !out) return fail(ZDA_ERR_ARG, "need at least one zone and an output pointer");
+    *out = nullptr;
+    for (int i = 0; i < nzones; ++i)
+        if (!zones[i]) return fail(ZDA_ERR_ARG, "zone %d is NULL", i);
+    const int dev = zones[0]->device;
+    for (int i = 1; i < nzones; ++i)
+        if (zones[i]->device != dev) return fail(ZDA_ERR_ARG, "zones must live on one device");
+    zda_batch *b = new (std::nothrow) zda_batch();
+    if (!b) return fail(ZDA_ERR_OOM, "host allocation failed");
+    b->zones.assign(zones, zones + nzones);
+    b->device = dev;
+    b->fused = true;
+    for (auto z : b->zones) b->fused = b->fused && zone_has_second_set(z);
+    b->tile_rows = b->fused ? 7 : 4;
+    DeviceGuard g(dev);
+    if (hipMalloc((void **)&b->n_base, sizeof(int)) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        zda_batch_destroy(b);
+        return fail(ZDA_ERR_HIP, "batch setup failed");
+    }
+    *out = b;
+    return ZDA_OK;
+}
+
+void zda_batch_destroy(zda_batch *b)
+{
+    if (!b) return;
+    DeviceGuard g(b->device);
+    (void)hipDeviceSynchronize();
+    if (b->tab) (void)hipFree(b->tab);
+    if (b->prefix) (void)hipFree(b->prefix);
+    if (b->n_base) (void)hipFree(b->n_base);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+}
+
+zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk)
+{
+    if (!b) return fail(ZDA_ERR_ARG, "NULL batch");
+    const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16;
+    const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15;
+    if (!split && !fused) return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16 (split) or 3, 7, 15 (fused)");
+    if (fused)
+        for (auto z : b->zones)
+            if (!zone_has_second_set(z)) return fail(ZDA_ERR_STATE, "a zone has no second buffer set");
+    if (kchunk)
+        for (size_t i = 0; i < b->zones.size(); ++i)
+            if (kchunk[i] < 1 || kchunk[i] > b->zones[i]->d.nz) return fail(ZDA_ERR_ARG, "kchunk[%zu] out of range", i);
+    b->fused = fused;
+    b->tile_rows = tile_rows;
+    if (kchunk)
+        for (size_t i = 0; i < b->zones.size(); ++i) b->zones[i]->kchunk = kchunk[i];
+    return ZDA_OK;
+}
+
+zda_status zda_batch_run(zda_batch *b, const zda_source *sources, int nsteps, const double *omega, int K,
+                         int dft_flags, void *stream)
+{
+    if (!b || !sources) return fail(ZDA_ERR_ARG, "NULL batch or sources");
+    if (dft_flags & ZDA_RUN_TIMING) return fail(ZDA_ERR_ARG, "per-kernel timing is not available for batches");
+    DeviceGuard g(b->device);
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t nz = b->zones.size();
+    std::vector<FwdPlan> plans(nz);
+    std::vector<std::array<StepArgs, 2>> ab(nz);
+    zda_status st;
+    for (size_t i = 0; i < nz; ++i) {
+        zda_zone *z = b->zones[i];
+        if ((st = forward_setup(z, &sources[i], nsteps, omega, K, dft_flags, hs, plans[i])) != ZDA_OK) return st;
+        if ((st = prepare_run(z, z->d.m, nsteps, sources[i].k_src, plans[i].P, plans[i].prof.data(), omega, K,
+                              plans[i].dplane, plans[i].dvol, plans[i].reset, hs, ab[i].data())) != ZDA_OK)
+            return st;
+    }
+    if ((st = batch_loop(b, ab, nsteps, hs)) != ZDA_OK) return st;
+    for (size_t i = 0; i < nz; ++i) forward_finish(b->zones[i], plans[i], nsteps, omega, K);
+    return ZDA_OK;
+}
+
+zda_status zda_batch_adjoint_grad(zda_batch *b, const float *const *dF_dE, float *const *grad_rho, void *stream)
+{
+    if (!b || !dF_dE || !grad_rho) return fail(ZDA_ERR_ARG, "NULL argument");
+    DeviceGuard g(b->device);
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t nz = b->zones.size();
+    int T = -1;
+    for (auto z : b->zones) {
+        if (!z->have_vol || z->last_K < 1) return fail(ZDA_ERR_STATE, "every zone needs a forward run with ZDA_DFT_VOLUME");
+        if (T >= 0 && z->last_T != T) return fail(ZDA_ERR_STATE, "zones ran different step counts");
+        T = z->last_T;
+    }
+    std::vector<AdjPlan> plans(nz);
+    std::vector<std::array<StepArgs, 2>> ab(nz);
+    zda_status st;
+    for (size_t i = 0; i < nz; ++i) {
+        zda_zone *z = b->zones[i];
+        if (!dF_dE[i] || !grad_rho[i]) return fail(ZDA_ERR_ARG, "NULL pointer for zone %zu", i);
+        if ((st = adjoint_setup(z, dF_dE[i], 1, 0.0, hs, plans[i])) != ZDA_OK) return st;
+        if ((st = prepare_run(z, -z->d.m, plans[i].T, z->d.k_mon, plans[i].K, plans[i].q.data(), z->last_omega,
+                              plans[i].K, nullptr, z->dft_vol_adj, true, hs, ab[i].data())) != ZDA_OK)
+            return st;
+    }
+    if ((st = batch_loop(b, ab, T, hs)) != ZDA_OK) return st;
+    for (size_t i = 0; i < nz; ++i)
+        if ((st = adjoint_finish(b->zones[i], plans[i], grad_rho[i], 1, hs)) != ZDA_OK) return st;
+    return ZDA_OK;
+}
+
+zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe_steps, const double *omega, int K,
+                              void *stream, zda_tune_result *res)
+{
+    if (!b || !sources || !res || probe_steps < 2) return fail(ZDA_ERR_ARG, "bad autotune arguments");
+    DeviceGuard g(b->device);
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t nz = b->zones.size();
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int probes = 0;
+    auto probe = [&](double &ms) -> zda_status {
+        HIP_TRY(hipEventRecord(e0, hs));
+        zda_status st = zda_batch_run(b, sources, probe_steps, omega, K, ZDA_DFT_PLANE, stream);
+        if (st != ZDA_OK) return st;
+        HIP_TRY(hipEventRecord(e1, hs));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        ms = t / probe_steps;
+        ++probes;
+        return ZDA_OK;
+    };
+    // 1) kernel family and tile shape with each zone's default depth
+    std::vector<int> rows_c = {2, 4, 8};
+    bool can_fuse = true;
+    for (auto z : b->zones) can_fuse = can_fuse && zone_has_second_set(z);
+    if (can_fuse) rows_c.insert(rows_c.end(), {3, 7, 15});
+    std::vector<int> kc(nz);
+    for (size_t i = 0; i < nz; ++i) kc[i] = b->zones[i]->kchunk;
+    double best = 1e300;
+    int best_rows = b->tile_rows;
+    zda_status st;
+    for (int rr : rows_c) {
+        if ((st = zda_batch_set_launch(b, rr, kc.data())) != ZDA_OK) return st;
+        double ms;
+        if ((st = probe(ms)) != ZDA_OK) return st;
+        if (ms < best) { best = ms; best_rows = rr; }
+    }
+    if ((st = zda_batch_set_launch(b, best_rows, kc.data())) != ZDA_OK) return st;
+    // 2) z-chunk depth per size class (thirds of the zones by cell count)
+    std::vector<size_t> order(nz);
+    for (size_t i = 0; i < nz; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t c) { return b->zones[a]->ncell < b->zones[c]->ncell; });
+    const int nclass = nz >= 3 ? 3 : (int)nz;
+    for (int cl = 0; cl < nclass; ++cl) {
+        const size_t lo = nz * cl / nclass, hi = nz * (cl + 1) / nclass;
+        const std::vector<int> kc0 = kc;
+        int best_div = 0;
+        for (int div : {1, 2, 4, 8, 16}) {
+            for (size_t q = lo; q < hi; ++q) {
+                const zda_zone *z = b->zones[order[q]];
+                kc[order[q]] = std::max(8, (z->d.nz + div - 1) / div);
+                if (kc[order[q]] > z->d.nz) kc[order[q]] = z->d.nz;
+            }
+            if ((st = zda_batch_set_launch(b, best_rows, kc.data())) != ZDA_OK) return st;
+            double ms;
+            if ((st = probe(ms)) != ZDA_OK) return st;
+            if (ms < best) { best = ms; best_div = div; }
+        }
+        kc = kc0;
+        if (best_div > 0)
+            for (size_t q = lo; q < hi; ++q) {
+                const zda_zone *z = b->zones[order[q]];
+                kc[order[q]] = std::min(z->d.nz, std::max(8, (z->d.nz + best_div - 1) / best_div));
+            }
+        if ((st = zda_batch_set_launch(b, best_rows, kc.data())) != ZDA_OK) return st;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    res->tile_rows = best_rows;
+    res->ms_per_step = best;
+    res->probes = probes;
+    return ZDA_OK;
+}
 
 }  // extern "C"

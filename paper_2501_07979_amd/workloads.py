@@ -135,4 +135,25 @@ def c3_small(steps=2500):
                     density="smoothed")
 
 
+def c4_zone(l, steps=4000):
+    """Zone l (1..48) of the batched lens: n rises with radius from 64 to
+    4096, Nr 64..512 and Nphi 128..1024 (uneven on purpose), Nz = 300,
+    smoothed design layer z in [30, 50), seed 4000 + l."""
+    t = (l - 1) / 47.0
+    n = int(round(64 + 4032 * t))
+    nr = 64 + int(round(448 * t))
+    nphi = 128 + int(round(896 * t))
+    om = _omegas((16.36, 20.0, 23.64))
+    wc, w = _pulse(om)
+    r_in = 200.0 * (n / 16.0) * (nphi / 64.0)
+    return Workload("c4_zone%02d_%dx%dx300" % (l, nr, nphi), r_in=r_in, nr=nr, nphi=nphi, nz=300, n_fold=n,
+                    pml=(8, 8, 8, 8), k_src=20, k_mon=60, design=(30, 50), steps=steps, omegas=om, omega_c=wc,
+                    width=w, seed=4000 + l, density="smoothed")
+
+
+def c4(nzones=48):
+    """The batched lens: 48 uneven zones (2.89e9 cells in total)."""
+    return [c4_zone(l) for l in range(1, nzones + 1)]
+
+
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c3_small": c3_small}

@@ -20,12 +20,15 @@ ZDA_MAX_FREQ = 8
 SRC_PLANE_CIRC, SRC_RADIAL, SRC_CUSTOM = 0, 1, 2
 DFT_PLANE, DFT_VOLUME, RUN_CONTINUE, RUN_TIMING = 1, 2, 4, 8
 MON_PLANE, MON_VOLUME, MON_ADJOINT_VOLUME = 0, 1, 2
+OPT_XCD_REMAP, OPT_NT_STORES = 1, 2
 COMP = {"Er": 0, "Ephi": 1, "Ez": 2, "Hr": 3, "Hphi": 4, "Hz": 5}
 
 EXPORTS = ["zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_zone_set_eps",
            "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields", "zda_adjoint_grad",
            "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_set_launch",
-           "zda_zone_last_timing",
+           "zda_zone_set_option",
+           "zda_zone_last_timing", "zda_batch_create", "zda_batch_destroy", "zda_batch_run",
+           "zda_batch_adjoint_grad", "zda_batch_set_launch", "zda_batch_autotune",
            "zda_status_str", "zda_last_error"]
 
 
@@ -36,7 +39,8 @@ class ZoneDesc(ctypes.Structure):
                 ("pml_z_lo", ctypes.c_int), ("pml_z_hi", ctypes.c_int), ("pml_order", ctypes.c_double),
                 ("pml_sigma_max_r", ctypes.c_double), ("pml_sigma_max_z", ctypes.c_double),
                 ("pml_alpha", ctypes.c_double), ("k_mon", ctypes.c_int), ("design_k0", ctypes.c_int),
-                ("design_k1", ctypes.c_int), ("eps_bg", ctypes.c_double), ("eps_hi", ctypes.c_double)]
+                ("design_k1", ctypes.c_int), ("eps_bg", ctypes.c_double), ("eps_hi", ctypes.c_double),
+                ("single_buffer", ctypes.c_int)]
 
 
 class Source(ctypes.Structure):
@@ -55,6 +59,10 @@ class ZoneInfo(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("h_launches", ctypes.c_int), ("e_launches", ctypes.c_int), ("h_ms", ctypes.c_double),
                 ("e_ms", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int), ("ms_per_step", ctypes.c_double), ("probes", ctypes.c_int)]
 
 
 class ZdaError(RuntimeError):
@@ -90,13 +98,22 @@ def load():
     lib.zda_zone_get_info.argtypes = [P, ctypes.POINTER(ZoneInfo)]
     lib.zda_zone_last_timing.argtypes = [P, ctypes.POINTER(Timing)]
     lib.zda_zone_set_launch.argtypes = [P, I, I]
+    lib.zda_zone_set_option.argtypes = [P, I, I]
+    lib.zda_batch_create.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(P)]
+    lib.zda_batch_destroy.argtypes = [P]
+    lib.zda_batch_destroy.restype = None
+    lib.zda_batch_run.argtypes = [P, ctypes.POINTER(Source), I, P, I, I, P]
+    lib.zda_batch_adjoint_grad.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
+    lib.zda_batch_set_launch.argtypes = [P, I, P]
+    lib.zda_batch_autotune.argtypes = [P, ctypes.POINTER(Source), I, P, I, P, ctypes.POINTER(TuneResult)]
     lib.zda_status_str.argtypes = [I]
     lib.zda_status_str.restype = ctypes.c_char_p
     lib.zda_last_error.argtypes = []
     lib.zda_last_error.restype = ctypes.c_char_p
     for name in ("zda_zone_create", "zda_zone_set_eps", "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields",
                  "zda_adjoint_grad", "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info",
-                 "zda_zone_last_timing", "zda_zone_set_launch"):
+                 "zda_zone_last_timing", "zda_zone_set_launch", "zda_zone_set_option", "zda_batch_create",
+                 "zda_batch_run", "zda_batch_adjoint_grad", "zda_batch_set_launch", "zda_batch_autotune"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -176,6 +193,9 @@ class Zone:
         inf = ZoneInfo()
         _check(load().zda_zone_get_info(self._h, ctypes.byref(inf)))
         return inf
+
+    def set_option(self, option, value):
+        _check(load().zda_zone_set_option(self._h, int(option), int(value)))
 
     def set_launch(self, kchunk, tile_rows):
         _check(load().zda_zone_set_launch(self._h, int(kchunk), int(tile_rows)))
@@ -261,3 +281,76 @@ class Zone:
         t = value if isinstance(value, torch.Tensor) else torch.as_tensor(np.asarray(value, np.complex64))
         t = t.to(device="cuda", dtype=torch.complex64).contiguous()
         _check(load().zda_zone_write_field(self._h, COMP[name], ctypes.c_void_p(t.data_ptr()), 1))
+
+
+def preset_source(kind=SRC_PLANE_CIRC, k_src=1, omega_c=0.0, width=1.0, n0=-1):
+    s = Source()
+    s.kind, s.k_src, s.omega_c, s.width, s.n0 = kind, k_src, omega_c, width, n0
+    return s
+
+
+class Batch:
+    """Zones of uneven size stepped together (one launch per time step,
+    graph-replayed time loop).  Keeps references to its zones."""
+
+    def __init__(self, zones):
+        torch = _torch()
+        self.zones = list(zones)
+        arr = (ctypes.c_void_p * len(self.zones))(*[z._h.value for z in self.zones])
+        h = ctypes.c_void_p()
+        _check(load().zda_batch_create(arr, len(self.zones), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().zda_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sources(self, sources):
+        arr = (Source * len(self.zones))()
+        for i, s in enumerate(sources):
+            arr[i] = s
+        return arr
+
+    def run(self, sources, nsteps, omegas, *, plane=True, volume=False, stream=None):
+        torch = _torch()
+        om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, np.float64)))
+        flags = (DFT_PLANE if plane else 0) | (DFT_VOLUME if volume else 0)
+        _check(load().zda_batch_run(self._h, self._sources(sources), int(nsteps), ctypes.c_void_p(om.ctypes.data),
+                                    int(om.size), flags, _stream_ptr(torch, stream)))
+        for z in self.zones:
+            z._K = int(om.size)
+
+    def adjoint_grad(self, dF_dE_list, stream=None):
+        torch = _torch()
+        gs = [torch.view_as_real(g.to(torch.complex64).contiguous()).contiguous() for g in dF_dE_list]
+        outs = []
+        for z in self.zones:
+            d = z.desc
+            outs.append(torch.empty((d.design_k1 - d.design_k0, d.nr, d.nphi), dtype=torch.float32, device="cuda"))
+        ga = (ctypes.c_void_p * len(gs))(*[g.data_ptr() for g in gs])
+        oa = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        _check(load().zda_batch_adjoint_grad(self._h, ga, oa, _stream_ptr(torch, stream)))
+        torch.cuda.current_stream().synchronize()
+        return outs
+
+    def set_launch(self, tile_rows, kchunk=None):
+        kc = None
+        if kchunk is not None:
+            kc = (ctypes.c_int * len(kchunk))(*[int(k) for k in kchunk])
+        _check(load().zda_batch_set_launch(self._h, int(tile_rows), kc))
+
+    def autotune(self, sources, probe_steps, omegas, stream=None):
+        torch = _torch()
+        om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, np.float64)))
+        res = TuneResult()
+        _check(load().zda_batch_autotune(self._h, self._sources(sources), int(probe_steps),
+                                         ctypes.c_void_p(om.ctypes.data), int(om.size), _stream_ptr(torch, stream),
+                                         ctypes.byref(res)))
+        return res

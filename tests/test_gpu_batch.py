@@ -1,0 +1,115 @@
+"""Batched uneven zones: one launch per time step over the tiles of every
+zone, the time loop replayed from a captured graph.  Each zone's result must
+equal the same zone run alone (the per-cell code is shared, so bitwise) and
+the oracle; the batched adjoint must equal the per-zone adjoint."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-batch]", *a, flush=True)
+
+
+def _zones(seed=61):
+    """Four zones whose n, nr and nphi grow with the zone index (ragged)."""
+    from paper_2501_07979_amd.workloads import Workload
+    out = []
+    for l, (n, nr, nphi) in enumerate([(16, 23, 64), (24, 30, 96), (40, 37, 130), (56, 44, 170)]):
+        r_in = 200.0 * (n / 16.0) * (nphi / 64.0)
+        om = (0.28, 0.33, 0.39)
+        out.append(Workload("batch%d" % l, r_in=r_in, nr=nr, nphi=nphi, nz=40, n_fold=n, pml=(5, 5, 5, 5),
+                            k_src=8, k_mon=30, design=(12, 16), k_sub=12, steps=150, omegas=om, omega_c=0.33,
+                            width=6.0, seed=seed + l, density="smoothed"))
+    return out
+
+
+@pytest.fixture(scope="module")
+def zda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_07979_amd import zda as Z
+    Z.load()
+    return Z
+
+
+@pytest.mark.parametrize("mode", ["fused", "split"])
+def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
+    wls = _zones()
+    eps = [w.eps() for w in wls]
+    singles = []
+    for w, e in zip(wls, eps):
+        z = zda.Zone(zda.default_desc(**w.desc_kwargs()), e)
+        if mode == "split":
+            z.set_launch(w.nz, 4)
+        z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width, volume=True)
+        singles.append((z.read_field("Ez").cpu().numpy(), z.dft(zda.MON_PLANE).cpu().numpy(),
+                        z.dft(zda.MON_VOLUME).cpu().numpy()))
+        z.close()
+    zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    b = zda.Batch(zones)
+    b.set_launch(7 if mode == "fused" else 4)
+    srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
+    _say("batch run", mode)
+    b.run(srcs, wls[0].steps, wls[0].omegas, volume=True)    # 150 steps: graph replays + eager tail
+    for z, (ez, pl, vol) in zip(zones, singles):
+        assert np.array_equal(z.read_field("Ez").cpu().numpy(), ez)
+        assert np.array_equal(z.dft(zda.MON_PLANE).cpu().numpy(), pl)
+        assert np.array_equal(z.dft(zda.MON_VOLUME).cpu().numpy(), vol)
+    # one zone against the oracle
+    w = wls[2]
+    o = oracle_mod.OracleZone(**w.desc_kwargs(), eps=eps[2])
+    ref = o.forward(w.steps, np.array(w.omegas), omega_c=w.omega_c, width=w.width, k_src=w.k_src)["plane"]
+    got = zones[2].dft(zda.MON_PLANE).cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    b.close()
+
+
+def test_batch_adjoint_equals_single_zone_adjoint(zda):
+    import torch
+    wls = _zones(seed=71)
+    for w in wls:
+        w.steps = 400
+    eps = [w.eps() for w in wls]
+    rng = np.random.default_rng(5)
+    dFs = [torch.tensor((rng.standard_normal((3, 2, w.nr, w.nphi)) +
+                         1j * rng.standard_normal((3, 2, w.nr, w.nphi))).astype(np.complex64), device="cuda")
+           for w in wls]
+    single = []
+    for w, e, g in zip(wls, eps, dFs):
+        z = zda.Zone(zda.default_desc(**w.desc_kwargs()), e)
+        z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width, volume=True)
+        single.append(z.adjoint_grad(g).cpu().numpy())
+        z.close()
+    zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    b = zda.Batch(zones)
+    srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
+    _say("batch forward + adjoint")
+    b.run(srcs, wls[0].steps, wls[0].omegas, volume=True)
+    grads = b.adjoint_grad(dFs)
+    for gb, gs in zip(grads, single):
+        assert np.array_equal(gb.cpu().numpy(), gs)
+    b.close()
+
+
+def test_batch_autotune_keeps_results(zda):
+    wls = _zones(seed=81)
+    eps = [w.eps() for w in wls]
+    zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    b = zda.Batch(zones)
+    srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
+    b.run(srcs, 120, wls[0].omegas)
+    before = [z.dft(zda.MON_PLANE).cpu().numpy() for z in zones]
+    _say("autotune")
+    res = b.autotune(srcs, 10, wls[0].omegas)
+    assert res.probes >= 6 and res.ms_per_step > 0
+    b.run(srcs, 120, wls[0].omegas)
+    after = [z.dft(zda.MON_PLANE).cpu().numpy() for z in zones]
+    for x, y in zip(before, after):
+        if res.tile_rows in (3, 7, 15):
+            assert np.array_equal(x, y)          # fused family is shape-independent bitwise
+        else:
+            assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(x)
+    b.close()

@@ -221,7 +221,7 @@ def test_fused_launch_shapes_are_bitwise_identical(zda):
     tile and chunk shape (halo values are recomputed, not approximated), so
     the fused step is deterministic across launch shapes."""
     from paper_2501_07979_amd.workloads import Workload
-    wl = Workload("determinism", r_in=90.0, nr=37, nphi=130, nz=41, n_fold=14, m=1, pml=(5, 6, 4, 7), k_src=9,
+    wl = Workload("determinism", r_in=360.0, nr=37, nphi=130, nz=41, n_fold=14, m=1, pml=(5, 6, 4, 7), k_src=9,
                   k_mon=30, design=(12, 17), k_sub=12, steps=120, omegas=(0.3,), omega_c=0.3, width=6.0)
     rng = np.random.default_rng(41)
     eps = (1.0 + 4.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
