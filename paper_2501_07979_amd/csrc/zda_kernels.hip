@@ -239,6 +239,30 @@ __device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, in
 }
 
 
+// access at a byte offset from a (wave-uniform) row base: the address is one
+// scalar base pair plus a 32-bit lane offset
+__device__ __forceinline__ float2 ldo(const float2 *row, unsigned off)
+{
+    return *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(row) + off);
+}
+__device__ __forceinline__ const float2 *pco(const float2 *row, unsigned off)
+{
+    return reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(row) + off);
+}
+__device__ __forceinline__ float2 *pto(float2 *row, unsigned off)
+{
+    return reinterpret_cast<float2 *>(reinterpret_cast<char *>(row) + off);
+}
+// a wave-uniform 64-bit value moved to scalar registers: the compiler then
+// keeps the row bases scalar instead of folding the lane offset into per-lane
+// 64-bit pointers
+__device__ __forceinline__ size_t uni64(size_t v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return ((size_t)hi << 32) | lo;
+}
+
 // store of a value no block of this launch reads again (the next buffer set)
 __device__ __forceinline__ void store_out(float2 *p, float2 v, bool nt)
 {
@@ -277,14 +301,18 @@ template <int TR>
 __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned p, unsigned gx, unsigned gy)
 {
     __shared__ float2 sHz[2][TR + 1][64], sHr[2][TR + 1][64], sHp[2][TR + 1][64], sV[2][TR + 1][64];
-    const int lane = threadIdx.x, ww = threadIdx.y;
+    const int lane = threadIdx.x;
+    // a wavefront works on one row: the row index, its coefficients and every
+    // row base address are wave-uniform (scalar registers); a lane only
+    // carries its byte offset within the row
+    const int ww = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const int nphi = a.nphi, nr = a.nr, nz = a.nz;
     const size_t plane = (size_t)nr * nphi;
     const int bx = (int)(p % gx), by = (int)((p / gx) % gy), bz = (int)(p / (gx * gy));
-    const int i0 = by * TR;
-    const int i = ww == 0 ? i0 - 1 : i0 + ww - 1;
+    const int i = by * TR + ww - 1;
+    const bool row_ok = i >= 0 && i < nr;
     const int jj = bx * 63 - 1 + lane;
-    const bool hval = i >= 0 && i < nr && jj < nphi;
+    const bool hval = row_ok && jj < nphi;
     const bool seam_lane = jj < 0;
     const int j = seam_lane ? nphi - 1 : jj;
     const bool owner = ww >= 1 && lane >= 1 && hval;
@@ -292,48 +320,60 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
     const int ke = min(kb + a.kchunk, nz);
     const int kstart = kb > 0 ? kb - 1 : kb;
     const bool nt = a.nt_stores;
-    const int ir = hval ? slab_row(i, nr, a.pr0, a.pr1) : -1;
-    const int ir1 = (hval && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
-    const RowCoef rc = a.rows[hval ? i : 0];
-    const int jp = (j + 1 < nphi) ? j + 1 : 0;
-    const bool wrap = (j + 1 >= nphi);
+    const int ir = row_ok ? slab_row(i, nr, a.pr0, a.pr1) : -1;
+    const int ir1 = (row_ok && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
+    const RowCoef rc = a.rows[row_ok ? i : 0];
+    // every field load is issued unconditionally (from a clamped row, column
+    // or plane where the neighbour lies outside) so that a plane's loads are
+    // all in flight together; out-of-range values are replaced afterwards
+    const int ic = min(max(i, 0), nr - 1);
+    const int jc = min(j, nphi - 1);
+    const bool wrap = (jc + 1 >= nphi);
+    const unsigned o = (unsigned)jc * 8u;             // complex sample j of a row
+    const unsigned ojp = wrap ? 0u : o + 8u;         // sample j + 1 (column 0 across the seam)
+    const unsigned oc = (unsigned)jc * 4u;            // real sample j of a row
+    const size_t rowc = (size_t)ic * nphi;
+    const bool ip_ok = ic + 1 < nr;
+    const size_t dip = ip_ok ? (size_t)nphi : 0;
     const size_t slabR = (size_t)nz * a.dR * nphi;
     const size_t slabZ = (size_t)a.dZ * plane;
     const float dt = a.dt;
     const int nd = a.k1 - a.k0;
 
-    size_t c = ((size_t)kstart * nr + (hval ? i : 0)) * nphi + j;
-    float2 er = zero2(), ep = zero2();
-    if (hval) { er = a.Er[c]; ep = a.Ep[c]; }
+    float2 er = ldo(a.Er + (size_t)kstart * plane + rowc, o);
+    float2 ep = ldo(a.Ep + (size_t)kstart * plane + rowc, o);
     float2 hr_km = zero2(), hp_km = zero2();
-    for (int k = kstart; k < ke; ++k, c += plane) {
+    for (int k = kstart; k < ke; ++k) {
+        const size_t c0 = (size_t)k * plane + rowc;
+        const bool kp_ok = k + 1 < nz;
+        const size_t dkp = kp_ok ? plane : 0;
         const bool store = owner && k >= kb;
         const int kz = slab_row(k, nz, a.pz0, a.pz1);
-        const ZCoef zc = a.zrows[k];
-        float2 hr = zero2(), hp = zero2(), hz = zero2(), v = zero2();
-        float2 ez = zero2(), er_kp = zero2(), ep_kp = zero2();
-        const size_t sr = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi + j : 0;
-        const size_t sz = kz >= 0 ? ((size_t)kz * nr + (hval ? i : 0)) * nphi + j : 0;
-        if (hval) {
-            const size_t row = c - j;
-            ez = a.Ez[c];
-            if (k + 1 < nz) { er_kp = a.Er[c + plane]; ep_kp = a.Ep[c + plane]; }
-            float2 ez_jp = a.Ez[row + jp], er_jp = a.Er[row + jp];
-            if (wrap) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
-            float2 ez_ip = zero2(), ep_ip = zero2();
-            if (i + 1 < nr) { ez_ip = a.Ez[c + nphi]; ep_ip = a.Ep[c + nphi]; }
-            hr = a.Hr[c];
-            hp = a.Hp[c];
-            hz = a.Hz[c];
+        ZCoef zc = {};
+        if (kz >= 0) zc = a.zrows[k];
+        const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
+        const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
+        const float2 *aR = a.auxR + sr0, *aZ = a.auxZ + sz0;
+        float2 *oR = a.oauxR + sr0, *oZ = a.oauxZ + sz0;
+        const float2 ez = ldo(a.Ez + c0, o);
+        float2 er_kp = ldo(a.Er + c0 + dkp, o), ep_kp = ldo(a.Ep + c0 + dkp, o);
+        float2 ez_jp = ldo(a.Ez + c0, ojp), er_jp = ldo(a.Er + c0, ojp);
+        float2 ez_ip = ldo(a.Ez + c0 + dip, o), ep_ip = ldo(a.Ep + c0 + dip, o);
+        float2 hr = ldo(a.Hr + c0, o), hp = ldo(a.Hp + c0, o), hz = ldo(a.Hz + c0, o);
+        float2 v = zero2();
+        if (!kp_ok) { er_kp = zero2(); ep_kp = zero2(); }
+        if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+        if (wrap) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+        {
             // H_r at (i, j+1/2, k+1/2)
             if (i > 0) {
                 float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
                 float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
                 if (ir >= 0)
-                    t1 = div_stretch2(t1, a.auxR + AUX_HR_T * slabR + sr, a.oauxR + AUX_HR_T * slabR + sr, store,
+                    t1 = div_stretch2(t1, pco(aR + AUX_HR_T * slabR, o), pto(oR + AUX_HR_T * slabR, o), store,
                                       rc.g1_t_int, rc.g2_t_int, a.cr, dt);
                 if (kz >= 0)
-                    t2 = div_stretch2(t2, a.auxZ + ZAUX_HR * slabZ + sz, a.oauxZ + ZAUX_HR * slabZ + sz, store,
+                    t2 = div_stretch2(t2, pco(aZ + ZAUX_HR * slabZ, o), pto(oZ + ZAUX_HR * slabZ, o), store,
                                       zc.g1_half, zc.g2_half, a.cz, dt);
                 hr = make_float2(hr.x - dt * (t1.x - t2.x), hr.y - dt * (t1.y - t2.y));
             }
@@ -342,41 +382,42 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
                 float2 t1 = c_scale(c_sub(er_kp, er), a.inv_dz);
                 float2 t2 = c_scale(c_sub(ez_ip, ez), a.inv_dr);
                 if (kz >= 0)
-                    t1 = div_stretch2(t1, a.auxZ + ZAUX_HP * slabZ + sz, a.oauxZ + ZAUX_HP * slabZ + sz, store,
+                    t1 = div_stretch2(t1, pco(aZ + ZAUX_HP * slabZ, o), pto(oZ + ZAUX_HP * slabZ, o), store,
                                       zc.g1_half, zc.g2_half, a.cz, dt);
                 if (ir >= 0)
-                    t2 = div_stretch2(t2, a.auxR + AUX_HP_S * slabR + sr, a.oauxR + AUX_HP_S * slabR + sr, store,
+                    t2 = div_stretch2(t2, pco(aR + AUX_HP_S * slabR, o), pto(oR + AUX_HP_S * slabR, o), store,
                                       rc.g1_s_half, rc.g2_s_half, a.cr, dt);
                 hp = make_float2(hp.x - dt * (t1.x - t2.x), hp.y - dt * (t1.y - t2.y));
                 if (ir >= 0) {
-                    const float2 vo = a.auxR[AUX_V_HP * slabR + sr];
+                    const float2 vo = ldo(aR + AUX_V_HP * slabR, o);
                     v = make_float2(a.cr * vo.x + dt * hp.x, a.cr * vo.y + dt * hp.y);
-                    if (store) a.oauxR[AUX_V_HP * slabR + sr] = v;
+                    if (store) *pto(oR + AUX_V_HP * slabR, o) = v;
                 }
             }
             // H_z at (i+1/2, j+1/2, k)
             if (k > 0) {
                 float2 t = c_add(c_scale(c_sub(ep_ip, ep), a.inv_dr), c_scale(c_add(ep_ip, ep), rc.inv_2r_half));
                 if (ir >= 0) {
-                    const float2 *U = a.auxR + AUX_U_EP * slabR;
-                    float2 u0 = U[sr];
-                    float2 u1 = ir1 >= 0 ? U[((size_t)k * a.dR + ir1) * nphi + j] : zero2();
+                    const float2 u0 = ldo(aR + AUX_U_EP * slabR, o);
+                    const float2 u1 =
+                        ir1 >= 0 ? ldo(a.auxR + AUX_U_EP * slabR + ((size_t)k * a.dR + ir1) * nphi, o) : zero2();
                     t = c_add(t, c_sub(c_scale(u1, rc.hz_c1), c_scale(u0, rc.hz_c0)));
-                    t = div_stretch2(t, a.auxR + AUX_HZ_S * slabR + sr, a.oauxR + AUX_HZ_S * slabR + sr, store,
+                    t = div_stretch2(t, pco(aR + AUX_HZ_S * slabR, o), pto(oR + AUX_HZ_S * slabR, o), store,
                                      rc.g1_s_half, rc.g2_s_half, a.cr, dt);
                 }
                 t = c_sub(t, c_scale(c_sub(er_jp, er), rc.inv_rdphi_half));
                 if (ir >= 0)
-                    t = div_stretch2(t, a.auxR + AUX_HZ_T * slabR + sr, a.oauxR + AUX_HZ_T * slabR + sr, store,
+                    t = div_stretch2(t, pco(aR + AUX_HZ_T * slabR, o), pto(oR + AUX_HZ_T * slabR, o), store,
                                      rc.g1_t_half, rc.g2_t_half, a.cr, dt);
                 hz = make_float2(hz.x - dt * t.x, hz.y - dt * t.y);
             }
             if (store) {
-                store_out(a.oHr + c, hr, nt);
-                store_out(a.oHp + c, hp, nt);
-                store_out(a.oHz + c, hz, nt);
+                store_out(pto(a.oHr + c0, o), hr, nt);
+                store_out(pto(a.oHp + c0, o), hp, nt);
+                store_out(pto(a.oHz + c0, o), hz, nt);
             }
         }
+        if (!hval) { hr = zero2(); hp = zero2(); hz = zero2(); v = zero2(); }
         const int buf = k & 1;
         if (seam_lane) {   // the halo column across the wedge boundary is j = -1
             sHz[buf][ww][lane] = c_mul(a.seam_m, hz);
@@ -394,14 +435,14 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
             const float2 hz_jm = sHz[buf][ww][lane - 1], hr_jm = sHr[buf][ww][lane - 1];
             const float2 hz_im = sHz[buf][ww - 1][lane], hp_im = sHp[buf][ww - 1][lane];
             const float2 v_im = sV[buf][ww - 1][lane];
-            const float ce = a.ceps[c];
+            const float ce = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a.ceps + c0) + oc);
             float2 jr = zero2(), jph = zero2();
             if (k == a.k_src) {
-                for (int p = 0; p < a.n_prof; ++p) {
-                    const float2 g = a.profile[(size_t)n * a.n_prof + p];
-                    const float2 *pat = a.pattern + (size_t)p * 2 * plane + (size_t)i * nphi + j;
-                    jr = c_fma(jr, pat[0], g);
-                    jph = c_fma(jph, pat[plane], g);
+                for (int q = 0; q < a.n_prof; ++q) {
+                    const float2 g = a.profile[(size_t)n * a.n_prof + q];
+                    const float2 *pat = a.pattern + (size_t)q * 2 * plane + rowc;
+                    jr = c_fma(jr, ldo(pat, o), g);
+                    jph = c_fma(jph, ldo(pat + plane, o), g);
                 }
             }
             float2 er_n = er, ep_n = ep, ez_n = ez;
@@ -410,10 +451,10 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
                 float2 t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
                 float2 t2 = c_scale(c_sub(hp, hp_km), a.inv_dz);
                 if (ir >= 0)
-                    t1 = div_stretch2(t1, a.auxR + AUX_ER_T * slabR + sr, a.oauxR + AUX_ER_T * slabR + sr, true,
+                    t1 = div_stretch2(t1, pco(aR + AUX_ER_T * slabR, o), pto(oR + AUX_ER_T * slabR, o), true,
                                       rc.g1_t_half, rc.g2_t_half, a.cr, dt);
                 if (kz >= 0)
-                    t2 = div_stretch2(t2, a.auxZ + ZAUX_ER * slabZ + sz, a.oauxZ + ZAUX_ER * slabZ + sz, true,
+                    t2 = div_stretch2(t2, pco(aZ + ZAUX_ER * slabZ, o), pto(oZ + ZAUX_ER * slabZ, o), true,
                                       zc.g1_int, zc.g2_int, a.cz, dt);
                 er_n = make_float2(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
             }
@@ -422,16 +463,15 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
                 float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
                 float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
                 if (kz >= 0)
-                    t1 = div_stretch2(t1, a.auxZ + ZAUX_EP * slabZ + sz, a.oauxZ + ZAUX_EP * slabZ + sz, true,
+                    t1 = div_stretch2(t1, pco(aZ + ZAUX_EP * slabZ, o), pto(oZ + ZAUX_EP * slabZ, o), true,
                                       zc.g1_int, zc.g2_int, a.cz, dt);
                 if (ir >= 0)
-                    t2 = div_stretch2(t2, a.auxR + AUX_EP_S * slabR + sr, a.oauxR + AUX_EP_S * slabR + sr, true,
+                    t2 = div_stretch2(t2, pco(aR + AUX_EP_S * slabR, o), pto(oR + AUX_EP_S * slabR, o), true,
                                       rc.g1_s_int, rc.g2_s_int, a.cr, dt);
                 ep_n = make_float2(ep.x + ce * (t1.x - t2.x - jph.x), ep.y + ce * (t1.y - t2.y - jph.y));
                 if (ir >= 0) {
-                    const float2 uo = a.auxR[AUX_U_EP * slabR + sr];
-                    a.oauxR[AUX_U_EP * slabR + sr] =
-                        make_float2(a.cr * uo.x + dt * ep_n.x, a.cr * uo.y + dt * ep_n.y);
+                    const float2 uo = ldo(aR + AUX_U_EP * slabR, o);
+                    *pto(oR + AUX_U_EP * slabR, o) = make_float2(a.cr * uo.x + dt * ep_n.x, a.cr * uo.y + dt * ep_n.y);
                 }
             }
             // E_z at (i, j, k+1/2)
@@ -439,34 +479,36 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
                 float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
                 if (ir >= 0) {
                     t = c_add(t, c_sub(c_scale(v, rc.ez_c1), c_scale(v_im, rc.ez_c0)));
-                    t = div_stretch2(t, a.auxR + AUX_EZ_S * slabR + sr, a.oauxR + AUX_EZ_S * slabR + sr, true,
+                    t = div_stretch2(t, pco(aR + AUX_EZ_S * slabR, o), pto(oR + AUX_EZ_S * slabR, o), true,
                                      rc.g1_s_int, rc.g2_s_int, a.cr, dt);
                 }
                 t = c_sub(t, c_scale(c_sub(hr, hr_jm), rc.inv_rdphi_int));
                 if (ir >= 0)
-                    t = div_stretch2(t, a.auxR + AUX_EZ_T * slabR + sr, a.oauxR + AUX_EZ_T * slabR + sr, true,
+                    t = div_stretch2(t, pco(aR + AUX_EZ_T * slabR, o), pto(oR + AUX_EZ_T * slabR, o), true,
                                      rc.g1_t_int, rc.g2_t_int, a.cr, dt);
                 ez_n = make_float2(ez.x + ce * t.x, ez.y + ce * t.y);
             }
-            store_out(a.oEr + c, er_n, nt);
-            store_out(a.oEp + c, ep_n, nt);
-            store_out(a.oEz + c, ez_n, nt);
+            store_out(pto(a.oEr + c0, o), er_n, nt);
+            store_out(pto(a.oEp + c0, o), ep_n, nt);
+            store_out(pto(a.oEz + c0, o), ez_n, nt);
             if (a.dft_plane && k == a.k_mon) {
                 for (int f = 0; f < a.K; ++f) {
                     const float2 tw = a.twiddle[(size_t)n * a.K + f];
-                    float2 *o = a.dft_plane + (size_t)f * 2 * plane + (size_t)i * nphi + j;
-                    o[0] = c_fma(o[0], tw, er_n);
-                    o[plane] = c_fma(o[plane], tw, ep_n);
+                    float2 *q0 = pto(a.dft_plane + (size_t)f * 2 * plane + rowc, o);
+                    float2 *q1 = pto(a.dft_plane + (size_t)f * 2 * plane + plane + rowc, o);
+                    *q0 = c_fma(*q0, tw, er_n);
+                    *q1 = c_fma(*q1, tw, ep_n);
                 }
             }
             if (a.dft_vol && k >= a.k0 && k < a.k1) {
                 const size_t vs = (size_t)nd * plane;
                 for (int f = 0; f < a.K; ++f) {
                     const float2 tw = a.twiddle[(size_t)n * a.K + f];
-                    float2 *o = a.dft_vol + (size_t)f * 3 * vs + (size_t)(k - a.k0) * plane + (size_t)i * nphi + j;
-                    o[0] = c_fma(o[0], tw, er_n);
-                    o[vs] = c_fma(o[vs], tw, ep_n);
-                    o[2 * vs] = c_fma(o[2 * vs], tw, ez_n);
+                    float2 *base = a.dft_vol + (size_t)f * 3 * vs + (size_t)(k - a.k0) * plane + rowc;
+                    float2 *q0 = pto(base, o), *q1 = pto(base + vs, o), *q2 = pto(base + 2 * vs, o);
+                    *q0 = c_fma(*q0, tw, er_n);
+                    *q1 = c_fma(*q1, tw, ep_n);
+                    *q2 = c_fma(*q2, tw, ez_n);
                 }
             }
         }

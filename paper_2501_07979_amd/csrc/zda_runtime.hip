@@ -1004,7 +1004,9 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-        for (int q = 0; q < S; ++q) launch_batch_step(ba[q & 1], total, b->tile_rows, b->fused, q, b->cap_stream);
+        // the fused step alternates buffer parities; the split kernels update one set in place
+        for (int q = 0; q < S; ++q)
+            launch_batch_step(ba[b->fused ? (q & 1) : 0], total, b->tile_rows, b->fused, q, b->cap_stream);
         launch_advance_step(b->n_base, S, b->cap_stream);
         HIP_TRY(hipStreamEndCapture(b->cap_stream, &graph));
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1020,7 +1022,8 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
             return fail(ZDA_ERR_HIP, "graph launch: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
     const int done = reps * S;
-    for (int q = 0; q < nsteps - done; ++q) launch_batch_step(ba[q & 1], total, b->tile_rows, b->fused, q, s);
+    for (int q = 0; q < nsteps - done; ++q)
+        launch_batch_step(ba[b->fused ? (q & 1) : 0], total, b->tile_rows, b->fused, q, s);
     HIP_TRY(hipGetLastError());
     for (auto z : b->zones) {
         z->n_done += nsteps;
