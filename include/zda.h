@@ -192,15 +192,20 @@ typedef struct {
 } zda_zone_info;
 
 /* Launch shape of the update kernels: each thread marches kchunk z-planes of
- * one (r, phi) column; a block covers tile_rows radial rows x 64 phi cells.
+ * one (r, phi) column.  tile_rows in {3, 7, 15} selects the fused one-launch
+ * step (a block owns tile_rows radial rows x 63 phi cells; needs the second
+ * buffer set), tile_rows in {1, 2, 4, 8, 16} the in-place H and E kernels
+ * (a block covers tile_rows rows x 64 phi cells).  The default is the fused
+ * step with 3 rows and 12-plane chunks (fewer planes for small zones).
  * Results do not depend on the shape.  ZDA_ERR_ARG for kchunk outside
- * [1, nz] or tile_rows not in {1, 2, 4, 8, 16}. */
+ * [1, nz] or any other tile_rows; ZDA_ERR_STATE for a fused shape on a zone
+ * without the second buffer set. */
 zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 
 /* Launch options of the fused step (results do not depend on them):
- * ZDA_OPT_XCD_REMAP (default 1) numbers the tiles so that each of the eight
+ * ZDA_OPT_XCD_REMAP (default 0) numbers the tiles so that each of the eight
  * XCDs works on one contiguous range of neighbouring tiles; ZDA_OPT_NT_STORES
- * (default 0) writes the next buffer set with non-temporal stores.
+ * (default 1) writes the next buffer set with non-temporal stores.
  * ZDA_ERR_ARG for an unknown option. */
 #define ZDA_OPT_XCD_REMAP 1
 #define ZDA_OPT_NT_STORES 2

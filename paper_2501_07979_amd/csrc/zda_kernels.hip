@@ -253,15 +253,6 @@ __device__ __forceinline__ float2 *pto(float2 *row, unsigned off)
 {
     return reinterpret_cast<float2 *>(reinterpret_cast<char *>(row) + off);
 }
-// a wave-uniform 64-bit value moved to scalar registers: the compiler then
-// keeps the row bases scalar instead of folding the lane offset into per-lane
-// 64-bit pointers
-__device__ __forceinline__ size_t uni64(size_t v)
-{
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-    return ((size_t)hi << 32) | lo;
-}
 
 // store of a value no block of this launch reads again (the next buffer set)
 __device__ __forceinline__ void store_out(float2 *p, float2 v, bool nt)

@@ -83,7 +83,7 @@ struct zda_zone {
     float2 *auxR[2] = {nullptr, nullptr}, *auxZ[2] = {nullptr, nullptr};
     int cur = 0;
     bool fused = true;
-    int xcd_remap = 1, nt_stores = 0;
+    int xcd_remap = 0, nt_stores = 1;
     RowCoef *rows = nullptr;
     ZCoef *zrows = nullptr;
     float2 *dft_plane = nullptr, *dft_vol = nullptr, *dft_vol_adj = nullptr;
@@ -666,14 +666,15 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     z->dR = d->pml_r_in + d->pml_r_out;
     z->dZ = d->pml_z_lo + d->pml_z_hi;
     z->nd = d->design_k1 - d->design_k0;
-    // default launch shape: fused step, 7 owned rows per block, z-chunks
-    // short enough for ~32 wavefronts per CU (256 CUs), at least 8 planes
+    // default launch shape (measured on the 512 x 1024 x 400 zone): fused
+    // step, 3 owned rows per block, 12-plane z-chunks; shorter chunks (down to
+    // 4 planes) while the grid has fewer than 2048 blocks
     {
-        z->tile_rows = 7;
-        const long waves = (long)((d->nphi + 62) / 63) * ((d->nr + 6) / 7) * 8;
-        long chunks = (32768 + waves - 1) / waves;
-        chunks = std::max(1L, std::min(chunks, (long)std::max(1, d->nz / 8)));
-        z->kchunk = (int)((d->nz + chunks - 1) / chunks);
+        z->tile_rows = 3;
+        const long tiles = (long)((d->nphi + 62) / 63) * ((d->nr + 2) / 3);
+        int kc = std::min(12, d->nz);
+        while (kc > 4 && tiles * ((d->nz + kc - 1) / kc) < 2048) --kc;
+        z->kchunk = kc;
     }
     std::vector<RowCoef> rows;
     std::vector<ZCoef> zr;
@@ -1051,7 +1052,7 @@ zda_status zda_batch_create(zda_zone *const *zones, int nzones, zda_batch **out)
     b->device = dev;
     b->fused = true;
     for (auto z : b->zones) b->fused = b->fused && zone_has_second_set(z);
-    b->tile_rows = b->fused ? 7 : 4;
+    b->tile_rows = b->fused ? 3 : 4;
     DeviceGuard g(dev);
     if (hipMalloc((void **)&b->n_base, sizeof(int)) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1152,7 +1153,15 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
     DeviceGuard g(b->device);
     hipStream_t hs = (hipStream_t)stream;
     const size_t nz = b->zones.size();
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct EventPair {
+        hipEvent_t &a, &b;
+        ~EventPair()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     int probes = 0;
@@ -1193,28 +1202,19 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
     for (int cl = 0; cl < nclass; ++cl) {
         const size_t lo = nz * cl / nclass, hi = nz * (cl + 1) / nclass;
         const std::vector<int> kc0 = kc;
-        int best_div = 0;
-        for (int div : {1, 2, 4, 8, 16}) {
-            for (size_t q = lo; q < hi; ++q) {
-                const zda_zone *z = b->zones[order[q]];
-                kc[order[q]] = std::max(8, (z->d.nz + div - 1) / div);
-                if (kc[order[q]] > z->d.nz) kc[order[q]] = z->d.nz;
-            }
+        int best_depth = 0;
+        for (int depth : {6, 8, 12, 20, 40}) {
+            for (size_t q = lo; q < hi; ++q) kc[order[q]] = std::min(depth, b->zones[order[q]]->d.nz);
             if ((st = zda_batch_set_launch(b, best_rows, kc.data())) != ZDA_OK) return st;
             double ms;
             if ((st = probe(ms)) != ZDA_OK) return st;
-            if (ms < best) { best = ms; best_div = div; }
+            if (ms < best) { best = ms; best_depth = depth; }
         }
         kc = kc0;
-        if (best_div > 0)
-            for (size_t q = lo; q < hi; ++q) {
-                const zda_zone *z = b->zones[order[q]];
-                kc[order[q]] = std::min(z->d.nz, std::max(8, (z->d.nz + best_div - 1) / best_div));
-            }
+        if (best_depth > 0)
+            for (size_t q = lo; q < hi; ++q) kc[order[q]] = std::min(best_depth, b->zones[order[q]]->d.nz);
         if ((st = zda_batch_set_launch(b, best_rows, kc.data())) != ZDA_OK) return st;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     res->tile_rows = best_rows;
     res->ms_per_step = best;
     res->probes = probes;
