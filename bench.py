@@ -4,10 +4,11 @@ A step is one leap-frog time step of the whole forward hot path over the
 production zone (n = 512 wedge, 512 x 1024 x 400 cells): the H half-step, the
 E half-step with the soft source sheet and the 3-frequency exit-plane DFT.
 K timed steps run inside one zda_fdtd_run after W warm-up steps; the value is
-cell-updates per second.  The dominant kernel's roofline uses its algorithmic
-bytes per launch over its average duration, both measured live with HIP
-events on the run's stream; the FP64 oracle is timed on the host cores on a
-few steps of the same zone.
+cell-updates per second.  The default kernel advances two steps per launch
+(one launch over the tiles without layer cells, one over the rest); the
+dominant kernel's roofline uses its algorithmic bytes per launch over its
+average duration, both measured live with HIP events on the run's stream;
+the FP64 oracle is timed on the host cores on a few steps of the same zone.
 """
 from __future__ import annotations
 
@@ -51,6 +52,25 @@ def algorithmic_bytes(wl, K):
     e = 76 * cells + 88 * r_cells + 32 * z_cells + K * 2 * 16 * plane + 16 * plane
     fused = 100 * cells + 176 * r_cells + 64 * z_cells + K * 2 * 16 * plane + 16 * plane
     return h, e, fused
+
+
+def two_step_interior_bytes(tm, K):
+    """Bytes the two-step kernel's launch over interior tiles must move: it
+    reads E, H (48 B) and dt/eps (4 B) of every owned cell once and writes E,
+    H (48 B) once for two time steps (no layer cells in these tiles); exit
+    plane cells add K x 2 x 16 B (DFT read+write, both steps folded into one
+    update), source cells 2 x 8 B (pattern)."""
+    return 100 * tm.e_cells + K * 32 * tm.e_mon_cells + 16 * tm.e_src_cells
+
+
+def two_step_zone_bytes(wl, K):
+    """Whole-zone minimum per two-step launch pair (interior and layer tiles):
+    100 B per cell, r-layer cells 10 auxiliaries x 16 B, z-layer cells 4 x 16
+    B, plus the DFT and source terms."""
+    plane = wl.nr * wl.nphi
+    r_cells = (wl.pml[0] + wl.pml[1]) * wl.nphi * wl.nz
+    z_cells = (wl.pml[2] + wl.pml[3]) * plane
+    return 100 * wl.cells + 160 * r_cells + 64 * z_cells + K * 32 * plane + 16 * plane
 
 
 def load_traffic(kernel, wl_name):
@@ -220,10 +240,23 @@ def main():
     gcells = wl.cells * args.steps / (ms / 1e3) / 1e9
     hb, eb, fused = algorithmic_bytes(wl, K)
     e_avg = tm.e_ms / tm.e_launches
-    if tm.h_launches == 0:      # fused step: one kernel per time step
-        kernel, kbytes, h_avg = "eh_fused_kernel", fused, 0.0
+    kernel_ms = {}
+    if tm.steps_per_launch == 2:   # two-step kernel: interior tiles + tiles with layer cells
+        kernel, kbytes = "eh2_kernel_interior", two_step_interior_bytes(tm, K)
+        kernel_ms = {"eh2_kernel_interior": round(e_avg, 5),
+                     "eh2_kernel_layer": round(tm.layer_ms / tm.layer_launches, 5)}
+        zone_min = two_step_zone_bytes(wl, K) / 2
+        family = "two-step"
+    elif tm.h_launches == 0:      # fused step: one kernel per time step
+        kernel, kbytes = "eh_fused_kernel", fused
+        kernel_ms = {"eh_fused_kernel": round(e_avg, 5)}
+        zone_min = fused
+        family = "fused one-step"
     else:
-        kernel, kbytes, h_avg = "e_step_kernel", eb, tm.h_ms / tm.h_launches
+        kernel, kbytes = "e_step_kernel", eb
+        kernel_ms = {"h_step_kernel": round(tm.h_ms / tm.h_launches, 5), "e_step_kernel": round(e_avg, 5)}
+        zone_min = hb + eb
+        family = "split"
     achieved = kbytes / (e_avg / 1e3) / 1e9
     traffic = load_traffic(kernel, wl.name)
     out = {
@@ -246,15 +279,17 @@ def main():
                      "r_in": wl.r_in, "pml": list(wl.pml)},
             "frequencies": K,
             "run_steps_of_full_job": wl.steps,
-            "h_kernel_ms": round(h_avg, 5),
-            "e_or_fused_kernel_ms": round(e_avg, 5),
+            "kernel_family": family,
+            "steps_per_launch": tm.steps_per_launch,
+            "kernel_ms_per_launch": kernel_ms,
             "wall_s": round(wall, 3),
-            "fused_min_bytes_per_cell_update": round(fused / wl.cells, 2),
-            "fused_min_roofline_frac": round(gcells * 1e9 * (fused / wl.cells) / (HBM_PEAK_GBS * 1e9), 4),
+            "min_hbm_bytes_per_cell_update": round(zone_min / wl.cells, 2),
+            "zone_min_bytes_roofline_frac": round(gcells * 1e9 * (zone_min / wl.cells) / (HBM_PEAK_GBS * 1e9), 4),
         },
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": kbytes},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": kbytes,
+                     "cells_per_launch": tm.e_cells, "steps_per_launch": tm.steps_per_launch},
     }
     if not args.no_design_iter and args.workload == "c2":
         print("bench: one design iteration on the gradient zone", file=sys.stderr, flush=True)

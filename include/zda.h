@@ -194,8 +194,10 @@ typedef struct {
 /* Launch shape of the update kernels: each thread marches kchunk z-planes of
  * one (r, phi) column.  tile_rows in {3, 7, 15} selects the fused one-launch
  * step (a block owns tile_rows radial rows x 63 phi cells; needs the second
- * buffer set), tile_rows in {1, 2, 4, 8, 16} the in-place H and E kernels
- * (a block covers tile_rows rows x 64 phi cells).  The default is the fused
+ * buffer set), tile_rows in {5, 13} the two-step kernel (two time steps per
+ * launch, a block owns tile_rows rows x 61 phi cells; needs the second set
+ * and the intermediate auxiliaries), tile_rows in {1, 2, 4, 8, 16} the
+ * in-place H and E kernels (a block covers tile_rows rows x 64 phi cells).  The default is the fused
  * step with 3 rows and 12-plane chunks (fewer planes for small zones).
  * Results do not depend on the shape.  ZDA_ERR_ARG for kchunk outside
  * [1, nz] or any other tile_rows; ZDA_ERR_STATE for a fused shape on a zone
@@ -214,10 +216,20 @@ zda_status zda_zone_set_option(zda_zone *z, int option, int value);
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);
 
 /* Per-kernel device time of the last zda_fdtd_run made with ZDA_RUN_TIMING
- * (HIP events on the run's stream around each launch).  Synchronises. */
+ * (HIP events on the run's stream around each launch).  Split kernels: h and
+ * e per step; fused step: e per step; two-step kernel: e = the launch over
+ * interior tiles (no layer cells), layer = the launch over the other tiles,
+ * both per pair of steps (an odd last step runs the fused step, untimed).
+ * Synchronises. */
 typedef struct {
     int h_launches, e_launches;
     double h_ms, e_ms;        /* summed kernel durations */
+    int steps_per_launch;     /* time steps one e launch advances: 1, or 2 (two-step) */
+    int layer_launches;       /* two-step: launches over the tiles holding layer cells */
+    double layer_ms;
+    size_t e_cells;           /* cells one e launch owns (two-step: the interior tiles) */
+    size_t e_mon_cells;       /* of them, cells in the exit-plane monitor */
+    size_t e_src_cells;       /* of them, cells in the source sheet */
 } zda_timing;
 
 zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);

@@ -51,12 +51,16 @@ struct StepArgs {
     int k0, k1;
     float2 *dft_vol;               // [K][3][k1-k0][nr][nphi] or null
     int kchunk;                    // planes per z-chunk
-    int tile_rows;                 // radial rows per block (1, 2, 4, 8, 16 split; 3, 7, 15 fused)
+    int tile_rows;                 // radial rows per block (1, 2, 4, 8, 16 split; 3, 7, 15 fused; 5, 13 two-step)
     // fused step: fields and auxiliaries read from the set above, written here
     float2 *oEr, *oEp, *oEz, *oHr, *oHp, *oHz;
     float2 *oauxR, *oauxZ;
     int xcd_remap;                 // fused: contiguous tile ranges per XCD
     int nt_stores;                 // fused: non-temporal stores of the next buffer set
+    // two-step launch: auxiliaries at the intermediate time level and the
+    // linear indices of the tiles this launch covers
+    float2 *mauxR, *mauxZ;
+    const unsigned *tiles;
 };
 
 // Batched launch over many zones: per-zone argument blocks in device memory
@@ -76,6 +80,12 @@ enum { ZAUX_HR, ZAUX_HP, ZAUX_ER, ZAUX_EP, N_AUX_Z };
 void launch_h_step(const StepArgs &a, int n, hipStream_t s);
 void launch_e_step(const StepArgs &a, int n, hipStream_t s);
 void launch_fused_step(const StepArgs &a, int n, hipStream_t s);
+// two leap-frog steps (n, n + 1) over the tiles listed in a.tiles; pml selects
+// the instantiation with the layer recursions
+void launch_two_step(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s);
+// tile grid of the two-step kernel (TR owned rows, 61 owned phi cells)
+void two_step_grid(const StepArgs &a, int TR, unsigned &gx, unsigned &gy, unsigned &gz);
+constexpr int TWO_STEP_COLS = 61;
 void launch_fill(float2 *p, size_t n, hipStream_t s);
 // tiles of one zone for the split (BY rows) or fused (TR owned rows) kernels
 unsigned tiles_split(const StepArgs &a, int BY);

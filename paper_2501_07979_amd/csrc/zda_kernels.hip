@@ -193,11 +193,12 @@ __device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, in
             if (ir >= 0) t2 = div_stretch(t2, a.auxR + AUX_EP_S * slabR + sr, rc.g1_s_int, rc.g2_s_int, a.cr, dt);
             ep = make_float2(ep.x + ce * (t1.x - t2.x - jp.x), ep.y + ce * (t1.y - t2.y - jp.y));
             a.Ep[c] = ep;
-            if (ir >= 0) {
-                float2 *u = a.auxR + AUX_U_EP * slabR + sr;
-                float2 uu = *u;
-                *u = make_float2(a.cr * uu.x + dt * ep.x, a.cr * uu.y + dt * ep.y);
-            }
+        }
+        // U = F E_phi advances on every r-layer cell (also where E_phi is held)
+        if (ir >= 0) {
+            float2 *u = a.auxR + AUX_U_EP * slabR + sr;
+            float2 uu = *u;
+            *u = make_float2(a.cr * uu.x + dt * ep.x, a.cr * uu.y + dt * ep.y);
         }
         // E_z at (i, j, k+1/2)
         if (i > 0) {
@@ -277,6 +278,146 @@ __device__ __forceinline__ float2 div_stretch2(float2 x, const float2 *src, floa
     return y;
 }
 
+// Auxiliary row bases of one cell row for the recursions: r-layer slab row
+// (k, ir) and z-layer slab row (kz, i) of one auxiliary set.
+struct AuxRows {
+    const float2 *sR, *sZ;   // read (time level before the half-step)
+    float2 *dR, *dZ;         // written (time level after it)
+};
+
+// H half-step of one cell, H^{n+1/2} = H^{n-1/2} - dt curl E^n, with the PML
+// divide-by-stretch recursions.  E^n at the cell and its +phi (jp), +r (ip)
+// and +z (kp) neighbours; u0, u1 are U = F E_phi at rows i and i + 1 (r-layer
+// only).  The auxiliaries of the cell are written when wr; v returns the
+// updated V = F H_phi (r-layer; zero elsewhere).  Inner boundary (i = 0):
+// H_r is not updated; bottom plane (k = 0): H_z is not updated.
+__device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, const ZCoef &zc, int i, int k, int ir,
+                                       int kz, size_t slabR, size_t slabZ, const AuxRows &x, unsigned o, bool wr,
+                                       float2 ez, float2 er, float2 ep, float2 ez_jp, float2 er_jp, float2 er_kp,
+                                       float2 ep_kp, float2 ez_ip, float2 ep_ip, float2 u0, float2 u1, float2 &hr,
+                                       float2 &hp, float2 &hz, float2 &v)
+{
+    const float dt = a.dt;
+    // H_r at (i, j+1/2, k+1/2)
+    if (i > 0) {
+        float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
+        float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
+        if (ir >= 0)
+            t1 = div_stretch2(t1, pco(x.sR + AUX_HR_T * slabR, o), pto(x.dR + AUX_HR_T * slabR, o), wr,
+                              rc.g1_t_int, rc.g2_t_int, a.cr, dt);
+        if (kz >= 0)
+            t2 = div_stretch2(t2, pco(x.sZ + ZAUX_HR * slabZ, o), pto(x.dZ + ZAUX_HR * slabZ, o), wr, zc.g1_half,
+                              zc.g2_half, a.cz, dt);
+        hr = make_float2(hr.x - dt * (t1.x - t2.x), hr.y - dt * (t1.y - t2.y));
+    }
+    // H_phi at (i+1/2, j, k+1/2)
+    {
+        float2 t1 = c_scale(c_sub(er_kp, er), a.inv_dz);
+        float2 t2 = c_scale(c_sub(ez_ip, ez), a.inv_dr);
+        if (kz >= 0)
+            t1 = div_stretch2(t1, pco(x.sZ + ZAUX_HP * slabZ, o), pto(x.dZ + ZAUX_HP * slabZ, o), wr, zc.g1_half,
+                              zc.g2_half, a.cz, dt);
+        if (ir >= 0)
+            t2 = div_stretch2(t2, pco(x.sR + AUX_HP_S * slabR, o), pto(x.dR + AUX_HP_S * slabR, o), wr,
+                              rc.g1_s_half, rc.g2_s_half, a.cr, dt);
+        hp = make_float2(hp.x - dt * (t1.x - t2.x), hp.y - dt * (t1.y - t2.y));
+        v = zero2();
+        if (ir >= 0) {
+            const float2 vo = ldo(x.sR + AUX_V_HP * slabR, o);
+            v = make_float2(a.cr * vo.x + dt * hp.x, a.cr * vo.y + dt * hp.y);
+            if (wr) *pto(x.dR + AUX_V_HP * slabR, o) = v;
+        }
+    }
+    // H_z at (i+1/2, j+1/2, k)
+    if (k > 0) {
+        float2 t = c_add(c_scale(c_sub(ep_ip, ep), a.inv_dr), c_scale(c_add(ep_ip, ep), rc.inv_2r_half));
+        if (ir >= 0) {
+            t = c_add(t, c_sub(c_scale(u1, rc.hz_c1), c_scale(u0, rc.hz_c0)));
+            t = div_stretch2(t, pco(x.sR + AUX_HZ_S * slabR, o), pto(x.dR + AUX_HZ_S * slabR, o), wr, rc.g1_s_half,
+                             rc.g2_s_half, a.cr, dt);
+        }
+        t = c_sub(t, c_scale(c_sub(er_jp, er), rc.inv_rdphi_half));
+        if (ir >= 0)
+            t = div_stretch2(t, pco(x.sR + AUX_HZ_T * slabR, o), pto(x.dR + AUX_HZ_T * slabR, o), wr, rc.g1_t_half,
+                             rc.g2_t_half, a.cr, dt);
+        hz = make_float2(hz.x - dt * t.x, hz.y - dt * t.y);
+    }
+}
+
+// E half-step of one cell, E^{n+1} = E^n + (dt/eps)(curl H^{n+1/2} - J), with
+// the PML recursions.  H^{n+1/2} at the cell and its -phi (jm), -r (im) and
+// -z (km) neighbours, V at rows i and i - 1, the source current (jr, jph).
+// The auxiliaries are always written (only owners call it with a write
+// target); u returns the updated U = F E_phi (r-layer, every cell).  Inner boundary:
+// E_phi and E_z are not updated; bottom plane: E_r and E_phi are not updated.
+__device__ __forceinline__ void e_cell(const StepArgs &a, const RowCoef &rc, const ZCoef &zc, int i, int k, int ir,
+                                       int kz, size_t slabR, size_t slabZ, const AuxRows &x, unsigned o, float ce,
+                                       float2 jr, float2 jph, float2 hr, float2 hr_jm, float2 hr_km, float2 hp,
+                                       float2 hp_im, float2 hp_km, float2 hz, float2 hz_jm, float2 hz_im, float2 v,
+                                       float2 v_im, float2 &er, float2 &ep, float2 &ez, float2 &u)
+{
+    const float dt = a.dt;
+    // E_r at (i+1/2, j, k)
+    if (k > 0) {
+        float2 t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
+        float2 t2 = c_scale(c_sub(hp, hp_km), a.inv_dz);
+        if (ir >= 0)
+            t1 = div_stretch2(t1, pco(x.sR + AUX_ER_T * slabR, o), pto(x.dR + AUX_ER_T * slabR, o), true,
+                              rc.g1_t_half, rc.g2_t_half, a.cr, dt);
+        if (kz >= 0)
+            t2 = div_stretch2(t2, pco(x.sZ + ZAUX_ER * slabZ, o), pto(x.dZ + ZAUX_ER * slabZ, o), true, zc.g1_int,
+                              zc.g2_int, a.cz, dt);
+        er = make_float2(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
+    }
+    // E_phi at (i, j+1/2, k)
+    u = zero2();
+    if (k > 0 && i > 0) {
+        float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
+        float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
+        if (kz >= 0)
+            t1 = div_stretch2(t1, pco(x.sZ + ZAUX_EP * slabZ, o), pto(x.dZ + ZAUX_EP * slabZ, o), true, zc.g1_int,
+                              zc.g2_int, a.cz, dt);
+        if (ir >= 0)
+            t2 = div_stretch2(t2, pco(x.sR + AUX_EP_S * slabR, o), pto(x.dR + AUX_EP_S * slabR, o), true,
+                              rc.g1_s_int, rc.g2_s_int, a.cr, dt);
+        ep = make_float2(ep.x + ce * (t1.x - t2.x - jph.x), ep.y + ce * (t1.y - t2.y - jph.y));
+    }
+    // U = F E_phi advances on every r-layer cell (also where E_phi is held)
+    if (ir >= 0) {
+        const float2 uo = ldo(x.sR + AUX_U_EP * slabR, o);
+        u = make_float2(a.cr * uo.x + dt * ep.x, a.cr * uo.y + dt * ep.y);
+        *pto(x.dR + AUX_U_EP * slabR, o) = u;
+    }
+    // E_z at (i, j, k+1/2)
+    if (i > 0) {
+        float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
+        if (ir >= 0) {
+            t = c_add(t, c_sub(c_scale(v, rc.ez_c1), c_scale(v_im, rc.ez_c0)));
+            t = div_stretch2(t, pco(x.sR + AUX_EZ_S * slabR, o), pto(x.dR + AUX_EZ_S * slabR, o), true,
+                             rc.g1_s_int, rc.g2_s_int, a.cr, dt);
+        }
+        t = c_sub(t, c_scale(c_sub(hr, hr_jm), rc.inv_rdphi_int));
+        if (ir >= 0)
+            t = div_stretch2(t, pco(x.sR + AUX_EZ_T * slabR, o), pto(x.dR + AUX_EZ_T * slabR, o), true,
+                             rc.g1_t_int, rc.g2_t_int, a.cr, dt);
+        ez = make_float2(ez.x + ce * t.x, ez.y + ce * t.y);
+    }
+}
+
+// Source current of the sheet at plane k_src for step n at one cell.
+__device__ __forceinline__ void sheet_current(const StepArgs &a, int n, size_t plane, size_t rowc, unsigned o,
+                                              float2 &jr, float2 &jph)
+{
+    jr = zero2();
+    jph = zero2();
+    for (int q = 0; q < a.n_prof; ++q) {
+        const float2 g = a.profile[(size_t)n * a.n_prof + q];
+        const float2 *pat = a.pattern + (size_t)q * 2 * plane + rowc;
+        jr = c_fma(jr, ldo(pat, o), g);
+        jph = c_fma(jph, ldo(pat + plane, o), g);
+    }
+}
+
 // One whole leap-frog step (H half-step, then E half-step with source and
 // DFT) per launch, reading fields and auxiliaries from one buffer set and
 // writing the next time level to the other, so no block ever reads a value
@@ -328,7 +469,6 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
     const size_t dip = ip_ok ? (size_t)nphi : 0;
     const size_t slabR = (size_t)nz * a.dR * nphi;
     const size_t slabZ = (size_t)a.dZ * plane;
-    const float dt = a.dt;
     const int nd = a.k1 - a.k0;
 
     float2 er = ldo(a.Er + (size_t)kstart * plane + rowc, o);
@@ -344,8 +484,7 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
         if (kz >= 0) zc = a.zrows[k];
         const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
         const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
-        const float2 *aR = a.auxR + sr0, *aZ = a.auxZ + sz0;
-        float2 *oR = a.oauxR + sr0, *oZ = a.oauxZ + sz0;
+        const AuxRows x = {a.auxR + sr0, a.auxZ + sz0, a.oauxR + sr0, a.oauxZ + sz0};
         const float2 ez = ldo(a.Ez + c0, o);
         float2 er_kp = ldo(a.Er + c0 + dkp, o), ep_kp = ldo(a.Ep + c0 + dkp, o);
         float2 ez_jp = ldo(a.Ez + c0, ojp), er_jp = ldo(a.Er + c0, ojp);
@@ -356,52 +495,13 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
         if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
         if (wrap) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
         {
-            // H_r at (i, j+1/2, k+1/2)
-            if (i > 0) {
-                float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
-                float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
-                if (ir >= 0)
-                    t1 = div_stretch2(t1, pco(aR + AUX_HR_T * slabR, o), pto(oR + AUX_HR_T * slabR, o), store,
-                                      rc.g1_t_int, rc.g2_t_int, a.cr, dt);
-                if (kz >= 0)
-                    t2 = div_stretch2(t2, pco(aZ + ZAUX_HR * slabZ, o), pto(oZ + ZAUX_HR * slabZ, o), store,
-                                      zc.g1_half, zc.g2_half, a.cz, dt);
-                hr = make_float2(hr.x - dt * (t1.x - t2.x), hr.y - dt * (t1.y - t2.y));
+            float2 u0 = zero2(), u1 = zero2();
+            if (ir >= 0 && k > 0) {
+                u0 = ldo(x.sR + AUX_U_EP * slabR, o);
+                if (ir1 >= 0) u1 = ldo(a.auxR + AUX_U_EP * slabR + ((size_t)k * a.dR + ir1) * nphi, o);
             }
-            // H_phi at (i+1/2, j, k+1/2)
-            {
-                float2 t1 = c_scale(c_sub(er_kp, er), a.inv_dz);
-                float2 t2 = c_scale(c_sub(ez_ip, ez), a.inv_dr);
-                if (kz >= 0)
-                    t1 = div_stretch2(t1, pco(aZ + ZAUX_HP * slabZ, o), pto(oZ + ZAUX_HP * slabZ, o), store,
-                                      zc.g1_half, zc.g2_half, a.cz, dt);
-                if (ir >= 0)
-                    t2 = div_stretch2(t2, pco(aR + AUX_HP_S * slabR, o), pto(oR + AUX_HP_S * slabR, o), store,
-                                      rc.g1_s_half, rc.g2_s_half, a.cr, dt);
-                hp = make_float2(hp.x - dt * (t1.x - t2.x), hp.y - dt * (t1.y - t2.y));
-                if (ir >= 0) {
-                    const float2 vo = ldo(aR + AUX_V_HP * slabR, o);
-                    v = make_float2(a.cr * vo.x + dt * hp.x, a.cr * vo.y + dt * hp.y);
-                    if (store) *pto(oR + AUX_V_HP * slabR, o) = v;
-                }
-            }
-            // H_z at (i+1/2, j+1/2, k)
-            if (k > 0) {
-                float2 t = c_add(c_scale(c_sub(ep_ip, ep), a.inv_dr), c_scale(c_add(ep_ip, ep), rc.inv_2r_half));
-                if (ir >= 0) {
-                    const float2 u0 = ldo(aR + AUX_U_EP * slabR, o);
-                    const float2 u1 =
-                        ir1 >= 0 ? ldo(a.auxR + AUX_U_EP * slabR + ((size_t)k * a.dR + ir1) * nphi, o) : zero2();
-                    t = c_add(t, c_sub(c_scale(u1, rc.hz_c1), c_scale(u0, rc.hz_c0)));
-                    t = div_stretch2(t, pco(aR + AUX_HZ_S * slabR, o), pto(oR + AUX_HZ_S * slabR, o), store,
-                                     rc.g1_s_half, rc.g2_s_half, a.cr, dt);
-                }
-                t = c_sub(t, c_scale(c_sub(er_jp, er), rc.inv_rdphi_half));
-                if (ir >= 0)
-                    t = div_stretch2(t, pco(aR + AUX_HZ_T * slabR, o), pto(oR + AUX_HZ_T * slabR, o), store,
-                                     rc.g1_t_half, rc.g2_t_half, a.cr, dt);
-                hz = make_float2(hz.x - dt * t.x, hz.y - dt * t.y);
-            }
+            h_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x, o, store, ez, er, ep, ez_jp, er_jp, er_kp, ep_kp, ez_ip,
+                   ep_ip, u0, u1, hr, hp, hz, v);
             if (store) {
                 store_out(pto(a.oHr + c0, o), hr, nt);
                 store_out(pto(a.oHp + c0, o), hp, nt);
@@ -428,57 +528,10 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
             const float2 v_im = sV[buf][ww - 1][lane];
             const float ce = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a.ceps + c0) + oc);
             float2 jr = zero2(), jph = zero2();
-            if (k == a.k_src) {
-                for (int q = 0; q < a.n_prof; ++q) {
-                    const float2 g = a.profile[(size_t)n * a.n_prof + q];
-                    const float2 *pat = a.pattern + (size_t)q * 2 * plane + rowc;
-                    jr = c_fma(jr, ldo(pat, o), g);
-                    jph = c_fma(jph, ldo(pat + plane, o), g);
-                }
-            }
-            float2 er_n = er, ep_n = ep, ez_n = ez;
-            // E_r at (i+1/2, j, k)
-            if (k > 0) {
-                float2 t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
-                float2 t2 = c_scale(c_sub(hp, hp_km), a.inv_dz);
-                if (ir >= 0)
-                    t1 = div_stretch2(t1, pco(aR + AUX_ER_T * slabR, o), pto(oR + AUX_ER_T * slabR, o), true,
-                                      rc.g1_t_half, rc.g2_t_half, a.cr, dt);
-                if (kz >= 0)
-                    t2 = div_stretch2(t2, pco(aZ + ZAUX_ER * slabZ, o), pto(oZ + ZAUX_ER * slabZ, o), true,
-                                      zc.g1_int, zc.g2_int, a.cz, dt);
-                er_n = make_float2(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
-            }
-            // E_phi at (i, j+1/2, k)
-            if (k > 0 && i > 0) {
-                float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
-                float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
-                if (kz >= 0)
-                    t1 = div_stretch2(t1, pco(aZ + ZAUX_EP * slabZ, o), pto(oZ + ZAUX_EP * slabZ, o), true,
-                                      zc.g1_int, zc.g2_int, a.cz, dt);
-                if (ir >= 0)
-                    t2 = div_stretch2(t2, pco(aR + AUX_EP_S * slabR, o), pto(oR + AUX_EP_S * slabR, o), true,
-                                      rc.g1_s_int, rc.g2_s_int, a.cr, dt);
-                ep_n = make_float2(ep.x + ce * (t1.x - t2.x - jph.x), ep.y + ce * (t1.y - t2.y - jph.y));
-                if (ir >= 0) {
-                    const float2 uo = ldo(aR + AUX_U_EP * slabR, o);
-                    *pto(oR + AUX_U_EP * slabR, o) = make_float2(a.cr * uo.x + dt * ep_n.x, a.cr * uo.y + dt * ep_n.y);
-                }
-            }
-            // E_z at (i, j, k+1/2)
-            if (i > 0) {
-                float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
-                if (ir >= 0) {
-                    t = c_add(t, c_sub(c_scale(v, rc.ez_c1), c_scale(v_im, rc.ez_c0)));
-                    t = div_stretch2(t, pco(aR + AUX_EZ_S * slabR, o), pto(oR + AUX_EZ_S * slabR, o), true,
-                                     rc.g1_s_int, rc.g2_s_int, a.cr, dt);
-                }
-                t = c_sub(t, c_scale(c_sub(hr, hr_jm), rc.inv_rdphi_int));
-                if (ir >= 0)
-                    t = div_stretch2(t, pco(aR + AUX_EZ_T * slabR, o), pto(oR + AUX_EZ_T * slabR, o), true,
-                                     rc.g1_t_int, rc.g2_t_int, a.cr, dt);
-                ez_n = make_float2(ez.x + ce * t.x, ez.y + ce * t.y);
-            }
+            if (k == a.k_src) sheet_current(a, n, plane, rowc, o, jr, jph);
+            float2 er_n = er, ep_n = ep, ez_n = ez, u;
+            e_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x, o, ce, jr, jph, hr, hr_jm, hr_km, hp, hp_im, hp_km, hz,
+                   hz_jm, hz_im, v, v_im, er_n, ep_n, ez_n, u);
             store_out(pto(a.oEr + c0, o), er_n, nt);
             store_out(pto(a.oEp + c0, o), ep_n, nt);
             store_out(pto(a.oEz + c0, o), ez_n, nt);
@@ -507,6 +560,217 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
         hp_km = hp;
         er = er_kp;
         ep = ep_kp;
+    }
+}
+
+// Two whole leap-frog steps (n and n + 1) per launch.  The launch reads the
+// fields and auxiliaries at time level n from one buffer set and writes level
+// n + 2 to the other, so each cell's six fields cross HBM once per two steps.
+// Block = (TR + 3) wavefronts x 64 lanes marching a z-chunk: wave w sits on
+// row i0 - 2 + w and lane l on phi cell j0 - 2 + l (j0 = 61 x tile column),
+// taken modulo nphi (physical cells; the Bloch seam factor is applied where a
+// neighbour value crosses from column nphi - 1 to 0).  Step one runs on every
+// lane and wave; its H^{n+1/2} reaches the E half-step through LDS.  Step two
+// lags one plane behind and needs E^{n+1} of the +phi, +r neighbours
+// (double-buffered LDS) and H^{n+3/2} of the -phi, -r neighbours (LDS); it
+// is exact on lanes 2..62 and waves 2..TR+1, which own their cells.  A chunk
+// starts two planes early and runs step one one plane past its end.  Every
+// block computes halo cells with the same inputs and the same arithmetic as
+// their owner, so the level-(n+1) auxiliaries that step one writes to the
+// intermediate set are identical whichever block writes them.
+template <int TR, bool PML>
+__device__ __forceinline__ void eh2_body(const StepArgs &a, int n, unsigned tile, unsigned gx, unsigned gy)
+{
+    constexpr int NW = TR + 3;
+    constexpr int NV = PML ? NW : 1;
+    __shared__ float2 s1z[NW][64], s1r[NW][64], s1p[NW][64], s1v[NV][64];
+    __shared__ float2 sEz[2][NW][64], sEr[2][NW][64], sEp[2][NW][64], sU[2][NV][64];
+    __shared__ float2 s2z[NW][64], s2r[NW][64], s2p[NW][64], s2v[NV][64];
+    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int nphi = a.nphi, nr = a.nr, nz = a.nz;
+    const size_t plane = (size_t)nr * nphi;
+    const int bx = (int)(tile % gx), by = (int)((tile / gx) % gy), bz = (int)(tile / (gx * gy));
+    const int i = by * TR + w - 2;
+    const bool row_ok = i >= 0 && i < nr;
+    const int jj = bx * TWO_STEP_COLS - 2 + lane;
+    const int pc = (jj + nphi) % nphi;                      // physical column
+    const bool cross_m = pc == 0;                           // lane - 1 holds column nphi - 1
+    const bool cross_p = pc == nphi - 1;                    // lane + 1 holds column 0
+    const bool own = lane >= 2 && lane <= 62 && jj < nphi && w >= 2 && w <= TR + 1 && row_ok;
+    const int kb = bz * a.kchunk;
+    const int ke = min(kb + a.kchunk, nz);
+    const int k_lo = max(kb - 2, 0);
+    const bool nt = a.nt_stores;
+    const int ir = (PML && row_ok) ? slab_row(i, nr, a.pr0, a.pr1) : -1;
+    const int ir1 = (PML && row_ok && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
+    const RowCoef rc = a.rows[row_ok ? i : 0];
+    const int ic = min(max(i, 0), nr - 1);
+    const unsigned o = (unsigned)pc * 8u;
+    const unsigned ojp = cross_p ? 0u : o + 8u;
+    const unsigned oc = (unsigned)pc * 4u;
+    const size_t rowc = (size_t)ic * nphi;
+    const bool ip_ok = ic + 1 < nr;
+    const size_t dip = ip_ok ? (size_t)nphi : 0;
+    const size_t slabR = (size_t)nz * a.dR * nphi;
+    const size_t slabZ = (size_t)a.dZ * plane;
+    const int nd = a.k1 - a.k0;
+
+    // carried along z: E^n at k; H^{n+1/2}, E^{n+1}, U^{n+1}, dt/eps at k - 1;
+    // H^{n+3/2} at k - 2
+    float2 er0 = ldo(a.Er + (size_t)k_lo * plane + rowc, o);
+    float2 ep0 = ldo(a.Ep + (size_t)k_lo * plane + rowc, o);
+    float2 h1r_p = zero2(), h1p_p = zero2(), h1z_p = zero2();
+    float2 e1r_p = zero2(), e1p_p = zero2(), e1z_p = zero2(), u1_p = zero2();
+    float2 h2r_km = zero2(), h2p_km = zero2();
+    float ce_p = 0.f;
+    for (int k = k_lo; k <= ke; ++k) {
+        const int km = k - 1;
+        float2 h1r = zero2(), h1p = zero2(), h1z = zero2(), v1 = zero2();
+        float2 e1r = zero2(), e1p = zero2(), e1z = zero2(), u1 = zero2();
+        float2 er_kp = zero2(), ep_kp = zero2();
+        float ce = 0.f;
+        const bool step1 = k < nz;
+        // ---- step one, H^{n+1/2} at plane k (every lane and wave)
+        int kz = -1;
+        ZCoef zc = {};
+        AuxRows x1 = {};
+        const size_t c0 = (size_t)min(k, nz - 1) * plane + rowc;
+        float2 ez0 = zero2();
+        if (step1) {
+            kz = PML ? slab_row(k, nz, a.pz0, a.pz1) : -1;
+            if (kz >= 0) zc = a.zrows[k];
+            const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
+            const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
+            x1 = {a.auxR + sr0, a.auxZ + sz0, a.mauxR + sr0, a.mauxZ + sz0};
+            const bool kp_ok = k + 1 < nz;
+            const size_t dkp = kp_ok ? plane : 0;
+            ez0 = ldo(a.Ez + c0, o);
+            er_kp = ldo(a.Er + c0 + dkp, o);
+            ep_kp = ldo(a.Ep + c0 + dkp, o);
+            float2 ez_jp = ldo(a.Ez + c0, ojp), er_jp = ldo(a.Er + c0, ojp);
+            float2 ez_ip = ldo(a.Ez + c0 + dip, o), ep_ip = ldo(a.Ep + c0 + dip, o);
+            h1r = ldo(a.Hr + c0, o);
+            h1p = ldo(a.Hp + c0, o);
+            h1z = ldo(a.Hz + c0, o);
+            ce = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a.ceps + c0) + oc);
+            if (!kp_ok) { er_kp = zero2(); ep_kp = zero2(); }
+            if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+            if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+            float2 u0 = zero2(), uu1 = zero2();
+            if (ir >= 0 && k > 0) {
+                u0 = ldo(x1.sR + AUX_U_EP * slabR, o);
+                if (ir1 >= 0) uu1 = ldo(a.auxR + AUX_U_EP * slabR + ((size_t)k * a.dR + ir1) * nphi, o);
+            }
+            h_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x1, o, row_ok, ez0, er0, ep0, ez_jp, er_jp, er_kp, ep_kp,
+                   ez_ip, ep_ip, u0, uu1, h1r, h1p, h1z, v1);
+            s1z[w][lane] = h1z;
+            s1r[w][lane] = h1r;
+            s1p[w][lane] = h1p;
+            if (PML) s1v[w][lane] = v1;
+        }
+        __syncthreads();
+        // ---- step one, E^{n+1} at plane k (exact on lanes >= 1, waves >= 1)
+        if (step1 && (k != k_lo || k == 0) && w >= 1 && row_ok) {
+            if (lane >= 1) {
+                float2 hz_jm = s1z[w][lane - 1], hr_jm = s1r[w][lane - 1];
+                if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+                const float2 hz_im = s1z[w - 1][lane], hp_im = s1p[w - 1][lane];
+                const float2 v_im = PML ? s1v[PML ? w - 1 : 0][lane] : zero2();
+                float2 jr = zero2(), jph = zero2();
+                if (k == a.k_src) sheet_current(a, n, plane, rowc, o, jr, jph);
+                e1r = er0;
+                e1p = ep0;
+                e1z = ez0;
+                e_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x1, o, ce, jr, jph, h1r, hr_jm, h1r_p, h1p, hp_im,
+                       h1p_p, h1z, hz_jm, hz_im, v1, v_im, e1r, e1p, e1z, u1);
+            }
+            sEz[k & 1][w][lane] = e1z;
+            sEr[k & 1][w][lane] = e1r;
+            sEp[k & 1][w][lane] = e1p;
+            if (PML) sU[k & 1][PML ? w : 0][lane] = u1;
+        }
+        // ---- step two, H^{n+3/2} at plane km (exact on lanes 1..62, waves 1..TR+1)
+        float2 h2r = zero2(), h2p = zero2(), h2z = zero2(), v2 = zero2();
+        const bool h2_plane = km >= 0 && (km > k_lo || km == 0);
+        const int kz2 = (PML && km >= 0) ? slab_row(km, nz, a.pz0, a.pz1) : -1;
+        ZCoef zc2 = {};
+        if (kz2 >= 0) zc2 = a.zrows[km];
+        const size_t c0m = (size_t)max(km, 0) * plane + rowc;
+        const size_t sr2 = ir >= 0 ? ((size_t)max(km, 0) * a.dR + ir) * nphi : 0;
+        const size_t sz2 = kz2 >= 0 ? ((size_t)kz2 * nr + ic) * nphi : 0;
+        const AuxRows x2 = {a.mauxR + sr2, a.mauxZ + sz2, a.oauxR + sr2, a.oauxZ + sz2};
+        const bool store = own && km >= kb && km < ke;
+        if (h2_plane && w >= 1 && w <= TR + 1 && row_ok && lane >= 1 && lane <= 62) {
+            const int b = km & 1;
+            float2 ez_jp = sEz[b][w][lane + 1], er_jp = sEr[b][w][lane + 1];
+            if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+            float2 ez_ip = sEz[b][w + 1][lane], ep_ip = sEp[b][w + 1][lane];
+            if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+            float2 uu1 = zero2();
+            if (PML && ir1 >= 0) uu1 = sU[b][PML ? w + 1 : 0][lane];
+            h2r = h1r_p;
+            h2p = h1p_p;
+            h2z = h1z_p;
+            // E^{n+1} at km + 1 is the plane step one just finished (zero above the top)
+            h_cell(a, rc, zc2, i, km, ir, kz2, slabR, slabZ, x2, o, store, e1z_p, e1r_p, e1p_p, ez_jp, er_jp, e1r,
+                   e1p, ez_ip, ep_ip, (ir >= 0 && km > 0) ? u1_p : zero2(), uu1, h2r, h2p, h2z, v2);
+        }
+        s2z[w][lane] = h2z;
+        s2r[w][lane] = h2r;
+        s2p[w][lane] = h2p;
+        if (PML) s2v[w][lane] = v2;
+        __syncthreads();
+        // ---- step two, E^{n+2} at plane km (owners), stores and DFT
+        if (store) {
+            float2 hz_jm = s2z[w][lane - 1], hr_jm = s2r[w][lane - 1];
+            if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+            const float2 hz_im = s2z[w - 1][lane], hp_im = s2p[w - 1][lane];
+            const float2 v_im = PML ? s2v[PML ? w - 1 : 0][lane] : zero2();
+            float2 jr = zero2(), jph = zero2();
+            if (km == a.k_src) sheet_current(a, n + 1, plane, rowc, o, jr, jph);
+            float2 er2 = e1r_p, ep2 = e1p_p, ez2 = e1z_p, u2;
+            e_cell(a, rc, zc2, i, km, ir, kz2, slabR, slabZ, x2, o, ce_p, jr, jph, h2r, hr_jm, h2r_km, h2p, hp_im,
+                   h2p_km, h2z, hz_jm, hz_im, v2, v_im, er2, ep2, ez2, u2);
+            store_out(pto(a.oHr + c0m, o), h2r, nt);
+            store_out(pto(a.oHp + c0m, o), h2p, nt);
+            store_out(pto(a.oHz + c0m, o), h2z, nt);
+            store_out(pto(a.oEr + c0m, o), er2, nt);
+            store_out(pto(a.oEp + c0m, o), ep2, nt);
+            store_out(pto(a.oEz + c0m, o), ez2, nt);
+            if (a.dft_plane && km == a.k_mon) {
+                for (int f = 0; f < a.K; ++f) {
+                    const float2 tw0 = a.twiddle[(size_t)n * a.K + f], tw1 = a.twiddle[(size_t)(n + 1) * a.K + f];
+                    float2 *q0 = pto(a.dft_plane + (size_t)f * 2 * plane + rowc, o);
+                    float2 *q1 = pto(a.dft_plane + (size_t)f * 2 * plane + plane + rowc, o);
+                    *q0 = c_fma(c_fma(*q0, tw0, e1r_p), tw1, er2);
+                    *q1 = c_fma(c_fma(*q1, tw0, e1p_p), tw1, ep2);
+                }
+            }
+            if (a.dft_vol && km >= a.k0 && km < a.k1) {
+                const size_t vs = (size_t)nd * plane;
+                for (int f = 0; f < a.K; ++f) {
+                    const float2 tw0 = a.twiddle[(size_t)n * a.K + f], tw1 = a.twiddle[(size_t)(n + 1) * a.K + f];
+                    float2 *base = a.dft_vol + (size_t)f * 3 * vs + (size_t)(km - a.k0) * plane + rowc;
+                    float2 *q0 = pto(base, o), *q1 = pto(base + vs, o), *q2 = pto(base + 2 * vs, o);
+                    *q0 = c_fma(c_fma(*q0, tw0, e1r_p), tw1, er2);
+                    *q1 = c_fma(c_fma(*q1, tw0, e1p_p), tw1, ep2);
+                    *q2 = c_fma(c_fma(*q2, tw0, e1z_p), tw1, ez2);
+                }
+            }
+        }
+        er0 = er_kp;
+        ep0 = ep_kp;
+        h1r_p = h1r;
+        h1p_p = h1p;
+        h1z_p = h1z;
+        e1r_p = e1r;
+        e1p_p = e1p;
+        e1z_p = e1z;
+        u1_p = u1;
+        ce_p = ce;
+        h2r_km = h2r;
+        h2p_km = h2p;
     }
 }
 
@@ -539,6 +803,12 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int
     const unsigned nblk = gx * gy * gridDim.z;
     const unsigned p = xcd_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), nblk, a.xcd_remap);
     eh_fused_body<TR>(a, n, p, gx, gy);
+}
+
+template <int TR, bool PML>
+__global__ __launch_bounds__(64 * (TR + 3)) void eh2_kernel(StepArgs a, int n, unsigned gx, unsigned gy)
+{
+    eh2_body<TR, PML>(a, n, a.tiles[blockIdx.x], gx, gy);
 }
 
 // Batched launches: one 1-D grid covers the tiles of many zones of uneven
@@ -717,6 +987,32 @@ void launch_fused_step(const StepArgs &a, int n, hipStream_t s)
 }
 
 void launch_e_step(const StepArgs &a, int n, hipStream_t s) { launch_step(a, n, s, false); }
+
+void two_step_grid(const StepArgs &a, int TR, unsigned &gx, unsigned &gy, unsigned &gz)
+{
+    gx = (unsigned)((a.nphi + TWO_STEP_COLS - 1) / TWO_STEP_COLS);
+    gy = (unsigned)((a.nr + TR - 1) / TR);
+    gz = (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
+}
+
+template <int TR>
+void launch_two_tr(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s)
+{
+    unsigned gx, gy, gz;
+    two_step_grid(a, TR, gx, gy, gz);
+    dim3 block(64, TR + 3, 1);
+    if (pml) hipLaunchKernelGGL((eh2_kernel<TR, true>), dim3(ntiles), block, 0, s, a, n, gx, gy);
+    else hipLaunchKernelGGL((eh2_kernel<TR, false>), dim3(ntiles), block, 0, s, a, n, gx, gy);
+}
+
+void launch_two_step(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s)
+{
+    if (ntiles == 0) return;
+    if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, pml, s);
+    else launch_two_tr<5>(a, n, ntiles, pml, s);
+}
+
+
 
 unsigned tiles_split(const StepArgs &a, int BY)
 {

@@ -83,7 +83,17 @@ struct zda_zone {
     float2 *auxR[2] = {nullptr, nullptr}, *auxZ[2] = {nullptr, nullptr};
     int cur = 0;
     bool fused = true;
+    bool two = false;              // two leap-frog steps per launch (tile_rows 5 or 13)
     int xcd_remap = 0, nt_stores = 1;
+    // two-step launches: auxiliaries at the intermediate time level, and the
+    // tile lists (interior tiles without layer cells first, then layer tiles)
+    float2 *mauxR = nullptr, *mauxZ = nullptr;
+    unsigned *tiles2 = nullptr;
+    size_t cap_tiles2 = 0;
+    bool has_m = false;
+    unsigned n_int = 0, n_pml = 0;
+    int tiles_tr = 0, tiles_kc = 0, tiles_src = -1, k_src_last = -1;
+    size_t int_cells = 0, int_mon_cells = 0, int_src_cells = 0;
     RowCoef *rows = nullptr;
     ZCoef *zrows = nullptr;
     float2 *dft_plane = nullptr, *dft_vol = nullptr, *dft_vol_adj = nullptr;
@@ -105,6 +115,7 @@ struct zda_zone {
     std::vector<hipEvent_t> ev;
     int timed_steps = 0;
     bool timed_fused = false;
+    bool timed_two = false;
 };
 
 namespace {
@@ -140,7 +151,8 @@ void free_all(zda_zone *z)
     for (auto &set : z->F)
         for (auto &f : set) if (f) (void)hipFree(f);
     void *ptrs[] = {z->ceps, z->auxR[0], z->auxZ[0], z->auxR[1], z->auxZ[1], z->rows, z->zrows, z->dft_plane,
-                    z->dft_vol, z->dft_vol_adj, z->pattern, z->profile, z->twiddle, z->scratch, z->flag};
+                    z->dft_vol, z->dft_vol_adj, z->pattern, z->profile, z->twiddle, z->scratch, z->flag,
+                    z->mauxR, z->mauxZ, z->tiles2};
     for (void *p : ptrs) if (p) (void)hipFree(p);
 }
 
@@ -245,6 +257,7 @@ StepArgs step_args(zda_zone *z, int m)
     a.ceps = z->ceps;
     a.auxR = z->auxR[s0]; a.auxZ = z->auxZ[s0];
     a.oauxR = z->auxR[s1]; a.oauxZ = z->auxZ[s1];
+    a.mauxR = z->mauxR; a.mauxZ = z->mauxZ;
     a.rows = z->rows; a.zrows = z->zrows;
     a.k_mon = d.k_mon;
     a.k0 = d.design_k0; a.k1 = d.design_k1;
@@ -262,6 +275,8 @@ zda_status reset_state(zda_zone *z, hipStream_t s)
         if (z->auxR[b]) launch_fill(z->auxR[b], (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, s);
         if (z->auxZ[b]) launch_fill(z->auxZ[b], (size_t)N_AUX_Z * z->dZ * z->plane, s);
     }
+    if (z->mauxR) launch_fill(z->mauxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, s);
+    if (z->mauxZ) launch_fill(z->mauxZ, (size_t)N_AUX_Z * z->dZ * z->plane, s);
     z->cur = 0;
     HIP_TRY(hipGetLastError());
     z->n_done = 0;
@@ -328,6 +343,58 @@ zda_status prepare_run(zda_zone *z, int m, int nsteps, int k_src, int P, const c
     return ZDA_OK;
 }
 
+// Tile lists of the two-step kernel for the zone's launch shape: interior
+// tiles, whose rows i0-2 .. i0+TR and planes kb-2 .. ke (clipped to the zone)
+// hold no layer cell, run the instantiation without the layer recursions;
+// the others run the full one.
+zda_status build_two_step_tiles(zda_zone *z, const StepArgs &a)
+{
+    const int TR = z->tile_rows, kc = z->kchunk;
+    if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last) return ZDA_OK;
+    unsigned gx, gy, gz;
+    two_step_grid(a, TR, gx, gy, gz);
+    const zda_zone_desc &d = z->d;
+    std::vector<unsigned> in, lay;
+    size_t cells = 0, mon = 0, src = 0;
+    for (unsigned bz = 0; bz < gz; ++bz) {
+        const int kb = (int)bz * kc, ke = std::min(kb + kc, d.nz);
+        const int klo = std::max(kb - 2, 0), khi = std::min(ke, d.nz - 1);
+        const bool zin = klo >= d.pml_z_lo && khi < d.nz - d.pml_z_hi;
+        for (unsigned by = 0; by < gy; ++by) {
+            const int i0 = (int)by * TR;
+            const int ilo = std::max(i0 - 2, 0), ihi = std::min(i0 + TR, d.nr - 1);
+            const bool rin = ilo >= d.pml_r_in && ihi < d.nr - d.pml_r_out;
+            const size_t rows = (size_t)(std::min(i0 + TR, d.nr) - i0);
+            for (unsigned bx = 0; bx < gx; ++bx) {
+                const unsigned t = bx + gx * (by + gy * bz);
+                if (zin && rin) {
+                    in.push_back(t);
+                    const int j0 = (int)bx * TWO_STEP_COLS;
+                    const size_t cols = (size_t)(std::min(j0 + TWO_STEP_COLS, d.nphi) - j0);
+                    cells += rows * cols * (size_t)(ke - kb);
+                    if (d.k_mon >= kb && d.k_mon < ke) mon += rows * cols;
+                    if (z->k_src_last >= kb && z->k_src_last < ke) src += rows * cols;
+                } else {
+                    lay.push_back(t);
+                }
+            }
+        }
+    }
+    in.insert(in.end(), lay.begin(), lay.end());
+    zda_status st = ensure(z, &z->tiles2, &z->cap_tiles2, in.size());
+    if (st != ZDA_OK) return st;
+    HIP_TRY(hipMemcpy(z->tiles2, in.data(), in.size() * sizeof(unsigned), hipMemcpyHostToDevice));
+    z->n_int = (unsigned)(in.size() - lay.size());
+    z->n_pml = (unsigned)lay.size();
+    z->int_cells = cells;
+    z->int_mon_cells = mon;
+    z->int_src_cells = src;
+    z->tiles_src = z->k_src_last;
+    z->tiles_tr = TR;
+    z->tiles_kc = kc;
+    return ZDA_OK;
+}
+
 zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *prof, const double *omega, int K,
                     float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, bool timing = false)
 {
@@ -336,15 +403,36 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     if (st != ZDA_OK) return st;
     const int ab_base = z->cur;
     const StepArgs &a = ab[0];
-    const bool fused = z->fused;
-    auto step = [&](int n) {
-        if (fused) {
-            launch_fused_step(ab[z->cur ^ ab_base], n, s);
+    const bool fused = z->fused, two = z->two;
+    z->k_src_last = k_src;
+    if (two && (st = build_two_step_tiles(z, a)) != ZDA_OK) return st;
+    // one step of the one-launch kernel (the fused step, or an odd last step
+    // of a two-step run)
+    auto one_step = [&](int n) {
+        if (fused || two) {
+            StepArgs b = ab[z->cur ^ ab_base];
+            if (two) b.tile_rows = 3;
+            launch_fused_step(b, n, s);
             z->cur ^= 1;
         } else {
             launch_h_step(a, n, s);
             launch_e_step(a, n, s);
         }
+    };
+    // steps n and n + 1 by the two-step kernel; ev (if given) brackets the
+    // interior-tile and the layer-tile launches
+    auto two_steps = [&](int n, hipEvent_t *ev) -> zda_status {
+        StepArgs b = ab[z->cur ^ ab_base];
+        b.tiles = z->tiles2;
+        if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+        launch_two_step(b, n, z->n_int, false, s);
+        if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+        if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+        b.tiles = z->tiles2 + z->n_int;
+        launch_two_step(b, n, z->n_pml, true, s);
+        if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+        z->cur ^= 1;
+        return ZDA_OK;
     };
     z->timed_steps = 0;
     if (timing) {
@@ -354,24 +442,38 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
             HIP_TRY(hipEventCreate(&e));
             z->ev.push_back(e);
         }
-        for (int n = 0; n < nsteps; ++n) {
-            if (fused) {
-                HIP_TRY(hipEventRecord(z->ev[4 * n + 2], s));
-                step(n);
-                HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
-            } else {
-                HIP_TRY(hipEventRecord(z->ev[4 * n], s));
-                launch_h_step(a, n, s);
-                HIP_TRY(hipEventRecord(z->ev[4 * n + 1], s));
-                HIP_TRY(hipEventRecord(z->ev[4 * n + 2], s));
-                launch_e_step(a, n, s);
-                HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
+        int groups = 0;
+        if (two) {
+            int n = 0;
+            for (; n + 1 < nsteps; n += 2, ++groups)
+                if ((st = two_steps(n, &z->ev[4 * (size_t)groups])) != ZDA_OK) return st;
+            if (n < nsteps) one_step(n);
+        } else {
+            for (int n = 0; n < nsteps; ++n, ++groups) {
+                if (fused) {
+                    HIP_TRY(hipEventRecord(z->ev[4 * n + 2], s));
+                    one_step(n);
+                    HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
+                } else {
+                    HIP_TRY(hipEventRecord(z->ev[4 * n], s));
+                    launch_h_step(a, n, s);
+                    HIP_TRY(hipEventRecord(z->ev[4 * n + 1], s));
+                    HIP_TRY(hipEventRecord(z->ev[4 * n + 2], s));
+                    launch_e_step(a, n, s);
+                    HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
+                }
             }
         }
-        z->timed_steps = nsteps;
-        z->timed_fused = fused;
+        z->timed_steps = groups;
+        z->timed_fused = fused || two;
+        z->timed_two = two;
+    } else if (two) {
+        int n = 0;
+        for (; n + 1 < nsteps; n += 2)
+            if ((st = two_steps(n, nullptr)) != ZDA_OK) return st;
+        if (n < nsteps) one_step(n);
     } else {
-        for (int n = 0; n < nsteps; ++n) step(n);
+        for (int n = 0; n < nsteps; ++n) one_step(n);
     }
     HIP_TRY(hipGetLastError());
     z->n_done += nsteps;
@@ -666,9 +768,11 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     z->dR = d->pml_r_in + d->pml_r_out;
     z->dZ = d->pml_z_lo + d->pml_z_hi;
     z->nd = d->design_k1 - d->design_k0;
-    // default launch shape (measured on the 512 x 1024 x 400 zone): fused
-    // step, 3 owned rows per block, 12-plane z-chunks; shorter chunks (down to
-    // 4 planes) while the grid has fewer than 2048 blocks
+    // default launch shape of the fused step (measured on the 512 x 1024 x
+    // 400 zone): 3 owned rows per block, 12-plane z-chunks; shorter chunks
+    // (down to 4 planes) while the grid has fewer than 2048 blocks.  Zones
+    // with room for the intermediate auxiliaries switch to the two-step
+    // kernel below.
     {
         z->tile_rows = 3;
         const long tiles = (long)((d->nphi + 62) / 63) * ((d->nr + 2) / 3);
@@ -697,10 +801,42 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
         if (s1 == ZDA_OK) s1 = dev_alloc(z, &z->auxZ[1], (size_t)N_AUX_Z * z->dZ * z->plane);
         if (s1 != ZDA_OK) {
             for (auto &f : z->F[1]) if (f) { (void)hipFree(f); z->bytes -= z->ncell * sizeof(float2); f = nullptr; }
-            if (z->auxR[1]) { (void)hipFree(z->auxR[1]); z->auxR[1] = nullptr; }
-            if (z->auxZ[1]) { (void)hipFree(z->auxZ[1]); z->auxZ[1] = nullptr; }
+            if (z->auxR[1]) {
+                (void)hipFree(z->auxR[1]);
+                z->bytes -= (size_t)N_AUX_R * d->nz * z->dR * d->nphi * sizeof(float2);
+                z->auxR[1] = nullptr;
+            }
+            if (z->auxZ[1]) {
+                (void)hipFree(z->auxZ[1]);
+                z->bytes -= (size_t)N_AUX_Z * z->dZ * z->plane * sizeof(float2);
+                z->auxZ[1] = nullptr;
+            }
             z->fused = false;
             z->tile_rows = 4;
+        } else {
+            // intermediate auxiliaries of the two-step kernel (optional)
+            zda_status s2 = dev_alloc(z, &z->mauxR, (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
+            if (s2 == ZDA_OK) s2 = dev_alloc(z, &z->mauxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
+            if (s2 == ZDA_OK) {
+                // default two-step shape: 13 owned rows, 48-plane chunks,
+                // halved (down to 8) while there are fewer than 1024 tiles
+                z->has_m = true;
+                z->two = true;
+                z->fused = false;
+                z->tile_rows = 13;
+                const long tiles = (long)((d->nphi + TWO_STEP_COLS - 1) / TWO_STEP_COLS) * ((d->nr + 12) / 13);
+                int kc = std::min(48, d->nz);
+                while (kc > 8 && tiles * ((d->nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
+                z->kchunk = kc;
+            } else {
+                if (z->mauxR) {
+                    (void)hipFree(z->mauxR);
+                    z->bytes -= (size_t)N_AUX_R * d->nz * z->dR * d->nphi * sizeof(float2);
+                    z->mauxR = nullptr;
+                }
+                z->mauxZ = nullptr;
+            }
+            (void)hipGetLastError();
         }
     }
     if (st == ZDA_OK) st = dev_alloc(z, &z->rows, (size_t)d->nr);
@@ -872,12 +1008,16 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
     if (kchunk < 1 || kchunk > z->d.nz) return fail(ZDA_ERR_ARG, "kchunk must be in [1, nz]");
     const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16;
     const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15;
-    if (!split && !fused) return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16 (split) or 3, 7, 15 (fused)");
-    if (fused && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set for the fused step");
-    if (fused && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set for the fused step");
+    const bool two = tile_rows == 5 || tile_rows == 13;
+    if (!split && !fused && !two)
+        return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16 (split), 3, 7, 15 (fused) or 5, 13 (two-step)");
+    if ((fused || two) && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set");
+    if ((fused || two) && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set");
+    if (two && !z->has_m) return fail(ZDA_ERR_STATE, "no intermediate auxiliaries for the two-step kernel");
     z->kchunk = kchunk;
     z->tile_rows = tile_rows;
     z->fused = fused;
+    z->two = two;
     return ZDA_OK;
 }
 
@@ -913,12 +1053,26 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t)
     HIP_TRY(hipEventSynchronize(z->ev[4 * (size_t)z->timed_steps - 1]));
     for (int n = 0; n < z->timed_steps; ++n) {
         float a = 0.f, b = 0.f;
-        if (!z->timed_fused) HIP_TRY(hipEventElapsedTime(&a, z->ev[4 * n], z->ev[4 * n + 1]));
+        if (!z->timed_fused || z->timed_two) HIP_TRY(hipEventElapsedTime(&a, z->ev[4 * n], z->ev[4 * n + 1]));
         HIP_TRY(hipEventElapsedTime(&b, z->ev[4 * n + 2], z->ev[4 * n + 3]));
-        t->h_ms += a;
-        t->e_ms += b;
+        if (z->timed_two) {
+            t->e_ms += a;        // interior tiles
+            t->layer_ms += b;    // tiles with layer cells
+        } else {
+            t->h_ms += a;
+            t->e_ms += b;
+        }
     }
     t->h_launches = z->timed_fused ? 0 : z->timed_steps;
+    t->steps_per_launch = z->timed_two ? 2 : 1;
+    t->layer_launches = z->timed_two ? z->timed_steps : 0;
+    t->e_cells = z->timed_two ? z->int_cells : z->ncell;
+    {
+        const size_t mon = (z->d.k_mon >= 0 && z->d.k_mon < z->d.nz) ? z->plane : 0;
+        t->e_mon_cells = z->timed_two ? z->int_mon_cells : mon;
+        const size_t src = (z->k_src_last >= 0 && z->k_src_last < z->d.nz) ? z->plane : 0;
+        t->e_src_cells = z->timed_two ? z->int_src_cells : src;
+    }
     t->e_launches = z->timed_steps;
     return ZDA_OK;
 }

@@ -58,7 +58,9 @@ class ZoneInfo(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("h_launches", ctypes.c_int), ("e_launches", ctypes.c_int), ("h_ms", ctypes.c_double),
-                ("e_ms", ctypes.c_double)]
+                ("e_ms", ctypes.c_double), ("steps_per_launch", ctypes.c_int), ("layer_launches", ctypes.c_int),
+                ("layer_ms", ctypes.c_double), ("e_cells", ctypes.c_size_t), ("e_mon_cells", ctypes.c_size_t),
+                ("e_src_cells", ctypes.c_size_t)]
 
 
 class TuneResult(ctypes.Structure):

@@ -26,10 +26,10 @@ def _rel(a, b):
 
 
 # launch shapes: (kchunk, tile_rows); tile_rows 3/7/15 select the fused
-# double-buffered step, 1/2/4/8/16 the split in-place H and E kernels;
-# None keeps the zone's default (fused)
+# double-buffered step, 5/13 the two-step kernel, 1/2/4/8/16 the split
+# in-place H and E kernels; None keeps the zone's default
 SHAPES = {"default": None, "fused_tr3_kc7": (7, 3), "fused_tr15_kc13": (13, 15), "split_r4_kc7": (7, 4),
-          "split_r1": (0, 1)}
+          "split_r1": (0, 1), "two_tr13_kc9": (9, 13), "two_tr5_kc6": (6, 5), "two_tr5_kc3": (3, 5)}
 
 
 def _zone_pair(zda, oracle_mod, wl, eps, shape=None):
@@ -41,7 +41,7 @@ def _zone_pair(zda, oracle_mod, wl, eps, shape=None):
     return g, o
 
 
-@pytest.mark.parametrize("shape", ["default", "split_r4_kc7"])
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr13_kc9"])
 def test_c1_parity_exit_plane_dft(zda, oracle_mod, shape):
     from paper_2501_07979_amd.workloads import c1
     wl = c1()
@@ -60,7 +60,8 @@ def test_c1_parity_exit_plane_dft(zda, oracle_mod, shape):
         assert e <= 1e-4, (c, e)
 
 
-@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "fused_tr15_kc13", "split_r4_kc7"])
+@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "fused_tr15_kc13", "split_r4_kc7", "two_tr13_kc9",
+                                   "two_tr5_kc6", "two_tr5_kc3"])
 @pytest.mark.parametrize("case", ["ragged_m1", "ragged_m0", "ragged_mneg", "no_pml"])
 def test_ragged_shapes_all_fields(zda, oracle_mod, case, shape):
     """Shapes that are not multiples of the tile (nphi 70, nr 37) with uneven
@@ -85,13 +86,14 @@ def test_ragged_shapes_all_fields(zda, oracle_mod, case, shape):
     assert _rel(g.dft(zda.MON_VOLUME).cpu().numpy(), ref["vol"]) <= 1e-5
 
 
-@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7"])
+@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr13_kc9", "two_tr5_kc3"])
 def test_random_state_steps_with_pml(zda, oracle_mod, shape):
     """Arbitrary initial fields (written through the ABI) stepped without
-    reset: every update term, PML auxiliary and the seam act from step 1."""
+    reset: every update term, PML auxiliary and the seam act from step 1
+    (an odd step count, so a two-step run ends with one single step)."""
     from paper_2501_07979_amd.workloads import Workload
     wl = Workload("random_state", r_in=60.0, nr=29, nphi=64, nz=33, n_fold=6, m=2, pml=(6, 5, 5, 6), k_src=3,
-                  k_mon=20, design=(10, 12), steps=40)
+                  k_mon=20, design=(10, 12), steps=41)
     rng = np.random.default_rng(22)
     eps = (1.0 + 3.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
     g, o = _zone_pair(zda, oracle_mod, wl, eps, SHAPES[shape])
@@ -146,7 +148,7 @@ def _objective(wts, plane):
     return np.sum(np.abs(s) ** 2), np.conj(s)[:, None, None, None] * wts
 
 
-@pytest.mark.parametrize("shape", ["default", "split_r4_kc7"])
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc6"])
 def test_gradient_parity_small_copy(zda, oracle_mod, shape):
     """Adjoint gradient over the design layer of the gradient zone's small
     copy (64 x 64 x 96, three frequencies) against the oracle's gradient."""
@@ -219,14 +221,15 @@ def test_production_zone_full_size_steps(zda, oracle_mod):
 def test_fused_launch_shapes_are_bitwise_identical(zda):
     """Every cell is computed by the same instruction sequence whatever the
     tile and chunk shape (halo values are recomputed, not approximated), so
-    the fused step is deterministic across launch shapes."""
+    the fused step and the two-step kernel give the same bits for every
+    launch shape."""
     from paper_2501_07979_amd.workloads import Workload
     wl = Workload("determinism", r_in=360.0, nr=37, nphi=130, nz=41, n_fold=14, m=1, pml=(5, 6, 4, 7), k_src=9,
                   k_mon=30, design=(12, 17), k_sub=12, steps=120, omegas=(0.3,), omega_c=0.3, width=6.0)
     rng = np.random.default_rng(41)
     eps = (1.0 + 4.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
     outs = []
-    for kc, tr in [(41, 7), (5, 3), (13, 15), (1, 7)]:
+    for kc, tr in [(41, 7), (5, 3), (13, 15), (1, 7), (9, 13), (41, 13), (4, 5), (1, 5)]:
         _say("determinism", kc, tr)
         g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
         g.set_launch(kc, tr)
@@ -253,7 +256,7 @@ def test_error_paths_on_device(zda):
         g.run(10, [0.3] * 9, k_src=5, omega_c=0.3, width=5.0)
     assert e.value.status == zda.ZDA_ERR_ARG
     with pytest.raises(zda.ZdaError) as e:
-        g.set_launch(10, 5)
+        g.set_launch(10, 6)
     assert e.value.status == zda.ZDA_ERR_ARG
     g.close()
     g.close()
