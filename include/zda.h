@@ -204,13 +204,18 @@ typedef struct {
  * without the second buffer set. */
 zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 
-/* Launch options of the fused step (results do not depend on them):
- * ZDA_OPT_XCD_REMAP (default 0) numbers the tiles so that each of the eight
- * XCDs works on one contiguous range of neighbouring tiles; ZDA_OPT_NT_STORES
- * (default 1) writes the next buffer set with non-temporal stores.
+/* Launch options of the fused step and the two-step kernel (results do not
+ * depend on them): ZDA_OPT_XCD_REMAP (default 0) numbers the tiles so that
+ * each of the eight XCDs works on one contiguous range of neighbouring
+ * tiles; ZDA_OPT_NT_STORES (default 1) writes the next buffer set with
+ * non-temporal stores; ZDA_OPT_LAYER_STREAM (default 0) runs the two-step
+ * launch over the tiles with layer cells on a second stream of the zone
+ * (default priority), concurrently with the launch over the interior tiles,
+ * joined back into the run's stream before the next pair of steps.
  * ZDA_ERR_ARG for an unknown option. */
 #define ZDA_OPT_XCD_REMAP 1
 #define ZDA_OPT_NT_STORES 2
+#define ZDA_OPT_LAYER_STREAM 3
 zda_status zda_zone_set_option(zda_zone *z, int option, int value);
 
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);

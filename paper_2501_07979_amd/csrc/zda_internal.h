@@ -60,7 +60,7 @@ struct StepArgs {
     // two-step launch: auxiliaries at the intermediate time level and the
     // linear indices of the tiles this launch covers
     float2 *mauxR, *mauxZ;
-    const unsigned *tiles;
+    const uint4 *tiles;            // {phi block, first row | rows << 16, kb | ke << 16, 0}
 };
 
 // Batched launch over many zones: per-zone argument blocks in device memory
@@ -83,8 +83,7 @@ void launch_fused_step(const StepArgs &a, int n, hipStream_t s);
 // two leap-frog steps (n, n + 1) over the tiles listed in a.tiles; pml selects
 // the instantiation with the layer recursions
 void launch_two_step(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s);
-// tile grid of the two-step kernel (TR owned rows, 61 owned phi cells)
-void two_step_grid(const StepArgs &a, int TR, unsigned &gx, unsigned &gy, unsigned &gz);
+// a two-step tile owns 61 phi cells, up to TR rows and a range of planes
 constexpr int TWO_STEP_COLS = 61;
 void launch_fill(float2 *p, size_t n, hipStream_t s);
 // tiles of one zone for the split (BY rows) or fused (TR owned rows) kernels

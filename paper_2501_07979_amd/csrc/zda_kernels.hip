@@ -563,6 +563,34 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
     }
 }
 
+// Field values one cell's step-one H half-step reads at plane k (plus dt/eps
+// at k), loaded unconditionally from in-range addresses: the +z neighbour is
+// plane k + 1 (plane k itself at the top), the +r neighbour row ic + dip.
+struct PlaneIn {
+    float2 ez, er_kp, ep_kp, ez_jp, er_jp, ez_ip, ep_ip, hr, hp, hz;
+    float ce;
+};
+
+__device__ __forceinline__ PlaneIn load_plane(const StepArgs &a, int k, size_t plane, size_t rowc, size_t dip,
+                                              unsigned o, unsigned ojp, unsigned oc)
+{
+    const size_t c0 = (size_t)k * plane + rowc;
+    const size_t dkp = k + 1 < a.nz ? plane : 0;
+    PlaneIn p;
+    p.ez = ldo(a.Ez + c0, o);
+    p.er_kp = ldo(a.Er + c0 + dkp, o);
+    p.ep_kp = ldo(a.Ep + c0 + dkp, o);
+    p.ez_jp = ldo(a.Ez + c0, ojp);
+    p.er_jp = ldo(a.Er + c0, ojp);
+    p.ez_ip = ldo(a.Ez + c0 + dip, o);
+    p.ep_ip = ldo(a.Ep + c0 + dip, o);
+    p.hr = ldo(a.Hr + c0, o);
+    p.hp = ldo(a.Hp + c0, o);
+    p.hz = ldo(a.Hz + c0, o);
+    p.ce = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a.ceps + c0) + oc);
+    return p;
+}
+
 // Two whole leap-frog steps (n and n + 1) per launch.  The launch reads the
 // fields and auxiliaries at time level n from one buffer set and writes level
 // n + 2 to the other, so each cell's six fields cross HBM once per two steps.
@@ -573,13 +601,14 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
 // lane and wave; its H^{n+1/2} reaches the E half-step through LDS.  Step two
 // lags one plane behind and needs E^{n+1} of the +phi, +r neighbours
 // (double-buffered LDS) and H^{n+3/2} of the -phi, -r neighbours (LDS); it
-// is exact on lanes 2..62 and waves 2..TR+1, which own their cells.  A chunk
+// is exact on lanes 2..62 and waves 2..nrow+1 (nrow <= TR owned rows), which
+// own their cells.  A chunk
 // starts two planes early and runs step one one plane past its end.  Every
 // block computes halo cells with the same inputs and the same arithmetic as
 // their owner, so the level-(n+1) auxiliaries that step one writes to the
 // intermediate set are identical whichever block writes them.
 template <int TR, bool PML>
-__device__ __forceinline__ void eh2_body(const StepArgs &a, int n, unsigned tile, unsigned gx, unsigned gy)
+__device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
 {
     constexpr int NW = TR + 3;
     constexpr int NV = PML ? NW : 1;
@@ -590,16 +619,17 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, unsigned tile
     const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const int nphi = a.nphi, nr = a.nr, nz = a.nz;
     const size_t plane = (size_t)nr * nphi;
-    const int bx = (int)(tile % gx), by = (int)((tile / gx) % gy), bz = (int)(tile / (gx * gy));
-    const int i = by * TR + w - 2;
-    const bool row_ok = i >= 0 && i < nr;
+    // tile: phi column block, first owned row and row count (<= TR), planes [kb, ke)
+    const int bx = (int)tile.x, i0 = (int)(tile.y & 0xffffu), nrow = (int)(tile.y >> 16);
+    const int kb = (int)(tile.z & 0xffffu), ke = (int)(tile.z >> 16);
+    const int i = i0 + w - 2;
+    const bool active = w <= nrow + 2;                      // waves above the top halo row idle
+    const bool row_ok = active && i >= 0 && i < nr;
     const int jj = bx * TWO_STEP_COLS - 2 + lane;
     const int pc = (jj + nphi) % nphi;                      // physical column
     const bool cross_m = pc == 0;                           // lane - 1 holds column nphi - 1
     const bool cross_p = pc == nphi - 1;                    // lane + 1 holds column 0
-    const bool own = lane >= 2 && lane <= 62 && jj < nphi && w >= 2 && w <= TR + 1 && row_ok;
-    const int kb = bz * a.kchunk;
-    const int ke = min(kb + a.kchunk, nz);
+    const bool own = lane >= 2 && lane <= 62 && jj < nphi && w >= 2 && w <= nrow + 1 && row_ok;
     const int k_lo = max(kb - 2, 0);
     const bool nt = a.nt_stores;
     const int ir = (PML && row_ok) ? slab_row(i, nr, a.pr0, a.pr1) : -1;
@@ -624,8 +654,18 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, unsigned tile
     float2 e1r_p = zero2(), e1p_p = zero2(), e1z_p = zero2(), u1_p = zero2();
     float2 h2r_km = zero2(), h2p_km = zero2();
     float ce_p = 0.f;
+    // without layer recursions the next plane's loads are issued one plane
+    // ahead, so they are in flight through this plane's barriers and updates
+    PlaneIn cur = load_plane(a, k_lo, plane, rowc, dip, o, ojp, oc);
     for (int k = k_lo; k <= ke; ++k) {
         const int km = k - 1;
+        PlaneIn in;
+        if (PML) {
+            in = load_plane(a, min(k, nz - 1), plane, rowc, dip, o, ojp, oc);
+        } else {
+            in = cur;
+            cur = load_plane(a, min(k + 1, min(ke, nz - 1)), plane, rowc, dip, o, ojp, oc);
+        }
         float2 h1r = zero2(), h1p = zero2(), h1z = zero2(), v1 = zero2();
         float2 e1r = zero2(), e1p = zero2(), e1z = zero2(), u1 = zero2();
         float2 er_kp = zero2(), ep_kp = zero2();
@@ -635,25 +675,23 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, unsigned tile
         int kz = -1;
         ZCoef zc = {};
         AuxRows x1 = {};
-        const size_t c0 = (size_t)min(k, nz - 1) * plane + rowc;
         float2 ez0 = zero2();
-        if (step1) {
+        if (step1 && active) {
             kz = PML ? slab_row(k, nz, a.pz0, a.pz1) : -1;
             if (kz >= 0) zc = a.zrows[k];
             const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
             const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
             x1 = {a.auxR + sr0, a.auxZ + sz0, a.mauxR + sr0, a.mauxZ + sz0};
             const bool kp_ok = k + 1 < nz;
-            const size_t dkp = kp_ok ? plane : 0;
-            ez0 = ldo(a.Ez + c0, o);
-            er_kp = ldo(a.Er + c0 + dkp, o);
-            ep_kp = ldo(a.Ep + c0 + dkp, o);
-            float2 ez_jp = ldo(a.Ez + c0, ojp), er_jp = ldo(a.Er + c0, ojp);
-            float2 ez_ip = ldo(a.Ez + c0 + dip, o), ep_ip = ldo(a.Ep + c0 + dip, o);
-            h1r = ldo(a.Hr + c0, o);
-            h1p = ldo(a.Hp + c0, o);
-            h1z = ldo(a.Hz + c0, o);
-            ce = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a.ceps + c0) + oc);
+            ez0 = in.ez;
+            er_kp = in.er_kp;
+            ep_kp = in.ep_kp;
+            float2 ez_jp = in.ez_jp, er_jp = in.er_jp;
+            float2 ez_ip = in.ez_ip, ep_ip = in.ep_ip;
+            h1r = in.hr;
+            h1p = in.hp;
+            h1z = in.hz;
+            ce = in.ce;
             if (!kp_ok) { er_kp = zero2(); ep_kp = zero2(); }
             if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
             if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
@@ -701,7 +739,7 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, unsigned tile
         const size_t sz2 = kz2 >= 0 ? ((size_t)kz2 * nr + ic) * nphi : 0;
         const AuxRows x2 = {a.mauxR + sr2, a.mauxZ + sz2, a.oauxR + sr2, a.oauxZ + sz2};
         const bool store = own && km >= kb && km < ke;
-        if (h2_plane && w >= 1 && w <= TR + 1 && row_ok && lane >= 1 && lane <= 62) {
+        if (h2_plane && w >= 1 && w <= nrow + 1 && row_ok && lane >= 1 && lane <= 62) {
             const int b = km & 1;
             float2 ez_jp = sEz[b][w][lane + 1], er_jp = sEr[b][w][lane + 1];
             if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
@@ -806,9 +844,9 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int
 }
 
 template <int TR, bool PML>
-__global__ __launch_bounds__(64 * (TR + 3)) void eh2_kernel(StepArgs a, int n, unsigned gx, unsigned gy)
+__global__ __launch_bounds__(64 * (TR + 3)) void eh2_kernel(StepArgs a, int n)
 {
-    eh2_body<TR, PML>(a, n, a.tiles[blockIdx.x], gx, gy);
+    eh2_body<TR, PML>(a, n, a.tiles[blockIdx.x]);
 }
 
 // Batched launches: one 1-D grid covers the tiles of many zones of uneven
@@ -988,21 +1026,12 @@ void launch_fused_step(const StepArgs &a, int n, hipStream_t s)
 
 void launch_e_step(const StepArgs &a, int n, hipStream_t s) { launch_step(a, n, s, false); }
 
-void two_step_grid(const StepArgs &a, int TR, unsigned &gx, unsigned &gy, unsigned &gz)
-{
-    gx = (unsigned)((a.nphi + TWO_STEP_COLS - 1) / TWO_STEP_COLS);
-    gy = (unsigned)((a.nr + TR - 1) / TR);
-    gz = (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
-}
-
 template <int TR>
 void launch_two_tr(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s)
 {
-    unsigned gx, gy, gz;
-    two_step_grid(a, TR, gx, gy, gz);
     dim3 block(64, TR + 3, 1);
-    if (pml) hipLaunchKernelGGL((eh2_kernel<TR, true>), dim3(ntiles), block, 0, s, a, n, gx, gy);
-    else hipLaunchKernelGGL((eh2_kernel<TR, false>), dim3(ntiles), block, 0, s, a, n, gx, gy);
+    if (pml) hipLaunchKernelGGL((eh2_kernel<TR, true>), dim3(ntiles), block, 0, s, a, n);
+    else hipLaunchKernelGGL((eh2_kernel<TR, false>), dim3(ntiles), block, 0, s, a, n);
 }
 
 void launch_two_step(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s)

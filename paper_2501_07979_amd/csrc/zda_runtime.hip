@@ -84,15 +84,18 @@ struct zda_zone {
     int cur = 0;
     bool fused = true;
     bool two = false;              // two leap-frog steps per launch (tile_rows 5 or 13)
-    int xcd_remap = 0, nt_stores = 1;
+    int xcd_remap = 0, nt_stores = 1, layer_stream = 0;
+    // second stream and join events for the concurrent layer-tile launch
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // two-step launches: auxiliaries at the intermediate time level, and the
     // tile lists (interior tiles without layer cells first, then layer tiles)
     float2 *mauxR = nullptr, *mauxZ = nullptr;
-    unsigned *tiles2 = nullptr;
+    uint4 *tiles2 = nullptr;
     size_t cap_tiles2 = 0;
     bool has_m = false;
     unsigned n_int = 0, n_pml = 0;
-    int tiles_tr = 0, tiles_kc = 0, tiles_src = -1, k_src_last = -1;
+    int tiles_tr = 0, tiles_kc = 0, tiles_src = -1, k_src_last = -1, tiles_xcd = -1;
     size_t int_cells = 0, int_mon_cells = 0, int_src_cells = 0;
     RowCoef *rows = nullptr;
     ZCoef *zrows = nullptr;
@@ -148,6 +151,9 @@ void free_all(zda_zone *z)
 {
     for (auto e : z->ev) (void)hipEventDestroy(e);
     z->ev.clear();
+    if (z->ev_fork) (void)hipEventDestroy(z->ev_fork);
+    if (z->ev_join) (void)hipEventDestroy(z->ev_join);
+    if (z->s2) (void)hipStreamDestroy(z->s2);
     for (auto &set : z->F)
         for (auto &f : set) if (f) (void)hipFree(f);
     void *ptrs[] = {z->ceps, z->auxR[0], z->auxZ[0], z->auxR[1], z->auxZ[1], z->rows, z->zrows, z->dft_plane,
@@ -343,47 +349,91 @@ zda_status prepare_run(zda_zone *z, int m, int nsteps, int k_src, int P, const c
     return ZDA_OK;
 }
 
-// Tile lists of the two-step kernel for the zone's launch shape: interior
-// tiles, whose rows i0-2 .. i0+TR and planes kb-2 .. ke (clipped to the zone)
-// hold no layer cell, run the instantiation without the layer recursions;
-// the others run the full one.
-zda_status build_two_step_tiles(zda_zone *z, const StepArgs &a)
+// [lo, hi) cut into near-equal pieces of at most len
+void split_range(int lo, int hi, int len, std::vector<std::pair<int, int>> &out)
+{
+    if (hi <= lo) return;
+    const long L = hi - lo, q = (L + len - 1) / len;
+    for (long p = 0; p < q; ++p) out.push_back({lo + (int)(L * p / q), lo + (int)(L * (p + 1) / q)});
+}
+
+// Tile lists of the two-step kernel for the zone's launch shape.  A tile
+// computes rows i0-2 .. i0+nrow and planes kb-2 .. ke; it runs the
+// instantiation without layer recursions when none of those rows and planes
+// is a layer cell, i.e. when its rows lie in [pr0+2, nr-pr1-1) and its planes
+// in [pz0+2, nz-pz1-1) (or reach an edge without a layer).  The layer bands
+// are cut separately so that the layer-tile launch covers little more than
+// the layers.
+zda_status build_two_step_tiles(zda_zone *z)
 {
     const int TR = z->tile_rows, kc = z->kchunk;
-    if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last) return ZDA_OK;
-    unsigned gx, gy, gz;
-    two_step_grid(a, TR, gx, gy, gz);
+    if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last &&
+        z->tiles_xcd == z->xcd_remap)
+        return ZDA_OK;
     const zda_zone_desc &d = z->d;
-    std::vector<unsigned> in, lay;
+    const int rA = d.pml_r_in > 0 ? std::min(d.pml_r_in + 2, d.nr) : 0;
+    const int rB = d.pml_r_out > 0 ? std::max(d.nr - d.pml_r_out - 1, rA) : d.nr;
+    const int zA = d.pml_z_lo > 0 ? std::min(d.pml_z_lo + 2, d.nz) : 0;
+    const int zB = d.pml_z_hi > 0 ? std::max(d.nz - d.pml_z_hi - 1, zA) : d.nz;
+    std::vector<std::pair<int, int>> rows, planes;
+    split_range(0, rA, TR, rows);
+    const size_t r_in0 = rows.size();
+    split_range(rA, rB, TR, rows);
+    const size_t r_in1 = rows.size();
+    split_range(rB, d.nr, TR, rows);
+    split_range(0, zA, kc, planes);
+    const size_t z_in0 = planes.size();
+    split_range(zA, zB, kc, planes);
+    const size_t z_in1 = planes.size();
+    split_range(zB, d.nz, kc, planes);
+    const int gx = (d.nphi + TWO_STEP_COLS - 1) / TWO_STEP_COLS;
+    std::vector<uint4> in, lay;
     size_t cells = 0, mon = 0, src = 0;
-    for (unsigned bz = 0; bz < gz; ++bz) {
-        const int kb = (int)bz * kc, ke = std::min(kb + kc, d.nz);
-        const int klo = std::max(kb - 2, 0), khi = std::min(ke, d.nz - 1);
-        const bool zin = klo >= d.pml_z_lo && khi < d.nz - d.pml_z_hi;
-        for (unsigned by = 0; by < gy; ++by) {
-            const int i0 = (int)by * TR;
-            const int ilo = std::max(i0 - 2, 0), ihi = std::min(i0 + TR, d.nr - 1);
-            const bool rin = ilo >= d.pml_r_in && ihi < d.nr - d.pml_r_out;
-            const size_t rows = (size_t)(std::min(i0 + TR, d.nr) - i0);
-            for (unsigned bx = 0; bx < gx; ++bx) {
-                const unsigned t = bx + gx * (by + gy * bz);
-                if (zin && rin) {
+    for (size_t pz = 0; pz < planes.size(); ++pz) {
+        const int kb = planes[pz].first, ke = planes[pz].second;
+        for (size_t pr = 0; pr < rows.size(); ++pr) {
+            const int i0 = rows[pr].first, nrow = rows[pr].second - rows[pr].first;
+            const bool interior = pz >= z_in0 && pz < z_in1 && pr >= r_in0 && pr < r_in1;
+            for (int bx = 0; bx < gx; ++bx) {
+                const uint4 t = make_uint4((unsigned)bx, (unsigned)i0 | ((unsigned)nrow << 16),
+                                           (unsigned)kb | ((unsigned)ke << 16), 0u);
+                if (interior) {
                     in.push_back(t);
-                    const int j0 = (int)bx * TWO_STEP_COLS;
+                    const int j0 = bx * TWO_STEP_COLS;
                     const size_t cols = (size_t)(std::min(j0 + TWO_STEP_COLS, d.nphi) - j0);
-                    cells += rows * cols * (size_t)(ke - kb);
-                    if (d.k_mon >= kb && d.k_mon < ke) mon += rows * cols;
-                    if (z->k_src_last >= kb && z->k_src_last < ke) src += rows * cols;
+                    cells += (size_t)nrow * cols * (size_t)(ke - kb);
+                    if (d.k_mon >= kb && d.k_mon < ke) mon += (size_t)nrow * cols;
+                    if (z->k_src_last >= kb && z->k_src_last < ke) src += (size_t)nrow * cols;
                 } else {
                     lay.push_back(t);
                 }
             }
         }
     }
+    // with ZDA_OPT_XCD_REMAP, each of the eight XCDs (which take the blocks
+    // of a launch round-robin) sweeps one contiguous range of the list, so
+    // tiles that share halo rows and columns meet in one L2
+    auto xcd_order = [](std::vector<uint4> &v) {
+        const size_t nb = v.size();
+        if (nb < 8) return;
+        std::vector<uint4> o(nb);
+        const size_t per = nb / 8, rem = nb % 8;
+        size_t b = 0;
+        for (size_t s = 0; b < nb; ++s)
+            for (size_t x = 0; x < 8 && b < nb; ++x) {
+                const size_t len = per + (x < rem ? 1 : 0);
+                if (s < len) o[b++] = v[x * per + std::min(x, rem) + s];
+            }
+        v.swap(o);
+    };
+    if (z->xcd_remap) {
+        xcd_order(in);
+        xcd_order(lay);
+    }
     in.insert(in.end(), lay.begin(), lay.end());
     zda_status st = ensure(z, &z->tiles2, &z->cap_tiles2, in.size());
     if (st != ZDA_OK) return st;
-    HIP_TRY(hipMemcpy(z->tiles2, in.data(), in.size() * sizeof(unsigned), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(z->tiles2, in.data(), in.size() * sizeof(uint4), hipMemcpyHostToDevice));
     z->n_int = (unsigned)(in.size() - lay.size());
     z->n_pml = (unsigned)lay.size();
     z->int_cells = cells;
@@ -392,6 +442,7 @@ zda_status build_two_step_tiles(zda_zone *z, const StepArgs &a)
     z->tiles_src = z->k_src_last;
     z->tiles_tr = TR;
     z->tiles_kc = kc;
+    z->tiles_xcd = z->xcd_remap;
     return ZDA_OK;
 }
 
@@ -405,7 +456,7 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     const StepArgs &a = ab[0];
     const bool fused = z->fused, two = z->two;
     z->k_src_last = k_src;
-    if (two && (st = build_two_step_tiles(z, a)) != ZDA_OK) return st;
+    if (two && (st = build_two_step_tiles(z)) != ZDA_OK) return st;
     // one step of the one-launch kernel (the fused step, or an odd last step
     // of a two-step run)
     auto one_step = [&](int n) {
@@ -421,16 +472,37 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     };
     // steps n and n + 1 by the two-step kernel; ev (if given) brackets the
     // interior-tile and the layer-tile launches
+    const bool conc = two && z->layer_stream && z->n_pml > 0;
+    if (conc && !z->s2) {
+        HIP_TRY(hipStreamCreateWithFlags(&z->s2, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&z->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&z->ev_join, hipEventDisableTiming));
+    }
     auto two_steps = [&](int n, hipEvent_t *ev) -> zda_status {
         StepArgs b = ab[z->cur ^ ab_base];
+        hipStream_t sl = s;
+        if (conc) {   // layer tiles on the zone's second stream, forked from and joined into s
+            HIP_TRY(hipEventRecord(z->ev_fork, s));
+            HIP_TRY(hipStreamWaitEvent(z->s2, z->ev_fork, 0));
+            sl = z->s2;
+            b.tiles = z->tiles2 + z->n_int;
+            if (ev) HIP_TRY(hipEventRecord(ev[2], sl));
+            launch_two_step(b, n, z->n_pml, true, sl);
+            if (ev) HIP_TRY(hipEventRecord(ev[3], sl));
+        }
         b.tiles = z->tiles2;
         if (ev) HIP_TRY(hipEventRecord(ev[0], s));
         launch_two_step(b, n, z->n_int, false, s);
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-        if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-        b.tiles = z->tiles2 + z->n_int;
-        launch_two_step(b, n, z->n_pml, true, s);
-        if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+        if (conc) {
+            HIP_TRY(hipEventRecord(z->ev_join, sl));
+            HIP_TRY(hipStreamWaitEvent(s, z->ev_join, 0));
+        } else {
+            if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+            b.tiles = z->tiles2 + z->n_int;
+            launch_two_step(b, n, z->n_pml, true, s);
+            if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+        }
         z->cur ^= 1;
         return ZDA_OK;
     };
@@ -817,7 +889,7 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
             // intermediate auxiliaries of the two-step kernel (optional)
             zda_status s2 = dev_alloc(z, &z->mauxR, (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
             if (s2 == ZDA_OK) s2 = dev_alloc(z, &z->mauxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
-            if (s2 == ZDA_OK) {
+            if (s2 == ZDA_OK && d->nr <= 65535 && d->nz <= 65535) {
                 // default two-step shape: 13 owned rows, 48-plane chunks,
                 // halved (down to 8) while there are fewer than 1024 tiles
                 z->has_m = true;
@@ -828,6 +900,8 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
                 int kc = std::min(48, d->nz);
                 while (kc > 8 && tiles * ((d->nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
                 z->kchunk = kc;
+            } else if (s2 == ZDA_OK) {
+                z->has_m = true;   // two-step tiles store rows and planes in 16 bits; not the default here
             } else {
                 if (z->mauxR) {
                     (void)hipFree(z->mauxR);
@@ -1014,6 +1088,7 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
     if ((fused || two) && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set");
     if ((fused || two) && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set");
     if (two && !z->has_m) return fail(ZDA_ERR_STATE, "no intermediate auxiliaries for the two-step kernel");
+    if (two && (z->d.nr > 65535 || z->d.nz > 65535)) return fail(ZDA_ERR_ARG, "two-step tiles need nr, nz <= 65535");
     z->kchunk = kchunk;
     z->tile_rows = tile_rows;
     z->fused = fused;
@@ -1027,6 +1102,7 @@ zda_status zda_zone_set_option(zda_zone *z, int option, int value)
     switch (option) {
     case ZDA_OPT_XCD_REMAP: z->xcd_remap = value ? 1 : 0; return ZDA_OK;
     case ZDA_OPT_NT_STORES: z->nt_stores = value ? 1 : 0; return ZDA_OK;
+    case ZDA_OPT_LAYER_STREAM: z->layer_stream = value ? 1 : 0; return ZDA_OK;
     default: return fail(ZDA_ERR_ARG, "unknown option %d", option);
     }
 }
@@ -1050,6 +1126,8 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t)
     DeviceGuard g(z->device);
     std::memset(t, 0, sizeof *t);
     if (z->timed_steps == 0) return fail(ZDA_ERR_STATE, "the last run was not timed");
+    // the last launch group's events (two streams when the layer tiles ran concurrently)
+    HIP_TRY(hipEventSynchronize(z->ev[4 * (size_t)z->timed_steps - 3]));
     HIP_TRY(hipEventSynchronize(z->ev[4 * (size_t)z->timed_steps - 1]));
     for (int n = 0; n < z->timed_steps; ++n) {
         float a = 0.f, b = 0.f;
