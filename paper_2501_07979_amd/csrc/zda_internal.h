@@ -71,6 +71,7 @@ struct BatchArgs {
     int nzones;
     const int *n_base;             // device step offset added to the launch's step index
     int xcd_remap;
+    const uint4 *tiles;            // two-step: tile descriptors, zone index in the fourth word
 };
 
 enum { AUX_HR_T, AUX_HP_S, AUX_HZ_S, AUX_HZ_T, AUX_V_HP,
@@ -90,6 +91,8 @@ void launch_fill(float2 *p, size_t n, hipStream_t s);
 unsigned tiles_split(const StepArgs &a, int BY);
 unsigned tiles_fused(const StepArgs &a, int TR);
 void launch_batch_step(const BatchArgs &b, unsigned nblocks, int tile_rows, bool fused, int n_rel, hipStream_t s);
+// two steps of every zone of a batch over the tiles listed in b.tiles
+void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, bool pml, int n_rel, hipStream_t s);
 void launch_advance_step(int *n_base, int by, hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);
 void launch_design_dt(float *ceps, const float *rho, size_t n, double eps_bg, double eps_hi, double dt,

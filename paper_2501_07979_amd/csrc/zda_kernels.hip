@@ -895,6 +895,15 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_batch(BatchArgs b, int
     eh_fused_body<TR>(a, n, g - b.prefix[zi], gx, gy);
 }
 
+template <int TR, bool PML>
+__global__ __launch_bounds__(64 * (TR + 3)) void eh2_batch(BatchArgs b, int n_rel)
+{
+    const uint4 tile = b.tiles[blockIdx.x];
+    const StepArgs a = b.tab[tile.w];
+    const int n = n_rel + (b.n_base ? *b.n_base : 0);
+    eh2_body<TR, PML>(a, n, tile);
+}
+
 __global__ void advance_step_kernel(int *n_base, int by)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *n_base += by;
@@ -1032,6 +1041,21 @@ void launch_two_tr(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStrea
     dim3 block(64, TR + 3, 1);
     if (pml) hipLaunchKernelGGL((eh2_kernel<TR, true>), dim3(ntiles), block, 0, s, a, n);
     else hipLaunchKernelGGL((eh2_kernel<TR, false>), dim3(ntiles), block, 0, s, a, n);
+}
+
+template <int TR>
+void launch_batch_two_tr(const BatchArgs &b, unsigned ntiles, bool pml, int n_rel, hipStream_t s)
+{
+    dim3 block(64, TR + 3, 1);
+    if (pml) hipLaunchKernelGGL((eh2_batch<TR, true>), dim3(ntiles), block, 0, s, b, n_rel);
+    else hipLaunchKernelGGL((eh2_batch<TR, false>), dim3(ntiles), block, 0, s, b, n_rel);
+}
+
+void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, bool pml, int n_rel, hipStream_t s)
+{
+    if (ntiles == 0) return;
+    if (tile_rows == 13) launch_batch_two_tr<13>(b, ntiles, pml, n_rel, s);
+    else launch_batch_two_tr<5>(b, ntiles, pml, n_rel, s);
 }
 
 void launch_two_step(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s)

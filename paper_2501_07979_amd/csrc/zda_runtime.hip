@@ -357,19 +357,21 @@ void split_range(int lo, int hi, int len, std::vector<std::pair<int, int>> &out)
     for (long p = 0; p < q; ++p) out.push_back({lo + (int)(L * p / q), lo + (int)(L * (p + 1) / q)});
 }
 
-// Tile lists of the two-step kernel for the zone's launch shape.  A tile
+// Tiles of the two-step kernel for one zone (TR rows, kc planes).  A tile
 // computes rows i0-2 .. i0+nrow and planes kb-2 .. ke; it runs the
 // instantiation without layer recursions when none of those rows and planes
 // is a layer cell, i.e. when its rows lie in [pr0+2, nr-pr1-1) and its planes
 // in [pz0+2, nz-pz1-1) (or reach an edge without a layer).  The layer bands
 // are cut separately so that the layer-tile launch covers little more than
-// the layers.
-zda_status build_two_step_tiles(zda_zone *z)
+// the layers.  The fourth word of each descriptor is `tag` (the zone's index
+// in a batch).
+struct TwoStepTiles {
+    std::vector<uint4> in, lay;
+    size_t cells = 0, mon = 0, src = 0;   // owned by the interior tiles
+};
+
+void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, bool xcd, unsigned tag, TwoStepTiles &t)
 {
-    const int TR = z->tile_rows, kc = z->kchunk;
-    if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last &&
-        z->tiles_xcd == z->xcd_remap)
-        return ZDA_OK;
     const zda_zone_desc &d = z->d;
     const int rA = d.pml_r_in > 0 ? std::min(d.pml_r_in + 2, d.nr) : 0;
     const int rB = d.pml_r_out > 0 ? std::max(d.nr - d.pml_r_out - 1, rA) : d.nr;
@@ -388,24 +390,23 @@ zda_status build_two_step_tiles(zda_zone *z)
     split_range(zB, d.nz, kc, planes);
     const int gx = (d.nphi + TWO_STEP_COLS - 1) / TWO_STEP_COLS;
     std::vector<uint4> in, lay;
-    size_t cells = 0, mon = 0, src = 0;
     for (size_t pz = 0; pz < planes.size(); ++pz) {
         const int kb = planes[pz].first, ke = planes[pz].second;
         for (size_t pr = 0; pr < rows.size(); ++pr) {
             const int i0 = rows[pr].first, nrow = rows[pr].second - rows[pr].first;
             const bool interior = pz >= z_in0 && pz < z_in1 && pr >= r_in0 && pr < r_in1;
             for (int bx = 0; bx < gx; ++bx) {
-                const uint4 t = make_uint4((unsigned)bx, (unsigned)i0 | ((unsigned)nrow << 16),
-                                           (unsigned)kb | ((unsigned)ke << 16), 0u);
+                const uint4 q = make_uint4((unsigned)bx, (unsigned)i0 | ((unsigned)nrow << 16),
+                                           (unsigned)kb | ((unsigned)ke << 16), tag);
                 if (interior) {
-                    in.push_back(t);
+                    in.push_back(q);
                     const int j0 = bx * TWO_STEP_COLS;
                     const size_t cols = (size_t)(std::min(j0 + TWO_STEP_COLS, d.nphi) - j0);
-                    cells += (size_t)nrow * cols * (size_t)(ke - kb);
-                    if (d.k_mon >= kb && d.k_mon < ke) mon += (size_t)nrow * cols;
-                    if (z->k_src_last >= kb && z->k_src_last < ke) src += (size_t)nrow * cols;
+                    t.cells += (size_t)nrow * cols * (size_t)(ke - kb);
+                    if (d.k_mon >= kb && d.k_mon < ke) t.mon += (size_t)nrow * cols;
+                    if (k_src >= kb && k_src < ke) t.src += (size_t)nrow * cols;
                 } else {
-                    lay.push_back(t);
+                    lay.push_back(q);
                 }
             }
         }
@@ -426,19 +427,34 @@ zda_status build_two_step_tiles(zda_zone *z)
             }
         v.swap(o);
     };
-    if (z->xcd_remap) {
+    if (xcd) {
         xcd_order(in);
         xcd_order(lay);
     }
-    in.insert(in.end(), lay.begin(), lay.end());
-    zda_status st = ensure(z, &z->tiles2, &z->cap_tiles2, in.size());
+    t.in.insert(t.in.end(), in.begin(), in.end());
+    t.lay.insert(t.lay.end(), lay.begin(), lay.end());
+}
+
+// The zone's own tile list (interior tiles first), rebuilt when the launch
+// shape, the source plane or the tile order changed.
+zda_status build_two_step_tiles(zda_zone *z)
+{
+    const int TR = z->tile_rows, kc = z->kchunk;
+    if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last &&
+        z->tiles_xcd == z->xcd_remap)
+        return ZDA_OK;
+    TwoStepTiles t;
+    two_step_tiles(z, TR, kc, z->k_src_last, z->xcd_remap != 0, 0u, t);
+    std::vector<uint4> all = t.in;
+    all.insert(all.end(), t.lay.begin(), t.lay.end());
+    zda_status st = ensure(z, &z->tiles2, &z->cap_tiles2, all.size());
     if (st != ZDA_OK) return st;
-    HIP_TRY(hipMemcpy(z->tiles2, in.data(), in.size() * sizeof(uint4), hipMemcpyHostToDevice));
-    z->n_int = (unsigned)(in.size() - lay.size());
-    z->n_pml = (unsigned)lay.size();
-    z->int_cells = cells;
-    z->int_mon_cells = mon;
-    z->int_src_cells = src;
+    HIP_TRY(hipMemcpy(z->tiles2, all.data(), all.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    z->n_int = (unsigned)t.in.size();
+    z->n_pml = (unsigned)t.lay.size();
+    z->int_cells = t.cells;
+    z->int_mon_cells = t.mon;
+    z->int_src_cells = t.src;
     z->tiles_src = z->k_src_last;
     z->tiles_tr = TR;
     z->tiles_kc = kc;
@@ -1191,11 +1207,18 @@ struct zda_batch {
     int graph_steps = 32;         // steps per captured graph (even)
     std::vector<StepArgs> h_tab;
     std::vector<unsigned> h_prefix;
+    bool two = false;             // two-step kernel (tile_rows 5 or 13)
+    uint4 *tiles = nullptr;       // two-step: interior tiles of every zone, then layer tiles
+    size_t cap_tiles = 0;
 };
 
 namespace {
 
 bool zone_has_second_set(const zda_zone *z) { return z->F[1][0] && (z->dR == 0 || z->auxR[1]) && (z->dZ == 0 || z->auxZ[1]); }
+bool zone_two_step_ok(const zda_zone *z)
+{
+    return zone_has_second_set(z) && z->has_m && z->d.nr <= 65535 && z->d.nz <= 65535;
+}
 
 // One batched time loop: ab[i][0..1] are zone i's step arguments (prepared).
 zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &ab, int nsteps, hipStream_t s)
@@ -1208,7 +1231,28 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
         b->h_tab[i] = ab[i][0];
         b->h_tab[nz + i] = ab[i][1];
         b->h_prefix[i] = total;
-        total += b->fused ? tiles_fused(ab[i][0], b->tile_rows) : tiles_split(ab[i][0], b->tile_rows);
+        if (!b->two) total += b->fused ? tiles_fused(ab[i][0], b->tile_rows) : tiles_split(ab[i][0], b->tile_rows);
+    }
+    unsigned n_in = 0, n_lay = 0;
+    if (b->two) {
+        TwoStepTiles t;
+        for (int i = 0; i < nz; ++i) {
+            const zda_zone *z = b->zones[i];
+            two_step_tiles(z, b->tile_rows, z->kchunk, ab[i][0].k_src, z->xcd_remap != 0, (unsigned)i, t);
+        }
+        std::vector<uint4> all = t.in;
+        all.insert(all.end(), t.lay.begin(), t.lay.end());
+        if (all.size() > b->cap_tiles) {
+            if (b->tiles) (void)hipFree(b->tiles);
+            b->tiles = nullptr;
+            b->cap_tiles = 0;
+            HIP_TRY(hipMalloc((void **)&b->tiles, all.size() * sizeof(uint4)));
+            b->cap_tiles = all.size();
+        }
+        HIP_TRY(hipMemcpyAsync(b->tiles, all.data(), all.size() * sizeof(uint4), hipMemcpyHostToDevice, s));
+        n_in = (unsigned)t.in.size();
+        n_lay = (unsigned)t.lay.size();
+        HIP_TRY(hipStreamSynchronize(s));   // the staging vector goes out of scope
     }
     if ((size_t)nz > b->cap) {
         if (b->tab) (void)hipFree(b->tab);
@@ -1230,7 +1274,17 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
         ba[p].nzones = nz;
         ba[p].n_base = b->n_base;
         ba[p].xcd_remap = b->zones[0]->xcd_remap;
+        ba[p].tiles = b->tiles;
     }
+    // steps q and q+1 of the two-step kernel: interior tiles of every zone,
+    // then their layer tiles; the pair alternates buffer parities
+    auto two_pair = [&](int q, hipStream_t st) {
+        BatchArgs x = ba[(q / 2) & 1];
+        x.tiles = b->tiles;
+        launch_batch_two(x, n_in, b->tile_rows, false, q, st);
+        x.tiles = b->tiles + n_in;
+        launch_batch_two(x, n_lay, b->tile_rows, true, q, st);
+    };
     const int S = b->graph_steps;
     const int reps = nsteps >= 2 * S ? nsteps / S : 0;
     if (reps > 0) {
@@ -1238,8 +1292,12 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
         hipGraphExec_t exec = nullptr;
         HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         // the fused step alternates buffer parities; the split kernels update one set in place
-        for (int q = 0; q < S; ++q)
-            launch_batch_step(ba[b->fused ? (q & 1) : 0], total, b->tile_rows, b->fused, q, b->cap_stream);
+        if (b->two) {
+            for (int q = 0; q < S; q += 2) two_pair(q, b->cap_stream);
+        } else {
+            for (int q = 0; q < S; ++q)
+                launch_batch_step(ba[b->fused ? (q & 1) : 0], total, b->tile_rows, b->fused, q, b->cap_stream);
+        }
         launch_advance_step(b->n_base, S, b->cap_stream);
         HIP_TRY(hipStreamEndCapture(b->cap_stream, &graph));
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1255,12 +1313,26 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
             return fail(ZDA_ERR_HIP, "graph launch: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
     const int done = reps * S;
-    for (int q = 0; q < nsteps - done; ++q)
-        launch_batch_step(ba[b->fused ? (q & 1) : 0], total, b->tile_rows, b->fused, q, s);
+    if (b->two) {
+        int q = 0;
+        for (; q + 1 < nsteps - done; q += 2) two_pair(q, s);
+        if (q < nsteps - done) {
+            // an odd last step: the fused step of each zone (absolute step index)
+            for (int i = 0; i < nz; ++i) {
+                StepArgs a1 = ab[i][((nsteps - done) / 2) & 1];
+                a1.tile_rows = 3;
+                launch_fused_step(a1, nsteps - 1, s);
+            }
+        }
+    } else {
+        for (int q = 0; q < nsteps - done; ++q)
+            launch_batch_step(ba[b->fused ? (q & 1) : 0], total, b->tile_rows, b->fused, q, s);
+    }
     HIP_TRY(hipGetLastError());
+    const int flips = b->two ? nsteps / 2 + (nsteps & 1) : (b->fused ? nsteps : 0);
     for (auto z : b->zones) {
         z->n_done += nsteps;
-        if (b->fused) z->cur ^= (nsteps & 1);
+        z->cur ^= (flips & 1);
     }
     return ZDA_OK;
 }
@@ -1302,6 +1374,7 @@ void zda_batch_destroy(zda_batch *b)
     (void)hipDeviceSynchronize();
     if (b->tab) (void)hipFree(b->tab);
     if (b->prefix) (void)hipFree(b->prefix);
+    if (b->tiles) (void)hipFree(b->tiles);
     if (b->n_base) (void)hipFree(b->n_base);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
@@ -1312,14 +1385,20 @@ zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk)
     if (!b) return fail(ZDA_ERR_ARG, "NULL batch");
     const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16;
     const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15;
-    if (!split && !fused) return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16 (split) or 3, 7, 15 (fused)");
+    const bool two = tile_rows == 5 || tile_rows == 13;
+    if (!split && !fused && !two)
+        return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16 (split), 3, 7, 15 (fused) or 5, 13 (two-step)");
     if (fused)
         for (auto z : b->zones)
             if (!zone_has_second_set(z)) return fail(ZDA_ERR_STATE, "a zone has no second buffer set");
+    if (two)
+        for (auto z : b->zones)
+            if (!zone_two_step_ok(z)) return fail(ZDA_ERR_STATE, "a zone cannot run the two-step kernel");
     if (kchunk)
         for (size_t i = 0; i < b->zones.size(); ++i)
             if (kchunk[i] < 1 || kchunk[i] > b->zones[i]->d.nz) return fail(ZDA_ERR_ARG, "kchunk[%zu] out of range", i);
     b->fused = fused;
+    b->two = two;
     b->tile_rows = tile_rows;
     if (kchunk)
         for (size_t i = 0; i < b->zones.size(); ++i) b->zones[i]->kchunk = kchunk[i];
@@ -1410,10 +1489,16 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
         return ZDA_OK;
     };
     // 1) kernel family and tile shape with each zone's default depth
+    // (the time-block depth: 1 for the split and fused kernels, 2 for the
+    // two-step kernel)
     std::vector<int> rows_c = {2, 4, 8};
-    bool can_fuse = true;
-    for (auto z : b->zones) can_fuse = can_fuse && zone_has_second_set(z);
+    bool can_fuse = true, can_two = true;
+    for (auto z : b->zones) {
+        can_fuse = can_fuse && zone_has_second_set(z);
+        can_two = can_two && zone_two_step_ok(z);
+    }
     if (can_fuse) rows_c.insert(rows_c.end(), {3, 7, 15});
+    if (can_two) rows_c.insert(rows_c.end(), {5, 13});
     std::vector<int> kc(nz);
     for (size_t i = 0; i < nz; ++i) kc[i] = b->zones[i]->kchunk;
     double best = 1e300;
@@ -1435,7 +1520,10 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
         const size_t lo = nz * cl / nclass, hi = nz * (cl + 1) / nclass;
         const std::vector<int> kc0 = kc;
         int best_depth = 0;
-        for (int depth : {6, 8, 12, 20, 40}) {
+        const bool two_rows = best_rows == 5 || best_rows == 13;
+        const std::vector<int> depths = two_rows ? std::vector<int>{16, 24, 32, 48, 96}
+                                                 : std::vector<int>{6, 8, 12, 20, 40};
+        for (int depth : depths) {
             for (size_t q = lo; q < hi; ++q) kc[order[q]] = std::min(depth, b->zones[order[q]]->d.nz);
             if ((st = zda_batch_set_launch(b, best_rows, kc.data())) != ZDA_OK) return st;
             double ms;

@@ -35,9 +35,12 @@ def zda():
     return Z
 
 
-@pytest.mark.parametrize("mode", ["fused", "split"])
+@pytest.mark.parametrize("mode", ["fused", "split", "two", "two_odd"])
 def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
     wls = _zones()
+    if mode == "two_odd":            # an odd step count ends with one fused step
+        for w in wls:
+            w.steps = 151
     eps = [w.eps() for w in wls]
     singles = []
     for w, e in zip(wls, eps):
@@ -50,10 +53,10 @@ def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
         z.close()
     zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
     b = zda.Batch(zones)
-    b.set_launch(7 if mode == "fused" else 4)
+    b.set_launch({"fused": 7, "split": 4, "two": 13, "two_odd": 5}[mode])
     srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
     _say("batch run", mode)
-    b.run(srcs, wls[0].steps, wls[0].omegas, volume=True)    # 150 steps: graph replays + eager tail
+    b.run(srcs, wls[0].steps, wls[0].omegas, volume=True)    # graph replays + eager tail
     for w, e, z, (ez, pl, vol) in zip(wls, eps, zones, singles):
         got = z.dft(zda.MON_PLANE).cpu().numpy()
         o = oracle_mod.OracleZone(**w.desc_kwargs(), eps=e)
@@ -107,8 +110,8 @@ def test_batch_autotune_keeps_results(zda):
     b.run(srcs, 120, wls[0].omegas)
     after = [z.dft(zda.MON_PLANE).cpu().numpy() for z in zones]
     for x, y in zip(before, after):
-        if res.tile_rows in (3, 7, 15):
-            assert np.array_equal(x, y)          # fused family is shape-independent bitwise
+        if res.tile_rows in (3, 5, 7, 13, 15):
+            assert np.array_equal(x, y)          # fused and two-step families are shape-independent bitwise
         else:
             assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(x)
     b.close()
