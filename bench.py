@@ -137,6 +137,37 @@ def design_iteration(steps=None):
             "finite_gradient": ok, "kind": "plain FDTD-adjoint (no surrogate)"}
 
 
+def surrogate_design(rounds=3, samples=64, train_iters=400, inner_iters=10, plain_iters=8):
+    """Design on the gradient zone's small copy (64 x 64 x 96, 3 frequencies,
+    2-D pattern extruded through the design layer): the surrogate's
+    trust-region loop (FDTD samples around the FDTD-verified base, BF16-MFMA
+    training, surrogate inner iterations, one FDTD judgement per round)
+    against plain FDTD-adjoint iterations from the same start."""
+    import torch
+    from paper_2501_07979_amd import objective, surrogate, zda
+    from paper_2501_07979_amd.workloads import c3_small
+    wl = c3_small()
+    base = surrogate.random_patterns(1, wl.nr, wl.nphi, seed=100)[0]
+    W = objective.focal_weights(wl, np.array(wl.omegas), objective.focal_length(wl.r_in + 0.5 * wl.nr)).cpu().numpy()
+    zone = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    net = surrogate.Surrogate(in_ch=2, width=48, out_ch=4 * len(wl.omegas), seed=1)
+    t0 = time.perf_counter()
+    _, F_tr, hist = surrogate.trust_region_design(net, wl, W, base, zone, rounds=rounds, samples=samples,
+                                                  radius=0.2, inner_iters=inner_iters, train_iters=train_iters)
+    t_tr = time.perf_counter() - t0
+    _, Fs, s_plain = surrogate.plain_design(wl, W, base, zone, plain_iters)
+    zone.close()
+    s_sur = float(np.median([h["s_per_surrogate_iter"] for h in hist[1:]] or [hist[0]["s_per_surrogate_iter"]]))
+    errs = [h["field_err_median"] for h in hist]
+    return {"workload": wl.name, "params": net.n_params(), "kernels": "BF16 MFMA 16x16x32, FP32 accumulate",
+            "surrogate_iters_per_s": round(1.0 / s_sur, 2), "plain_iters_per_s": round(1.0 / s_plain, 3),
+            "field_err_median_per_round": [round(e, 4) for e in errs],
+            "trust_region": {"rounds": rounds, "samples_per_round": samples, "wall_s": round(t_tr, 2),
+                             "F_start": round(hist[0]["F_base"], 4), "F_end_fdtd": round(F_tr, 4),
+                             "accepted": [h["accepted"] for h in hist]},
+            "plain": {"iters": plain_iters, "wall_s": round(s_plain * plain_iters, 2), "F_end": round(Fs[-1], 4)}}
+
+
 def batch_lens(steps, warmup, autotune=True):
     """The 48-zone lens (2.89e9 cells, n from 64 to 4096): every zone stepped
     by one batched launch per time step, time loop replayed from a graph."""
@@ -181,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-design-iter", action="store_true",
                     help="skip the gradient-zone design iteration reported beside the headline")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate-vs-plain design comparison on the gradient zone's small copy")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 4 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -294,6 +327,9 @@ def main():
     if not args.no_design_iter and args.workload == "c2":
         print("bench: one design iteration on the gradient zone", file=sys.stderr, flush=True)
         out["design_iteration"] = design_iteration()
+    if not args.no_surrogate and args.workload == "c2":
+        print("bench: surrogate vs plain design iterations", file=sys.stderr, flush=True)
+        out["surrogate_design"] = surrogate_design()
     if not args.no_cpu_baseline:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -1,0 +1,504 @@
+"""Design surrogate: a small dilated convolutional network that maps a zone's
+design-layer pattern to its complex exit-plane DFT fields, so that inner
+design iterations can run on it; the FDTD (libzda) generates its training
+samples and stays the judge, re-verifying every k-th iterate.
+
+Every layer runs on the hand-written gfx950 kernels of libzsur.so (BF16 MFMA
+GEMM with FP32 accumulation, im2col/col2im, activation gradient, MSE, Adam);
+torch tensors only hold device memory.  Activations are channel-major
+[C][B][H][W] (H = r rows, W = phi columns).  Convolutions are 3x3 with
+dilation d, periodic in phi and zero-padded in r; the targets are the fields
+with the Bloch phase removed (u = E e^{-i m phi}), which are phi-periodic, so
+the periodic padding matches them.
+
+The pattern is two-dimensional, extruded through the design layer (the
+paper's zones are patterned with pillars that run through the layer); the
+fields are the exit-plane E_r and E_phi at every DFT frequency.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EXPORTS = ["zsur_gemm", "zsur_im2col", "zsur_col2im", "zsur_act_grad", "zsur_rowsum", "zsur_mse", "zsur_to_bf16",
+           "zsur_adam", "zsur_last_error"]
+ACT_NONE, ACT_LEAKY = 0, 1
+_lib = None
+
+
+class ZsurError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("zsur status %d: %s" % (status, msg))
+        self.status = status
+
+
+def load():
+    """Load libzsur.so (built in-tree by build.py); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = os.path.join(HERE, "libzsur.so")
+    if not os.path.exists(path):
+        raise RuntimeError("libzsur.so is not built (run paper_2501_07979_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    P, I, L, F, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_float, ctypes.c_size_t
+    lib.zsur_gemm.argtypes = [I, I, I, P, L, L, P, L, L, P, L, P, P, I, F, I, P, P]
+    lib.zsur_im2col.argtypes = [P, I, I, I, I, I, P, P]
+    lib.zsur_col2im.argtypes = [P, I, I, I, I, I, P, P]
+    lib.zsur_act_grad.argtypes = [P, P, P, P, S, F, P]
+    lib.zsur_rowsum.argtypes = [P, I, I, P, P]
+    lib.zsur_mse.argtypes = [P, P, S, P, P, P, P]
+    lib.zsur_to_bf16.argtypes = [P, P, S, P]
+    lib.zsur_adam.argtypes = [P, P, P, P, S, F, F, F, F, I, P, P]
+    lib.zsur_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ck(st):
+    if st != 0:
+        raise ZsurError(st, load().zsur_last_error().decode())
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class _Layer:
+    def __init__(self, cin, cout, k, dil, act, rng, device):
+        import torch
+        self.cin, self.cout, self.k, self.dil, self.act = cin, cout, k, dil, act
+        fan_in = cin * k * k
+        bound = np.sqrt(6.0 / fan_in) * (1.0 if act else 0.5)
+        w = rng.uniform(-bound, bound, (cout, fan_in)).astype(np.float32)
+        self.w = torch.tensor(w, device=device)
+        self.b = torch.zeros(cout, dtype=torch.float32, device=device)
+        self.wb = torch.empty((cout, fan_in), dtype=torch.int16, device=device)
+        _ck(load().zsur_to_bf16(_p(self.w), _p(self.wb), self.w.numel(), _stream()))
+        self.gw = torch.zeros_like(self.w)
+        self.gb = torch.zeros_like(self.b)
+        self.mw, self.vw = torch.zeros_like(self.w), torch.zeros_like(self.w)
+        self.mb, self.vb = torch.zeros_like(self.b), torch.zeros_like(self.b)
+
+
+class Surrogate:
+    """in_ch -> 3x3 conv (act) -> 3x3 dilated convs (act) -> 1x1 conv -> out_ch."""
+
+    def __init__(self, in_ch=2, width=48, out_ch=12, dilations=(1, 2, 4, 8, 1, 2, 4, 8), slope=0.1, seed=0,
+                 device="cuda"):
+        rng = np.random.default_rng(seed)
+        self.slope = float(slope)
+        self.device = device
+        self.layers = [_Layer(in_ch, width, 3, 1, True, rng, device)]
+        for d in dilations:
+            self.layers.append(_Layer(width, width, 3, d, True, rng, device))
+        self.layers.append(_Layer(width, out_ch, 1, 1, False, rng, device))
+        self.in_ch, self.out_ch = in_ch, out_ch
+        self.t = 0
+        self._cache = None
+        self._work = None
+
+    def n_params(self):
+        return sum(l.w.numel() + l.b.numel() for l in self.layers)
+
+    # ---- forward / backward
+    def forward(self, x, keep=False):
+        """x: FP32 [in_ch][B][H][W] on the device -> FP32 [out_ch][B][H][W]."""
+        import torch
+        lib = load()
+        _, B, H, W = x.shape
+        N = B * H * W
+        s = _stream()
+        cache = []
+        h = x.contiguous()
+        hb = None
+        for l in self.layers:
+            y = torch.empty((l.cout, B, H, W), dtype=torch.float32, device=x.device)
+            yb = torch.empty((l.cout, B, H, W), dtype=torch.int16, device=x.device)
+            if l.k == 3:
+                cols = torch.empty((l.cin * 9, N), dtype=torch.int16, device=x.device)
+                _ck(lib.zsur_im2col(_p(h), l.cin, B, H, W, l.dil, _p(cols), s))
+                K = l.cin * 9
+            else:
+                if hb is None:
+                    hb = torch.empty_like(h, dtype=torch.int16)
+                    _ck(lib.zsur_to_bf16(_p(h), _p(hb), h.numel(), s))
+                cols = hb
+                K = l.cin
+            _ck(lib.zsur_gemm(l.cout, N, K, _p(l.wb), K, 1, _p(cols), N, 1, _p(y), N, _p(yb), _p(l.b),
+                              ACT_LEAKY if l.act else ACT_NONE, self.slope, 1, None, s))
+            if keep:
+                cache.append((h, cols, y))
+            h, hb = y, yb
+        self._cache = (cache, (B, H, W)) if keep else None
+        return h
+
+    def backward(self, dy, need_dx=False):
+        """dy: FP32 d(loss)/d(output); fills every layer's gw, gb and returns
+        d(loss)/d(input) when need_dx."""
+        import torch
+        lib = load()
+        assert self._cache is not None, "forward(keep=True) first"
+        cache, (B, H, W) = self._cache
+        N = B * H * W
+        s = _stream()
+        g = dy.contiguous()
+        dx = None
+        for li in range(len(self.layers) - 1, -1, -1):
+            l = self.layers[li]
+            h, cols, y = cache[li]
+            dz = torch.empty_like(g)
+            dzb = torch.empty(g.shape, dtype=torch.int16, device=g.device)
+            _ck(lib.zsur_act_grad(_p(y), _p(g), _p(dz), _p(dzb), g.numel(), self.slope if l.act else 1.0, s))
+            _ck(lib.zsur_rowsum(_p(dz), l.cout, N, _p(l.gb), s))
+            K = l.cin * (9 if l.k == 3 else 1)
+            split = max(1, min(64, N // 2048))
+            need = split * l.cout * K
+            if self._work is None or self._work.numel() < need:
+                self._work = torch.empty(need, dtype=torch.float32, device=g.device)
+            # dW[co][kk] = sum_n dZ[co][n] cols[kk][n]
+            _ck(lib.zsur_gemm(l.cout, K, N, _p(dzb), N, 1, _p(cols), 1, N, _p(l.gw), K, None, None, ACT_NONE, 1.0,
+                              split, _p(self._work), s))
+            if li == 0 and not need_dx:
+                break
+            # dcols[kk][n] = sum_co W[co][kk] dZ[co][n]
+            dcols = torch.empty((K, N), dtype=torch.float32, device=g.device)
+            _ck(lib.zsur_gemm(K, N, l.cout, _p(l.wb), 1, K, _p(dzb), N, 1, _p(dcols), N, None, None, ACT_NONE, 1.0,
+                              1, None, s))
+            if l.k == 3:
+                gin = torch.empty((l.cin, B, H, W), dtype=torch.float32, device=g.device)
+                _ck(lib.zsur_col2im(_p(dcols), l.cin, B, H, W, l.dil, _p(gin), s))
+            else:
+                gin = dcols.view(l.cin, B, H, W)
+            g = gin
+            if li == 0:
+                dx = gin
+        return dx
+
+    def adam_step(self, lr, b1=0.9, b2=0.999, eps=1e-8):
+        lib = load()
+        s = _stream()
+        self.t += 1
+        for l in self.layers:
+            _ck(lib.zsur_adam(_p(l.w), _p(l.gw), _p(l.mw), _p(l.vw), l.w.numel(), lr, b1, b2, eps, self.t,
+                              _p(l.wb), s))
+            _ck(lib.zsur_adam(_p(l.b), _p(l.gb), _p(l.mb), _p(l.vb), l.b.numel(), lr, b1, b2, eps, self.t, None,
+                              s))
+
+    def mse(self, pred, target):
+        """(loss tensor [1], d(loss)/d(pred)) for the mean squared error."""
+        import torch
+        d = torch.empty_like(pred)
+        loss = torch.empty(1, dtype=torch.float32, device=pred.device)
+        partial = torch.empty(1024, dtype=torch.float32, device=pred.device)
+        _ck(load().zsur_mse(_p(pred), _p(target.contiguous()), pred.numel(), _p(d), _p(loss), _p(partial),
+                            _stream()))
+        return loss, d
+
+
+# ---- zone <-> network representation
+
+def features(rho2d, nr, device="cuda"):
+    """Network input for a batch of 2-D patterns rho2d [B][nr][nphi]: channel 0
+    the pattern, channel 1 the normalised radial index."""
+    import torch
+    rho2d = torch.as_tensor(rho2d, dtype=torch.float32, device=device)
+    B, _, nphi = rho2d.shape
+    rr = (torch.arange(nr, dtype=torch.float32, device=device) / max(nr - 1, 1) - 0.5)
+    x = torch.empty((2, B, nr, nphi), dtype=torch.float32, device=device)
+    x[0] = rho2d
+    x[1] = rr[None, :, None].expand(B, nr, nphi)
+    return x
+
+
+def bloch_phases(wl):
+    """e^{-i m phi} at the E_r (phi_j) and E_phi (phi_{j+1/2}) sample points."""
+    tau = 2 * np.pi / wl.n_fold
+    dphi = tau / wl.nphi
+    j = np.arange(wl.nphi)
+    return np.exp(-1j * wl.m * j * dphi), np.exp(-1j * wl.m * (j + 0.5) * dphi)
+
+
+def plane_to_targets(plane, wl):
+    """Exit-plane DFT [K][2][nr][nphi] complex -> 4K real channels
+    [Re u_r, Im u_r, Re u_phi, Im u_phi per frequency] with u = E e^{-i m phi}."""
+    pr, pp = bloch_phases(wl)
+    plane = np.asarray(plane)
+    out = []
+    for k in range(plane.shape[0]):
+        ur, up = plane[k, 0] * pr[None, :], plane[k, 1] * pp[None, :]
+        out += [ur.real, ur.imag, up.real, up.imag]
+    return np.stack(out).astype(np.float32)
+
+
+def targets_to_plane(t, wl):
+    """Inverse of plane_to_targets (numpy, complex128)."""
+    pr, pp = bloch_phases(wl)
+    t = np.asarray(t, dtype=np.float64)
+    K = t.shape[0] // 4
+    plane = np.empty((K, 2, t.shape[1], t.shape[2]), np.complex128)
+    for k in range(K):
+        plane[k, 0] = (t[4 * k] + 1j * t[4 * k + 1]) / pr[None, :]
+        plane[k, 1] = (t[4 * k + 2] + 1j * t[4 * k + 3]) / pp[None, :]
+    return plane
+
+
+def random_patterns(n, nr, nphi, seed, sigma=2.5, beta=6.0):
+    """Seeded smoothed 2-D patterns in [0, 1] (periodic in phi), the kind of
+    grey density an optimiser passes through."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    out = np.empty((n, nr, nphi), np.float32)
+    for q in range(n):
+        f = gaussian_filter(rng.random((nr, nphi)), sigma=sigma, mode=("reflect", "wrap"))
+        f = (f - f.mean()) / max(f.std(), 1e-12)
+        out[q] = (0.5 + 0.5 * np.tanh(beta * 0.25 * f)).astype(np.float32)
+    return out
+
+
+def perturbed_patterns(base, n, radius, seed, sigma=2.5):
+    """n patterns inside the trust region around `base`: base + a smoothed
+    seeded perturbation of max-norm `radius`, clipped to [0, 1]."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    nr, nphi = base.shape
+    out = np.empty((n, nr, nphi), np.float32)
+    for q in range(n):
+        f = gaussian_filter(rng.standard_normal((nr, nphi)), sigma=sigma, mode=("reflect", "wrap"))
+        f *= radius * rng.uniform(0.3, 1.0) / max(np.abs(f).max(), 1e-12)
+        out[q] = np.clip(base + f, 0.0, 1.0).astype(np.float32)
+    return out
+
+
+def generate_samples(wl, patterns, zones_per_batch=8, log=None):
+    """FDTD exit-plane fields of every pattern (extruded through the design
+    layer), run as batches of zones of the workload's geometry."""
+    import torch
+    from . import zda
+    n = len(patterns)
+    nd = wl.design[1] - wl.design[0]
+    zb = min(zones_per_batch, n)
+    zones = [zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps()) for _ in range(zb)]
+    batch = zda.Batch(zones)
+    src = zda.preset_source(k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+    out = np.empty((n, 4 * len(wl.omegas), wl.nr, wl.nphi), np.float32)
+    for q0 in range(0, n, zb):
+        qs = list(range(q0, min(n, q0 + zb)))
+        for z, q in zip(zones, qs):
+            z.set_design(np.repeat(patterns[q][None], nd, axis=0))
+        batch.run([src] * len(zones), wl.steps, wl.omegas)
+        for z, q in zip(zones, qs):
+            out[q] = plane_to_targets(z.dft(zda.MON_PLANE).cpu().numpy(), wl)
+        if log:
+            log("samples %d/%d" % (qs[-1] + 1, n))
+    torch.cuda.synchronize()
+    batch.close()
+    for z in zones:
+        z.close()
+    return out
+
+
+def train(net, X, T, iters, batch=16, lr=2e-3, lr_end=2e-4, seed=0, log=None):
+    """Adam on the MSE between net(X) and T (device tensors, samples along
+    dimension 1), with a geometric learning-rate decay."""
+    import torch
+    rng = np.random.default_rng(seed)
+    n = X.shape[1]
+    losses = []
+    for it in range(iters):
+        idx = torch.as_tensor(rng.choice(n, size=min(batch, n), replace=False), device=X.device)
+        xb = X[:, idx].contiguous()
+        tb = T[:, idx].contiguous()
+        y = net.forward(xb, keep=True)
+        loss, d = net.mse(y, tb)
+        net.backward(d)
+        net.adam_step(lr * (lr_end / lr) ** (it / max(iters - 1, 1)))
+        if it % 50 == 0 or it == iters - 1:
+            losses.append((it, float(loss.item())))
+            if log:
+                log("train it %d loss %.4e" % losses[-1])
+    return losses
+
+
+def field_errors(net, X, T, wl, scale):
+    """Relative L2 error of the predicted complex exit-plane fields per sample."""
+    errs = []
+    for q in range(X.shape[1]):
+        y = net.forward(X[:, q:q + 1].contiguous()).cpu().numpy()[:, 0] * scale
+        t = T[:, q].cpu().numpy() * scale
+        a, b = targets_to_plane(y, wl), targets_to_plane(t, wl)
+        errs.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+    return np.array(errs)
+
+
+def design_loop(net, wl, rho0, weights, scale, iters, check_every, lr=0.02, zone=None, log=None, base_fields=None,
+                radius=None):
+    """Inner design iterations on the surrogate: maximise the focal objective
+    F = sum_k |sum W_k E_k|^2 over a 2-D pattern (Adam on rho, clipped to
+    [0, 1] and, with `radius`, to the trust region |rho - rho0| <= radius);
+    the network predicts the fields, or with `base_fields` (targets of rho0,
+    the same channel layout) their change from rho0.  Every check_every-th
+    iterate the FDTD evaluates F at the same pattern.  Returns the pattern,
+    seconds per surrogate iteration and the checks."""
+    import torch
+    from . import zda
+    Wt = torch.as_tensor(weights, dtype=torch.complex64, device="cuda")
+    pr, pp = bloch_phases(wl)
+    ph = torch.as_tensor(np.stack([1 / pr, 1 / pp]), dtype=torch.complex64, device="cuda")   # e^{+i m phi}
+    rho = torch.as_tensor(rho0, dtype=torch.float32, device="cuda").clone()
+    lo = hi = None
+    if radius is not None:
+        lo = (rho - radius).clamp(0.0, 1.0)
+        hi = (rho + radius).clamp(0.0, 1.0)
+    base = None
+    if base_fields is not None:
+        base = torch.as_tensor(base_fields, dtype=torch.float32, device="cuda")
+    m = torch.zeros_like(rho)
+    v = torch.zeros_like(rho)
+    nd = wl.design[1] - wl.design[0]
+    K = len(wl.omegas)
+    checks = []
+    t_sur = 0.0
+    for it in range(1, iters + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = features(rho[None], wl.nr)
+        x.requires_grad_(False)
+        y = net.forward(x, keep=True)
+        yv = y[:, 0].detach().clone().requires_grad_(True)
+        tv = yv if base is None else yv + base
+        u = torch.complex(tv[0::2], tv[1::2]).view(K, 2, wl.nr, wl.nphi) * scale
+        plane = u * ph[None, :, None, :]
+        a = (Wt * plane).sum(dim=(1, 2, 3))
+        F = (a.abs() ** 2).sum()
+        F.backward()
+        dy = (-yv.grad).contiguous()[:, None]       # ascend F: descend -F
+        dx = net.backward(dy, need_dx=True)
+        g = dx[0, 0]
+        lib = load()
+        _ck(lib.zsur_adam(_p(rho), _p(g.contiguous()), _p(m), _p(v), rho.numel(), lr, 0.9, 0.999, 1e-8, it, None,
+                          _stream()))
+        rho.clamp_(0.0, 1.0)
+        if lo is not None:
+            torch.maximum(rho, lo, out=rho)
+            torch.minimum(rho, hi, out=rho)
+        torch.cuda.synchronize()
+        t_sur += time.perf_counter() - t0
+        if zone is not None and (it % check_every == 0 or it == iters):
+            zone.set_design(np.repeat(rho.cpu().numpy()[None], nd, axis=0))
+            zone.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+            pl = zone.dft(zda.MON_PLANE)
+            a_true = (Wt * pl).sum(dim=(1, 2, 3))
+            F_true = float((a_true.abs() ** 2).sum().item())
+            checks.append({"iter": it, "F_surrogate": float(F.item()), "F_fdtd": F_true,
+                           "rel_gap": abs(float(F.item()) - F_true) / max(F_true, 1e-30)})
+            if log:
+                log("design it %d F_sur %.4e F_fdtd %.4e" % (it, float(F.item()), F_true))
+    return rho.cpu().numpy(), t_sur / iters, checks
+
+
+def fdtd_objective(zone, wl, rho2d, weights):
+    """The judge: F = sum_k |sum W_k E_k|^2 of the FDTD exit-plane fields of
+    the pattern rho2d extruded through the design layer."""
+    import torch
+    from . import zda
+    nd = wl.design[1] - wl.design[0]
+    zone.set_design(np.repeat(np.asarray(rho2d, np.float32)[None], nd, axis=0))
+    zone.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+    Wt = torch.as_tensor(weights, dtype=torch.complex64, device="cuda")
+    a = (Wt * zone.dft(zda.MON_PLANE)).sum(dim=(1, 2, 3))
+    return float((a.abs() ** 2).sum().item())
+
+
+def trust_region_design(net, wl, weights, rho0, zone, rounds=4, samples=96, radius=0.25, inner_iters=10,
+                        train_iters=600, lr=0.02, seed=0, log=None):
+    """Surrogate-accelerated design with the FDTD as judge.  Each round:
+    FDTD samples of perturbations (max-norm `radius`) around the current
+    base, fine-tuning of the network on the field change from the base,
+    `inner_iters` surrogate iterations inside the trust region, and one FDTD
+    evaluation of the candidate: accepted (radius x 1.5) if it raises the
+    FDTD objective, rejected (radius / 2) otherwise."""
+    import torch
+    base = np.asarray(rho0, np.float32)
+    F_base = fdtd_objective(zone, wl, base, weights)
+    hist = []
+    for r in range(rounds):
+        t0 = time.perf_counter()
+        pats = np.concatenate([base[None], perturbed_patterns(base, samples, radius, seed + 1000 * r)])
+        T = generate_samples(wl, pats)
+        t_gen = time.perf_counter() - t0
+        Tb, R = T[0], T[1:] - T[0][None]
+        scale = float(np.abs(R).std())
+        X = features(pats[1:], wl.nr)
+        Rt = torch.tensor(np.ascontiguousarray(np.moveaxis(R / scale, 0, 1)), device="cuda")
+        nh = max(4, samples // 8)             # held out for the field errors
+        t0 = time.perf_counter()
+        train(net, X[:, :-nh].contiguous(), Rt[:, :-nh].contiguous(), train_iters, seed=seed + r)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        errs = []
+        for q in range(samples - nh, samples):
+            y = net.forward(X[:, q:q + 1].contiguous()).cpu().numpy()[:, 0] * scale + Tb
+            a, b = targets_to_plane(y, wl), targets_to_plane(T[1 + q], wl)
+            errs.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+        cand, t_it, checks = design_loop(net, wl, base, weights, scale, inner_iters, inner_iters, lr=lr, zone=zone,
+                                         base_fields=Tb / scale, radius=radius)
+        F_cand = checks[-1]["F_fdtd"]
+        accept = F_cand > F_base
+        hist.append({"round": r, "radius": radius, "F_base": F_base, "F_candidate_fdtd": F_cand,
+                     "F_candidate_surrogate": checks[-1]["F_surrogate"], "accepted": bool(accept),
+                     "field_err_median": float(np.median(errs)), "field_err_p90": float(np.percentile(errs, 90)),
+                     "s_per_surrogate_iter": t_it, "sample_s": t_gen, "train_s": t_train})
+        if log:
+            log("round %d radius %.3f F %.4e -> %.4e (%s), field err median %.3f" %
+                (r, radius, F_base, F_cand, "accept" if accept else "reject", np.median(errs)))
+        if accept:
+            base, F_base = cand, F_cand
+            radius = min(radius * 1.5, 0.5)
+        else:
+            radius *= 0.5
+    return base, F_base, hist
+
+
+def plain_design(wl, weights, rho0, zone, iters, lr=0.02):
+    """Plain FDTD-adjoint design iterations on the same 2-D pattern space
+    (forward run, focal objective, adjoint run through torch.autograd, Adam
+    on rho clipped to [0, 1]).  Returns the pattern, the objective history
+    and seconds per iteration."""
+    import torch
+    from .autograd import zone_fdtd
+    nd = wl.design[1] - wl.design[0]
+    Wt = torch.as_tensor(weights, dtype=torch.complex64, device="cuda")
+    rho = torch.tensor(np.asarray(rho0, np.float32), device="cuda", requires_grad=True)
+    opt_m = torch.zeros_like(rho)
+    opt_v = torch.zeros_like(rho)
+    Fs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(1, iters + 1):
+        rho3 = rho[None].expand(nd, wl.nr, wl.nphi).contiguous()
+        plane = zone_fdtd(rho3, zone, nsteps=wl.steps, omegas=wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c,
+                          width=wl.width)
+        a = (Wt * plane).sum(dim=(1, 2, 3))
+        F = (a.abs() ** 2).sum()
+        (-F).backward()
+        with torch.no_grad():
+            g = rho.grad.contiguous()
+            _ck(load().zsur_adam(_p(rho), _p(g), _p(opt_m), _p(opt_v), rho.numel(), lr, 0.9, 0.999, 1e-8, it, None,
+                                 _stream()))
+            rho.clamp_(0.0, 1.0)
+        rho.grad = None
+        Fs.append(float(F.item()))
+    torch.cuda.synchronize()
+    return rho.detach().cpu().numpy(), Fs, (time.perf_counter() - t0) / iters
