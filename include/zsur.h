@@ -51,7 +51,8 @@ zsur_status zsur_gemm(int M, int N, int K, const uint16_t *A, long sam, long sak
                       int split, float *work, void *stream);
 
 /* cols[(c*9 + ky*3 + kx)][b*H*W + y*W + x] = bf16( x_in[c][b][y + d(ky-1)][(x + d(kx-1)) mod W] ),
- * zero where y + d(ky-1) is outside [0, H).  x_in FP32 [C][B][H][W]. */
+ * zero where y + d(ky-1) is outside [0, H).  x_in FP32 [C][B][H][W].
+ * B*H*W < 2^31 and C*9 <= 65535. */
 zsur_status zsur_im2col(const float *x, int C, int B, int H, int W, int dil, uint16_t *cols, void *stream);
 
 /* The adjoint of zsur_im2col: dx[c][b][y][x] = sum of dcols entries that
@@ -63,8 +64,9 @@ zsur_status zsur_col2im(const float *dcols, int C, int B, int H, int W, int dil,
 zsur_status zsur_act_grad(const float *y, const float *dy, float *dz, uint16_t *dzb, size_t n, float slope,
                           void *stream);
 
-/* out[m] = sum_n x[m*N + n] (FP32, fixed order). */
-zsur_status zsur_rowsum(const float *x, int M, int N, float *out, void *stream);
+/* out[m] = sum_n x[m*N + n] (FP32, fixed order: 64 slices per row summed
+ * in order); partial holds at least 64*M floats.  M <= 65535. */
+zsur_status zsur_rowsum(const float *x, int M, int N, float *out, float *partial, void *stream);
 
 /* Mean squared error: d[i] = 2 (p[i] - t[i]) / n, loss[0] = sum (p - t)^2 / n
  * (two-pass, fixed order; `partial` holds at least 1024 floats). */

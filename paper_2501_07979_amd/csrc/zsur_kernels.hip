@@ -60,10 +60,54 @@ __device__ __forceinline__ float act_apply(float v, int act, float slope)
 // result lane l, register r is C[4 (l / 16) + r][l % 16] of the 16 x 16 tile.
 constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;
 
+// operand tile loads: mode 1 and 2 read eight consecutive elements along the
+// operand's unit-stride index with one 16 B load (mode 1: along k, mode 2:
+// along the tile's row index m or n), mode 0 one element at a time
+__device__ __forceinline__ void tile_load(uint16_t (*S)[LDK], const uint16_t *__restrict__ P, long s_row, long s_k,
+                                          int mode, int r0, int R, int k0, int kend, int tid)
+{
+    if (mode == 1) {                  // k contiguous: row tid/4, eight k from (tid%4)*8
+        const int rr = tid >> 2, kk = (tid & 3) * 8;
+        const int gr = r0 + rr, gk = k0 + kk;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gr < R) {
+            if (gk + 7 < kend) {
+                v = *reinterpret_cast<const uint4 *>(P + (long)gr * s_row + gk);
+            } else {
+                uint16_t t[8];
+                for (int e = 0; e < 8; ++e) t[e] = (gk + e < kend) ? P[(long)gr * s_row + gk + e] : (uint16_t)0;
+                __builtin_memcpy(&v, t, sizeof v);
+            }
+        }
+        *reinterpret_cast<uint4 *>(&S[rr][kk]) = v;
+    } else if (mode == 2) {           // row index contiguous: k tid/8, eight rows from (tid%8)*8
+        const int kk = tid >> 3, rr = (tid & 7) * 8;
+        const int gr = r0 + rr, gk = k0 + kk;
+        uint16_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (gk < kend) {
+            if (gr + 7 < R) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(P + gr + (long)gk * s_k);
+                __builtin_memcpy(t, &v, sizeof t);
+            } else {
+                for (int e = 0; e < 8; ++e) t[e] = (gr + e < R) ? P[(long)(gr + e) + (long)gk * s_k] : (uint16_t)0;
+            }
+        }
+        for (int e = 0; e < 8; ++e) S[rr + e][kk] = t[e];
+    } else {
+        for (int e = tid; e < 64 * TK; e += 256) {
+            int rr, kk;
+            if (s_k == 1) { rr = e / TK; kk = e % TK; }
+            else { rr = e % 64; kk = e / 64; }
+            const int gr = r0 + rr, gk = k0 + kk;
+            S[rr][kk] = (gr < R && gk < kend) ? P[(long)gr * s_row + (long)gk * s_k] : (uint16_t)0;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const uint16_t *__restrict__ A, long sam,
                                                    long sak, const uint16_t *__restrict__ B, long sbk, long sbn,
                                                    float *C, long ldc, uint16_t *Cb, const float *bias, int act,
-                                                   float slope, int split, float *work)
+                                                   float slope, int split, float *work, int amode, int bmode)
 {
     __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
@@ -76,21 +120,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const ui
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        // operand tiles, the element order following the operand's unit stride
-        for (int e = tid; e < TM * TK; e += 256) {
-            int mm, kk;
-            if (sak == 1) { mm = e / TK; kk = e % TK; }
-            else { mm = e % TM; kk = e / TM; }
-            const int gm = m0 + mm, gk = k0 + kk;
-            As[mm][kk] = (gm < M && gk < kend) ? A[(long)gm * sam + (long)gk * sak] : (uint16_t)0;
-        }
-        for (int e = tid; e < TN * TK; e += 256) {
-            int nn, kk;
-            if (sbn == 1) { nn = e % TN; kk = e / TN; }
-            else { nn = e / TK; kk = e % TK; }
-            const int gn = n0 + nn, gk = k0 + kk;
-            Bs[nn][kk] = (gn < N && gk < kend) ? B[(long)gk * sbk + (long)gn * sbn] : (uint16_t)0;
-        }
+        tile_load(As, A, sam, sak, amode, m0, M, k0, kend, tid);
+        tile_load(Bs, B, sbn, sbk, bmode, n0, N, k0, kend, tid);
         __syncthreads();
         const int g8 = 8 * (lane >> 4), r16 = lane & 15;
         for (int i = 0; i < 2; ++i) {
@@ -135,21 +166,27 @@ __global__ void splitk_reduce(int M, int N, int split, const float *work, float 
     if (Cb) Cb[(long)m * ldc + n] = f2bf(v);
 }
 
+// grid: x over groups of four pixels, y over the C*9 rows of cols
 __global__ void im2col_kernel(const float *x, int C, int B, int H, int W, int dil, uint16_t *cols)
 {
-    const long N = (long)B * H * W;
-    const long total = (long)C * 9 * N;
-    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (long)gridDim.x * blockDim.x) {
-        const long n = q % N;
-        const int row = (int)(q / N);
-        const int c = row / 9, t = row % 9, ky = t / 3, kx = t % 3;
-        const int xw = (int)(n % W), y = (int)((n / W) % H), b = (int)(n / ((long)W * H));
+    const int N = B * H * W;
+    const int row = blockIdx.y;
+    const int c = row / 9, t = row % 9, ky = t / 3, kx = t % 3;
+    const int n0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (n0 >= N) return;
+    const float *xc = x + (size_t)c * N;
+    uint16_t *out = cols + (size_t)row * N;
+    int xw = n0 % W, y = (n0 / W) % H, b = n0 / (W * H);
+    for (int e = 0; e < 4 && n0 + e < N; ++e) {
         const int ys = y + dil * (ky - 1);
         int xs = (xw + dil * (kx - 1)) % W;
         if (xs < 0) xs += W;
-        float v = 0.f;
-        if (ys >= 0 && ys < H) v = x[(((long)c * B + b) * H + ys) * W + xs];
-        cols[q] = f2bf(v);
+        const float v = (ys >= 0 && ys < H) ? xc[((size_t)b * H + ys) * W + xs] : 0.f;
+        out[n0 + e] = f2bf(v);
+        if (++xw == W) {
+            xw = 0;
+            if (++y == H) { y = 0; ++b; }
+        }
     }
 }
 
@@ -199,11 +236,26 @@ __device__ float block_sum(float v)
     return r;
 }
 
-__global__ void rowsum_kernel(const float *x, int N, float *out)
+// two passes: block (m, p) sums slice p of row m, then one block per row
+// adds the slices in order
+constexpr int ROW_SLICES = 64;
+
+__global__ void rowsum_pass1(const float *x, int N, float *partial)
+{
+    const long m = blockIdx.y;
+    const int p = blockIdx.x;
+    const int len = (N + ROW_SLICES - 1) / ROW_SLICES;
+    const int lo = p * len, hi = min(N, lo + len);
+    float v = 0.f;
+    for (int n = lo + (int)threadIdx.x; n < hi; n += 256) v += x[m * N + n];
+    v = block_sum(v);
+    if (threadIdx.x == 0) partial[m * ROW_SLICES + p] = v;
+}
+
+__global__ void rowsum_pass2(const float *partial, float *out)
 {
     const long m = blockIdx.x;
-    float v = 0.f;
-    for (int n = threadIdx.x; n < N; n += 256) v += x[m * N + n];
+    float v = (int)threadIdx.x < ROW_SLICES ? partial[m * ROW_SLICES + threadIdx.x] : 0.f;
     v = block_sum(v);
     if (threadIdx.x == 0) out[m] = v;
 }
@@ -268,9 +320,18 @@ zsur_status zsur_gemm(int M, int N, int K, const uint16_t *A, long sam, long sak
     if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C || split < 1 || (split > 1 && !work))
         return fail(ZSUR_ERR_ARG, "zsur_gemm: bad sizes or pointers (M %d N %d K %d split %d)", M, N, K, split);
     hipStream_t s = (hipStream_t)stream;
+    // vector tile loads where the unit-stride index, the other stride and the
+    // base allow 16 B-aligned chunks of eight
+    auto mode = [](const uint16_t *P, long s_row, long s_k) {
+        if (((uintptr_t)P & 15u) != 0) return 0;
+        if (s_k == 1 && s_row % 8 == 0) return 1;
+        if (s_row == 1 && s_k % 8 == 0) return 2;
+        return 0;
+    };
+    const int amode = mode(A, sam, sak), bmode = mode(B, sbn, sbk);
     dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, split);
     hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, Cb, bias, act,
-                       slope, split, work);
+                       slope, split, work, amode, bmode);
     if (split > 1)
         hipLaunchKernelGGL(splitk_reduce, dim3(grid_for((size_t)M * N, 1u << 30)), dim3(256), 0, s, M, N, split,
                            work, C, ldc, Cb, bias, act, slope);
@@ -280,8 +341,10 @@ zsur_status zsur_gemm(int M, int N, int K, const uint16_t *A, long sam, long sak
 zsur_status zsur_im2col(const float *x, int C, int B, int H, int W, int dil, uint16_t *cols, void *stream)
 {
     if (C <= 0 || B <= 0 || H <= 0 || W <= 0 || dil < 1 || !x || !cols) return fail(ZSUR_ERR_ARG, "zsur_im2col");
-    hipLaunchKernelGGL(im2col_kernel, dim3(grid_for((size_t)C * 9 * B * H * W)), dim3(256), 0, (hipStream_t)stream,
-                       x, C, B, H, W, dil, cols);
+    if ((long)B * H * W > 0x7fffffffL || C * 9 > 65535) return fail(ZSUR_ERR_ARG, "zsur_im2col: too large");
+    const int N = B * H * W;
+    dim3 grid((unsigned)((N + 1023) / 1024), (unsigned)(C * 9));
+    hipLaunchKernelGGL(im2col_kernel, grid, dim3(256), 0, (hipStream_t)stream, x, C, B, H, W, dil, cols);
     return launched("zsur_im2col");
 }
 
@@ -302,10 +365,11 @@ zsur_status zsur_act_grad(const float *y, const float *dy, float *dz, uint16_t *
     return launched("zsur_act_grad");
 }
 
-zsur_status zsur_rowsum(const float *x, int M, int N, float *out, void *stream)
+zsur_status zsur_rowsum(const float *x, int M, int N, float *out, float *partial, void *stream)
 {
-    if (!x || !out || M <= 0 || N <= 0) return fail(ZSUR_ERR_ARG, "zsur_rowsum");
-    hipLaunchKernelGGL(rowsum_kernel, dim3(M), dim3(256), 0, (hipStream_t)stream, x, N, out);
+    if (!x || !out || !partial || M <= 0 || N <= 0 || M > 65535) return fail(ZSUR_ERR_ARG, "zsur_rowsum");
+    hipLaunchKernelGGL(rowsum_pass1, dim3(ROW_SLICES, M), dim3(256), 0, (hipStream_t)stream, x, N, partial);
+    hipLaunchKernelGGL(rowsum_pass2, dim3(M), dim3(256), 0, (hipStream_t)stream, partial, out);
     return launched("zsur_rowsum");
 }
 

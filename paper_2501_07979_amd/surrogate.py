@@ -50,7 +50,7 @@ def load():
     lib.zsur_im2col.argtypes = [P, I, I, I, I, I, P, P]
     lib.zsur_col2im.argtypes = [P, I, I, I, I, I, P, P]
     lib.zsur_act_grad.argtypes = [P, P, P, P, S, F, P]
-    lib.zsur_rowsum.argtypes = [P, I, I, P, P]
+    lib.zsur_rowsum.argtypes = [P, I, I, P, P, P]
     lib.zsur_mse.argtypes = [P, P, S, P, P, P, P]
     lib.zsur_to_bf16.argtypes = [P, P, S, P]
     lib.zsur_adam.argtypes = [P, P, P, P, S, F, F, F, F, I, P, P]
@@ -161,12 +161,14 @@ class Surrogate:
             dz = torch.empty_like(g)
             dzb = torch.empty(g.shape, dtype=torch.int16, device=g.device)
             _ck(lib.zsur_act_grad(_p(y), _p(g), _p(dz), _p(dzb), g.numel(), self.slope if l.act else 1.0, s))
-            _ck(lib.zsur_rowsum(_p(dz), l.cout, N, _p(l.gb), s))
             K = l.cin * (9 if l.k == 3 else 1)
-            split = max(1, min(64, N // 2048))
-            need = split * l.cout * K
+            # split-K over pixels: about 1024 blocks, at least 256 pixels per slice
+            tiles = ((l.cout + 63) // 64) * ((K + 63) // 64)
+            split = int(max(1, min((1024 + tiles - 1) // tiles, N // 256)))
+            need = max(split * l.cout * K, 64 * l.cout)
             if self._work is None or self._work.numel() < need:
                 self._work = torch.empty(need, dtype=torch.float32, device=g.device)
+            _ck(lib.zsur_rowsum(_p(dz), l.cout, N, _p(l.gb), _p(self._work), s))
             # dW[co][kk] = sum_n dZ[co][n] cols[kk][n]
             _ck(lib.zsur_gemm(l.cout, K, N, _p(dzb), N, 1, _p(cols), 1, N, _p(l.gw), K, None, None, ACT_NONE, 1.0,
                               split, _p(self._work), s))

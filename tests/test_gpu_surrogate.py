@@ -36,13 +36,14 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
 
 
+@pytest.mark.parametrize("dims", [(70, 130, 100), (72, 136, 104)])   # element-wise / 16 B tile loads
 @pytest.mark.parametrize("a_rowmajor", [True, False])
 @pytest.mark.parametrize("b_rowmajor", [True, False])
 @pytest.mark.parametrize("split", [1, 3])
-def test_gemm_every_layout_matches_fp64(sur, a_rowmajor, b_rowmajor, split):
+def test_gemm_every_layout_matches_fp64(sur, a_rowmajor, b_rowmajor, split, dims):
     import torch
     from oracle.surrogate_ref import bf16_round
-    M, N, K = 70, 130, 100
+    M, N, K = dims
     rng = np.random.default_rng(7 + 2 * a_rowmajor + b_rowmajor + 5 * split)
     a_bits, a_val = _bf16_bits(rng.standard_normal((M, K)))
     b_bits, b_val = _bf16_bits(rng.standard_normal((K, N)))
