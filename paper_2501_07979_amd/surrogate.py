@@ -504,3 +504,29 @@ def plain_design(wl, weights, rho0, zone, iters, lr=0.02):
         Fs.append(float(F.item()))
     torch.cuda.synchronize()
     return rho.detach().cpu().numpy(), Fs, (time.perf_counter() - t0) / iters
+
+
+def bench_train(steps=60, batch=16, width=48, size=64, seed=0):
+    """Times training steps of the surrogate on seeded random data of the
+    design-zone shape (2 input channels, 12 outputs, size x size)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    X = torch.tensor(rng.standard_normal((2, batch * 4, size, size)).astype(np.float32), device="cuda")
+    T = torch.tensor(rng.standard_normal((12, batch * 4, size, size)).astype(np.float32), device="cuda")
+    net = Surrogate(in_ch=2, width=width, out_ch=12, seed=1)
+    train(net, X, T, 5, batch=batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    train(net, X, T, steps, batch=batch)
+    torch.cuda.synchronize()
+    return {"params": net.n_params(), "batch": batch, "ms_per_step": 1e3 * (time.perf_counter() - t0) / steps}
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="design-surrogate training benchmark")
+    ap.add_argument("--bench-train", type=int, default=60, help="timed training steps")
+    ap.add_argument("--batch", type=int, default=16)
+    args = ap.parse_args()
+    print(json.dumps(bench_train(args.bench_train, args.batch)))
