@@ -81,9 +81,11 @@ enum { ZAUX_HR, ZAUX_HP, ZAUX_ER, ZAUX_EP, N_AUX_Z };
 void launch_h_step(const StepArgs &a, int n, hipStream_t s);
 void launch_e_step(const StepArgs &a, int n, hipStream_t s);
 void launch_fused_step(const StepArgs &a, int n, hipStream_t s);
-// two leap-frog steps (n, n + 1) over the tiles listed in a.tiles; pml selects
-// the instantiation with the layer recursions
-void launch_two_step(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s);
+// two leap-frog steps (n, n + 1) over the tiles listed in a.tiles; lay 0
+// runs the instantiation without layer recursions (tiles whose computed rows
+// and planes hold no layer cell), any other value the one with the r- and
+// z-layer recursions
+void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream_t s);
 // a two-step tile owns 61 phi cells, up to TR rows and a range of planes
 constexpr int TWO_STEP_COLS = 61;
 void launch_fill(float2 *p, size_t n, hipStream_t s);
@@ -92,7 +94,7 @@ unsigned tiles_split(const StepArgs &a, int BY);
 unsigned tiles_fused(const StepArgs &a, int TR);
 void launch_batch_step(const BatchArgs &b, unsigned nblocks, int tile_rows, bool fused, int n_rel, hipStream_t s);
 // two steps of every zone of a batch over the tiles listed in b.tiles
-void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, bool pml, int n_rel, hipStream_t s);
+void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, int lay, int n_rel, hipStream_t s);
 void launch_advance_step(int *n_base, int by, hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);
 void launch_design_dt(float *ceps, const float *rho, size_t n, double eps_bg, double eps_hi, double dt,

@@ -607,11 +607,13 @@ __device__ __forceinline__ PlaneIn load_plane(const StepArgs &a, int k, size_t p
 // block computes halo cells with the same inputs and the same arithmetic as
 // their owner, so the level-(n+1) auxiliaries that step one writes to the
 // intermediate set are identical whichever block writes them.
-template <int TR, bool PML>
+template <int TR, int LAY>
 __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
 {
+    // LAY bit 0: the tile's rows include r-layer rows; bit 1: its planes include z-layer planes
+    constexpr bool PR = (LAY & 1) != 0, PZ = (LAY & 2) != 0;
     constexpr int NW = TR + 3;
-    constexpr int NV = PML ? NW : 1;
+    constexpr int NV = PR ? NW : 1;
     __shared__ float2 s1z[NW][64], s1r[NW][64], s1p[NW][64], s1v[NV][64];
     __shared__ float2 sEz[2][NW][64], sEr[2][NW][64], sEp[2][NW][64], sU[2][NV][64];
     __shared__ float2 s2z[NW][64], s2r[NW][64], s2p[NW][64], s2v[NV][64];
@@ -632,8 +634,8 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
     const bool own = lane >= 2 && lane <= 62 && jj < nphi && w >= 2 && w <= nrow + 1 && row_ok;
     const int k_lo = max(kb - 2, 0);
     const bool nt = a.nt_stores;
-    const int ir = (PML && row_ok) ? slab_row(i, nr, a.pr0, a.pr1) : -1;
-    const int ir1 = (PML && row_ok && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
+    const int ir = (PR && row_ok) ? slab_row(i, nr, a.pr0, a.pr1) : -1;
+    const int ir1 = (PR && row_ok && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
     const RowCoef rc = a.rows[row_ok ? i : 0];
     const int ic = min(max(i, 0), nr - 1);
     const unsigned o = (unsigned)pc * 8u;
@@ -654,13 +656,14 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
     float2 e1r_p = zero2(), e1p_p = zero2(), e1z_p = zero2(), u1_p = zero2();
     float2 h2r_km = zero2(), h2p_km = zero2();
     float ce_p = 0.f;
-    // without layer recursions the next plane's loads are issued one plane
-    // ahead, so they are in flight through this plane's barriers and updates
+    // the next plane's loads are issued one plane ahead (where the registers
+    // allow), so they are in flight through this plane's barriers and updates
+    constexpr bool PF = !PR;
     PlaneIn cur = load_plane(a, k_lo, plane, rowc, dip, o, ojp, oc);
     for (int k = k_lo; k <= ke; ++k) {
         const int km = k - 1;
         PlaneIn in;
-        if (PML) {
+        if (!PF) {
             in = load_plane(a, min(k, nz - 1), plane, rowc, dip, o, ojp, oc);
         } else {
             in = cur;
@@ -677,7 +680,7 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
         AuxRows x1 = {};
         float2 ez0 = zero2();
         if (step1 && active) {
-            kz = PML ? slab_row(k, nz, a.pz0, a.pz1) : -1;
+            kz = PZ ? slab_row(k, nz, a.pz0, a.pz1) : -1;
             if (kz >= 0) zc = a.zrows[k];
             const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
             const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
@@ -705,7 +708,7 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
             s1z[w][lane] = h1z;
             s1r[w][lane] = h1r;
             s1p[w][lane] = h1p;
-            if (PML) s1v[w][lane] = v1;
+            if (PR) s1v[w][lane] = v1;
         }
         __syncthreads();
         // ---- step one, E^{n+1} at plane k (exact on lanes >= 1, waves >= 1)
@@ -714,7 +717,7 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
                 float2 hz_jm = s1z[w][lane - 1], hr_jm = s1r[w][lane - 1];
                 if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
                 const float2 hz_im = s1z[w - 1][lane], hp_im = s1p[w - 1][lane];
-                const float2 v_im = PML ? s1v[PML ? w - 1 : 0][lane] : zero2();
+                const float2 v_im = PR ? s1v[PR ? w - 1 : 0][lane] : zero2();
                 float2 jr = zero2(), jph = zero2();
                 if (k == a.k_src) sheet_current(a, n, plane, rowc, o, jr, jph);
                 e1r = er0;
@@ -726,12 +729,12 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
             sEz[k & 1][w][lane] = e1z;
             sEr[k & 1][w][lane] = e1r;
             sEp[k & 1][w][lane] = e1p;
-            if (PML) sU[k & 1][PML ? w : 0][lane] = u1;
+            if (PR) sU[k & 1][PR ? w : 0][lane] = u1;
         }
         // ---- step two, H^{n+3/2} at plane km (exact on lanes 1..62, waves 1..TR+1)
         float2 h2r = zero2(), h2p = zero2(), h2z = zero2(), v2 = zero2();
         const bool h2_plane = km >= 0 && (km > k_lo || km == 0);
-        const int kz2 = (PML && km >= 0) ? slab_row(km, nz, a.pz0, a.pz1) : -1;
+        const int kz2 = (PZ && km >= 0) ? slab_row(km, nz, a.pz0, a.pz1) : -1;
         ZCoef zc2 = {};
         if (kz2 >= 0) zc2 = a.zrows[km];
         const size_t c0m = (size_t)max(km, 0) * plane + rowc;
@@ -746,7 +749,7 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
             float2 ez_ip = sEz[b][w + 1][lane], ep_ip = sEp[b][w + 1][lane];
             if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
             float2 uu1 = zero2();
-            if (PML && ir1 >= 0) uu1 = sU[b][PML ? w + 1 : 0][lane];
+            if (PR && ir1 >= 0) uu1 = sU[b][PR ? w + 1 : 0][lane];
             h2r = h1r_p;
             h2p = h1p_p;
             h2z = h1z_p;
@@ -757,14 +760,14 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
         s2z[w][lane] = h2z;
         s2r[w][lane] = h2r;
         s2p[w][lane] = h2p;
-        if (PML) s2v[w][lane] = v2;
+        if (PR) s2v[w][lane] = v2;
         __syncthreads();
         // ---- step two, E^{n+2} at plane km (owners), stores and DFT
         if (store) {
             float2 hz_jm = s2z[w][lane - 1], hr_jm = s2r[w][lane - 1];
             if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
             const float2 hz_im = s2z[w - 1][lane], hp_im = s2p[w - 1][lane];
-            const float2 v_im = PML ? s2v[PML ? w - 1 : 0][lane] : zero2();
+            const float2 v_im = PR ? s2v[PR ? w - 1 : 0][lane] : zero2();
             float2 jr = zero2(), jph = zero2();
             if (km == a.k_src) sheet_current(a, n + 1, plane, rowc, o, jr, jph);
             float2 er2 = e1r_p, ep2 = e1p_p, ez2 = e1z_p, u2;
@@ -843,10 +846,10 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int
     eh_fused_body<TR>(a, n, p, gx, gy);
 }
 
-template <int TR, bool PML>
+template <int TR, int LAY>
 __global__ __launch_bounds__(64 * (TR + 3)) void eh2_kernel(StepArgs a, int n)
 {
-    eh2_body<TR, PML>(a, n, a.tiles[blockIdx.x]);
+    eh2_body<TR, LAY>(a, n, a.tiles[blockIdx.x]);
 }
 
 // Batched launches: one 1-D grid covers the tiles of many zones of uneven
@@ -895,13 +898,13 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_batch(BatchArgs b, int
     eh_fused_body<TR>(a, n, g - b.prefix[zi], gx, gy);
 }
 
-template <int TR, bool PML>
+template <int TR, int LAY>
 __global__ __launch_bounds__(64 * (TR + 3)) void eh2_batch(BatchArgs b, int n_rel)
 {
     const uint4 tile = b.tiles[blockIdx.x];
     const StepArgs a = b.tab[tile.w];
     const int n = n_rel + (b.n_base ? *b.n_base : 0);
-    eh2_body<TR, PML>(a, n, tile);
+    eh2_body<TR, LAY>(a, n, tile);
 }
 
 __global__ void advance_step_kernel(int *n_base, int by)
@@ -1036,36 +1039,34 @@ void launch_fused_step(const StepArgs &a, int n, hipStream_t s)
 void launch_e_step(const StepArgs &a, int n, hipStream_t s) { launch_step(a, n, s, false); }
 
 template <int TR>
-void launch_two_tr(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s)
+void launch_batch_two_tr(const BatchArgs &b, unsigned ntiles, int lay, int n_rel, hipStream_t s)
 {
     dim3 block(64, TR + 3, 1);
-    if (pml) hipLaunchKernelGGL((eh2_kernel<TR, true>), dim3(ntiles), block, 0, s, a, n);
-    else hipLaunchKernelGGL((eh2_kernel<TR, false>), dim3(ntiles), block, 0, s, a, n);
+    if (lay == 0) hipLaunchKernelGGL((eh2_batch<TR, 0>), dim3(ntiles), block, 0, s, b, n_rel);
+    else hipLaunchKernelGGL((eh2_batch<TR, 3>), dim3(ntiles), block, 0, s, b, n_rel);
+}
+
+void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, int lay, int n_rel, hipStream_t s)
+{
+    if (ntiles == 0) return;
+    if (tile_rows == 13) launch_batch_two_tr<13>(b, ntiles, lay, n_rel, s);
+    else launch_batch_two_tr<5>(b, ntiles, lay, n_rel, s);
 }
 
 template <int TR>
-void launch_batch_two_tr(const BatchArgs &b, unsigned ntiles, bool pml, int n_rel, hipStream_t s)
+void launch_two_tr(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream_t s)
 {
     dim3 block(64, TR + 3, 1);
-    if (pml) hipLaunchKernelGGL((eh2_batch<TR, true>), dim3(ntiles), block, 0, s, b, n_rel);
-    else hipLaunchKernelGGL((eh2_batch<TR, false>), dim3(ntiles), block, 0, s, b, n_rel);
+    if (lay == 0) hipLaunchKernelGGL((eh2_kernel<TR, 0>), dim3(ntiles), block, 0, s, a, n);
+    else hipLaunchKernelGGL((eh2_kernel<TR, 3>), dim3(ntiles), block, 0, s, a, n);
 }
 
-void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, bool pml, int n_rel, hipStream_t s)
+void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream_t s)
 {
     if (ntiles == 0) return;
-    if (tile_rows == 13) launch_batch_two_tr<13>(b, ntiles, pml, n_rel, s);
-    else launch_batch_two_tr<5>(b, ntiles, pml, n_rel, s);
+    if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, lay, s);
+    else launch_two_tr<5>(a, n, ntiles, lay, s);
 }
-
-void launch_two_step(const StepArgs &a, int n, unsigned ntiles, bool pml, hipStream_t s)
-{
-    if (ntiles == 0) return;
-    if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, pml, s);
-    else launch_two_tr<5>(a, n, ntiles, pml, s);
-}
-
-
 
 unsigned tiles_split(const StepArgs &a, int BY)
 {

@@ -94,7 +94,7 @@ struct zda_zone {
     uint4 *tiles2 = nullptr;
     size_t cap_tiles2 = 0;
     bool has_m = false;
-    unsigned n_int = 0, n_pml = 0;
+    unsigned n_int = 0, n_pml = 0, n_lay[4] = {0, 0, 0, 0};
     int tiles_tr = 0, tiles_kc = 0, tiles_src = -1, k_src_last = -1, tiles_xcd = -1;
     size_t int_cells = 0, int_mon_cells = 0, int_src_cells = 0;
     RowCoef *rows = nullptr;
@@ -366,7 +366,9 @@ void split_range(int lo, int hi, int len, std::vector<std::pair<int, int>> &out)
 // the layers.  The fourth word of each descriptor is `tag` (the zone's index
 // in a batch).
 struct TwoStepTiles {
-    std::vector<uint4> in, lay;
+    // by the layer recursions a tile runs: [0] none, [3] the r- and z-layer
+    // recursions ([1] and [2] stay empty)
+    std::vector<uint4> v[4];
     size_t cells = 0, mon = 0, src = 0;   // owned by the interior tiles
 };
 
@@ -389,24 +391,27 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, bool xcd, unsi
     const size_t z_in1 = planes.size();
     split_range(zB, d.nz, kc, planes);
     const int gx = (d.nphi + TWO_STEP_COLS - 1) / TWO_STEP_COLS;
-    std::vector<uint4> in, lay;
+    std::vector<uint4> v[4];
     for (size_t pz = 0; pz < planes.size(); ++pz) {
         const int kb = planes[pz].first, ke = planes[pz].second;
+        const bool zl = !(pz >= z_in0 && pz < z_in1);
         for (size_t pr = 0; pr < rows.size(); ++pr) {
             const int i0 = rows[pr].first, nrow = rows[pr].second - rows[pr].first;
-            const bool interior = pz >= z_in0 && pz < z_in1 && pr >= r_in0 && pr < r_in1;
+            const bool rl = !(pr >= r_in0 && pr < r_in1);
+            // every tile with layer cells goes to one launch of the full
+            // instantiation: separate launches for the z-only and r-only tiles
+            // (leaner instantiations) measured slower on the 512 x 1024 x 400
+            // zone, their partly filled last rounds outweighing the gain
+            const int lay = (rl || zl) ? 3 : 0;
             for (int bx = 0; bx < gx; ++bx) {
-                const uint4 q = make_uint4((unsigned)bx, (unsigned)i0 | ((unsigned)nrow << 16),
-                                           (unsigned)kb | ((unsigned)ke << 16), tag);
-                if (interior) {
-                    in.push_back(q);
+                v[lay].push_back(make_uint4((unsigned)bx, (unsigned)i0 | ((unsigned)nrow << 16),
+                                            (unsigned)kb | ((unsigned)ke << 16), tag));
+                if (lay == 0) {
                     const int j0 = bx * TWO_STEP_COLS;
                     const size_t cols = (size_t)(std::min(j0 + TWO_STEP_COLS, d.nphi) - j0);
                     t.cells += (size_t)nrow * cols * (size_t)(ke - kb);
                     if (d.k_mon >= kb && d.k_mon < ke) t.mon += (size_t)nrow * cols;
                     if (k_src >= kb && k_src < ke) t.src += (size_t)nrow * cols;
-                } else {
-                    lay.push_back(q);
                 }
             }
         }
@@ -414,8 +419,8 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, bool xcd, unsi
     // with ZDA_OPT_XCD_REMAP, each of the eight XCDs (which take the blocks
     // of a launch round-robin) sweeps one contiguous range of the list, so
     // tiles that share halo rows and columns meet in one L2
-    auto xcd_order = [](std::vector<uint4> &v) {
-        const size_t nb = v.size();
+    auto xcd_order = [](std::vector<uint4> &u) {
+        const size_t nb = u.size();
         if (nb < 8) return;
         std::vector<uint4> o(nb);
         const size_t per = nb / 8, rem = nb % 8;
@@ -423,16 +428,14 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, bool xcd, unsi
         for (size_t s = 0; b < nb; ++s)
             for (size_t x = 0; x < 8 && b < nb; ++x) {
                 const size_t len = per + (x < rem ? 1 : 0);
-                if (s < len) o[b++] = v[x * per + std::min(x, rem) + s];
+                if (s < len) o[b++] = u[x * per + std::min(x, rem) + s];
             }
-        v.swap(o);
+        u.swap(o);
     };
-    if (xcd) {
-        xcd_order(in);
-        xcd_order(lay);
+    for (int q = 0; q < 4; ++q) {
+        if (xcd) xcd_order(v[q]);
+        t.v[q].insert(t.v[q].end(), v[q].begin(), v[q].end());
     }
-    t.in.insert(t.in.end(), in.begin(), in.end());
-    t.lay.insert(t.lay.end(), lay.begin(), lay.end());
 }
 
 // The zone's own tile list (interior tiles first), rebuilt when the launch
@@ -445,13 +448,16 @@ zda_status build_two_step_tiles(zda_zone *z)
         return ZDA_OK;
     TwoStepTiles t;
     two_step_tiles(z, TR, kc, z->k_src_last, z->xcd_remap != 0, 0u, t);
-    std::vector<uint4> all = t.in;
-    all.insert(all.end(), t.lay.begin(), t.lay.end());
+    std::vector<uint4> all;
+    for (int q = 0; q < 4; ++q) {
+        z->n_lay[q] = (unsigned)t.v[q].size();
+        all.insert(all.end(), t.v[q].begin(), t.v[q].end());
+    }
     zda_status st = ensure(z, &z->tiles2, &z->cap_tiles2, all.size());
     if (st != ZDA_OK) return st;
     HIP_TRY(hipMemcpy(z->tiles2, all.data(), all.size() * sizeof(uint4), hipMemcpyHostToDevice));
-    z->n_int = (unsigned)t.in.size();
-    z->n_pml = (unsigned)t.lay.size();
+    z->n_int = z->n_lay[0];
+    z->n_pml = z->n_lay[1] + z->n_lay[2] + z->n_lay[3];
     z->int_cells = t.cells;
     z->int_mon_cells = t.mon;
     z->int_src_cells = t.src;
@@ -494,6 +500,16 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
         HIP_TRY(hipEventCreateWithFlags(&z->ev_fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&z->ev_join, hipEventDisableTiming));
     }
+    // the three layer-tile lists (r rows only, z planes only, both), each
+    // with its own instantiation
+    auto layer_launches = [&](StepArgs b, int n, hipStream_t st) {
+        size_t off = z->n_lay[0];
+        for (int q = 1; q < 4; ++q) {
+            b.tiles = z->tiles2 + off;
+            launch_two_step(b, n, z->n_lay[q], q, st);
+            off += z->n_lay[q];
+        }
+    };
     auto two_steps = [&](int n, hipEvent_t *ev) -> zda_status {
         StepArgs b = ab[z->cur ^ ab_base];
         hipStream_t sl = s;
@@ -501,22 +517,20 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
             HIP_TRY(hipEventRecord(z->ev_fork, s));
             HIP_TRY(hipStreamWaitEvent(z->s2, z->ev_fork, 0));
             sl = z->s2;
-            b.tiles = z->tiles2 + z->n_int;
             if (ev) HIP_TRY(hipEventRecord(ev[2], sl));
-            launch_two_step(b, n, z->n_pml, true, sl);
+            layer_launches(b, n, sl);
             if (ev) HIP_TRY(hipEventRecord(ev[3], sl));
         }
         b.tiles = z->tiles2;
         if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-        launch_two_step(b, n, z->n_int, false, s);
+        launch_two_step(b, n, z->n_int, 0, s);
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
         if (conc) {
             HIP_TRY(hipEventRecord(z->ev_join, sl));
             HIP_TRY(hipStreamWaitEvent(s, z->ev_join, 0));
         } else {
             if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-            b.tiles = z->tiles2 + z->n_int;
-            launch_two_step(b, n, z->n_pml, true, s);
+            layer_launches(b, n, s);
             if (ev) HIP_TRY(hipEventRecord(ev[3], s));
         }
         z->cur ^= 1;
@@ -1233,15 +1247,18 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
         b->h_prefix[i] = total;
         if (!b->two) total += b->fused ? tiles_fused(ab[i][0], b->tile_rows) : tiles_split(ab[i][0], b->tile_rows);
     }
-    unsigned n_in = 0, n_lay = 0;
+    unsigned n_lay[4] = {0, 0, 0, 0};
     if (b->two) {
         TwoStepTiles t;
         for (int i = 0; i < nz; ++i) {
             const zda_zone *z = b->zones[i];
             two_step_tiles(z, b->tile_rows, z->kchunk, ab[i][0].k_src, z->xcd_remap != 0, (unsigned)i, t);
         }
-        std::vector<uint4> all = t.in;
-        all.insert(all.end(), t.lay.begin(), t.lay.end());
+        std::vector<uint4> all;
+        for (int q = 0; q < 4; ++q) {
+            n_lay[q] = (unsigned)t.v[q].size();
+            all.insert(all.end(), t.v[q].begin(), t.v[q].end());
+        }
         if (all.size() > b->cap_tiles) {
             if (b->tiles) (void)hipFree(b->tiles);
             b->tiles = nullptr;
@@ -1250,8 +1267,6 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
             b->cap_tiles = all.size();
         }
         HIP_TRY(hipMemcpyAsync(b->tiles, all.data(), all.size() * sizeof(uint4), hipMemcpyHostToDevice, s));
-        n_in = (unsigned)t.in.size();
-        n_lay = (unsigned)t.lay.size();
         HIP_TRY(hipStreamSynchronize(s));   // the staging vector goes out of scope
     }
     if ((size_t)nz > b->cap) {
@@ -1280,10 +1295,12 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
     // then their layer tiles; the pair alternates buffer parities
     auto two_pair = [&](int q, hipStream_t st) {
         BatchArgs x = ba[(q / 2) & 1];
-        x.tiles = b->tiles;
-        launch_batch_two(x, n_in, b->tile_rows, false, q, st);
-        x.tiles = b->tiles + n_in;
-        launch_batch_two(x, n_lay, b->tile_rows, true, q, st);
+        size_t off = 0;
+        for (int l = 0; l < 4; ++l) {
+            x.tiles = b->tiles + off;
+            launch_batch_two(x, n_lay[l], b->tile_rows, l, q, st);
+            off += n_lay[l];
+        }
     };
     const int S = b->graph_steps;
     const int reps = nsteps >= 2 * S ? nsteps / S : 0;
