@@ -57,7 +57,8 @@ class _Params(ctypes.Structure):
                 ("pml_r_in", ctypes.c_int), ("pml_r_out", ctypes.c_int),
                 ("pml_z_lo", ctypes.c_int), ("pml_z_hi", ctypes.c_int),
                 ("pml_order", ctypes.c_double), ("pml_sigma_max_r", ctypes.c_double),
-                ("pml_sigma_max_z", ctypes.c_double), ("pml_alpha", ctypes.c_double)]
+                ("pml_sigma_max_z", ctypes.c_double), ("pml_alpha", ctypes.c_double),
+                ("axis", ctypes.c_int)]
 
 
 _lib = None
@@ -122,7 +123,7 @@ class OracleZone:
 
     def __init__(self, *, r_in, nr, nphi, nz, n_fold, m, dr=1.0, dz=1.0, courant=0.5,
                  pml=(0, 0, 0, 0), pml_order=3.0, pml_sigma_max=(0.0, 0.0), pml_alpha=0.05,
-                 k_mon=None, design=None, eps_bg=1.0, eps_hi=6.25, eps=None):
+                 k_mon=None, design=None, eps_bg=1.0, eps_hi=6.25, eps=None, axis=0):
         self.r_in, self.nr, self.nphi, self.nz = float(r_in), int(nr), int(nphi), int(nz)
         self.n_fold, self.m = int(n_fold), int(m)
         self.dr, self.dz, self.courant = float(dr), float(dz), float(courant)
@@ -130,16 +131,18 @@ class OracleZone:
         self.k_mon = k_mon
         self.design = design            # (k0, k1) or None
         self.eps_bg, self.eps_hi = float(eps_bg), float(eps_hi)
+        self.axis = int(axis)
         p = _Params(self.r_in, self.dr, self.dz, self.courant, self.nr, self.nphi, self.nz,
                     self.n_fold, *self.pml, float(pml_order), float(pml_sigma_max[0]),
-                    float(pml_sigma_max[1]), float(pml_alpha))
+                    float(pml_sigma_max[1]), float(pml_alpha), self.axis)
         lib = _load()
         self._h = lib.ora_create(ctypes.byref(p))
         if not self._h:
             raise ValueError("oracle: bad zone parameters")
         self.dt = lib.ora_dt(self._h)
-        self.dphi = 2.0 * np.pi / (self.n_fold * self.nphi)
-        self.tau = 2.0 * np.pi / self.n_fold
+        # continuous zone (n_fold = 0, nphi = 1): dphi = tau = 1, seams 1 +- i m
+        self.dphi = 2.0 * np.pi / (self.n_fold * self.nphi) if self.n_fold > 0 else 1.0
+        self.tau = 2.0 * np.pi / self.n_fold if self.n_fold > 0 else 1.0
         self.shape = (self.nz, self.nr, self.nphi)
         self.eps = np.ones(self.shape, np.float32)
         if eps is not None:
@@ -203,6 +206,8 @@ class OracleZone:
         m = self.m if m is None else m
         phi_j = np.arange(self.nphi) * self.dphi
         phi_h = (np.arange(self.nphi) + 0.5) * self.dphi
+        if self.n_fold == 0:            # continuous zone: every component at phi = 0
+            phi_j = phi_h = np.zeros(self.nphi)
         pat = np.zeros((2, self.nr, self.nphi), np.complex128)
         if kind == "plane_circ":
             if abs(m) != 1:

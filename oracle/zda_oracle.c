@@ -26,6 +26,17 @@
  *  All six arrays are complex, [nz][nr][nphi], phi fastest.  The box is PEC:
  *  E_r, E_phi vanish at k = 0 (and k = nz, outside storage); E_phi, E_z
  *  vanish at i = 0 (and i = nr).  H_r at i = 0 and H_z at k = 0 stay zero.
+ *  Axis zone (axis = 1, r_in = dr/2, no inner layer): the axis is the row
+ *  r_{-1/2} = 0, where nothing is stored.  The z components there are
+ *  single-valued scalars that the Bloch condition F(phi + tau) =
+ *  exp(i m tau) F(phi) forces to zero unless exp(i m tau) = 1, which axis
+ *  zones must avoid; so row i = 0 is updated like any other row with
+ *  H_z(-1/2) = 0, and the H_phi(-1/2) term of curlH_z carries the weight
+ *  r_{-1/2} = 0.  H_r at i = 0 is updated.
+ *  Continuous zone (n_fold = 0, nphi = 1, the n -> infinity limit of the
+ *  first zone): fields carry exp(i m phi) exactly; the seam factors are
+ *  1 +- i m with dphi = tau = 1, so the phi differences are exactly
+ *  +-i m F / r and every component sits at phi = 0.
  *  Leap-frog (mu = 1, eps0 = mu0 = c = 1):
  *    H^{n+1/2} = H^{n-1/2} - dt * curlE(E^n)
  *    E^{n+1}   = E^n + (dt/eps) * (curlH(H^{n+1/2}) - J^{n+1/2})
@@ -51,6 +62,7 @@ typedef struct {
     int nr, nphi, nz, n_fold;
     int pml_r_in, pml_r_out, pml_z_lo, pml_z_hi;
     double pml_order, pml_sigma_max_r, pml_sigma_max_z, pml_alpha;
+    int axis;                       /* 1: the zone contains the axis (r_in = dr / 2) */
 } ora_params;
 
 enum { ER = 0, EP = 1, EZ = 2, HR = 3, HP = 4, HZ = 5 };
@@ -128,12 +140,14 @@ void ora_destroy(ora_zone *z)
  */
 ora_zone *ora_create(const ora_params *p)
 {
-    if (!p || p->nr < 1 || p->nphi < 1 || p->nz < 1 || p->n_fold < 1) return NULL;
+    if (!p || p->nr < 1 || p->nphi < 1 || p->nz < 1 || p->n_fold < 0) return NULL;
+    if (p->n_fold == 0 && p->nphi != 1) return NULL;          /* continuous zone */
+    if (p->axis && (p->pml_r_in != 0 || fabs(p->r_in - 0.5 * p->dr) > 1e-12 * p->dr)) return NULL;
     ora_zone *z = (ora_zone *)calloc(1, sizeof(ora_zone));
     if (!z) return NULL;
     z->p = *p;
     z->dt = p->courant * (p->dr < p->dz ? p->dr : p->dz);
-    z->dphi = 2.0 * M_PI / ((double)p->n_fold * p->nphi);
+    z->dphi = p->n_fold > 0 ? 2.0 * M_PI / ((double)p->n_fold * p->nphi) : 1.0;
     z->ncell = (size_t)p->nz * p->nr * p->nphi;
     z->dR = p->pml_r_in + p->pml_r_out;
     z->dZ = p->pml_z_lo + p->pml_z_hi;
@@ -291,7 +305,7 @@ static void step_h(ora_zone *z, cplx seam_p)
                 cplx ez_ip = i + 1 < nr ? Ez[cidx(z, k, i + 1, j)] : 0.0;
                 cplx ep_ip = i + 1 < nr ? Ep[cidx(z, k, i + 1, j)] : 0.0;
                 /* H_r at (i, j+1/2, k+1/2): dEz/dphi / R_i - dEphi/dz / s_z */
-                if (i > 0) {
+                if (i > 0 || p->axis) {
                     cplx t1 = (ez_jp - Ez[c]) / (r_i * dph);
                     cplx t2 = (ep_kp - Ep[c]) / dz;
                     t1 = divide_stretch(t1, ir >= 0 ? &z->auxR[A_HR_T][sr] : NULL, z->sgt_r[0][i], z->cr, dt);
@@ -371,23 +385,26 @@ static void step_e(ora_zone *z, cplx seam_m, int k_src, const cplx *Jr, const cp
                     cplx j_r = src ? Jr[(size_t)i * np + j] : 0.0;
                     Er[c] += ce * (t1 - t2 - j_r);
                 }
-                /* E_phi at (i, j+1/2, k): dHr/dz / s_z - dHz/dr / s_r */
-                if (k > 0 && i > 0) {
+                /* E_phi at (i, j+1/2, k): dHr/dz / s_z - dHz/dr / s_r (H_z on the axis is 0) */
+                if (k > 0 && (i > 0 || p->axis)) {
+                    cplx hz_im = i > 0 ? Hz[cidx(z, k, i - 1, j)] : 0.0;
                     cplx t1 = (Hr[c] - Hr[cidx(z, k - 1, i, j)]) / dz;
-                    cplx t2 = (Hz[c] - Hz[cidx(z, k, i - 1, j)]) / dr;
+                    cplx t2 = (Hz[c] - hz_im) / dr;
                     t1 = divide_stretch(t1, kz >= 0 ? &z->auxZ[Z_EP][sz] : NULL, z->sig_z[0][k], z->cz, dt);
                     t2 = divide_stretch(t2, ir >= 0 ? &z->auxR[A_EP_S][sr] : NULL, z->sig_r[0][i], z->cr, dt);
                     cplx j_p = src ? Jp[(size_t)i * np + j] : 0.0;
                     Ep[c] += ce * (t1 - t2 - j_p);
                 }
-                /* E_z at (i, j, k+1/2): [d(R Hphi)/dr / l - dHr/dphi] / R */
-                if (i > 0) {
-                    cplx hp_im = Hp[cidx(z, k, i - 1, j)];
+                /* E_z at (i, j, k+1/2): [d(R Hphi)/dr / l - dHr/dphi] / R
+                 * (on the axis row the H_phi(-1/2) term has weight r = 0) */
+                if (i > 0 || p->axis) {
+                    cplx hp_im = i > 0 ? Hp[cidx(z, k, i - 1, j)] : 0.0;
                     cplx t = (Hp[c] - hp_im) / dr + (Hp[c] + hp_im) / (2.0 * r_i);
                     if (ir >= 0) {
                         cplx v1 = z->auxR[A_V_HP][sr];
                         cplx v0 = irm >= 0 ? z->auxR[A_V_HP][((size_t)k * z->dR + irm) * np + j] : 0.0;
-                        t += (z->Sig_r[1][i] * v1 - z->Sig_r[1][i - 1] * v0) / (r_i * dr);
+                        double S0 = i > 0 ? z->Sig_r[1][i - 1] : 0.0;
+                        t += (z->Sig_r[1][i] * v1 - S0 * v0) / (r_i * dr);
                         t = divide_stretch(t, &z->auxR[A_EZ_S][sr], z->sig_r[0][i], z->cr, dt);
                     }
                     t -= (Hr[c] - hr_jm) / (r_i * dph);
@@ -423,8 +440,16 @@ int ora_run(ora_zone *z, int m, int nsteps, long n_start,
     if (P > 0 && (k_src < 1 || k_src >= p->nz || !pat || !prof)) return -1;
     if (dft_plane && (k_mon < 0 || k_mon >= p->nz)) return -1;
     if (dft_vol && (k0 < 0 || k1 > p->nz || k0 >= k1)) return -1;
-    double tau = 2.0 * M_PI / p->n_fold;
-    cplx seam_p = cexp(I * m * tau), seam_m = cexp(-I * m * tau);
+    cplx seam_p, seam_m;
+    if (p->n_fold > 0) {
+        double tau = 2.0 * M_PI / p->n_fold;
+        seam_p = cexp(I * m * tau);
+        seam_m = cexp(-I * m * tau);
+    } else {                        /* continuous zone: exact i m derivative */
+        seam_p = 1.0 + I * m;
+        seam_m = 1.0 - I * m;
+    }
+    if (p->axis && cabs(seam_p - 1.0) < 1e-12) return -1;   /* axis scalars would not vanish */
     cplx *Jr = NULL, *Jp = NULL;
     if (P > 0) {
         Jr = (cplx *)malloc(plane * sizeof(cplx));
