@@ -60,9 +60,9 @@ typedef enum {
  * eps = eps_bg + rho (eps_hi - eps_bg).
  */
 typedef struct {
-    double r_in;            /* inner radius (> 0), length units */
+    double r_in;            /* inner radius (> 0), length units; dr / 2 for an axis zone */
     int nr, nphi, nz;       /* cells */
-    int n_fold;             /* wedge angle tau = 2 pi / n_fold */
+    int n_fold;             /* wedge angle tau = 2 pi / n_fold; 0 = continuous zone (nphi = 1) */
     int m;                  /* Bloch angular momentum of the forward run */
     double dr, dz;          /* grid steps */
     double courant;         /* dt = courant * min(dr, dz) */
@@ -72,6 +72,7 @@ typedef struct {
     int design_k0, design_k1;
     double eps_bg, eps_hi;
     int single_buffer;      /* 1: one field set only (in-place split kernels; half the memory) */
+    int axis;               /* 1: the zone contains the axis (r_in = dr / 2, no inner r-layer) */
 } zda_zone_desc;
 
 typedef struct zda_zone zda_zone;
@@ -81,11 +82,24 @@ typedef struct zda_zone zda_zone;
 void zda_zone_desc_default(zda_zone_desc *d);
 
 /*
+ * Zones of the first radial band (the paper's zone 1 and its neighbours):
+ *  - axis = 1: the axis is the radial half-point r_{-1/2} = 0, so
+ *    r_in = dr / 2 and nothing is stored on it.  The z components there are
+ *    single-valued scalars, which the Bloch condition forces to zero unless
+ *    exp(i m tau) = 1; the first row is then updated like any other (H_z on
+ *    the axis = 0, the H_phi term at r_{-1/2} has weight 0) instead of being a
+ *    PEC wall.  Runs whose seam phase is 1 (m = 0 mod n, or m = 0 in a
+ *    continuous zone) are refused (ZDA_ERR_UNSUPPORTED).
+ *  - n_fold = 0: continuous zone, the n -> infinity limit: nphi = 1, the
+ *    fields carry exp(i m phi) exactly (seam factors 1 +- i m, dphi = 1, so
+ *    the phi differences are exactly +-i m F / r), every component at phi = 0.
  * Create a zone on the current HIP device.  eps: nz*nr*nphi FP32 [k][i][j]
- * (may be NULL: eps = 1).  Errors: ZDA_ERR_ARG (sizes < 1, n_fold < 1, PML
- * wider than half the extent, k_mon or design layer out of range),
- * ZDA_ERR_CFL (courant * min(dr,dz) * sqrt(1/dr^2 + 1/(r_in dphi)^2 + 1/dz^2)
- * >= 1), ZDA_ERR_UNSUPPORTED (r_in <= 0), ZDA_ERR_OOM.
+ * (may be NULL: eps = 1).  Errors: ZDA_ERR_ARG (sizes < 1, n_fold < 0,
+ * n_fold = 0 with nphi != 1, PML wider than half the extent, k_mon or design
+ * layer out of range, axis with r_in != dr/2 or an inner r-layer),
+ * ZDA_ERR_CFL (courant * min(dr,dz) * sqrt(1/dr^2 + q^2 + 1/dz^2) >= 1 with
+ * q = 1/(r_in dphi), or |m|/(2 r_in) in a continuous zone), ZDA_ERR_UNSUPPORTED
+ * (r_in <= 0), ZDA_ERR_OOM.
  */
 zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_device,
                            zda_zone **out);

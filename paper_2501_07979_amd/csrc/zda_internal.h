@@ -31,7 +31,8 @@ struct StepArgs {
     int dR, dZ;                    // slab thicknesses
     float dt, inv_dr, inv_dz;
     float cr, cz;                  // exp(-alpha dt)
-    float2 seam_p, seam_m;         // exp(+i m tau), exp(-i m tau)
+    float2 seam_p, seam_m;         // exp(+i m tau), exp(-i m tau); 1 +- i m in a continuous zone
+    int axis;                      // 1: row 0 is next to the axis (updated, no wall)
     // fields [nz][nr][nphi]
     float2 *Er, *Ep, *Ez, *Hr, *Hp, *Hz;
     const float *ceps;             // dt/eps per cell

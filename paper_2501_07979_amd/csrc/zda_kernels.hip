@@ -85,8 +85,8 @@ __device__ __forceinline__ void h_step_body(const StepArgs &a, int n, int bx, in
         const size_t sz = kz >= 0 ? ((size_t)kz * nr + i) * nphi + j : 0;
         const ZCoef zc = a.zrows[k];
 
-        // H_r at (i, j+1/2, k+1/2)
-        if (i > 0) {
+        // H_r at (i, j+1/2, k+1/2); row 0 is a wall unless it borders the axis
+        if (i > 0 || a.axis) {
             float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
             float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
             if (ir >= 0) t1 = div_stretch(t1, a.auxR + AUX_HR_T * slabR + sr, rc.g1_t_int, rc.g2_t_int, a.cr, dt);
@@ -185,8 +185,8 @@ __device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, in
             er = make_float2(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
             a.Er[c] = er;
         }
-        // E_phi at (i, j+1/2, k)
-        if (k > 0 && i > 0) {
+        // E_phi at (i, j+1/2, k) (H_z on the axis is zero)
+        if (k > 0 && (i > 0 || a.axis)) {
             float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
             float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
             if (kz >= 0) t1 = div_stretch(t1, a.auxZ + ZAUX_EP * slabZ + sz, zc.g1_int, zc.g2_int, a.cz, dt);
@@ -200,8 +200,8 @@ __device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, in
             float2 uu = *u;
             *u = make_float2(a.cr * uu.x + dt * ep.x, a.cr * uu.y + dt * ep.y);
         }
-        // E_z at (i, j, k+1/2)
-        if (i > 0) {
+        // E_z at (i, j, k+1/2) (next to the axis the H_phi term at r = 0 has weight 0)
+        if (i > 0 || a.axis) {
             float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
             if (ir >= 0) {
                 const float2 *V = a.auxR + AUX_V_HP * slabR;
@@ -290,7 +290,8 @@ struct AuxRows {
 // and +z (kp) neighbours; u0, u1 are U = F E_phi at rows i and i + 1 (r-layer
 // only).  The auxiliaries of the cell are written when wr; v returns the
 // updated V = F H_phi (r-layer; zero elsewhere).  Inner boundary (i = 0):
-// H_r is not updated; bottom plane (k = 0): H_z is not updated.
+// H_r is not updated unless the row borders the axis; bottom plane (k = 0):
+// H_z is not updated.
 __device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, const ZCoef &zc, int i, int k, int ir,
                                        int kz, size_t slabR, size_t slabZ, const AuxRows &x, unsigned o, bool wr,
                                        float2 ez, float2 er, float2 ep, float2 ez_jp, float2 er_jp, float2 er_kp,
@@ -299,7 +300,7 @@ __device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, con
 {
     const float dt = a.dt;
     // H_r at (i, j+1/2, k+1/2)
-    if (i > 0) {
+    if (i > 0 || a.axis) {
         float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
         float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
         if (ir >= 0)
@@ -348,8 +349,10 @@ __device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, con
 // the PML recursions.  H^{n+1/2} at the cell and its -phi (jm), -r (im) and
 // -z (km) neighbours, V at rows i and i - 1, the source current (jr, jph).
 // The auxiliaries are always written (only owners call it with a write
-// target); u returns the updated U = F E_phi (r-layer, every cell).  Inner boundary:
-// E_phi and E_z are not updated; bottom plane: E_r and E_phi are not updated.
+// target); u returns the updated U = F E_phi (r-layer, every cell).  Inner
+// boundary: E_phi and E_z are not updated, except next to the axis, where the
+// -r neighbours (H_z on the axis, H_phi at r = 0) count as zero whatever the
+// caller passes; bottom plane: E_r and E_phi are not updated.
 __device__ __forceinline__ void e_cell(const StepArgs &a, const RowCoef &rc, const ZCoef &zc, int i, int k, int ir,
                                        int kz, size_t slabR, size_t slabZ, const AuxRows &x, unsigned o, float ce,
                                        float2 jr, float2 jph, float2 hr, float2 hr_jm, float2 hr_km, float2 hp,
@@ -357,6 +360,7 @@ __device__ __forceinline__ void e_cell(const StepArgs &a, const RowCoef &rc, con
                                        float2 v_im, float2 &er, float2 &ep, float2 &ez, float2 &u)
 {
     const float dt = a.dt;
+    if (i == 0) { hz_im = zero2(); hp_im = zero2(); v_im = zero2(); }
     // E_r at (i+1/2, j, k)
     if (k > 0) {
         float2 t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
@@ -371,7 +375,7 @@ __device__ __forceinline__ void e_cell(const StepArgs &a, const RowCoef &rc, con
     }
     // E_phi at (i, j+1/2, k)
     u = zero2();
-    if (k > 0 && i > 0) {
+    if (k > 0 && (i > 0 || a.axis)) {
         float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
         float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
         if (kz >= 0)
@@ -389,7 +393,7 @@ __device__ __forceinline__ void e_cell(const StepArgs &a, const RowCoef &rc, con
         *pto(x.dR + AUX_U_EP * slabR, o) = u;
     }
     // E_z at (i, j, k+1/2)
-    if (i > 0) {
+    if (i > 0 || a.axis) {
         float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
         if (ir >= 0) {
             t = c_add(t, c_sub(c_scale(v, rc.ez_c1), c_scale(v_im, rc.ez_c0)));

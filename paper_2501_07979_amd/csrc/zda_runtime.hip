@@ -252,9 +252,15 @@ StepArgs step_args(zda_zone *z, int m)
     a.inv_dr = (float)(1.0 / d.dr);
     a.inv_dz = (float)(1.0 / d.dz);
     a.cr = (float)z->cr; a.cz = (float)z->cz;
-    const double ph = m * z->tau;
-    a.seam_p = make_float2((float)std::cos(ph), (float)std::sin(ph));
-    a.seam_m = make_float2((float)std::cos(ph), (float)-std::sin(ph));
+    if (d.n_fold > 0) {
+        const double ph = m * z->tau;
+        a.seam_p = make_float2((float)std::cos(ph), (float)std::sin(ph));
+        a.seam_m = make_float2((float)std::cos(ph), (float)-std::sin(ph));
+    } else {   // continuous zone: 1 +- i m (exact i m derivative with dphi = 1)
+        a.seam_p = make_float2(1.f, (float)m);
+        a.seam_m = make_float2(1.f, (float)-m);
+    }
+    a.axis = d.axis ? 1 : 0;
     const int s0 = z->cur, s1 = z->cur ^ 1;
     a.Er = z->F[s0][0]; a.Ep = z->F[s0][1]; a.Ez = z->F[s0][2];
     a.Hr = z->F[s0][3]; a.Hp = z->F[s0][4]; a.Hz = z->F[s0][5];
@@ -307,6 +313,10 @@ int default_n0(double w, double dt) { return (int)std::lround(6.0 * w / dt); }
 zda_status prepare_run(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *prof, const double *omega, int K,
                        float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, StepArgs ab[2])
 {
+    // next to the axis the z components there are single-valued scalars; they
+    // vanish (and the scheme holds) only when the seam phase is not 1
+    if (z->d.axis && (z->d.n_fold > 0 ? m % z->d.n_fold == 0 : m == 0))
+        return fail(ZDA_ERR_UNSUPPORTED, "axis zone with seam phase 1 (m = %d): the axis scalars do not vanish", m);
     const size_t T = (size_t)std::max(nsteps, 1);
     zda_status st;
     if ((st = ensure(z, &z->profile, &z->cap_profile, T * std::max(P, 1))) != ZDA_OK) return st;
@@ -622,8 +632,11 @@ zda_status forward_setup(zda_zone *z, const zda_source *s, int nsteps, const dou
             for (int j = 0; j < d.nphi; ++j) {
                 cd jr, jp;
                 if (s->kind == ZDA_SRC_PLANE_CIRC) {
-                    jr = -std::exp(cd(0.0, d.m * j * z->dphi)) / d.dz;
-                    jp = cd(0.0, -sgn) * std::exp(cd(0.0, d.m * (j + 0.5) * z->dphi)) / d.dz;
+                    // sample points phi_j, phi_{j+1/2} (all at phi = 0 in a continuous zone)
+                    const double pj = d.n_fold > 0 ? j * z->dphi : 0.0;
+                    const double ph = d.n_fold > 0 ? (j + 0.5) * z->dphi : 0.0;
+                    jr = -std::exp(cd(0.0, d.m * pj)) / d.dz;
+                    jp = cd(0.0, -sgn) * std::exp(cd(0.0, d.m * ph)) / d.dz;
                 } else {
                     jr = -1.0 / d.dz;
                     jp = 0.0;
@@ -840,10 +853,13 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
 {
     if (!d || !out) return fail(ZDA_ERR_ARG, "NULL descriptor or output");
     *out = nullptr;
-    if (d->nr < 1 || d->nphi < 1 || d->nz < 2 || d->n_fold < 1)
-        return fail(ZDA_ERR_ARG, "sizes must be >= 1 (nz >= 2) and n_fold >= 1");
+    if (d->nr < 1 || d->nphi < 1 || d->nz < 2 || d->n_fold < 0)
+        return fail(ZDA_ERR_ARG, "sizes must be >= 1 (nz >= 2) and n_fold >= 0");
+    if (d->n_fold == 0 && d->nphi != 1) return fail(ZDA_ERR_ARG, "a continuous zone (n_fold = 0) has nphi = 1");
     if (!(d->dr > 0) || !(d->dz > 0) || !(d->courant > 0)) return fail(ZDA_ERR_ARG, "dr, dz, courant must be > 0");
-    if (!(d->r_in > 0)) return fail(ZDA_ERR_UNSUPPORTED, "r_in must be > 0 (the axis zone is not supported)");
+    if (!(d->r_in > 0)) return fail(ZDA_ERR_UNSUPPORTED, "r_in must be > 0 (an axis zone has r_in = dr / 2)");
+    if (d->axis && (d->pml_r_in != 0 || std::abs(d->r_in - 0.5 * d->dr) > 1e-12 * d->dr))
+        return fail(ZDA_ERR_ARG, "an axis zone has r_in = dr / 2 and no inner r-layer");
     if (d->pml_r_in < 0 || d->pml_r_out < 0 || d->pml_z_lo < 0 || d->pml_z_hi < 0 ||
         2 * d->pml_r_in > d->nr || 2 * d->pml_r_out > d->nr || 2 * d->pml_z_lo > d->nz || 2 * d->pml_z_hi > d->nz)
         return fail(ZDA_ERR_ARG, "PML widths must be in [0, extent/2]");
@@ -852,17 +868,20 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
         (d->design_k0 < 0 || d->design_k1 > d->nz || d->design_k0 >= d->design_k1))
         return fail(ZDA_ERR_ARG, "design layer must satisfy 0 <= k0 < k1 <= nz");
     if (!(d->pml_order > 0) || d->pml_alpha < 0) return fail(ZDA_ERR_ARG, "bad PML profile");
-    const double dphi = 2.0 * M_PI / ((double)d->n_fold * d->nphi);
+    // continuous zone: dphi = tau = 1 and the phi difference is exactly i m / r,
+    // whose CFL term is (m / (2 r))^2 (a Yee direction contributes (1/h)^2)
+    const double dphi = d->n_fold > 0 ? 2.0 * M_PI / ((double)d->n_fold * d->nphi) : 1.0;
     const double dt = d->courant * std::min(d->dr, d->dz);
-    const double cfl = dt * std::sqrt(1.0 / (d->dr * d->dr) + 1.0 / std::pow(d->r_in * dphi, 2) + 1.0 / (d->dz * d->dz));
-    if (cfl >= 1.0) return fail(ZDA_ERR_CFL, "Courant number %.4f >= 1 (dt sqrt(1/dr^2+1/(r_in dphi)^2+1/dz^2))", cfl);
+    const double q = d->n_fold > 0 ? 1.0 / (d->r_in * dphi) : std::abs((double)d->m) / (2.0 * d->r_in);
+    const double cfl = dt * std::sqrt(1.0 / (d->dr * d->dr) + q * q + 1.0 / (d->dz * d->dz));
+    if (cfl >= 1.0) return fail(ZDA_ERR_CFL, "Courant number %.4f >= 1 (dt sqrt(1/dr^2+q^2+1/dz^2))", cfl);
 
     zda_zone *z = new (std::nothrow) zda_zone();
     if (!z) return fail(ZDA_ERR_OOM, "host allocation failed");
     z->d = *d;
     if (hipGetDevice(&z->device) != hipSuccess) { delete z; return fail(ZDA_ERR_HIP, "no HIP device"); }
     z->dphi = dphi;
-    z->tau = 2.0 * M_PI / d->n_fold;
+    z->tau = d->n_fold > 0 ? 2.0 * M_PI / d->n_fold : 1.0;
     z->dt = dt;
     z->cfl = cfl;
     z->plane = (size_t)d->nr * d->nphi;

@@ -39,6 +39,7 @@ class Workload:
     width: float = 20.0
     seed: int = 1
     density: str = "bernoulli"       # or "smoothed"
+    axis: int = 0                    # 1: the zone contains the axis (r_in = dr / 2)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -48,7 +49,7 @@ class Workload:
     def desc_kwargs(self):
         return dict(r_in=self.r_in, nr=self.nr, nphi=self.nphi, nz=self.nz, n_fold=self.n_fold, m=self.m,
                     dr=self.dr, dz=self.dz, courant=self.courant, pml=self.pml, k_mon=self.k_mon,
-                    design=self.design, eps_bg=self.eps_bg, eps_hi=self.eps_hi)
+                    design=self.design, eps_bg=self.eps_bg, eps_hi=self.eps_hi, axis=self.axis)
 
     def rho(self):
         """Design density over the design layer, [k1-k0][nr][nphi] float32."""

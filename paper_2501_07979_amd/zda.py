@@ -40,7 +40,7 @@ class ZoneDesc(ctypes.Structure):
                 ("pml_sigma_max_r", ctypes.c_double), ("pml_sigma_max_z", ctypes.c_double),
                 ("pml_alpha", ctypes.c_double), ("k_mon", ctypes.c_int), ("design_k0", ctypes.c_int),
                 ("design_k1", ctypes.c_int), ("eps_bg", ctypes.c_double), ("eps_hi", ctypes.c_double),
-                ("single_buffer", ctypes.c_int)]
+                ("single_buffer", ctypes.c_int), ("axis", ctypes.c_int)]
 
 
 class Source(ctypes.Structure):
@@ -138,8 +138,10 @@ def default_desc(**kw) -> ZoneDesc:
             d.pml_r_in, d.pml_r_out, d.pml_z_lo, d.pml_z_hi = v
         elif k == "design":
             d.design_k0, d.design_k1 = v
-        else:
+        elif k in {f[0] for f in ZoneDesc._fields_}:
             setattr(d, k, v)
+        else:
+            raise TypeError("unknown zone descriptor field %r" % k)
     return d
 
 

@@ -115,3 +115,40 @@ def test_batch_autotune_keeps_results(zda):
         else:
             assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(x)
     b.close()
+
+
+@pytest.mark.parametrize("mode", ["fused", "two", "two_odd"])
+def test_batch_with_the_axis_zone(zda, oracle_mod, mode):
+    """The first zones of a lens in one batch: the continuous zone that
+    contains the axis (nphi = 1) next to two wedges; each equals its own run
+    bitwise and the oracle to 1e-5."""
+    from paper_2501_07979_amd.workloads import Workload
+    steps = 151 if mode == "two_odd" else 150
+    om = (0.28, 0.33, 0.39)
+    common = dict(nz=40, k_src=8, k_mon=30, design=(12, 16), k_sub=12, steps=steps, omegas=om, omega_c=0.33,
+                  width=6.0, density="smoothed")
+    wls = [Workload("axis", r_in=0.5, nr=40, nphi=1, n_fold=0, pml=(0, 5, 5, 5), axis=1, seed=81, **common),
+           Workload("ring2", r_in=40.5, nr=30, nphi=64, n_fold=4, pml=(5, 5, 5, 5), seed=82, **common),
+           Workload("ring3", r_in=70.5, nr=30, nphi=64, n_fold=8, pml=(5, 5, 5, 5), seed=83, **common)]
+    eps = [w.eps() for w in wls]
+    singles = []
+    for w, e in zip(wls, eps):
+        z = zda.Zone(zda.default_desc(**w.desc_kwargs()), e)
+        z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width)
+        singles.append(z.dft(zda.MON_PLANE).cpu().numpy())
+        z.close()
+    zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    b = zda.Batch(zones)
+    b.set_launch({"fused": 7, "two": 13, "two_odd": 5}[mode])
+    srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
+    _say("batch with the axis zone", mode)
+    b.run(srcs, steps, om)
+    for w, e, z, pl in zip(wls, eps, zones, singles):
+        got = z.dft(zda.MON_PLANE).cpu().numpy()
+        o = oracle_mod.OracleZone(**w.desc_kwargs(), eps=e)
+        ref = o.forward(w.steps, np.array(om), omega_c=w.omega_c, width=w.width, k_src=w.k_src)["plane"]
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        _say(w.name, mode, "batch vs oracle rel L2 %.2e" % rel)
+        assert rel <= 1e-5
+        assert np.array_equal(got, pl)
+    b.close()
