@@ -226,10 +226,17 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
  * launch over the tiles with layer cells on a second stream of the zone
  * (default priority), concurrently with the launch over the interior tiles,
  * joined back into the run's stream before the next pair of steps.
- * ZDA_ERR_ARG for an unknown option. */
+ * ZDA_OPT_TILE_PATCH (default 0 = off; takes precedence over
+ * ZDA_OPT_XCD_REMAP) orders the two-step tiles of each plane chunk in
+ * patches of `value >> 8` row bands x at most `value & 0xff` phi columns,
+ * patch q going to XCD q mod 8 (the XCDs take a launch's blocks
+ * round-robin), so that the tiles one XCD holds at a time share halo lines
+ * in its L2.  ZDA_ERR_ARG for an unknown option or a patch value with a
+ * zero or > 255 field. */
 #define ZDA_OPT_XCD_REMAP 1
 #define ZDA_OPT_NT_STORES 2
 #define ZDA_OPT_LAYER_STREAM 3
+#define ZDA_OPT_TILE_PATCH 4
 zda_status zda_zone_set_option(zda_zone *z, int option, int value);
 
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);

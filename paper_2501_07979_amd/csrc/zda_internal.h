@@ -87,8 +87,16 @@ void launch_fused_step(const StepArgs &a, int n, hipStream_t s);
 // and planes hold no layer cell), any other value the one with the r- and
 // z-layer recursions
 void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream_t s);
-// a two-step tile owns 61 phi cells, up to TR rows and a range of planes
-constexpr int TWO_STEP_COLS = 61;
+// phi cells a tile owns.  56 (448 B) puts every tile's stores on 64 B
+// boundaries of the row (for rows of a multiple of 8 cells), so no 64 B
+// block of a field is written partly by two blocks (such blocks cost the
+// memory a read-modify-write); 61 computes fewer halo cells per owned cell.
+// The two-step tiles without layer cells are store-bound and take 56, the
+// layer tiles (dearer per cell) 61; a two-step tile owns its phi cells, up to
+// TR rows and a range of planes.
+constexpr int two_step_cols(int lay) { return lay == 0 ? 56 : 61; }
+// a fused-step tile owns FUSED_COLS phi cells and TR rows
+constexpr int FUSED_COLS = 56;
 void launch_fill(float2 *p, size_t n, hipStream_t s);
 // tiles of one zone for the split (BY rows) or fused (TR owned rows) kernels
 unsigned tiles_split(const StepArgs &a, int BY);

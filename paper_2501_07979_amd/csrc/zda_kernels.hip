@@ -428,8 +428,9 @@ __device__ __forceinline__ void sheet_current(const StepArgs &a, int n, size_t p
 // another block of the same launch writes.  Block = (TR + 1) wavefronts x 64
 // lanes marching a z-chunk: wave 0 recomputes H on the radial halo row
 // i0 - 1, waves 1..TR own rows i0 .. i0 + TR - 1; lane l sits on phi cell
-// j0 - 1 + l (j0 = 63 blockIdx.x), lane 0 recomputes H on the azimuthal halo
-// column (across the wedge seam for the first tile), lanes 1..63 own.  Each
+// j0 - 1 + l (j0 = FUSED_COLS x tile column), lane 0 recomputes H on the
+// azimuthal halo column (across the wedge seam for the first tile), lanes
+// 1..FUSED_COLS own (the lanes above compute cells they do not store).  Each
 // plane's H^{n+1/2} goes through LDS (two buffers, one barrier per plane) to
 // the owners' E half-step.  A chunk starts one plane early to rebuild
 // H^{n+1/2} at k = kb - 1 for the E half-step at kb.
@@ -447,11 +448,11 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
     const int bx = (int)(p % gx), by = (int)((p / gx) % gy), bz = (int)(p / (gx * gy));
     const int i = by * TR + ww - 1;
     const bool row_ok = i >= 0 && i < nr;
-    const int jj = bx * 63 - 1 + lane;
+    const int jj = bx * FUSED_COLS - 1 + lane;
     const bool hval = row_ok && jj < nphi;
     const bool seam_lane = jj < 0;
     const int j = seam_lane ? nphi - 1 : jj;
-    const bool owner = ww >= 1 && lane >= 1 && hval;
+    const bool owner = ww >= 1 && lane >= 1 && lane <= FUSED_COLS && hval;
     const int kb = bz * a.kchunk;
     const int ke = min(kb + a.kchunk, nz);
     const int kstart = kb > 0 ? kb - 1 : kb;
@@ -599,14 +600,15 @@ __device__ __forceinline__ PlaneIn load_plane(const StepArgs &a, int k, size_t p
 // fields and auxiliaries at time level n from one buffer set and writes level
 // n + 2 to the other, so each cell's six fields cross HBM once per two steps.
 // Block = (TR + 3) wavefronts x 64 lanes marching a z-chunk: wave w sits on
-// row i0 - 2 + w and lane l on phi cell j0 - 2 + l (j0 = 61 x tile column),
+// row i0 - 2 + w and lane l on phi cell j0 - 2 + l (j0 = COLS x tile column,
+// COLS = two_step_cols(LAY)),
 // taken modulo nphi (physical cells; the Bloch seam factor is applied where a
 // neighbour value crosses from column nphi - 1 to 0).  Step one runs on every
 // lane and wave; its H^{n+1/2} reaches the E half-step through LDS.  Step two
 // lags one plane behind and needs E^{n+1} of the +phi, +r neighbours
 // (double-buffered LDS) and H^{n+3/2} of the -phi, -r neighbours (LDS); it
-// is exact on lanes 2..62 and waves 2..nrow+1 (nrow <= TR owned rows), which
-// own their cells.  A chunk
+// is exact on lanes 2..62 and waves 2..nrow+1 (nrow <= TR owned rows); lanes
+// 2..COLS+1 of those waves own their cells.  A chunk
 // starts two planes early and runs step one one plane past its end.  Every
 // block computes halo cells with the same inputs and the same arithmetic as
 // their owner, so the level-(n+1) auxiliaries that step one writes to the
@@ -631,11 +633,12 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
     const int i = i0 + w - 2;
     const bool active = w <= nrow + 2;                      // waves above the top halo row idle
     const bool row_ok = active && i >= 0 && i < nr;
-    const int jj = bx * TWO_STEP_COLS - 2 + lane;
+    constexpr int COLS = two_step_cols(LAY);
+    const int jj = bx * COLS - 2 + lane;
     const int pc = (jj + nphi) % nphi;                      // physical column
     const bool cross_m = pc == 0;                           // lane - 1 holds column nphi - 1
     const bool cross_p = pc == nphi - 1;                    // lane + 1 holds column 0
-    const bool own = lane >= 2 && lane <= 62 && jj < nphi && w >= 2 && w <= nrow + 1 && row_ok;
+    const bool own = lane >= 2 && lane < 2 + COLS && jj < nphi && w >= 2 && w <= nrow + 1 && row_ok;
     const int k_lo = max(kb - 2, 0);
     const bool nt = a.nt_stores;
     const int ir = (PR && row_ok) ? slab_row(i, nr, a.pr0, a.pr1) : -1;
@@ -897,7 +900,7 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_batch(BatchArgs b, int
     const unsigned g = xcd_order(blockIdx.x, gridDim.x, b.xcd_remap);
     const int zi = batch_zone(b.prefix, b.nzones, g);
     const StepArgs a = b.tab[zi];
-    const unsigned gx = (a.nphi + 62) / 63, gy = (a.nr + TR - 1) / TR;
+    const unsigned gx = (a.nphi + FUSED_COLS - 1) / FUSED_COLS, gy = (a.nr + TR - 1) / TR;
     const int n = n_rel + (b.n_base ? *b.n_base : 0);
     eh_fused_body<TR>(a, n, g - b.prefix[zi], gx, gy);
 }
@@ -1027,7 +1030,7 @@ template <int TR>
 void launch_fused_tr(const StepArgs &a, int n, hipStream_t s)
 {
     dim3 block(64, TR + 1, 1);
-    dim3 grid((a.nphi + 62) / 63, (a.nr + TR - 1) / TR, (a.nz + a.kchunk - 1) / a.kchunk);
+    dim3 grid((a.nphi + FUSED_COLS - 1) / FUSED_COLS, (a.nr + TR - 1) / TR, (a.nz + a.kchunk - 1) / a.kchunk);
     hipLaunchKernelGGL(eh_fused_kernel<TR>, grid, block, 0, s, a, n);
 }
 
@@ -1080,7 +1083,7 @@ unsigned tiles_split(const StepArgs &a, int BY)
 
 unsigned tiles_fused(const StepArgs &a, int TR)
 {
-    return (unsigned)((a.nphi + 62) / 63) * (unsigned)((a.nr + TR - 1) / TR) *
+    return (unsigned)((a.nphi + FUSED_COLS - 1) / FUSED_COLS) * (unsigned)((a.nr + TR - 1) / TR) *
            (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
 }
 

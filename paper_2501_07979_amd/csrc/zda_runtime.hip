@@ -85,6 +85,7 @@ struct zda_zone {
     bool fused = true;
     bool two = false;              // two leap-frog steps per launch (tile_rows 5 or 13)
     int xcd_remap = 0, nt_stores = 1, layer_stream = 0;
+    int tile_patch = 0;            // (bands << 8) | columns of an XCD's patch of two-step tiles, 0 = off
     // second stream and join events for the concurrent layer-tile launch
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -382,7 +383,15 @@ struct TwoStepTiles {
     size_t cells = 0, mon = 0, src = 0;   // owned by the interior tiles
 };
 
-void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, bool xcd, unsigned tag, TwoStepTiles &t)
+// Order code of a zone's two-step tile list: 0 natural (plane chunk, row
+// band, phi column), 1 contiguous range per XCD, otherwise a patch shape
+// (bands << 8) | columns.
+int tile_order(const zda_zone *z)
+{
+    return z->tile_patch ? z->tile_patch : (z->xcd_remap ? 1 : 0);
+}
+
+void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, unsigned tag, TwoStepTiles &t)
 {
     const zda_zone_desc &d = z->d;
     const int rA = d.pml_r_in > 0 ? std::min(d.pml_r_in + 2, d.nr) : 0;
@@ -400,7 +409,7 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, bool xcd, unsi
     split_range(zA, zB, kc, planes);
     const size_t z_in1 = planes.size();
     split_range(zB, d.nz, kc, planes);
-    const int gx = (d.nphi + TWO_STEP_COLS - 1) / TWO_STEP_COLS;
+    auto gx_of = [&](int lay) { return (d.nphi + two_step_cols(lay) - 1) / two_step_cols(lay); };
     std::vector<uint4> v[4];
     for (size_t pz = 0; pz < planes.size(); ++pz) {
         const int kb = planes[pz].first, ke = planes[pz].second;
@@ -413,12 +422,13 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, bool xcd, unsi
             // (leaner instantiations) measured slower on the 512 x 1024 x 400
             // zone, their partly filled last rounds outweighing the gain
             const int lay = (rl || zl) ? 3 : 0;
-            for (int bx = 0; bx < gx; ++bx) {
+            const int cw = two_step_cols(lay);
+            for (int bx = 0; bx < gx_of(lay); ++bx) {
                 v[lay].push_back(make_uint4((unsigned)bx, (unsigned)i0 | ((unsigned)nrow << 16),
                                             (unsigned)kb | ((unsigned)ke << 16), tag));
                 if (lay == 0) {
-                    const int j0 = bx * TWO_STEP_COLS;
-                    const size_t cols = (size_t)(std::min(j0 + TWO_STEP_COLS, d.nphi) - j0);
+                    const int j0 = bx * cw;
+                    const size_t cols = (size_t)(std::min(j0 + cw, d.nphi) - j0);
                     t.cells += (size_t)nrow * cols * (size_t)(ke - kb);
                     if (d.k_mon >= kb && d.k_mon < ke) t.mon += (size_t)nrow * cols;
                     if (k_src >= kb && k_src < ke) t.src += (size_t)nrow * cols;
@@ -442,8 +452,45 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, bool xcd, unsi
             }
         u.swap(o);
     };
+    // patch order: within each plane chunk, the (row band x phi column) grid
+    // is cut into patches of PA bands x at most PB columns; patch q goes to
+    // XCD q mod 8, which works through its patches in turn, so the tiles that
+    // one XCD holds at a time are 2-D neighbours and share their halo lines in
+    // its L2, while the eight XCDs together still sweep one compact region
+    auto patch_order = [](std::vector<uint4> &u, int gx, int PA, int PB) {
+        if (u.size() < 8) return;
+        std::vector<std::pair<int, int>> cgs;
+        split_range(0, gx, std::max(PB, 1), cgs);
+        std::vector<std::vector<uint4>> seq(8);
+        size_t q = 0, a = 0;
+        while (a < u.size()) {                       // one plane chunk: tiles [a, b)
+            size_t b = a;
+            while (b < u.size() && u[b].z == u[a].z) ++b;
+            std::vector<size_t> band;                // first tile of each row band
+            for (size_t c = a; c < b; ++c)
+                if (c == a || u[c].y != u[c - 1].y) band.push_back(c);
+            band.push_back(b);
+            for (size_t g = 0; g + 1 < band.size(); g += (size_t)std::max(PA, 1)) {
+                const size_t g1 = std::min(g + (size_t)std::max(PA, 1), band.size() - 1);
+                for (const auto &cg : cgs) {
+                    std::vector<uint4> &s = seq[q++ % 8];
+                    for (size_t bb = g; bb < g1; ++bb)
+                        for (size_t c = band[bb]; c < band[bb + 1]; ++c)
+                            if ((int)u[c].x >= cg.first && (int)u[c].x < cg.second) s.push_back(u[c]);
+                }
+            }
+            a = b;
+        }
+        std::vector<uint4> o;
+        o.reserve(u.size());
+        for (size_t s = 0; o.size() < u.size(); ++s)
+            for (int x = 0; x < 8; ++x)
+                if (s < seq[x].size()) o.push_back(seq[x][s]);
+        u.swap(o);
+    };
     for (int q = 0; q < 4; ++q) {
-        if (xcd) xcd_order(v[q]);
+        if (order == 1) xcd_order(v[q]);
+        else if (order > 1) patch_order(v[q], gx_of(q), order >> 8, order & 0xff);
         t.v[q].insert(t.v[q].end(), v[q].begin(), v[q].end());
     }
 }
@@ -454,10 +501,10 @@ zda_status build_two_step_tiles(zda_zone *z)
 {
     const int TR = z->tile_rows, kc = z->kchunk;
     if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last &&
-        z->tiles_xcd == z->xcd_remap)
+        z->tiles_xcd == tile_order(z))
         return ZDA_OK;
     TwoStepTiles t;
-    two_step_tiles(z, TR, kc, z->k_src_last, z->xcd_remap != 0, 0u, t);
+    two_step_tiles(z, TR, kc, z->k_src_last, tile_order(z), 0u, t);
     std::vector<uint4> all;
     for (int q = 0; q < 4; ++q) {
         z->n_lay[q] = (unsigned)t.v[q].size();
@@ -474,7 +521,7 @@ zda_status build_two_step_tiles(zda_zone *z)
     z->tiles_src = z->k_src_last;
     z->tiles_tr = TR;
     z->tiles_kc = kc;
-    z->tiles_xcd = z->xcd_remap;
+    z->tiles_xcd = tile_order(z);
     return ZDA_OK;
 }
 
@@ -896,7 +943,7 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     // kernel below.
     {
         z->tile_rows = 3;
-        const long tiles = (long)((d->nphi + 62) / 63) * ((d->nr + 2) / 3);
+        const long tiles = (long)((d->nphi + FUSED_COLS - 1) / FUSED_COLS) * ((d->nr + 2) / 3);
         int kc = std::min(12, d->nz);
         while (kc > 4 && tiles * ((d->nz + kc - 1) / kc) < 2048) --kc;
         z->kchunk = kc;
@@ -945,7 +992,7 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
                 z->two = true;
                 z->fused = false;
                 z->tile_rows = 13;
-                const long tiles = (long)((d->nphi + TWO_STEP_COLS - 1) / TWO_STEP_COLS) * ((d->nr + 12) / 13);
+                const long tiles = (long)((d->nphi + two_step_cols(0) - 1) / two_step_cols(0)) * ((d->nr + 12) / 13);
                 int kc = std::min(48, d->nz);
                 while (kc > 8 && tiles * ((d->nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
                 z->kchunk = kc;
@@ -1152,6 +1199,11 @@ zda_status zda_zone_set_option(zda_zone *z, int option, int value)
     case ZDA_OPT_XCD_REMAP: z->xcd_remap = value ? 1 : 0; return ZDA_OK;
     case ZDA_OPT_NT_STORES: z->nt_stores = value ? 1 : 0; return ZDA_OK;
     case ZDA_OPT_LAYER_STREAM: z->layer_stream = value ? 1 : 0; return ZDA_OK;
+    case ZDA_OPT_TILE_PATCH:
+        if (value < 0 || (value != 0 && ((value >> 8) < 1 || (value >> 8) > 255 || (value & 0xff) < 1)))
+            return fail(ZDA_ERR_ARG, "tile patch must be 0 or (bands << 8) | columns with both in [1, 255]");
+        z->tile_patch = value;
+        return ZDA_OK;
     default: return fail(ZDA_ERR_ARG, "unknown option %d", option);
     }
 }
@@ -1271,7 +1323,7 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
         TwoStepTiles t;
         for (int i = 0; i < nz; ++i) {
             const zda_zone *z = b->zones[i];
-            two_step_tiles(z, b->tile_rows, z->kchunk, ab[i][0].k_src, z->xcd_remap != 0, (unsigned)i, t);
+            two_step_tiles(z, b->tile_rows, z->kchunk, ab[i][0].k_src, tile_order(z), (unsigned)i, t);
         }
         std::vector<uint4> all;
         for (int q = 0; q < 4; ++q) {

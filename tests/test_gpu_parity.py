@@ -229,13 +229,14 @@ def test_fused_launch_shapes_are_bitwise_identical(zda):
     rng = np.random.default_rng(41)
     eps = (1.0 + 4.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
     outs = []
-    for kc, tr, opt in [(41, 7, 0), (5, 3, 0), (13, 15, 0), (1, 7, 0), (9, 13, 0), (41, 13, 0), (4, 5, 0), (1, 5, 0),
-                        (9, 13, zda.OPT_LAYER_STREAM), (4, 5, zda.OPT_XCD_REMAP)]:
-        _say("determinism", kc, tr, opt)
+    for kc, tr, opt, val in [(41, 7, 0, 0), (5, 3, 0, 0), (13, 15, 0, 0), (1, 7, 0, 0), (9, 13, 0, 0), (41, 13, 0, 0),
+                             (4, 5, 0, 0), (1, 5, 0, 0), (9, 13, zda.OPT_LAYER_STREAM, 1), (4, 5, zda.OPT_XCD_REMAP, 1),
+                             (9, 13, zda.OPT_TILE_PATCH, (2 << 8) | 2), (4, 5, zda.OPT_TILE_PATCH, (3 << 8) | 1)]:
+        _say("determinism", kc, tr, opt, val)
         g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
         g.set_launch(kc, tr)
         if opt:
-            g.set_option(opt, 1)
+            g.set_option(opt, val)
         g.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
         outs.append([g.read_field(c).cpu().numpy() for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz")] +
                     [g.dft(zda.MON_PLANE).cpu().numpy()])
