@@ -33,3 +33,29 @@ class ZoneFDTD(torch.autograd.Function):
 
 def zone_fdtd(rho, zone, **run_kw):
     return ZoneFDTD.apply(rho, zone, run_kw)
+
+
+class BatchFDTD(torch.autograd.Function):
+    """Several zones stepped together in one batch (one launch per time step
+    over every zone's tiles): rho_z -> exit-plane DFT of each zone; the
+    backward is one batched adjoint run (-m) and the overlaps."""
+
+    @staticmethod
+    def forward(ctx, batch, run_kw, *rhos):
+        for z, r in zip(batch.zones, rhos):
+            z.set_design(r.detach().contiguous())
+        sources = [zda.preset_source(k_src=run_kw["k_src"], omega_c=run_kw["omega_c"], width=run_kw["width"])
+                   for _ in batch.zones]
+        batch.run(sources, run_kw["nsteps"], run_kw["omegas"], volume=True)
+        ctx.batch = batch
+        return tuple(z.dft(zda.MON_PLANE) for z in batch.zones)
+
+    @staticmethod
+    def backward(ctx, *grad_planes):
+        gs = [(g.conj() * 0.5).to(torch.complex64).contiguous() for g in grad_planes]
+        return (None, None, *ctx.batch.adjoint_grad(gs))
+
+
+def batch_fdtd(rhos, batch, **run_kw):
+    return BatchFDTD.apply(batch, run_kw, *rhos)
+

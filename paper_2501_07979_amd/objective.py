@@ -15,7 +15,10 @@ ring integral is n times the wedge integral:
   G_k(R) = (F / R) (i k - 1/R) e^{i k R} / R,  R = sqrt(r^2 + F^2),
 
 E_r and E_phi taken at their own staggered points, PML cells excluded.
-F = sum_k |a_k|^2.
+F = sum_k |a_k|^2.  A continuous zone (n_fold = 0, the n -> infinity limit,
+one phi sample carrying e^{i m phi} exactly) has a rotation-invariant
+integrand, so its ring integral is 2 pi times the phi = 0 sample.  A lens
+assembled from concentric zones sums the zones' phasors a_k before |.|^2.
 """
 from __future__ import annotations
 
@@ -32,12 +35,16 @@ def focal_length(r_mid, na=0.3):
 
 def focal_weights(wl, omegas, focal, device="cuda"):
     """Complex weights w[K][2][nr][nphi] with a_k = sum w * Ehat (E_r, E_phi)."""
-    n = wl.n_fold
-    dphi = 2 * np.pi / (n * wl.nphi)
+    if wl.n_fold > 0:
+        n = wl.n_fold
+        dphi = 2 * np.pi / (n * wl.nphi)
+        phi_j = np.arange(wl.nphi) * dphi
+        phi_h = phi_j + 0.5 * dphi
+    else:                       # continuous zone: one sample at phi = 0 stands for the whole ring
+        n, dphi = 1, 2 * np.pi
+        phi_j = phi_h = np.zeros(1)
     ri = wl.r_in + np.arange(wl.nr) * wl.dr
     rh = ri + 0.5 * wl.dr
-    phi_j = np.arange(wl.nphi) * dphi
-    phi_h = phi_j + 0.5 * dphi
     active = np.zeros(wl.nr)
     active[wl.pml[0]:wl.nr - wl.pml[1]] = 1.0
     W = np.zeros((len(omegas), 2, wl.nr, wl.nphi), np.complex128)

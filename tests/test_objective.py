@@ -68,3 +68,26 @@ def test_filter_and_projection_are_differentiable_and_periodic():
     assert torch.allclose(torch.roll(objective.gaussian_filter_phi_periodic(rho, 1.5), 5, dims=2), shifted)
     assert torch.autograd.gradcheck(lambda r: objective.tanh_projection(
         objective.gaussian_filter_phi_periodic(r, 1.0), 4.0).sum(), (rho,))
+
+
+def test_continuous_zone_weights_equal_wedge_weights_on_a_pure_mode():
+    """A field carrying e^{i phi} exactly (m = 1) gives the same focal phasor
+    whether it is held by a continuous zone (one sample at phi = 0) or by
+    any n-fold wedge sampling it at its staggered points: the integrand of
+    the ring integral is rotation-invariant."""
+    rng = np.random.default_rng(5)
+    kw = dict(r_in=0.5, nr=16, nz=10, m=1, pml=(0, 3, 2, 2), axis=1)
+    cont = Workload("cont", nphi=1, n_fold=0, **kw)
+    om = (0.3, 0.41)
+    F = 90.0
+    Wc = objective.focal_weights(cont, om, F, device="cpu").numpy().astype(np.complex128)
+    E0 = rng.standard_normal((2, 2, kw["nr"])) + 1j * rng.standard_normal((2, 2, kw["nr"]))
+    a_c = np.einsum("kaij,kaij->k", Wc, E0[..., None])
+    for n, nphi in ((5, 7), (16, 3)):
+        wedge = Workload("wedge", nphi=nphi, n_fold=n, **kw)
+        Ww = objective.focal_weights(wedge, om, F, device="cpu").numpy().astype(np.complex128)
+        dphi = 2 * np.pi / (n * nphi)
+        phase = np.stack([np.exp(1j * np.arange(nphi) * dphi), np.exp(1j * (np.arange(nphi) + 0.5) * dphi)])
+        plane = E0[..., None] * phase[None, :, None, :]
+        a_w = np.einsum("kaij,kaij->k", Ww, plane)
+        assert np.allclose(a_w, a_c, rtol=1e-6, atol=0), (n, nphi, a_w, a_c)
