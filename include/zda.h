@@ -31,6 +31,7 @@
 #define ZDA_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -259,6 +260,23 @@ typedef struct {
 } zda_timing;
 
 zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
+
+/* The two-step kernel's launch plan for a zone described by d, computed on
+ * the host (no device is touched; a zone created from d with the same
+ * tile_rows, kchunk and tile order runs exactly these tiles).  tile_rows: 5
+ * or 13; kchunk >= 1 planes per chunk; k_src: the source plane (only the
+ * cell counts depend on it); order: 0 natural, 1 contiguous range per XCD
+ * (ZDA_OPT_XCD_REMAP), else a patch code (ZDA_OPT_TILE_PATCH).  out (may be
+ * NULL to query the count): 4 uint32 per tile, {phi block, first owned row |
+ * row count << 16, first plane | end plane << 16, kind}, kind 0 for the
+ * interior tiles (their computed rows i0-2 .. i0+rows and planes kb-2 .. ke
+ * hold no layer cell; they own 56 phi cells) and 3 for the layer tiles (61
+ * phi cells), interior tiles first; cap: capacity of out in tiles.
+ * *ntiles and *n_interior receive the counts.  Errors: ZDA_ERR_ARG (sizes
+ * < 1, nr or nz > 65535, a layer wider than half the extent, tile_rows not 5
+ * or 13, kchunk < 1, a patch field of 0, out too small). */
+zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kchunk, int k_src, int order,
+                                   uint32_t *out, size_t cap, size_t *ntiles, size_t *n_interior);
 
 /*
  * Batches: many zones of uneven size (the lens-scale schedule in which n

@@ -1221,6 +1221,39 @@ zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info)
     return ZDA_OK;
 }
 
+zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kchunk, int k_src, int order,
+                                   uint32_t *out, size_t cap, size_t *ntiles, size_t *n_interior)
+{
+    if (!d || !ntiles || !n_interior) return fail(ZDA_ERR_ARG, "NULL argument");
+    if (d->nr < 1 || d->nphi < 1 || d->nz < 2 || d->nr > 65535 || d->nz > 65535)
+        return fail(ZDA_ERR_ARG, "sizes must be in [1, 65535] (nz >= 2)");
+    if (d->pml_r_in < 0 || d->pml_r_out < 0 || d->pml_z_lo < 0 || d->pml_z_hi < 0 ||
+        2 * std::max(d->pml_r_in, d->pml_r_out) > d->nr || 2 * std::max(d->pml_z_lo, d->pml_z_hi) > d->nz)
+        return fail(ZDA_ERR_ARG, "layers must be >= 0 and at most half the extent");
+    if (tile_rows != 5 && tile_rows != 13) return fail(ZDA_ERR_ARG, "two-step tile_rows is 5 or 13");
+    if (kchunk < 1) return fail(ZDA_ERR_ARG, "kchunk must be >= 1");
+    if (order > 1 && ((order >> 8) < 1 || (order >> 8) > 255 || (order & 0xff) < 1))
+        return fail(ZDA_ERR_ARG, "tile patch must be (bands << 8) | columns with both in [1, 255]");
+    zda_zone z;
+    z.d = *d;
+    TwoStepTiles t;
+    two_step_tiles(&z, tile_rows, std::min(kchunk, d->nz), k_src, order < 0 ? 0 : order, 0u, t);
+    *n_interior = t.v[0].size();
+    *ntiles = t.v[0].size() + t.v[1].size() + t.v[2].size() + t.v[3].size();
+    if (!out) return ZDA_OK;
+    if (cap < *ntiles) return fail(ZDA_ERR_ARG, "out holds %zu tiles, the plan has %zu", cap, *ntiles);
+    size_t p = 0;
+    for (int q = 0; q < 4; ++q)
+        for (const uint4 &u : t.v[q]) {
+            out[4 * p] = u.x;
+            out[4 * p + 1] = u.y;
+            out[4 * p + 2] = u.z;
+            out[4 * p + 3] = (uint32_t)q;
+            ++p;
+        }
+    return ZDA_OK;
+}
+
 zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t)
 {
     if (!z || !t) return fail(ZDA_ERR_ARG, "NULL argument");

@@ -27,7 +27,7 @@ EXPORTS = ["zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_
            "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields", "zda_adjoint_grad",
            "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_set_launch",
            "zda_zone_set_option",
-           "zda_zone_last_timing", "zda_batch_create", "zda_batch_destroy", "zda_batch_run",
+           "zda_zone_last_timing", "zda_plan_two_step_tiles", "zda_batch_create", "zda_batch_destroy", "zda_batch_run",
            "zda_batch_adjoint_grad", "zda_batch_set_launch", "zda_batch_autotune",
            "zda_status_str", "zda_last_error"]
 
@@ -101,6 +101,8 @@ def load():
     lib.zda_zone_last_timing.argtypes = [P, ctypes.POINTER(Timing)]
     lib.zda_zone_set_launch.argtypes = [P, I, I]
     lib.zda_zone_set_option.argtypes = [P, I, I]
+    lib.zda_plan_two_step_tiles.argtypes = [ctypes.POINTER(ZoneDesc), I, I, I, I, P, ctypes.c_size_t,
+                                            ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.zda_batch_create.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(P)]
     lib.zda_batch_destroy.argtypes = [P]
     lib.zda_batch_destroy.restype = None
@@ -358,3 +360,17 @@ class Batch:
                                          ctypes.c_void_p(om.ctypes.data), int(om.size), _stream_ptr(torch, stream),
                                          ctypes.byref(res)))
         return res
+
+
+def plan_two_step_tiles(desc: ZoneDesc, tile_rows=13, kchunk=48, k_src=1, order=0):
+    """The two-step launch plan (host only): uint32 array [ntiles][4] of
+    {phi block, i0 | rows << 16, kb | ke << 16, kind} and the interior count."""
+    lib = load()
+    n, ni = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.zda_plan_two_step_tiles(ctypes.byref(desc), tile_rows, kchunk, k_src, order, None, 0,
+                                       ctypes.byref(n), ctypes.byref(ni)))
+    out = np.zeros((n.value, 4), np.uint32)
+    _check(lib.zda_plan_two_step_tiles(ctypes.byref(desc), tile_rows, kchunk, k_src, order,
+                                       ctypes.c_void_p(out.ctypes.data), n.value, ctypes.byref(n), ctypes.byref(ni)))
+    return out, ni.value
+

@@ -84,3 +84,15 @@ def test_workloads_are_cfl_stable():
         cfl = dt * np.sqrt(1 / w.dr ** 2 + 1 / (w.r_in * dphi) ** 2 + 1 / w.dz ** 2)
         assert cfl < 1, name
         assert abs(w.r_in * dphi - 1.2272) < 1e-3, name
+
+
+def test_first_band_descriptor_validation_without_gpu(lib):
+    """Axis zone and continuous zone checks precede every HIP call."""
+    from paper_2501_07979_amd import zda
+    base = dict(r_in=0.5, nr=40, nphi=1, nz=40, n_fold=0, m=1, pml=(0, 4, 4, 4), k_mon=30, design=(10, 12), axis=1)
+    assert _create(lib, **dict(base, nphi=4))[0] == zda.ZDA_ERR_ARG            # continuous zone has nphi = 1
+    assert _create(lib, **dict(base, pml=(3, 4, 4, 4)))[0] == zda.ZDA_ERR_ARG  # no inner r-layer next to the axis
+    assert _create(lib, **dict(base, r_in=0.7))[0] == zda.ZDA_ERR_ARG          # the axis sits at r_in - dr/2
+    assert _create(lib, **dict(base, n_fold=-1))[0] == zda.ZDA_ERR_ARG
+    st, msg = _create(lib, **dict(base, m=5))                                   # (m / 2 r_in)^2 term of the CFL
+    assert st == zda.ZDA_ERR_CFL and "Courant" in msg

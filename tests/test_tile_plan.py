@@ -1,0 +1,73 @@
+"""Host logic of the two-step launch plan (no GPU): the tiles own every cell
+of the zone exactly once; the interior tiles compute no layer cell (their
+rows i0-2 .. i0+rows and planes kb-2 .. ke, clipped to the zone, avoid both
+layers), so they may run the instantiation without layer recursions; the
+owned columns of interior tiles start on 64 B boundaries; every tile order
+is a permutation of the natural one."""
+import numpy as np
+import pytest
+
+ZONES = {
+    "production_like": dict(nr=64, nphi=128, nz=60, pml=(12, 12, 12, 12)),
+    "ragged": dict(nr=37, nphi=130, nz=41, pml=(5, 6, 4, 7)),
+    "no_layers": dict(nr=29, nphi=64, nz=33, pml=(0, 0, 0, 0)),
+    "axis_zone": dict(nr=45, nphi=1, nz=50, pml=(0, 6, 4, 7)),
+    "thin": dict(nr=3, nphi=5, nz=4, pml=(1, 1, 1, 1)),
+}
+
+
+def _desc(zda, nr, nphi, nz, pml):
+    return zda.default_desc(r_in=1000.0, nr=nr, nphi=nphi, nz=nz, n_fold=8, m=1, pml=pml, k_mon=nz - 2,
+                            design=(1, 2))
+
+
+@pytest.mark.parametrize("tile_rows", [5, 13])
+@pytest.mark.parametrize("kchunk", [3, 9, 48])
+@pytest.mark.parametrize("name", list(ZONES))
+def test_tiles_cover_each_cell_once(name, kchunk, tile_rows):
+    from paper_2501_07979_amd import zda
+    z = ZONES[name]
+    d = _desc(zda, **z)
+    tiles, n_int = zda.plan_two_step_tiles(d, tile_rows, kchunk, k_src=2)
+    nr, nphi, nz = z["nr"], z["nphi"], z["nz"]
+    pr0, pr1, pz0, pz1 = z["pml"]
+    own = np.zeros((nz, nr, nphi), np.int32)
+    for q, (bx, y, zz, kind) in enumerate(tiles):
+        i0, rows = int(y & 0xFFFF), int(y >> 16)
+        kb, ke = int(zz & 0xFFFF), int(zz >> 16)
+        cols = 56 if kind == 0 else 61
+        assert (kind == 0) == (q < n_int)
+        assert 1 <= rows <= tile_rows and kb < ke
+        j0 = int(bx) * cols
+        assert j0 < nphi
+        own[kb:ke, i0:i0 + rows, j0:min(j0 + cols, nphi)] += 1
+        if kind == 0:
+            assert (j0 * 8) % 64 == 0
+            r_lo, r_hi = max(i0 - 2, 0), min(i0 + rows, nr - 1)
+            k_lo, k_hi = max(kb - 2, 0), min(ke, nz - 1)
+            assert pr0 <= r_lo and r_hi < nr - pr1, (i0, rows)
+            assert pz0 <= k_lo and k_hi < nz - pz1, (kb, ke)
+    assert own.min() == 1 and own.max() == 1
+
+
+@pytest.mark.parametrize("order", [1, (4 << 8) | 8, (1 << 8) | 3, (2 << 8) | 1])
+def test_tile_orders_are_permutations(order):
+    from paper_2501_07979_amd import zda
+    for z in ZONES.values():
+        d = _desc(zda, **z)
+        base, n0 = zda.plan_two_step_tiles(d, 13, 9, k_src=2)
+        other, n1 = zda.plan_two_step_tiles(d, 13, 9, k_src=2, order=order)
+        assert n0 == n1
+        for part in (slice(0, n0), slice(n0, None)):
+            a = sorted(map(tuple, base[part].tolist()))
+            b = sorted(map(tuple, other[part].tolist()))
+            assert a == b
+
+
+def test_plan_rejects_bad_arguments():
+    from paper_2501_07979_amd import zda
+    d = _desc(zda, **ZONES["ragged"])
+    for tr, kc, order in [(7, 9, 0), (13, 0, 0), (13, 9, (0 << 8) | 4)]:
+        with pytest.raises(zda.ZdaError) as e:
+            zda.plan_two_step_tiles(d, tr, kc, order=order)
+        assert e.value.status == zda.ZDA_ERR_ARG
