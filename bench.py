@@ -230,12 +230,26 @@ def main():
     if args.workload == "c4":
         cells, ms, tune = batch_lens(args.steps, args.warmup)
         gc = cells * args.steps / (ms / 1e3) / 1e9
-        print(json.dumps({"metric": METRIC, "value": round(gc, 4), "unit": "Gcell-updates/s", "n_gpus": 1,
-                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+        # the same lens in waves of zones that fit with both buffer sets (two-step kernel)
+        from paper_2501_07979_amd import lens
+        from paper_2501_07979_amd.workloads import c4
+        free, _ = torch.cuda.mem_get_info()
+        print("bench: the lens in waves (two-step kernel)", file=sys.stderr, flush=True)
+        _, ms_w, nwaves = lens.run_in_waves(c4(), args.steps, int(0.8 * free), warmup=args.warmup,
+                                            keep_fields=False)
+        gw = cells * args.steps / (ms_w / 1e3) / 1e9
+        best_waves = gw > gc
+        print(json.dumps({"metric": METRIC, "value": round(max(gc, gw), 4), "unit": "Gcell-updates/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": round((ms_w if best_waves else ms) / args.steps, 4),
                           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
                           "data": "synthetic",
                           "config": {"workload": "c4_batched_lens_48_zones", "cells": cells, "frequencies": 3,
-                                     "autotune": tune}}), flush=True)
+                                     "schedule": "waves, two-step" if best_waves else "one batch, single buffer",
+                                     "one_batch_single_buffer": {"gcell_updates_per_s": round(gc, 4),
+                                                                 "autotune": tune},
+                                     "waves_two_step": {"gcell_updates_per_s": round(gw, 4), "waves": nwaves,
+                                                        "budget_bytes": int(0.8 * free)}}}), flush=True)
         return
     wl = WORKLOADS[args.workload]()
     K = len(wl.omegas)

@@ -10,6 +10,7 @@ respect to every zone's design density comes from one batched adjoint run.
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import objective, zda
@@ -49,3 +50,57 @@ class Lens:
         self.batch.close()
         for z in self.zones:
             z.close()
+
+
+def zone_device_bytes(w, both_sets=True, max_freq=8):
+    """Device memory of a zone (fields, dt/eps, PML auxiliaries with the
+    two-step kernel's intermediate set, exit-plane DFT), in bytes."""
+    cells, plane = w.nr * w.nphi * w.nz, w.nr * w.nphi
+    d_r, d_z = w.pml[0] + w.pml[1], w.pml[2] + w.pml[3]
+    sets = 3 if both_sets else 1
+    aux = (10 * w.nz * d_r * w.nphi + 4 * d_z * plane) * 8 * sets
+    return cells * (48 * (2 if both_sets else 1) + 4) + aux + max_freq * 2 * plane * 8
+
+
+def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=13, warmup=0, keep_fields=True):
+    """Runs every zone for nsteps steps with both buffer sets (so the batched
+    two-step kernel applies) in waves: consecutive zones whose memory fits
+    budget_bytes form one batch, which is created, run and released before
+    the next.  Zones are independent, so this equals one batch of all of
+    them.  Returns the exit-plane DFTs (complex64 host arrays, in the order of
+    workloads) and the summed stepping time in ms (events around each wave's
+    timed run, after `warmup` untimed steps)."""
+    waves, cur, used = [], [], 0
+    for w in workloads:
+        b = zone_device_bytes(w)
+        if cur and used + b > budget_bytes:
+            waves.append(cur)
+            cur, used = [], 0
+        cur.append(w)
+        used += b
+    if cur:
+        waves.append(cur)
+    planes, total_ms = [], 0.0
+    st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for wave in waves:
+        zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps()) for w in wave]
+        batch = zda.Batch(zones)
+        batch.set_launch(tile_rows)
+        srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wave]
+        if warmup:
+            batch.run(srcs, warmup, wave[0].omegas)
+        torch.cuda.synchronize()
+        st.record()
+        batch.run(srcs, nsteps, wave[0].omegas)
+        en.record()
+        torch.cuda.synchronize()
+        total_ms += st.elapsed_time(en)
+        if keep_fields:
+            planes.extend(np.asarray(z.dft(zda.MON_PLANE).cpu()) for z in zones)
+        batch.close()
+        for z in zones:
+            z.close()
+        del zones, batch
+        torch.cuda.empty_cache()
+    return planes, total_ms, len(waves)
+

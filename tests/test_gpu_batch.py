@@ -152,3 +152,27 @@ def test_batch_with_the_axis_zone(zda, oracle_mod, mode):
         assert rel <= 1e-5
         assert np.array_equal(got, pl)
     b.close()
+
+
+def test_lens_in_waves_equals_one_batch(zda):
+    """A lens run in waves of zones (each wave one batch, released before the
+    next) gives every zone's exit-plane DFT bitwise equal to one batch of all
+    zones."""
+    from paper_2501_07979_amd import lens
+    wls = _zones(seed=75)
+    eps = [w.eps() for w in wls]
+    zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    b = zda.Batch(zones)
+    b.set_launch(13)
+    b.run([zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls], wls[0].steps,
+          wls[0].omegas)
+    ref = [z.dft(zda.MON_PLANE).cpu().numpy() for z in zones]
+    b.close()
+    for z in zones:
+        z.close()
+    budget = lens.zone_device_bytes(wls[0]) + lens.zone_device_bytes(wls[1]) + 1
+    _say("lens in waves, budget", budget)
+    planes, ms, nwaves = lens.run_in_waves(wls, wls[0].steps, budget)
+    assert nwaves >= 2 and ms > 0
+    for a, r in zip(planes, ref):
+        assert np.array_equal(a, r)
