@@ -720,8 +720,12 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
         __syncthreads();
         // ---- step one, E^{n+1} at plane k (exact on lanes >= 1, waves >= 1)
         if (step1 && (k != k_lo || k == 0) && w >= 1 && row_ok) {
-            if (lane >= 1) {
-                float2 hz_jm = s1z[w][lane - 1], hr_jm = s1r[w][lane - 1];
+            // lane 0's E^{n+1} feeds no owned cell; without layer recursions
+            // (no auxiliary stores) it is computed like the others, from a
+            // clamped neighbour, so the half-step runs without a lane mask
+            if (!PR && !PZ || lane >= 1) {
+                const int lm = lane > 0 ? lane - 1 : 0;
+                float2 hz_jm = s1z[w][lm], hr_jm = s1r[w][lm];
                 if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
                 const float2 hz_im = s1z[w - 1][lane], hp_im = s1p[w - 1][lane];
                 const float2 v_im = PR ? s1v[PR ? w - 1 : 0][lane] : zero2();
@@ -749,9 +753,12 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
         const size_t sz2 = kz2 >= 0 ? ((size_t)kz2 * nr + ic) * nphi : 0;
         const AuxRows x2 = {a.mauxR + sr2, a.mauxZ + sz2, a.oauxR + sr2, a.oauxZ + sz2};
         const bool store = own && km >= kb && km < ke;
-        if (h2_plane && w >= 1 && w <= nrow + 1 && row_ok && lane >= 1 && lane <= 62) {
+        // lanes 0 and 63 feed no owned cell: without layer recursions they
+        // compute from clamped neighbours instead of being masked off
+        if (h2_plane && w >= 1 && w <= nrow + 1 && row_ok && (!PR && !PZ || (lane >= 1 && lane <= 62))) {
             const int b = km & 1;
-            float2 ez_jp = sEz[b][w][lane + 1], er_jp = sEr[b][w][lane + 1];
+            const int lp = lane < 63 ? lane + 1 : 63;
+            float2 ez_jp = sEz[b][w][lp], er_jp = sEr[b][w][lp];
             if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
             float2 ez_ip = sEz[b][w + 1][lane], ep_ip = sEp[b][w + 1][lane];
             if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
