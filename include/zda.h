@@ -238,6 +238,12 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 #define ZDA_OPT_NT_STORES 2
 #define ZDA_OPT_LAYER_STREAM 3
 #define ZDA_OPT_TILE_PATCH 4
+/* ZDA_OPT_LAYER_KCHUNK: planes per chunk of the two-step tiles of the r-layer
+ * bands (outside the z-layers).  -1 (default): the zone's kchunk, halved
+ * (down to 12) while the layer-tile launch would hold fewer than 512 tiles,
+ * so that its long r-band tiles do not leave most CUs idle; 0: the zone's
+ * kchunk. */
+#define ZDA_OPT_LAYER_KCHUNK 5
 zda_status zda_zone_set_option(zda_zone *z, int option, int value);
 
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);

@@ -86,6 +86,8 @@ struct zda_zone {
     bool two = false;              // two leap-frog steps per launch (tile_rows 5 or 13)
     int xcd_remap = 0, nt_stores = 1, layer_stream = 0;
     int tile_patch = 0;            // (bands << 8) | columns of an XCD's patch of two-step tiles, 0 = off
+    int layer_kchunk = -1;         // planes per chunk of the r-layer band tiles (-1: automatic)
+    int tiles_lkc = -2;
     // second stream and join events for the concurrent layer-tile launch
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -410,6 +412,19 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
     const size_t z_in1 = planes.size();
     split_range(zB, d.nz, kc, planes);
     auto gx_of = [&](int lay) { return (d.nphi + two_step_cols(lay) - 1) / two_step_cols(lay); };
+    // chunk depth of the r-layer band tiles: given, or halved from kc (down
+    // to 12 planes) while the layer launch would hold fewer than 512 tiles
+    // (two blocks per CU)
+    int lkc = z->layer_kchunk > 0 ? std::min(z->layer_kchunk, kc) : kc;
+    if (z->layer_kchunk < 0) {
+        const size_t r_bands = r_in0 + (rows.size() - r_in1), z_chunks = z_in0 + (planes.size() - z_in1);
+        const size_t z_tiles = z_chunks * (r_in1 - r_in0) * (size_t)gx_of(3);
+        const size_t in_planes = (size_t)(z_in1 > z_in0 ? planes[z_in1 - 1].second - planes[z_in0].first : 0);
+        auto layer_tiles = [&](int c) {
+            return z_tiles + r_bands * (size_t)gx_of(3) * (z_chunks + (in_planes + c - 1) / c);
+        };
+        while (r_bands > 0 && lkc / 2 >= 12 && layer_tiles(lkc) < 512) lkc /= 2;
+    }
     std::vector<uint4> v[4];
     for (size_t pz = 0; pz < planes.size(); ++pz) {
         const int kb = planes[pz].first, ke = planes[pz].second;
@@ -423,17 +438,23 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
             // zone, their partly filled last rounds outweighing the gain
             const int lay = (rl || zl) ? 3 : 0;
             const int cw = two_step_cols(lay);
-            for (int bx = 0; bx < gx_of(lay); ++bx) {
-                v[lay].push_back(make_uint4((unsigned)bx, (unsigned)i0 | ((unsigned)nrow << 16),
-                                            (unsigned)kb | ((unsigned)ke << 16), tag));
-                if (lay == 0) {
-                    const int j0 = bx * cw;
-                    const size_t cols = (size_t)(std::min(j0 + cw, d.nphi) - j0);
-                    t.cells += (size_t)nrow * cols * (size_t)(ke - kb);
-                    if (d.k_mon >= kb && d.k_mon < ke) t.mon += (size_t)nrow * cols;
-                    if (k_src >= kb && k_src < ke) t.src += (size_t)nrow * cols;
+            // r-layer band tiles carry ten recursions per cell: where they
+            // are few, shorter chunks spread them over more blocks
+            std::vector<std::pair<int, int>> sub;
+            if (rl && !zl && lkc < kc) split_range(kb, ke, lkc, sub);
+            else sub.push_back({kb, ke});
+            for (const auto &sk : sub)
+                for (int bx = 0; bx < gx_of(lay); ++bx) {
+                    v[lay].push_back(make_uint4((unsigned)bx, (unsigned)i0 | ((unsigned)nrow << 16),
+                                                (unsigned)sk.first | ((unsigned)sk.second << 16), tag));
+                    if (lay == 0) {
+                        const int j0 = bx * cw;
+                        const size_t cols = (size_t)(std::min(j0 + cw, d.nphi) - j0);
+                        t.cells += (size_t)nrow * cols * (size_t)(ke - kb);
+                        if (d.k_mon >= kb && d.k_mon < ke) t.mon += (size_t)nrow * cols;
+                        if (k_src >= kb && k_src < ke) t.src += (size_t)nrow * cols;
+                    }
                 }
-            }
         }
     }
     // with ZDA_OPT_XCD_REMAP, each of the eight XCDs (which take the blocks
@@ -501,7 +522,7 @@ zda_status build_two_step_tiles(zda_zone *z)
 {
     const int TR = z->tile_rows, kc = z->kchunk;
     if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last &&
-        z->tiles_xcd == tile_order(z))
+        z->tiles_xcd == tile_order(z) && z->tiles_lkc == z->layer_kchunk)
         return ZDA_OK;
     TwoStepTiles t;
     two_step_tiles(z, TR, kc, z->k_src_last, tile_order(z), 0u, t);
@@ -522,6 +543,7 @@ zda_status build_two_step_tiles(zda_zone *z)
     z->tiles_tr = TR;
     z->tiles_kc = kc;
     z->tiles_xcd = tile_order(z);
+    z->tiles_lkc = z->layer_kchunk;
     return ZDA_OK;
 }
 
@@ -1199,6 +1221,10 @@ zda_status zda_zone_set_option(zda_zone *z, int option, int value)
     case ZDA_OPT_XCD_REMAP: z->xcd_remap = value ? 1 : 0; return ZDA_OK;
     case ZDA_OPT_NT_STORES: z->nt_stores = value ? 1 : 0; return ZDA_OK;
     case ZDA_OPT_LAYER_STREAM: z->layer_stream = value ? 1 : 0; return ZDA_OK;
+    case ZDA_OPT_LAYER_KCHUNK:
+        if (value < -1) return fail(ZDA_ERR_ARG, "layer chunk depth must be >= -1");
+        z->layer_kchunk = value;
+        return ZDA_OK;
     case ZDA_OPT_TILE_PATCH:
         if (value < 0 || (value != 0 && ((value >> 8) < 1 || (value >> 8) > 255 || (value & 0xff) < 1)))
             return fail(ZDA_ERR_ARG, "tile patch must be 0 or (bands << 8) | columns with both in [1, 255]");

@@ -20,7 +20,7 @@ ZDA_MAX_FREQ = 8
 SRC_PLANE_CIRC, SRC_RADIAL, SRC_CUSTOM = 0, 1, 2
 DFT_PLANE, DFT_VOLUME, RUN_CONTINUE, RUN_TIMING = 1, 2, 4, 8
 MON_PLANE, MON_VOLUME, MON_ADJOINT_VOLUME = 0, 1, 2
-OPT_XCD_REMAP, OPT_NT_STORES, OPT_LAYER_STREAM, OPT_TILE_PATCH = 1, 2, 3, 4
+OPT_XCD_REMAP, OPT_NT_STORES, OPT_LAYER_STREAM, OPT_TILE_PATCH, OPT_LAYER_KCHUNK = 1, 2, 3, 4, 5
 COMP = {"Er": 0, "Ephi": 1, "Ez": 2, "Hr": 3, "Hphi": 4, "Hz": 5}
 
 EXPORTS = ["zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_zone_set_eps",
