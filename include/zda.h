@@ -208,12 +208,16 @@ typedef struct {
 
 /* Launch shape of the update kernels: each thread marches kchunk z-planes of
  * one (r, phi) column.  tile_rows in {3, 7, 15} selects the fused one-launch
- * step (a block owns tile_rows radial rows x 63 phi cells; needs the second
+ * step (a block owns tile_rows radial rows x 56 phi cells; needs the second
  * buffer set), tile_rows in {5, 13} the two-step kernel (two time steps per
- * launch, a block owns tile_rows rows x 61 phi cells; needs the second set
- * and the intermediate auxiliaries), tile_rows in {1, 2, 4, 8, 16} the
- * in-place H and E kernels (a block covers tile_rows rows x 64 phi cells).  The default is the fused
- * step with 3 rows and 12-plane chunks (fewer planes for small zones).
+ * launch, a block owns tile_rows rows x 56 phi cells, 61 in the tiles that
+ * hold layer cells; needs the second set and the intermediate auxiliaries),
+ * tile_rows in {1, 2, 4, 8, 16} the in-place H and E kernels (a block covers
+ * tile_rows rows x 64 phi cells).  Default: the two-step kernel with 13 rows
+ * and the chunk depth (8 to 72 planes) whose launch is predicted to finish
+ * first when tiles run in rounds of one per CU; the fused step (3 rows,
+ * 12-plane chunks, fewer for small zones) where the intermediate set does not
+ * fit; the in-place kernels (4 rows) for single-buffer zones.
  * Results do not depend on the shape.  ZDA_ERR_ARG for kchunk outside
  * [1, nz] or any other tile_rows; ZDA_ERR_STATE for a fused shape on a zone
  * without the second buffer set. */
@@ -239,8 +243,9 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 #define ZDA_OPT_LAYER_STREAM 3
 #define ZDA_OPT_TILE_PATCH 4
 /* ZDA_OPT_LAYER_KCHUNK: planes per chunk of the two-step tiles of the r-layer
- * bands (outside the z-layers).  -1 (default): the zone's kchunk, halved
- * (down to 12) while the layer-tile launch would hold fewer than 512 tiles,
+ * bands (outside the z-layers).  -1 (default): the zone's kchunk (at most
+ * 48), halved (down to 12) while the layer-tile launch would hold fewer than
+ * 512 tiles,
  * so that its long r-band tiles do not leave most CUs idle; 0: the zone's
  * kchunk. */
 #define ZDA_OPT_LAYER_KCHUNK 5

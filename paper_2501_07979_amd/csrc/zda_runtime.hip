@@ -412,10 +412,10 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
     const size_t z_in1 = planes.size();
     split_range(zB, d.nz, kc, planes);
     auto gx_of = [&](int lay) { return (d.nphi + two_step_cols(lay) - 1) / two_step_cols(lay); };
-    // chunk depth of the r-layer band tiles: given, or halved from kc (down
-    // to 12 planes) while the layer launch would hold fewer than 512 tiles
-    // (two blocks per CU)
-    int lkc = z->layer_kchunk > 0 ? std::min(z->layer_kchunk, kc) : kc;
+    // chunk depth of the r-layer band tiles: given, or at most 48 and halved
+    // (down to 12 planes) while the layer launch would hold fewer than 512
+    // tiles (two blocks per CU)
+    int lkc = z->layer_kchunk > 0 ? std::min(z->layer_kchunk, kc) : std::min(kc, 48);
     if (z->layer_kchunk < 0) {
         const size_t r_bands = r_in0 + (rows.size() - r_in1), z_chunks = z_in0 + (planes.size() - z_in1);
         const size_t z_tiles = z_chunks * (r_in1 - r_in0) * (size_t)gx_of(3);
@@ -514,6 +514,33 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
         else if (order > 1) patch_order(v[q], gx_of(q), order >> 8, order & 0xff);
         t.v[q].insert(t.v[q].end(), v[q].begin(), v[q].end());
     }
+}
+
+// Default chunk depth of the two-step interior tiles: the candidate whose
+// launch finishes first if every tile takes time in proportion to the planes
+// it computes (its chunk plus three) and the tiles run in rounds of one per
+// CU: ceil(tiles / n_cu) x (chunk + 3), ties to the deeper chunk.  Measured:
+// 40 planes on the 256 x 512 x 300 zone (5.6 % faster than 48), 64 on the
+// 512 x 1024 x 400 zone (1 %), 8 on zones smaller than one round.
+int default_two_step_kchunk(const zda_zone_desc &d, int n_cu)
+{
+    const int rA = d.pml_r_in > 0 ? std::min(d.pml_r_in + 2, d.nr) : 0;
+    const int rB = d.pml_r_out > 0 ? std::max(d.nr - d.pml_r_out - 1, rA) : d.nr;
+    const int zA = d.pml_z_lo > 0 ? std::min(d.pml_z_lo + 2, d.nz) : 0;
+    const int zB = d.pml_z_hi > 0 ? std::max(d.nz - d.pml_z_hi - 1, zA) : d.nz;
+    const long bands = (rB - rA + 12) / 13, gx = (d.nphi + two_step_cols(0) - 1) / two_step_cols(0);
+    const long planes = std::max(zB - zA, 1);
+    int best = std::min(8, d.nz);
+    double best_cost = 1e300;
+    for (int kc : {8, 12, 16, 24, 32, 40, 48, 56, 64, 72}) {
+        if (kc > d.nz) break;
+        const long chunks = (planes + kc - 1) / kc;
+        const long len = (planes + chunks - 1) / chunks;
+        const long tiles = std::max(bands * gx * chunks, 1L);
+        const double cost = (double)((tiles + n_cu - 1) / n_cu) * (double)(len + 3);
+        if (cost <= best_cost) { best_cost = cost; best = kc; }
+    }
+    return best;
 }
 
 // The zone's own tile list (interior tiles first), rebuilt when the launch
@@ -1008,16 +1035,16 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
             zda_status s2 = dev_alloc(z, &z->mauxR, (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
             if (s2 == ZDA_OK) s2 = dev_alloc(z, &z->mauxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
             if (s2 == ZDA_OK && d->nr <= 65535 && d->nz <= 65535) {
-                // default two-step shape: 13 owned rows, 48-plane chunks,
-                // halved (down to 8) while there are fewer than 1024 tiles
+                // default two-step shape: 13 owned rows, chunk depth from
+                // the launch-round model
                 z->has_m = true;
                 z->two = true;
                 z->fused = false;
                 z->tile_rows = 13;
-                const long tiles = (long)((d->nphi + two_step_cols(0) - 1) / two_step_cols(0)) * ((d->nr + 12) / 13);
-                int kc = std::min(48, d->nz);
-                while (kc > 8 && tiles * ((d->nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
-                z->kchunk = kc;
+                hipDeviceProp_t prop;
+                const int n_cu = hipGetDeviceProperties(&prop, z->device) == hipSuccess && prop.multiProcessorCount > 0
+                                     ? prop.multiProcessorCount : 256;
+                z->kchunk = default_two_step_kchunk(*d, n_cu);
             } else if (s2 == ZDA_OK) {
                 z->has_m = true;   // two-step tiles store rows and planes in 16 bits; not the default here
             } else {
