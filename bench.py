@@ -73,14 +73,17 @@ def two_step_zone_bytes(wl, K):
     return 100 * wl.cells + 160 * r_cells + 64 * z_cells + K * 32 * plane + 16 * plane
 
 
-def load_traffic(kernel, wl_name):
+def load_traffic(kernel, wl_name, launch=None):
     """HBM traffic per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    and (when the summary records it) the same launch shape."""
     path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (kernel, wl_name))
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_sha") != kernel_hash():
+        return None
+    if launch is not None and rec.get("launch") is not None and rec["launch"] != launch:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -285,6 +288,8 @@ def main():
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     tm = zone.last_timing()
+    info = zone.info()
+    launch = {"tile_rows": info.tile_rows, "kchunk": info.kchunk}
     # sanity: the run produced finite monitors
     plane = zone.dft(zda.MON_PLANE)
     assert torch.isfinite(torch.view_as_real(plane)).all().item()
@@ -311,7 +316,7 @@ def main():
         zone_min = hb + eb
         family = "split"
     achieved = kbytes / (e_avg / 1e3) / 1e9
-    traffic = load_traffic(kernel, wl.name)
+    traffic = load_traffic(kernel, wl.name, launch)
     out = {
         "metric": METRIC,
         "value": round(gcells, 4),
@@ -333,6 +338,7 @@ def main():
             "frequencies": K,
             "run_steps_of_full_job": wl.steps,
             "kernel_family": family,
+            "launch": launch,
             "steps_per_launch": tm.steps_per_launch,
             "kernel_ms_per_launch": kernel_ms,
             "wall_s": round(wall, 3),
