@@ -231,7 +231,8 @@ def test_fused_launch_shapes_are_bitwise_identical(zda):
     outs = []
     for kc, tr, opt, val in [(41, 7, 0, 0), (5, 3, 0, 0), (13, 15, 0, 0), (1, 7, 0, 0), (9, 13, 0, 0), (41, 13, 0, 0),
                              (4, 5, 0, 0), (1, 5, 0, 0), (9, 13, zda.OPT_LAYER_STREAM, 1), (4, 5, zda.OPT_XCD_REMAP, 1),
-                             (9, 13, zda.OPT_TILE_PATCH, (2 << 8) | 2), (4, 5, zda.OPT_TILE_PATCH, (3 << 8) | 1)]:
+                             (9, 13, zda.OPT_TILE_PATCH, (2 << 8) | 2), (4, 5, zda.OPT_TILE_PATCH, (3 << 8) | 1),
+                             (24, 13, zda.OPT_LAYER_KCHUNK, 0), (24, 13, zda.OPT_LAYER_KCHUNK, 5)]:
         _say("determinism", kc, tr, opt, val)
         g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
         g.set_launch(kc, tr)
