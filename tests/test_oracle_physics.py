@@ -7,7 +7,8 @@
 * PEC annular-cavity TM resonances at the Bessel cross-product zeros,
   converging at second order under grid refinement;
 * n-fold symmetry: an n-wedge run tiled with exp(i m l tau) equals the
-  full-circle run;
+  full-circle run; conjugate symmetry: order -m with the conjugated source
+  gives the conjugate fields;
 * adjoint gradient vs FP64 central finite differences; one broadband adjoint
   run equals the sum of single-frequency runs;
 * late-time stability of the regularised r-PML, PML reflection bound, and a
@@ -181,6 +182,29 @@ def test_nfold_tiling(oracle_mod):
         assert np.abs(tiled - ff).max() < 1e-11 * np.abs(ff).max()
     tiled = np.concatenate([ow["plane"] * np.exp(1j * l * tau) for l in range(n)], axis=3)
     assert np.abs(tiled - of["plane"]).max() < 1e-11 * np.abs(of["plane"]).max()
+
+
+def test_conjugate_symmetry_m_to_minus_m(oracle_mod):
+    """For real permittivity and real layer coefficients the scheme commutes
+    with complex conjugation up to m -> -m: the run with Bloch order -m and
+    the conjugated source gives the conjugate of every field of the run with
+    +m (so the x-polarised response is the real part of the m = +1 run)."""
+    O = oracle_mod
+    rng = np.random.default_rng(7)
+    kw = dict(r_in=30.0, nr=14, nphi=6, nz=16, n_fold=5, pml=(3, 3, 3, 3), k_mon=12)
+    zp = O.OracleZone(m=1, **kw)
+    zm = O.OracleZone(m=-1, **kw)
+    eps = (1 + 4 * rng.random(zp.shape)).astype(np.float32)
+    zp.set_eps(eps)
+    zm.set_eps(eps)
+    pat = rng.standard_normal((1, 2, 14, 6)) + 1j * rng.standard_normal((1, 2, 14, 6))
+    T = 300
+    g = O.pulse(T, zp.dt, 0.3, 6.0)[0] * (1.0 + 0.5j)
+    zp.run(T, patterns=pat, profiles=g[None], k_src=4)
+    zm.run(T, patterns=np.conj(pat), profiles=np.conj(g)[None], k_src=4)
+    for c in E_COMPS + H_COMPS:
+        fp, fm = zp.get_field(c), zm.get_field(c)
+        assert np.abs(fm - np.conj(fp)).max() < 1e-12 * np.abs(fp).max(), c
 
 
 def _grad_zone(O, rng, omegas=(0.3, 0.36)):
