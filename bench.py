@@ -150,7 +150,7 @@ def surrogate_design(rounds=3, samples=64, train_iters=400, inner_iters=10, plai
     """Design on the gradient zone's small copy (64 x 64 x 96, 3 frequencies,
     2-D pattern extruded through the design layer): the surrogate's
     trust-region loop (FDTD samples around the FDTD-verified base, BF16-MFMA
-    training, surrogate inner iterations, one FDTD judgement per round)
+    training, surrogate inner iterations, one FDTD verification per round)
     against plain FDTD-adjoint iterations from the same start."""
     import torch
     from paper_2501_07979_amd import objective, surrogate, zda

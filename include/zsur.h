@@ -2,7 +2,7 @@
  * zsur.h -- C ABI of the surrogate kernels (gfx950): a small convolutional
  * network that maps a zone's design-layer pattern to its complex exit-plane
  * DFT fields, so that inner design iterations can run on it while the FDTD
- * (libzda) stays the judge that re-verifies every k-th iterate.  The
+ * (libzda) stays the arbiter that re-verifies every k-th iterate.  The
  * surrogate is not part of arXiv 2501.07979; it is the learned accelerator
  * of its inverse-design loop (the paper's gradient is the adjoint of the
  * section "Differentiable FDTD in cylindrical coordinates", which the

@@ -1,7 +1,7 @@
 """Design surrogate: a small dilated convolutional network that maps a zone's
 design-layer pattern to its complex exit-plane DFT fields, so that inner
 design iterations can run on it; the FDTD (libzda) generates its training
-samples and stays the judge, re-verifying every k-th iterate.
+samples and stays the arbiter, re-verifying every k-th iterate.
 
 Every layer runs on the hand-written gfx950 kernels of libzsur.so (BF16 MFMA
 GEMM with FP32 accumulation, im2col/col2im, activation gradient, MSE, Adam);
@@ -411,7 +411,7 @@ def design_loop(net, wl, rho0, weights, scale, iters, check_every, lr=0.02, zone
 
 
 def fdtd_objective(zone, wl, rho2d, weights):
-    """The judge: F = sum_k |sum W_k E_k|^2 of the FDTD exit-plane fields of
+    """The arbiter: F = sum_k |sum W_k E_k|^2 of the FDTD exit-plane fields of
     the pattern rho2d extruded through the design layer."""
     import torch
     from . import zda
@@ -425,7 +425,7 @@ def fdtd_objective(zone, wl, rho2d, weights):
 
 def trust_region_design(net, wl, weights, rho0, zone, rounds=4, samples=96, radius=0.25, inner_iters=10,
                         train_iters=600, lr=0.02, seed=0, log=None):
-    """Surrogate-accelerated design with the FDTD as judge.  Each round:
+    """Surrogate-accelerated design with the FDTD as arbiter.  Each round:
     FDTD samples of perturbations (max-norm `radius`) around the current
     base, fine-tuning of the network on the field change from the base,
     `inner_iters` surrogate iterations inside the trust region, and one FDTD

@@ -82,7 +82,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError("libzda.so is not built (run __graft_entry__.build() or paper_2501_07979_amd/build.py)")
+        raise RuntimeError("libzda.so is not built (run python paper_2501_07979_amd/build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lib.zda_zone_desc_default.argtypes = [ctypes.POINTER(ZoneDesc)]
