@@ -214,7 +214,7 @@ typedef struct {
  * hold layer cells; needs the second set and the intermediate auxiliaries),
  * tile_rows in {1, 2, 4, 8, 16} the in-place H and E kernels (a block covers
  * tile_rows rows x 64 phi cells).  Default: the two-step kernel with 13 rows
- * and the chunk depth (8 to 72 planes) whose launch is predicted to finish
+ * and the chunk depth (3 to 72 planes) whose launch is predicted to finish
  * first when tiles run in rounds of one per CU; the fused step (3 rows,
  * 12-plane chunks, fewer for small zones) where the intermediate set does not
  * fit; the in-place kernels (4 rows) for single-buffer zones.
