@@ -213,12 +213,16 @@ typedef struct {
  * launch, a block owns tile_rows rows x 56 phi cells, 61 in the tiles that
  * hold layer cells; needs the second set and the intermediate auxiliaries),
  * tile_rows in {1, 2, 4, 8, 16} the in-place H and E kernels (a block covers
- * tile_rows rows x 64 phi cells).  Default: the two-step kernel with 13 rows
+ * tile_rows rows x 64 phi cells), tile_rows = 32 the in-place kernels with a
+ * flat mapping (a block covers 256 consecutive cells of the (r, phi) plane,
+ * so narrow wedges keep every lane busy).  Default: for zones of at most 16
+ * phi cells (and the continuous zone) the flat in-place kernels; otherwise
+ * the two-step kernel with 13 rows
  * and the chunk depth (3 to 72 planes) whose launch is predicted to finish
  * first when tiles run in rounds of one per CU; the fused step (3 rows,
  * 12-plane chunks, fewer for small zones) where the intermediate set does not
  * fit; the in-place kernels (4 rows) for single-buffer zones.
- * Results do not depend on the shape.  ZDA_ERR_ARG for kchunk outside
+ * Results do not depend on the shape (beyond rounding).  ZDA_ERR_ARG for kchunk outside
  * [1, nz] or any other tile_rows; ZDA_ERR_STATE for a fused shape on a zone
  * without the second buffer set. */
 zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);

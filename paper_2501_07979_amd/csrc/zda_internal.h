@@ -97,6 +97,11 @@ void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStre
 constexpr int two_step_cols(int lay) { return lay == 0 ? 56 : 61; }
 // a fused-step tile owns FUSED_COLS phi cells and TR rows
 constexpr int FUSED_COLS = 56;
+// tile_rows code of the in-place kernels with the flat (r, phi) mapping, its
+// block size, and the widest zone (phi cells) that takes it by default
+constexpr int FLAT_ROWS = 32;
+constexpr int FLAT_BLOCK_HOST = 256;
+constexpr int NARROW_PHI = 16;
 void launch_fill(float2 *p, size_t n, hipStream_t s);
 // tiles of one zone for the split (BY rows) or fused (TR owned rows) kernels
 unsigned tiles_split(const StepArgs &a, int BY);

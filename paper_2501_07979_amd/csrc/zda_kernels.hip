@@ -48,14 +48,34 @@ __device__ __forceinline__ int slab_row(int q, int n, int d0, int d1)
 }
 
 constexpr int BX = 64;   // one wavefront along phi
+// flat mapping of the in-place kernels: a block of FLAT_BLOCK threads covers
+// consecutive cells of the (r, phi) plane (row-major, so still one contiguous
+// segment per wavefront); narrow wedges (few phi cells) keep every lane busy
+constexpr int FLAT_BLOCK = FLAT_BLOCK_HOST;
+
+// (i, j) of this thread in the in-place kernels, false if outside the zone
+template <int BY, bool FLAT>
+__device__ __forceinline__ bool split_cell(const StepArgs &a, int bx, int by, int &i, int &j)
+{
+    if constexpr (FLAT) {
+        const unsigned q = (unsigned)bx * FLAT_BLOCK + threadIdx.x;
+        if (q >= (unsigned)a.nr * (unsigned)a.nphi) return false;
+        i = (int)(q / (unsigned)a.nphi);
+        j = (int)(q - (unsigned)i * (unsigned)a.nphi);
+        return true;
+    } else {
+        j = bx * BX + threadIdx.x;
+        i = by * BY + threadIdx.y;
+        return j < a.nphi && i < a.nr;
+    }
+}
 
 // H^{n+1/2} = H^{n-1/2} - dt curlE(E^n); also advances V = F H_phi in the r-layer.
-template <int BY>
+template <int BY, bool FLAT = false>
 __device__ __forceinline__ void h_step_body(const StepArgs &a, int n, int bx, int by, int bz)
 {
-    const int j = bx * BX + threadIdx.x;
-    const int i = by * BY + threadIdx.y;
-    if (j >= a.nphi || i >= a.nr) return;
+    int i, j;
+    if (!split_cell<BY, FLAT>(a, bx, by, i, j)) return;
     const int kb = bz * a.kchunk;
     const int ke = min(kb + a.kchunk, a.nz);
     const int nphi = a.nphi, nr = a.nr, nz = a.nz;
@@ -131,12 +151,11 @@ __device__ __forceinline__ void h_step_body(const StepArgs &a, int n, int bx, in
 
 // E^{n+1} = E^n + (dt/eps)(curlH(H^{n+1/2}) - J^{n+1/2}); source sheet, DFT
 // accumulation and U = F E_phi in the r-layer fused.
-template <int BY>
+template <int BY, bool FLAT = false>
 __device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, int by, int bz)
 {
-    const int j = bx * BX + threadIdx.x;
-    const int i = by * BY + threadIdx.y;
-    if (j >= a.nphi || i >= a.nr) return;
+    int i, j;
+    if (!split_cell<BY, FLAT>(a, bx, by, i, j)) return;
     const int kb = bz * a.kchunk;
     const int ke = min(kb + a.kchunk, a.nz);
     const int nphi = a.nphi, nr = a.nr, nz = a.nz;
@@ -851,6 +870,16 @@ __global__ __launch_bounds__(BX * BY) void e_step_kernel(StepArgs a, int n)
     e_step_body<BY>(a, n, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+__global__ __launch_bounds__(FLAT_BLOCK) void h_step_flat(StepArgs a, int n)
+{
+    h_step_body<1, true>(a, n, blockIdx.x, 0, blockIdx.z);
+}
+
+__global__ __launch_bounds__(FLAT_BLOCK) void e_step_flat(StepArgs a, int n)
+{
+    e_step_body<1, true>(a, n, blockIdx.x, 0, blockIdx.z);
+}
+
 template <int TR>
 __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int n)
 {
@@ -930,6 +959,26 @@ __global__ __launch_bounds__(BX * BY) void e_step_batch(BatchArgs b, int n_rel)
     const unsigned gx = (a.nphi + BX - 1) / BX, gy = (a.nr + BY - 1) / BY;
     const int n = n_rel + (b.n_base ? *b.n_base : 0);
     e_step_body<BY>(a, n, local % gx, (local / gx) % gy, local / (gx * gy));
+}
+
+__global__ __launch_bounds__(FLAT_BLOCK) void h_flat_batch(BatchArgs b, int n_rel)
+{
+    const int zi = batch_zone(b.prefix, b.nzones, blockIdx.x);
+    const StepArgs a = zone_args(b.tab, zi);
+    const unsigned local = blockIdx.x - b.prefix[zi];
+    const unsigned gq = ((unsigned)a.nr * (unsigned)a.nphi + FLAT_BLOCK - 1) / FLAT_BLOCK;
+    const int n = n_rel + (b.n_base ? *b.n_base : 0);
+    h_step_body<1, true>(a, n, local % gq, 0, local / gq);
+}
+
+__global__ __launch_bounds__(FLAT_BLOCK) void e_flat_batch(BatchArgs b, int n_rel)
+{
+    const int zi = batch_zone(b.prefix, b.nzones, blockIdx.x);
+    const StepArgs a = zone_args(b.tab, zi);
+    const unsigned local = blockIdx.x - b.prefix[zi];
+    const unsigned gq = ((unsigned)a.nr * (unsigned)a.nphi + FLAT_BLOCK - 1) / FLAT_BLOCK;
+    const int n = n_rel + (b.n_base ? *b.n_base : 0);
+    e_step_body<1, true>(a, n, local % gq, 0, local / gq);
 }
 
 template <int TR>
@@ -1054,6 +1103,13 @@ void launch_pair(const StepArgs &a, int n, hipStream_t s, bool h)
 
 void launch_step(const StepArgs &a, int n, hipStream_t s, bool h)
 {
+    if (a.tile_rows == FLAT_ROWS) {
+        dim3 grid(((unsigned)a.nr * (unsigned)a.nphi + FLAT_BLOCK - 1) / FLAT_BLOCK, 1,
+                  (a.nz + a.kchunk - 1) / a.kchunk);
+        if (h) hipLaunchKernelGGL(h_step_flat, grid, dim3(FLAT_BLOCK), 0, s, a, n);
+        else hipLaunchKernelGGL(e_step_flat, grid, dim3(FLAT_BLOCK), 0, s, a, n);
+        return;
+    }
     switch (a.tile_rows) {
     case 1: launch_pair<1>(a, n, s, h); break;
     case 2: launch_pair<2>(a, n, s, h); break;
@@ -1116,6 +1172,9 @@ void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStre
 
 unsigned tiles_split(const StepArgs &a, int BY)
 {
+    if (BY == FLAT_ROWS)
+        return (((unsigned)a.nr * (unsigned)a.nphi + FLAT_BLOCK - 1) / FLAT_BLOCK) *
+               (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
     return (unsigned)((a.nphi + BX - 1) / BX) * (unsigned)((a.nr + BY - 1) / BY) *
            (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
 }
@@ -1149,6 +1208,10 @@ void launch_batch_step(const BatchArgs &b, unsigned nblocks, int tile_rows, bool
         }
     } else {
         switch (tile_rows) {
+        case FLAT_ROWS:
+            hipLaunchKernelGGL(h_flat_batch, dim3(nblocks), dim3(FLAT_BLOCK), 0, s, b, n_rel);
+            hipLaunchKernelGGL(e_flat_batch, dim3(nblocks), dim3(FLAT_BLOCK), 0, s, b, n_rel);
+            break;
         case 1: launch_batch_split<1>(b, nblocks, n_rel, s); break;
         case 2: launch_batch_split<2>(b, nblocks, n_rel, s); break;
         case 8: launch_batch_split<8>(b, nblocks, n_rel, s); break;

@@ -993,6 +993,7 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     // (down to 4 planes) while the grid has fewer than 2048 blocks.  Zones
     // with room for the intermediate auxiliaries switch to the two-step
     // kernel below.
+    const bool narrow = d->nphi <= NARROW_PHI;
     {
         z->tile_rows = 3;
         const long tiles = (long)((d->nphi + FUSED_COLS - 1) / FUSED_COLS) * ((d->nr + 2) / 3);
@@ -1060,6 +1061,22 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
             }
             (void)hipGetLastError();
         }
+    }
+    // narrow wedges (a few phi cells, down to the continuous zone's one):
+    // the tiled kernels would leave most lanes of each wavefront idle, so the
+    // in-place kernels with the flat (r, phi) mapping are the default there
+    // (measured on 1250-row zones: 11 phi cells 10.2 -> 32.6, 16 cells
+    // 14.0 -> 36.2, the continuous zone 1.1 -> 13.2 Gcell-updates/s against
+    // the two-step kernel); short chunks, down to 2 planes, while the grid
+    // has fewer than 8192 blocks
+    if (st == ZDA_OK && narrow) {
+        z->fused = false;
+        z->two = false;
+        z->tile_rows = FLAT_ROWS;
+        const long blocks = ((long)d->nr * d->nphi + FLAT_BLOCK_HOST - 1) / FLAT_BLOCK_HOST;
+        int kc = std::min(12, d->nz);
+        while (kc > 2 && blocks * ((d->nz + kc - 1) / kc) < 8192) --kc;
+        z->kchunk = kc;
     }
     if (st == ZDA_OK) st = dev_alloc(z, &z->rows, (size_t)d->nr);
     if (st == ZDA_OK) st = dev_alloc(z, &z->zrows, (size_t)d->nz);
@@ -1228,11 +1245,13 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
 {
     if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
     if (kchunk < 1 || kchunk > z->d.nz) return fail(ZDA_ERR_ARG, "kchunk must be in [1, nz]");
-    const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16;
+    const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
+                       tile_rows == FLAT_ROWS;
     const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15;
     const bool two = tile_rows == 5 || tile_rows == 13;
     if (!split && !fused && !two)
-        return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16 (split), 3, 7, 15 (fused) or 5, 13 (two-step)");
+        return fail(ZDA_ERR_ARG,
+                    "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15 (fused) or 5, 13 (two-step)");
     if ((fused || two) && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set");
     if ((fused || two) && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set");
     if (two && !z->has_m) return fail(ZDA_ERR_STATE, "no intermediate auxiliaries for the two-step kernel");
@@ -1560,11 +1579,13 @@ void zda_batch_destroy(zda_batch *b)
 zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk)
 {
     if (!b) return fail(ZDA_ERR_ARG, "NULL batch");
-    const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16;
+    const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
+                       tile_rows == FLAT_ROWS;
     const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15;
     const bool two = tile_rows == 5 || tile_rows == 13;
     if (!split && !fused && !two)
-        return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16 (split), 3, 7, 15 (fused) or 5, 13 (two-step)");
+        return fail(ZDA_ERR_ARG,
+                    "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15 (fused) or 5, 13 (two-step)");
     if (fused)
         for (auto z : b->zones)
             if (!zone_has_second_set(z)) return fail(ZDA_ERR_STATE, "a zone has no second buffer set");
@@ -1668,7 +1689,7 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
     // 1) kernel family and tile shape with each zone's default depth
     // (the time-block depth: 1 for the split and fused kernels, 2 for the
     // two-step kernel)
-    std::vector<int> rows_c = {2, 4, 8};
+    std::vector<int> rows_c = {2, 4, 8, FLAT_ROWS};
     bool can_fuse = true, can_two = true;
     for (auto z : b->zones) {
         can_fuse = can_fuse && zone_has_second_set(z);

@@ -1,4 +1,4 @@
-"""GPU parity of the zones of the first radial band against the FP64 oracle:
+"""GPU parity of the zones of the first radial band, and of narrow wedges, against the FP64 oracle:
 the zone that contains the axis (r_in = dr / 2, row 0 updated with the axis
 scalars at zero, outer r-layer only) and the continuous zone (n_fold = 0,
 nphi = 1, fields carrying exp(i m phi) exactly), in every kernel family.
@@ -12,7 +12,7 @@ from test_gpu_parity import SHAPES, _objective, _rel
 pytestmark = pytest.mark.gpu
 
 COMPS = ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz")
-FAMILIES = ["default", "fused_tr3_kc7", "split_r4_kc7", "split_r1", "two_tr13_kc9", "two_tr5_kc3"]
+FAMILIES = ["default", "fused_tr3_kc7", "split_r4_kc7", "split_r1", "two_tr13_kc9", "two_tr5_kc3", "flat_kc5"]
 
 
 def _say(*a):
@@ -52,13 +52,16 @@ def _workload(case):
         common.update(width=0.5, k_mon=20)
         return Workload(case, r_in=0.5, nr=37, nphi=70, nz=50, n_fold=2, m=1, courant=0.02, pml=(0, 6, 4, 7),
                         steps=900, axis=1, **common)
+    if case == "narrow_wedge":          # a wedge ~10 phi cells wide, as in the paper's lenses
+        return Workload(case, r_in=600.0, nr=40, nphi=11, nz=50, n_fold=360, m=1, pml=(5, 6, 4, 7), steps=300,
+                        **common)
     if case == "continuous_annulus":    # continuous zone away from the axis, layers on both sides
         return Workload(case, r_in=30.0, nr=45, nphi=1, nz=50, n_fold=0, m=3, pml=(5, 6, 4, 7), steps=300,
                         **common)
     raise KeyError(case)
 
 
-CASES = ["axis_continuous", "axis_continuous_m2", "axis_wedge", "continuous_annulus"]
+CASES = ["axis_continuous", "axis_continuous_m2", "axis_wedge", "continuous_annulus", "narrow_wedge"]
 
 
 @pytest.mark.parametrize("shape", FAMILIES)
@@ -91,7 +94,7 @@ def test_first_band_zones_source_driven(zda, oracle_mod, case, shape):
     g.close()
 
 
-@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr5_kc3"])
+@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr5_kc3", "flat_kc5"])
 @pytest.mark.parametrize("case", ["axis_continuous", "axis_wedge"])
 def test_axis_zone_random_state(zda, oracle_mod, case, shape):
     """Arbitrary fields on every cell that the axis zone updates (row 0
@@ -118,7 +121,7 @@ def test_axis_zone_random_state(zda, oracle_mod, case, shape):
     g.close()
 
 
-@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc3"])
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc3", "flat_kc5"])
 def test_axis_zone_gradient_parity(zda, oracle_mod, shape):
     """Adjoint gradient over the design layer of a continuous zone containing
     the axis (the adjoint runs with -m: seams 1 -+ i m) against the oracle."""

@@ -35,7 +35,7 @@ def zda():
     return Z
 
 
-@pytest.mark.parametrize("mode", ["fused", "split", "two", "two_odd"])
+@pytest.mark.parametrize("mode", ["fused", "split", "flat", "two", "two_odd"])
 def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
     wls = _zones()
     if mode == "two_odd":            # an odd step count ends with one fused step
@@ -47,13 +47,15 @@ def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
         z = zda.Zone(zda.default_desc(**w.desc_kwargs()), e)
         if mode == "split":
             z.set_launch(w.nz, 4)
+        if mode == "flat":
+            z.set_launch(w.nz, 32)
         z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width, volume=True)
         singles.append((z.read_field("Ez").cpu().numpy(), z.dft(zda.MON_PLANE).cpu().numpy(),
                         z.dft(zda.MON_VOLUME).cpu().numpy()))
         z.close()
     zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
     b = zda.Batch(zones)
-    b.set_launch({"fused": 7, "split": 4, "two": 13, "two_odd": 5}[mode])
+    b.set_launch({"fused": 7, "split": 4, "flat": 32, "two": 13, "two_odd": 5}[mode])
     srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
     _say("batch run", mode)
     b.run(srcs, wls[0].steps, wls[0].omegas, volume=True)    # graph replays + eager tail

@@ -27,9 +27,11 @@ def _rel(a, b):
 
 # launch shapes: (kchunk, tile_rows); tile_rows 3/7/15 select the fused
 # double-buffered step, 5/13 the two-step kernel, 1/2/4/8/16 the split
-# in-place H and E kernels; None keeps the zone's default
+# in-place H and E kernels, 32 the in-place kernels with the flat (r, phi)
+# mapping; None keeps the zone's default
 SHAPES = {"default": None, "fused_tr3_kc7": (7, 3), "fused_tr15_kc13": (13, 15), "split_r4_kc7": (7, 4),
-          "split_r1": (0, 1), "two_tr13_kc9": (9, 13), "two_tr5_kc6": (6, 5), "two_tr5_kc3": (3, 5)}
+          "split_r1": (0, 1), "two_tr13_kc9": (9, 13), "two_tr5_kc6": (6, 5), "two_tr5_kc3": (3, 5),
+          "flat_kc5": (5, 32)}
 
 
 def _zone_pair(zda, oracle_mod, wl, eps, shape=None):
@@ -61,7 +63,7 @@ def test_c1_parity_exit_plane_dft(zda, oracle_mod, shape):
 
 
 @pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "fused_tr15_kc13", "split_r4_kc7", "two_tr13_kc9",
-                                   "two_tr5_kc6", "two_tr5_kc3"])
+                                   "two_tr5_kc6", "two_tr5_kc3", "flat_kc5"])
 @pytest.mark.parametrize("case", ["ragged_m1", "ragged_m0", "ragged_mneg", "no_pml"])
 def test_ragged_shapes_all_fields(zda, oracle_mod, case, shape):
     """Shapes that are not multiples of the tile (nphi 70, nr 37) with uneven
@@ -86,7 +88,8 @@ def test_ragged_shapes_all_fields(zda, oracle_mod, case, shape):
     assert _rel(g.dft(zda.MON_VOLUME).cpu().numpy(), ref["vol"]) <= 1e-5
 
 
-@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr13_kc9", "two_tr5_kc3"])
+@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr13_kc9", "two_tr5_kc3",
+                                   "flat_kc5"])
 def test_random_state_steps_with_pml(zda, oracle_mod, shape):
     """Arbitrary initial fields (written through the ABI) stepped without
     reset: every update term, PML auxiliary and the seam act from step 1
