@@ -32,24 +32,47 @@ class Lens:
         self.radius = max(w.r_in + w.nr * w.dr for w in self.workloads)
         self.focal = objective.focal_length(self.radius, na)
         self.zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps()) for w in self.workloads]
-        self.batch = zda.Batch(self.zones)
+        # one batch per kernel family: narrow wedges and the continuous zone on
+        # the flat in-place kernels, the others on the two-step kernel
+        self.groups = []
+        for narrow in (True, False):
+            idx = [q for q, w in enumerate(self.workloads) if is_narrow(w) == narrow]
+            if idx:
+                b = zda.Batch([self.zones[q] for q in idx])
+                b.set_launch(FLAT if narrow else TWO_STEP)
+                self.groups.append((idx, b))
         self.weights = [objective.focal_weights(w, w.omegas, self.focal) for w in self.workloads]
         self.run_kw = dict(nsteps=w0.steps, omegas=w0.omegas, k_src=w0.k_src, omega_c=w0.omega_c, width=w0.width)
 
     def phasors(self, rhos):
         """Focal phasors a_k of the whole lens for design densities rhos
         (one [k1-k0][nr][nphi] float32 CUDA tensor per zone)."""
-        planes = batch_fdtd(rhos, self.batch, **self.run_kw)
-        return sum((p * w).sum(dim=(1, 2, 3)) for p, w in zip(planes, self.weights))
+        a = 0
+        for idx, b in self.groups:
+            planes = batch_fdtd([rhos[q] for q in idx], b, **self.run_kw)
+            a = a + sum((p * self.weights[q]).sum(dim=(1, 2, 3)) for p, q in zip(planes, idx))
+        return a
 
     def objective(self, rhos):
         a = self.phasors(rhos)
         return (a.abs() ** 2).sum(), a
 
     def close(self):
-        self.batch.close()
+        for _, b in self.groups:
+            b.close()
         for z in self.zones:
             z.close()
+
+
+# batch launch codes: the two-step kernel (13 rows) and the flat in-place kernels
+TWO_STEP, FLAT = 13, 32
+NARROW_PHI = 16
+
+
+def is_narrow(w):
+    """Zones of at most 16 phi cells (and the continuous zone) run on the flat
+    in-place kernels, whose lanes all work however narrow the wedge."""
+    return w.nphi <= NARROW_PHI
 
 
 def zone_device_bytes(w, both_sets=True, max_freq=8):
@@ -62,30 +85,38 @@ def zone_device_bytes(w, both_sets=True, max_freq=8):
     return cells * (48 * (2 if both_sets else 1) + 4) + aux + max_freq * 2 * plane * 8
 
 
-def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=13, warmup=0, keep_fields=True):
+def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=None, warmup=0, keep_fields=True):
     """Runs every zone for nsteps steps with both buffer sets (so the batched
-    two-step kernel applies) in waves: consecutive zones whose memory fits
-    budget_bytes form one batch, which is created, run and released before
-    the next.  Zones are independent, so this equals one batch of all of
-    them.  Returns the exit-plane DFTs (complex64 host arrays, in the order of
-    workloads) and the summed stepping time in ms (events around each wave's
-    timed run, after `warmup` untimed steps)."""
-    waves, cur, used = [], [], 0
-    for w in workloads:
+    two-step kernel applies) in waves: consecutive zones of one kernel family
+    whose memory fits budget_bytes form one batch, which is created, run and
+    released before the next (narrow wedges and the continuous zone run on the
+    flat in-place kernels, the others on the two-step kernel, unless
+    tile_rows fixes one launch for all).  Zones are independent, so this
+    equals one batch of all of them.  Returns the exit-plane DFTs (complex64
+    host arrays, in the order of workloads), the summed stepping time in ms
+    (events around each wave's timed run, after `warmup` untimed steps) and
+    the number of waves."""
+    order = sorted(range(len(workloads)), key=lambda q: is_narrow(workloads[q]) if tile_rows is None else 0)
+    waves, cur, used, fam = [], [], 0, None
+    for q in order:
+        w = workloads[q]
+        f = tile_rows if tile_rows is not None else (FLAT if is_narrow(w) else TWO_STEP)
         b = zone_device_bytes(w)
-        if cur and used + b > budget_bytes:
-            waves.append(cur)
+        if cur and (used + b > budget_bytes or f != fam):
+            waves.append((fam, cur))
             cur, used = [], 0
-        cur.append(w)
+        cur.append(q)
         used += b
+        fam = f
     if cur:
-        waves.append(cur)
-    planes, total_ms = [], 0.0
+        waves.append((fam, cur))
+    planes, total_ms = [None] * len(workloads), 0.0
     st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for wave in waves:
+    for fam, idx in waves:
+        wave = [workloads[q] for q in idx]
         zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps()) for w in wave]
         batch = zda.Batch(zones)
-        batch.set_launch(tile_rows)
+        batch.set_launch(fam)
         srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wave]
         if warmup:
             batch.run(srcs, warmup, wave[0].omegas)
@@ -96,11 +127,12 @@ def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=13, warmup=0, keep_f
         torch.cuda.synchronize()
         total_ms += st.elapsed_time(en)
         if keep_fields:
-            planes.extend(np.asarray(z.dft(zda.MON_PLANE).cpu()) for z in zones)
+            for q, z in zip(idx, zones):
+                planes[q] = np.asarray(z.dft(zda.MON_PLANE).cpu())
         batch.close()
         for z in zones:
             z.close()
         del zones, batch
         torch.cuda.empty_cache()
-    return planes, total_ms, len(waves)
+    return (planes if keep_fields else []), total_ms, len(waves)
 

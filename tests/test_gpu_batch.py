@@ -178,3 +178,28 @@ def test_lens_in_waves_equals_one_batch(zda):
     assert nwaves >= 2 and ms > 0
     for a, r in zip(planes, ref):
         assert np.array_equal(a, r)
+
+
+def test_waves_group_zones_by_kernel_family(zda):
+    """A lens with the continuous axis zone (flat in-place kernels) and wedges
+    (two-step kernel) in waves: each zone's exit-plane DFT is bitwise that of
+    the zone run alone with its default launch."""
+    from paper_2501_07979_amd import lens
+    from paper_2501_07979_amd.workloads import Workload
+    om = (0.28, 0.33, 0.39)
+    common = dict(nz=40, k_src=8, k_mon=30, design=(12, 16), k_sub=12, steps=150, omegas=om, omega_c=0.33,
+                  width=6.0, density="smoothed")
+    wls = [Workload("ring2", r_in=40.5, nr=30, nphi=64, n_fold=4, pml=(5, 5, 5, 5), seed=85, **common),
+           Workload("axis", r_in=0.5, nr=40, nphi=1, n_fold=0, pml=(0, 5, 5, 5), axis=1, seed=84, **common),
+           Workload("ring3", r_in=70.5, nr=30, nphi=64, n_fold=8, pml=(5, 5, 5, 5), seed=86, **common)]
+    ref = []
+    for w in wls:
+        z = zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps())
+        z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width)
+        ref.append(z.dft(zda.MON_PLANE).cpu().numpy())
+        z.close()
+    _say("waves by family")
+    planes, ms, nwaves = lens.run_in_waves(wls, wls[0].steps, 1 << 40)
+    assert nwaves == 2
+    for a, r in zip(planes, ref):
+        assert np.array_equal(a, r)
