@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "lwir"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-design-iter", action="store_true",
                     help="skip the gradient-zone design iteration reported beside the headline")
@@ -236,6 +236,26 @@ def main():
     from paper_2501_07979_amd.workloads import WORKLOADS
 
     torch.cuda.set_device(0)
+    if args.workload == "lwir":
+        # a lens shaped like the paper's LWIR design: 16 zones, narrow wedges
+        from paper_2501_07979_amd import lens
+        from paper_2501_07979_amd.workloads import lwir_lens
+        wls = lwir_lens()
+        cells = sum(w.cells for w in wls)
+        free, _ = torch.cuda.mem_get_info()
+        print("bench: LWIR-shaped lens, %d zones, %d cells" % (len(wls), cells), file=sys.stderr, flush=True)
+        _, ms, nwaves = lens.run_in_waves(wls, args.steps, int(0.8 * free), warmup=args.warmup, keep_fields=False)
+        gc = cells * args.steps / (ms / 1e3) / 1e9
+        t_run = wls[0].steps * cells / (gc * 1e9)
+        print(json.dumps({"metric": METRIC, "value": round(gc, 4), "unit": "Gcell-updates/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                          "data": "synthetic",
+                          "config": {"workload": "lwir_shaped_lens_16_zones", "cells": cells, "frequencies": 1,
+                                     "zones": [w.name for w in wls], "waves": nwaves,
+                                     "s_per_design_iteration_at_%d_steps" % wls[0].steps: round(2 * t_run, 2)}}),
+              flush=True)
+        return
     if args.workload == "c4":
         cells, ms, tune = batch_lens(args.steps, args.warmup)
         gc = cells * args.steps / (ms / 1e3) / 1e9

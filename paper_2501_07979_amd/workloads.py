@@ -157,4 +157,29 @@ def c4(nzones=48):
     return [c4_zone(l) for l in range(1, nzones + 1)]
 
 
+def lwir_lens(nz=180, steps=10000):
+    """A lens shaped like the paper's 0.8 cm LWIR design (section "Centimeter-
+    scale metalens at long-wave infrared"), at dr = dz = lambda / 50: 16 zones
+    of 25 lambda (1250 cells) radially; zone 1 continuous and containing the
+    axis, zone l >= 2 an n = 720 l wedge with r dphi <= 0.021 lambda at its
+    outer edge (11 phi cells); silicon (n = 3.42) substrate and a 0.6 lambda
+    design layer, air above; 12-cell PML on every face (outer only next to
+    the axis).  The height (180 cells) and the step count are this
+    workload's choices: the paper gives neither."""
+    lam = 50.0
+    om = (2 * np.pi / lam,)
+    eps_si = 3.42 ** 2
+    common = dict(nz=nz, m=1, courant=0.35, k_src=30, k_mon=nz - 20, design=(60, 90), k_sub=60, steps=steps,
+                  omegas=om, omega_c=om[0], width=4 * lam, eps_hi=eps_si, eps_sub=eps_si, density="smoothed")
+    zones = [Workload("lwir_zone01_continuous_1250x1x%d" % nz, r_in=0.5, nr=1250, nphi=1, n_fold=0,
+                      pml=(0, 12, 12, 12), axis=1, seed=7001, **common)]
+    for l in range(2, 17):
+        n = 720 * l
+        r_in = 1250.0 * (l - 1) + 0.5
+        nphi = int(np.ceil((r_in + 1250.0) * 2 * np.pi / n / (0.021 * lam)))
+        zones.append(Workload("lwir_zone%02d_1250x%dx%d" % (l, nphi, nz), r_in=r_in, nr=1250, nphi=nphi, n_fold=n,
+                              pml=(12, 12, 12, 12), seed=7000 + l, **common))
+    return zones
+
+
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c3_small": c3_small}
