@@ -100,6 +100,10 @@ constexpr int FUSED_COLS = 56;
 // tile_rows code of the in-place kernels with the flat (r, phi) mapping, its
 // block size, and the widest zone (phi cells) that takes it by default
 constexpr int FLAT_ROWS = 32;
+// tile_rows code of the fused one-step kernel with the flat mapping (whole
+// rows per block: needs nphi <= FLAT_FUSED_MAX_PHI)
+constexpr int FLAT_FUSED_ROWS = 33;
+constexpr int FLAT_FUSED_MAX_PHI = 64;
 constexpr int FLAT_BLOCK_HOST = 256;
 constexpr int NARROW_PHI = 16;
 void launch_fill(float2 *p, size_t n, hipStream_t s);

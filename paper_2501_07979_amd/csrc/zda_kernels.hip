@@ -587,6 +587,136 @@ __device__ __forceinline__ void eh_fused_body(const StepArgs &a, int n, unsigned
     }
 }
 
+// One whole leap-frog step with the flat (r, phi) mapping, for narrow wedges:
+// a block of FLAT_BLOCK threads holds R = FLAT_BLOCK / nphi - 1 whole rows
+// i0 .. i0 + R - 1 plus the halo row i0 - 1 below them, thread t on row
+// i0 - 1 + t / nphi, column t % nphi.  Every thread computes H^{n+1/2} of its
+// cell from E^n (global loads; the +phi neighbour of the last column is
+// column 0 times the seam factor); H goes through LDS to the E half-step of
+// the owned rows, whose -phi neighbour of column 0 is the row's last column
+// times the inverse seam factor and whose -r neighbour is one row (nphi
+// threads) back.  Reads set A, writes set B; one barrier per plane.
+__device__ __forceinline__ void eh_flat_body(const StepArgs &a, int n, unsigned brow, unsigned bz)
+{
+    __shared__ float2 sHz[2][FLAT_BLOCK], sHr[2][FLAT_BLOCK], sHp[2][FLAT_BLOCK], sV[2][FLAT_BLOCK];
+    const int t = threadIdx.x;
+    const int nphi = a.nphi, nr = a.nr, nz = a.nz;
+    const int R = FLAT_BLOCK / nphi - 1;                // owned rows per block
+    const size_t plane = (size_t)nr * nphi;
+    const int ri = t / nphi, j = t - ri * nphi;         // ri = 0: the halo row
+    const int i = (int)brow * R - 1 + ri;
+    const bool in_block = ri <= R;
+    const bool row_ok = in_block && i >= 0 && i < nr;
+    const bool owner = row_ok && ri >= 1;
+    const int kb = (int)bz * a.kchunk;
+    const int ke = min(kb + a.kchunk, nz);
+    const int kstart = kb > 0 ? kb - 1 : kb;
+    const bool nt = a.nt_stores;
+    const int ir = row_ok ? slab_row(i, nr, a.pr0, a.pr1) : -1;
+    const int ir1 = (row_ok && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
+    const RowCoef rc = a.rows[row_ok ? i : 0];
+    const int ic = min(max(i, 0), nr - 1);
+    const bool wrap = j + 1 >= nphi;
+    const unsigned o = (unsigned)j * 8u;
+    const unsigned ojp = wrap ? 0u : o + 8u;
+    const unsigned oc = (unsigned)j * 4u;
+    const size_t rowc = (size_t)ic * nphi;
+    const bool ip_ok = ic + 1 < nr;
+    const size_t dip = ip_ok ? (size_t)nphi : 0;
+    const size_t slabR = (size_t)nz * a.dR * nphi;
+    const size_t slabZ = (size_t)a.dZ * plane;
+    const int nd = a.k1 - a.k0;
+    // LDS slots of the -phi neighbour (the row's last column across the seam)
+    // and of the -r neighbour
+    const int t_jm = j > 0 ? t - 1 : t + nphi - 1;
+    const int t_im = t >= nphi ? t - nphi : t;
+
+    float2 er = ldo(a.Er + (size_t)kstart * plane + rowc, o);
+    float2 ep = ldo(a.Ep + (size_t)kstart * plane + rowc, o);
+    float2 hr_km = zero2(), hp_km = zero2();
+    for (int k = kstart; k < ke; ++k) {
+        const size_t c0 = (size_t)k * plane + rowc;
+        const bool kp_ok = k + 1 < nz;
+        const size_t dkp = kp_ok ? plane : 0;
+        const bool store = owner && k >= kb;
+        const int kz = slab_row(k, nz, a.pz0, a.pz1);
+        ZCoef zc = {};
+        if (kz >= 0) zc = a.zrows[k];
+        const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
+        const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
+        const AuxRows x = {a.auxR + sr0, a.auxZ + sz0, a.oauxR + sr0, a.oauxZ + sz0};
+        const float2 ez = ldo(a.Ez + c0, o);
+        float2 er_kp = ldo(a.Er + c0 + dkp, o), ep_kp = ldo(a.Ep + c0 + dkp, o);
+        float2 ez_jp = ldo(a.Ez + c0, ojp), er_jp = ldo(a.Er + c0, ojp);
+        float2 ez_ip = ldo(a.Ez + c0 + dip, o), ep_ip = ldo(a.Ep + c0 + dip, o);
+        float2 hr = ldo(a.Hr + c0, o), hp = ldo(a.Hp + c0, o), hz = ldo(a.Hz + c0, o);
+        float2 v = zero2();
+        if (!kp_ok) { er_kp = zero2(); ep_kp = zero2(); }
+        if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+        if (wrap) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+        {
+            float2 u0 = zero2(), u1 = zero2();
+            if (ir >= 0 && k > 0) {
+                u0 = ldo(x.sR + AUX_U_EP * slabR, o);
+                if (ir1 >= 0) u1 = ldo(a.auxR + AUX_U_EP * slabR + ((size_t)k * a.dR + ir1) * nphi, o);
+            }
+            h_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x, o, store, ez, er, ep, ez_jp, er_jp, er_kp, ep_kp, ez_ip,
+                   ep_ip, u0, u1, hr, hp, hz, v);
+            if (store) {
+                store_out(pto(a.oHr + c0, o), hr, nt);
+                store_out(pto(a.oHp + c0, o), hp, nt);
+                store_out(pto(a.oHz + c0, o), hz, nt);
+            }
+        }
+        if (!row_ok) { hr = zero2(); hp = zero2(); hz = zero2(); v = zero2(); }
+        const int buf = k & 1;
+        sHz[buf][t] = hz;
+        sHr[buf][t] = hr;
+        sHp[buf][t] = hp;
+        sV[buf][t] = v;
+        __syncthreads();
+        if (store) {
+            float2 hz_jm = sHz[buf][t_jm], hr_jm = sHr[buf][t_jm];
+            if (j == 0) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+            const float2 hz_im = sHz[buf][t_im], hp_im = sHp[buf][t_im];
+            const float2 v_im = sV[buf][t_im];
+            const float ce = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a.ceps + c0) + oc);
+            float2 jr = zero2(), jph = zero2();
+            if (k == a.k_src) sheet_current(a, n, plane, rowc, o, jr, jph);
+            float2 er_n = er, ep_n = ep, ez_n = ez, u;
+            e_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x, o, ce, jr, jph, hr, hr_jm, hr_km, hp, hp_im, hp_km, hz,
+                   hz_jm, hz_im, v, v_im, er_n, ep_n, ez_n, u);
+            store_out(pto(a.oEr + c0, o), er_n, nt);
+            store_out(pto(a.oEp + c0, o), ep_n, nt);
+            store_out(pto(a.oEz + c0, o), ez_n, nt);
+            if (a.dft_plane && k == a.k_mon) {
+                for (int f = 0; f < a.K; ++f) {
+                    const float2 tw = a.twiddle[(size_t)n * a.K + f];
+                    float2 *q0 = pto(a.dft_plane + (size_t)f * 2 * plane + rowc, o);
+                    float2 *q1 = pto(a.dft_plane + (size_t)f * 2 * plane + plane + rowc, o);
+                    *q0 = c_fma(*q0, tw, er_n);
+                    *q1 = c_fma(*q1, tw, ep_n);
+                }
+            }
+            if (a.dft_vol && k >= a.k0 && k < a.k1) {
+                const size_t vs = (size_t)nd * plane;
+                for (int f = 0; f < a.K; ++f) {
+                    const float2 tw = a.twiddle[(size_t)n * a.K + f];
+                    float2 *base = a.dft_vol + (size_t)f * 3 * vs + (size_t)(k - a.k0) * plane + rowc;
+                    float2 *q0 = pto(base, o), *q1 = pto(base + vs, o), *q2 = pto(base + 2 * vs, o);
+                    *q0 = c_fma(*q0, tw, er_n);
+                    *q1 = c_fma(*q1, tw, ep_n);
+                    *q2 = c_fma(*q2, tw, ez_n);
+                }
+            }
+        }
+        hr_km = hr;
+        hp_km = hp;
+        er = er_kp;
+        ep = ep_kp;
+    }
+}
+
 // Field values one cell's step-one H half-step reads at plane k (plus dt/eps
 // at k), loaded unconditionally from in-range addresses: the +z neighbour is
 // plane k + 1 (plane k itself at the top), the +r neighbour row ic + dip.
@@ -880,6 +1010,11 @@ __global__ __launch_bounds__(FLAT_BLOCK) void e_step_flat(StepArgs a, int n)
     e_step_body<1, true>(a, n, blockIdx.x, 0, blockIdx.z);
 }
 
+__global__ __launch_bounds__(FLAT_BLOCK) void eh_flat_kernel(StepArgs a, int n)
+{
+    eh_flat_body(a, n, blockIdx.x, blockIdx.y);
+}
+
 template <int TR>
 __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int n)
 {
@@ -991,6 +1126,17 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_batch(BatchArgs b, int
     const unsigned gx = (a.nphi + FUSED_COLS - 1) / FUSED_COLS, gy = (a.nr + TR - 1) / TR;
     const int n = n_rel + (b.n_base ? *b.n_base : 0);
     eh_fused_body<TR>(a, n, g - b.prefix[zi], gx, gy);
+}
+
+__global__ __launch_bounds__(FLAT_BLOCK) void eh_flat_batch(BatchArgs b, int n_rel)
+{
+    const int zi = batch_zone(b.prefix, b.nzones, blockIdx.x);
+    const StepArgs a = zone_args(b.tab, zi);
+    const unsigned local = blockIdx.x - b.prefix[zi];
+    const unsigned R = FLAT_BLOCK / a.nphi - 1;
+    const unsigned gq = ((unsigned)a.nr + R - 1) / R;
+    const int n = n_rel + (b.n_base ? *b.n_base : 0);
+    eh_flat_body(a, n, local % gq, local / gq);
 }
 
 template <int TR, int LAY>
@@ -1131,6 +1277,12 @@ void launch_fused_tr(const StepArgs &a, int n, hipStream_t s)
 
 void launch_fused_step(const StepArgs &a, int n, hipStream_t s)
 {
+    if (a.tile_rows == FLAT_FUSED_ROWS) {
+        const unsigned R = FLAT_BLOCK / a.nphi - 1;
+        dim3 grid(((unsigned)a.nr + R - 1) / R, (a.nz + a.kchunk - 1) / a.kchunk, 1);
+        hipLaunchKernelGGL(eh_flat_kernel, grid, dim3(FLAT_BLOCK), 0, s, a, n);
+        return;
+    }
     switch (a.tile_rows) {
     case 3: launch_fused_tr<3>(a, n, s); break;
     case 15: launch_fused_tr<15>(a, n, s); break;
@@ -1181,6 +1333,10 @@ unsigned tiles_split(const StepArgs &a, int BY)
 
 unsigned tiles_fused(const StepArgs &a, int TR)
 {
+    if (TR == FLAT_FUSED_ROWS) {
+        const unsigned R = FLAT_BLOCK / a.nphi - 1;
+        return (((unsigned)a.nr + R - 1) / R) * (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
+    }
     return (unsigned)((a.nphi + FUSED_COLS - 1) / FUSED_COLS) * (unsigned)((a.nr + TR - 1) / TR) *
            (unsigned)((a.nz + a.kchunk - 1) / a.kchunk);
 }
@@ -1202,6 +1358,9 @@ void launch_batch_step(const BatchArgs &b, unsigned nblocks, int tile_rows, bool
 {
     if (fused) {
         switch (tile_rows) {
+        case FLAT_FUSED_ROWS:
+            hipLaunchKernelGGL(eh_flat_batch, dim3(nblocks), dim3(FLAT_BLOCK), 0, s, b, n_rel);
+            break;
         case 3: launch_batch_fused<3>(b, nblocks, n_rel, s); break;
         case 15: launch_batch_fused<15>(b, nblocks, n_rel, s); break;
         default: launch_batch_fused<7>(b, nblocks, n_rel, s); break;

@@ -1247,15 +1247,17 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
     if (kchunk < 1 || kchunk > z->d.nz) return fail(ZDA_ERR_ARG, "kchunk must be in [1, nz]");
     const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
                        tile_rows == FLAT_ROWS;
-    const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15;
+    const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15 || tile_rows == FLAT_FUSED_ROWS;
     const bool two = tile_rows == 5 || tile_rows == 13;
     if (!split && !fused && !two)
         return fail(ZDA_ERR_ARG,
-                    "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15 (fused) or 5, 13 (two-step)");
+                    "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused) or 5, 13 (two-step)");
     if ((fused || two) && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set");
     if ((fused || two) && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set");
     if (two && !z->has_m) return fail(ZDA_ERR_STATE, "no intermediate auxiliaries for the two-step kernel");
     if (two && (z->d.nr > 65535 || z->d.nz > 65535)) return fail(ZDA_ERR_ARG, "two-step tiles need nr, nz <= 65535");
+    if (tile_rows == FLAT_FUSED_ROWS && z->d.nphi > FLAT_FUSED_MAX_PHI)
+        return fail(ZDA_ERR_ARG, "the flat fused step needs nphi <= %d", FLAT_FUSED_MAX_PHI);
     z->kchunk = kchunk;
     z->tile_rows = tile_rows;
     z->fused = fused;
@@ -1581,14 +1583,18 @@ zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk)
     if (!b) return fail(ZDA_ERR_ARG, "NULL batch");
     const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
                        tile_rows == FLAT_ROWS;
-    const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15;
+    const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15 || tile_rows == FLAT_FUSED_ROWS;
     const bool two = tile_rows == 5 || tile_rows == 13;
     if (!split && !fused && !two)
         return fail(ZDA_ERR_ARG,
-                    "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15 (fused) or 5, 13 (two-step)");
+                    "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused) or 5, 13 (two-step)");
     if (fused)
         for (auto z : b->zones)
             if (!zone_has_second_set(z)) return fail(ZDA_ERR_STATE, "a zone has no second buffer set");
+    if (tile_rows == FLAT_FUSED_ROWS)
+        for (auto z : b->zones)
+            if (z->d.nphi > FLAT_FUSED_MAX_PHI)
+                return fail(ZDA_ERR_ARG, "the flat fused step needs nphi <= %d", FLAT_FUSED_MAX_PHI);
     if (two)
         for (auto z : b->zones)
             if (!zone_two_step_ok(z)) return fail(ZDA_ERR_STATE, "a zone cannot run the two-step kernel");

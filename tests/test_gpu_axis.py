@@ -12,7 +12,8 @@ from test_gpu_parity import SHAPES, _objective, _rel
 pytestmark = pytest.mark.gpu
 
 COMPS = ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz")
-FAMILIES = ["default", "fused_tr3_kc7", "split_r4_kc7", "split_r1", "two_tr13_kc9", "two_tr5_kc3", "flat_kc5"]
+FAMILIES = ["default", "fused_tr3_kc7", "split_r4_kc7", "split_r1", "two_tr13_kc9", "two_tr5_kc3", "flat_kc5",
+            "flatfused_kc5"]
 
 
 def _say(*a):
@@ -30,6 +31,8 @@ def zda():
 
 
 def _zones(zda, oracle_mod, wl, eps, shape):
+    if shape is not None and shape[1] == 33 and wl.nphi > 64:
+        pytest.skip("the flat fused step takes zones of at most 64 phi cells")
     g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
     if shape is not None:
         kc, tr = shape
@@ -94,8 +97,9 @@ def test_first_band_zones_source_driven(zda, oracle_mod, case, shape):
     g.close()
 
 
-@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr5_kc3", "flat_kc5"])
-@pytest.mark.parametrize("case", ["axis_continuous", "axis_wedge"])
+@pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr5_kc3", "flat_kc5",
+                                   "flatfused_kc5"])
+@pytest.mark.parametrize("case", ["axis_continuous", "axis_wedge", "narrow_wedge"])
 def test_axis_zone_random_state(zda, oracle_mod, case, shape):
     """Arbitrary fields on every cell that the axis zone updates (row 0
     included; only the bottom-plane wall is held), 41 steps without reset."""
@@ -121,7 +125,7 @@ def test_axis_zone_random_state(zda, oracle_mod, case, shape):
     g.close()
 
 
-@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc3", "flat_kc5"])
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc3", "flat_kc5", "flatfused_kc5"])
 def test_axis_zone_gradient_parity(zda, oracle_mod, shape):
     """Adjoint gradient over the design layer of a continuous zone containing
     the axis (the adjoint runs with -m: seams 1 -+ i m) against the oracle."""

@@ -119,7 +119,7 @@ def test_batch_autotune_keeps_results(zda):
     b.close()
 
 
-@pytest.mark.parametrize("mode", ["fused", "two", "two_odd"])
+@pytest.mark.parametrize("mode", ["fused", "two", "two_odd", "flatfused"])
 def test_batch_with_the_axis_zone(zda, oracle_mod, mode):
     """The first zones of a lens in one batch: the continuous zone that
     contains the axis (nphi = 1) next to two wedges; each equals its own run
@@ -136,12 +136,14 @@ def test_batch_with_the_axis_zone(zda, oracle_mod, mode):
     singles = []
     for w, e in zip(wls, eps):
         z = zda.Zone(zda.default_desc(**w.desc_kwargs()), e)
+        if mode == "flatfused":
+            z.set_launch(z.info().kchunk, 33)
         z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width)
         singles.append(z.dft(zda.MON_PLANE).cpu().numpy())
         z.close()
     zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
     b = zda.Batch(zones)
-    b.set_launch({"fused": 7, "two": 13, "two_odd": 5}[mode])
+    b.set_launch({"fused": 7, "two": 13, "two_odd": 5, "flatfused": 33}[mode])
     srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
     _say("batch with the axis zone", mode)
     b.run(srcs, steps, om)
@@ -181,9 +183,9 @@ def test_lens_in_waves_equals_one_batch(zda):
 
 
 def test_waves_group_zones_by_kernel_family(zda):
-    """A lens with the continuous axis zone (flat in-place kernels) and wedges
-    (two-step kernel) in waves: each zone's exit-plane DFT is bitwise that of
-    the zone run alone with its default launch."""
+    """A lens with the continuous axis zone (flat-mapped fused step) and
+    wedges (two-step kernel) in waves: each zone's exit-plane DFT is bitwise
+    that of the zone run alone with the same kernel family."""
     from paper_2501_07979_amd import lens
     from paper_2501_07979_amd.workloads import Workload
     om = (0.28, 0.33, 0.39)
@@ -195,6 +197,8 @@ def test_waves_group_zones_by_kernel_family(zda):
     ref = []
     for w in wls:
         z = zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps())
+        if lens.is_narrow(w):
+            z.set_launch(z.info().kchunk, lens.FLAT)
         z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width)
         ref.append(z.dft(zda.MON_PLANE).cpu().numpy())
         z.close()

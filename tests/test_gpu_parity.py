@@ -28,13 +28,16 @@ def _rel(a, b):
 # launch shapes: (kchunk, tile_rows); tile_rows 3/7/15 select the fused
 # double-buffered step, 5/13 the two-step kernel, 1/2/4/8/16 the split
 # in-place H and E kernels, 32 the in-place kernels with the flat (r, phi)
-# mapping; None keeps the zone's default
+# mapping, 33 the fused step with the flat mapping (nphi <= 64); None keeps
+# the zone's default
 SHAPES = {"default": None, "fused_tr3_kc7": (7, 3), "fused_tr15_kc13": (13, 15), "split_r4_kc7": (7, 4),
           "split_r1": (0, 1), "two_tr13_kc9": (9, 13), "two_tr5_kc6": (6, 5), "two_tr5_kc3": (3, 5),
-          "flat_kc5": (5, 32)}
+          "flat_kc5": (5, 32), "flatfused_kc5": (5, 33)}
 
 
 def _zone_pair(zda, oracle_mod, wl, eps, shape=None):
+    if shape is not None and shape[1] == 33 and wl.nphi > 64:
+        pytest.skip("the flat fused step takes zones of at most 64 phi cells")
     g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
     if shape is not None:
         kc, tr = shape
@@ -89,7 +92,7 @@ def test_ragged_shapes_all_fields(zda, oracle_mod, case, shape):
 
 
 @pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr13_kc9", "two_tr5_kc3",
-                                   "flat_kc5"])
+                                   "flat_kc5", "flatfused_kc5"])
 def test_random_state_steps_with_pml(zda, oracle_mod, shape):
     """Arbitrary initial fields (written through the ABI) stepped without
     reset: every update term, PML auxiliary and the seam act from step 1
