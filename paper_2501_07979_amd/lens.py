@@ -88,17 +88,11 @@ def zone_device_bytes(w, both_sets=True, max_freq=8):
     return cells * (48 * (2 if both_sets else 1) + 4) + aux + max_freq * 2 * plane * 8
 
 
-def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=None, warmup=0, keep_fields=True):
-    """Runs every zone for nsteps steps with both buffer sets (so the batched
-    two-step kernel applies) in waves: consecutive zones of one kernel family
-    whose memory fits budget_bytes form one batch, which is created, run and
-    released before the next (narrow wedges and the continuous zone run on the
-    flat-mapped fused step, the others on the two-step kernel, unless
-    tile_rows fixes one launch for all).  Zones are independent, so this
-    equals one batch of all of them.  Returns the exit-plane DFTs (complex64
-    host arrays, in the order of workloads), the summed stepping time in ms
-    (events around each wave's timed run, after `warmup` untimed steps) and
-    the number of waves."""
+def plan_waves(workloads, budget_bytes, tile_rows=None):
+    """Waves of zone indices [(launch code, [indices])]: zones of one kernel
+    family (or all, if tile_rows fixes the launch), in their order, cut where
+    the next zone would take the wave past budget_bytes with both buffer sets;
+    narrow zones after the others."""
     order = sorted(range(len(workloads)), key=lambda q: is_narrow(workloads[q]) if tile_rows is None else 0)
     waves, cur, used, fam = [], [], 0, None
     for q in order:
@@ -113,6 +107,21 @@ def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=None, warmup=0, keep
         fam = f
     if cur:
         waves.append((fam, cur))
+    return waves
+
+
+def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=None, warmup=0, keep_fields=True):
+    """Runs every zone for nsteps steps with both buffer sets (so the batched
+    two-step kernel applies) in waves: consecutive zones of one kernel family
+    whose memory fits budget_bytes form one batch, which is created, run and
+    released before the next (narrow wedges and the continuous zone run on the
+    flat-mapped fused step, the others on the two-step kernel, unless
+    tile_rows fixes one launch for all).  Zones are independent, so this
+    equals one batch of all of them.  Returns the exit-plane DFTs (complex64
+    host arrays, in the order of workloads), the summed stepping time in ms
+    (events around each wave's timed run, after `warmup` untimed steps) and
+    the number of waves."""
+    waves = plan_waves(workloads, budget_bytes, tile_rows)
     planes, total_ms = [None] * len(workloads), 0.0
     st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for fam, idx in waves:
