@@ -215,7 +215,12 @@ typedef struct {
  * tile_rows in {1, 2, 4, 8, 16} the in-place H and E kernels (a block covers
  * tile_rows rows x 64 phi cells), tile_rows = 32 the in-place kernels with a
  * flat mapping (a block covers 256 consecutive cells of the (r, phi) plane,
- * so narrow wedges keep every lane busy).  Default: for zones of at most 16
+ * so narrow wedges keep every lane busy), tile_rows = 33 the fused step with
+ * a flat mapping (a block holds 256 / nphi whole rows and owns all but one;
+ * nphi <= 64), tile_rows = 34 the two-step kernel with a flat mapping (a
+ * block holds 256 / nphi whole rows and owns all but three, the radial halo;
+ * nphi <= 32; an odd last step of a run takes the flat fused step; needs what
+ * the two-step kernel needs).  Default: for zones of at most 16
  * phi cells (and the continuous zone) the flat in-place kernels; otherwise
  * the two-step kernel with 13 rows
  * and the chunk depth (3 to 72 planes) whose launch is predicted to finish
@@ -223,7 +228,8 @@ typedef struct {
  * 12-plane chunks, fewer for small zones) where the intermediate set does not
  * fit; the in-place kernels (4 rows) for single-buffer zones.
  * Results do not depend on the shape (beyond rounding).  ZDA_ERR_ARG for kchunk outside
- * [1, nz] or any other tile_rows; ZDA_ERR_STATE for a fused shape on a zone
+ * [1, nz], any other tile_rows, or a flat fused (two-step) shape on a zone
+ * wider than 64 (32) phi cells; ZDA_ERR_STATE for a fused shape on a zone
  * without the second buffer set. */
 zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 
@@ -278,8 +284,9 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
 
 /* The two-step kernel's launch plan for a zone described by d, computed on
  * the host (no device is touched; a zone created from d with the same
- * tile_rows, kchunk and tile order runs exactly these tiles).  tile_rows: 5
- * or 13; kchunk >= 1 planes per chunk; k_src: the source plane (only the
+ * tile_rows, kchunk and tile order runs exactly these tiles).  tile_rows: 5,
+ * 13 or 34 (flat mapping: tiles own 256 / nphi - 3 rows and every phi cell,
+ * nphi <= 32); kchunk >= 1 planes per chunk; k_src: the source plane (only the
  * cell counts depend on it); order: 0 natural, 1 contiguous range per XCD
  * (ZDA_OPT_XCD_REMAP), else a patch code (ZDA_OPT_TILE_PATCH).  out (may be
  * NULL to query the count): 4 uint32 per tile, {phi block, first owned row |
@@ -288,8 +295,9 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
  * hold no layer cell; they own 56 phi cells) and 3 for the layer tiles (61
  * phi cells), interior tiles first; cap: capacity of out in tiles.
  * *ntiles and *n_interior receive the counts.  Errors: ZDA_ERR_ARG (sizes
- * < 1, nr or nz > 65535, a layer wider than half the extent, tile_rows not 5
- * or 13, kchunk < 1, a patch field of 0, out too small). */
+ * < 1, nr or nz > 65535, a layer wider than half the extent, tile_rows not 5,
+ * 13 or 34, 34 with nphi > 32, kchunk < 1, a patch field of 0, out too
+ * small). */
 zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kchunk, int k_src, int order,
                                    uint32_t *out, size_t cap, size_t *ntiles, size_t *n_interior);
 

@@ -52,7 +52,8 @@ struct StepArgs {
     int k0, k1;
     float2 *dft_vol;               // [K][3][k1-k0][nr][nphi] or null
     int kchunk;                    // planes per z-chunk
-    int tile_rows;                 // radial rows per block (1, 2, 4, 8, 16 split; 3, 7, 15 fused; 5, 13 two-step)
+    int tile_rows;                 // radial rows per block (1, 2, 4, 8, 16 split; 3, 7, 15 fused; 5, 13 two-step),
+                                   // or a flat-mapping code (32, 33, 34)
     // fused step: fields and auxiliaries read from the set above, written here
     float2 *oEr, *oEp, *oEz, *oHr, *oHp, *oHz;
     float2 *oauxR, *oauxZ;
@@ -105,6 +106,12 @@ constexpr int FLAT_ROWS = 32;
 constexpr int FLAT_FUSED_ROWS = 33;
 constexpr int FLAT_FUSED_MAX_PHI = 64;
 constexpr int FLAT_BLOCK_HOST = 256;
+// tile_rows code of the two-step kernel with the flat mapping: a block holds
+// FLAT_BLOCK_HOST / nphi whole rows, three of them the radial halo, so a tile
+// owns flat_two_rows(nphi) rows and every phi cell (nphi <= FLAT_TWO_MAX_PHI)
+constexpr int FLAT_TWO_ROWS = 34;
+constexpr int FLAT_TWO_MAX_PHI = 32;
+constexpr int flat_two_rows(int nphi) { return FLAT_BLOCK_HOST / nphi - 3; }
 constexpr int NARROW_PHI = 16;
 void launch_fill(float2 *p, size_t n, hipStream_t s);
 // tiles of one zone for the split (BY rows) or fused (TR owned rows) kernels

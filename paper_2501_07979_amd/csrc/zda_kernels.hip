@@ -978,6 +978,221 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
     }
 }
 
+// The two-step schedule above with the flat (r, phi) mapping, for narrow
+// zones (nphi <= FLAT_TWO_MAX_PHI): a block of FLAT_BLOCK threads holds
+// RB = FLAT_BLOCK / nphi whole rows, thread t on row slot s = t / nphi
+// (radial row i0 - 2 + s) and phi cell j = t mod nphi, so a block's loads and
+// stores cover consecutive cells.  Slots 0, 1 and nrow + 2 are the radial
+// halo (nrow <= RB - 3 owned rows); the +-phi neighbours are the adjacent
+// threads of the row, across the Bloch seam (with its factor) at j = 0 and
+// j = nphi - 1, so every column is exact and owned: no azimuthal halo.  The
+// tile's phi block (first word) is 0.
+template <int LAY>
+__device__ __forceinline__ void eh2_flat_body(const StepArgs &a, int n, uint4 tile)
+{
+    constexpr bool PR = (LAY & 1) != 0, PZ = (LAY & 2) != 0;
+    constexpr int NB = FLAT_BLOCK;
+    constexpr int NV = PR ? NB : 1;
+    __shared__ float2 s1z[NB], s1r[NB], s1p[NB], s1v[NV];
+    __shared__ float2 sEz[2][NB], sEr[2][NB], sEp[2][NB], sU[2][NV];
+    __shared__ float2 s2z[NB], s2r[NB], s2p[NB], s2v[NV];
+    const int t = threadIdx.x;
+    const int nphi = a.nphi, nr = a.nr, nz = a.nz;
+    const size_t plane = (size_t)nr * nphi;
+    const int i0 = (int)(tile.y & 0xffffu), nrow = (int)(tile.y >> 16);
+    const int kb = (int)(tile.z & 0xffffu), ke = (int)(tile.z >> 16);
+    const int sl = t / nphi, j = t - sl * nphi;
+    const int i = i0 + sl - 2;
+    const bool active = sl <= nrow + 2;                     // slots above the top halo row idle
+    const bool row_ok = active && i >= 0 && i < nr;
+    const bool cross_m = j == 0;                            // -phi neighbour is column nphi - 1
+    const bool cross_p = j == nphi - 1;                     // +phi neighbour is column 0
+    const bool own = sl >= 2 && sl <= nrow + 1 && row_ok;
+    // LDS slots of the neighbours; only active slots read them, and the
+    // clamps keep every index inside the arrays whatever the thread
+    const int t_jm = min(cross_m ? t + nphi - 1 : t - 1, NB - 1);
+    const int t_jp = cross_p ? t - (nphi - 1) : min(t + 1, NB - 1);
+    const int t_im = sl >= 1 ? t - nphi : t;
+    const int t_ip = min(t + nphi, NB - 1);
+    const int k_lo = max(kb - 2, 0);
+    const bool nt = a.nt_stores;
+    const int ir = (PR && row_ok) ? slab_row(i, nr, a.pr0, a.pr1) : -1;
+    const int ir1 = (PR && row_ok && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
+    const RowCoef rc = a.rows[row_ok ? i : 0];
+    const int ic = min(max(i, 0), nr - 1);
+    const unsigned o = (unsigned)j * 8u;
+    const unsigned ojp = cross_p ? 0u : o + 8u;
+    const unsigned oc = (unsigned)j * 4u;
+    const size_t rowc = (size_t)ic * nphi;
+    const bool ip_ok = ic + 1 < nr;
+    const size_t dip = ip_ok ? (size_t)nphi : 0;
+    const size_t slabR = (size_t)nz * a.dR * nphi;
+    const size_t slabZ = (size_t)a.dZ * plane;
+    const int nd = a.k1 - a.k0;
+
+    // carried along z as in the two-step kernel: E^n at k; H^{n+1/2},
+    // E^{n+1}, U^{n+1}, dt/eps at k - 1; H^{n+3/2} at k - 2
+    float2 er0 = ldo(a.Er + (size_t)k_lo * plane + rowc, o);
+    float2 ep0 = ldo(a.Ep + (size_t)k_lo * plane + rowc, o);
+    float2 h1r_p = zero2(), h1p_p = zero2(), h1z_p = zero2();
+    float2 e1r_p = zero2(), e1p_p = zero2(), e1z_p = zero2(), u1_p = zero2();
+    float2 h2r_km = zero2(), h2p_km = zero2();
+    float ce_p = 0.f;
+    constexpr bool PF = !PR;
+    PlaneIn cur = load_plane(a, k_lo, plane, rowc, dip, o, ojp, oc);
+    for (int k = k_lo; k <= ke; ++k) {
+        const int km = k - 1;
+        PlaneIn in;
+        if (!PF) {
+            in = load_plane(a, min(k, nz - 1), plane, rowc, dip, o, ojp, oc);
+        } else {
+            in = cur;
+            cur = load_plane(a, min(k + 1, min(ke, nz - 1)), plane, rowc, dip, o, ojp, oc);
+        }
+        float2 h1r = zero2(), h1p = zero2(), h1z = zero2(), v1 = zero2();
+        float2 e1r = zero2(), e1p = zero2(), e1z = zero2(), u1 = zero2();
+        float2 er_kp = zero2(), ep_kp = zero2();
+        float ce = 0.f;
+        const bool step1 = k < nz;
+        // ---- step one, H^{n+1/2} at plane k (every active slot)
+        int kz = -1;
+        ZCoef zc = {};
+        AuxRows x1 = {};
+        float2 ez0 = zero2();
+        if (step1 && active) {
+            kz = PZ ? slab_row(k, nz, a.pz0, a.pz1) : -1;
+            if (kz >= 0) zc = a.zrows[k];
+            const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
+            const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
+            x1 = {a.auxR + sr0, a.auxZ + sz0, a.mauxR + sr0, a.mauxZ + sz0};
+            const bool kp_ok = k + 1 < nz;
+            ez0 = in.ez;
+            er_kp = in.er_kp;
+            ep_kp = in.ep_kp;
+            float2 ez_jp = in.ez_jp, er_jp = in.er_jp;
+            float2 ez_ip = in.ez_ip, ep_ip = in.ep_ip;
+            h1r = in.hr;
+            h1p = in.hp;
+            h1z = in.hz;
+            ce = in.ce;
+            if (!kp_ok) { er_kp = zero2(); ep_kp = zero2(); }
+            if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+            if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+            float2 u0 = zero2(), uu1 = zero2();
+            if (ir >= 0 && k > 0) {
+                u0 = ldo(x1.sR + AUX_U_EP * slabR, o);
+                if (ir1 >= 0) uu1 = ldo(a.auxR + AUX_U_EP * slabR + ((size_t)k * a.dR + ir1) * nphi, o);
+            }
+            h_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x1, o, row_ok, ez0, er0, ep0, ez_jp, er_jp, er_kp, ep_kp,
+                   ez_ip, ep_ip, u0, uu1, h1r, h1p, h1z, v1);
+            s1z[t] = h1z;
+            s1r[t] = h1r;
+            s1p[t] = h1p;
+            if (PR) s1v[PR ? t : 0] = v1;
+        }
+        __syncthreads();
+        // ---- step one, E^{n+1} at plane k (exact on slots >= 1)
+        if (step1 && (k != k_lo || k == 0) && sl >= 1 && row_ok) {
+            float2 hz_jm = s1z[t_jm], hr_jm = s1r[t_jm];
+            if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+            const float2 hz_im = s1z[t_im], hp_im = s1p[t_im];
+            const float2 v_im = PR ? s1v[PR ? t_im : 0] : zero2();
+            float2 jr = zero2(), jph = zero2();
+            if (k == a.k_src) sheet_current(a, n, plane, rowc, o, jr, jph);
+            e1r = er0;
+            e1p = ep0;
+            e1z = ez0;
+            e_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x1, o, ce, jr, jph, h1r, hr_jm, h1r_p, h1p, hp_im, h1p_p,
+                   h1z, hz_jm, hz_im, v1, v_im, e1r, e1p, e1z, u1);
+            sEz[k & 1][t] = e1z;
+            sEr[k & 1][t] = e1r;
+            sEp[k & 1][t] = e1p;
+            if (PR) sU[k & 1][PR ? t : 0] = u1;
+        }
+        // ---- step two, H^{n+3/2} at plane km (exact on slots 1 .. nrow + 1)
+        float2 h2r = zero2(), h2p = zero2(), h2z = zero2(), v2 = zero2();
+        const bool h2_plane = km >= 0 && (km > k_lo || km == 0);
+        const int kz2 = (PZ && km >= 0) ? slab_row(km, nz, a.pz0, a.pz1) : -1;
+        ZCoef zc2 = {};
+        if (kz2 >= 0) zc2 = a.zrows[km];
+        const size_t c0m = (size_t)max(km, 0) * plane + rowc;
+        const size_t sr2 = ir >= 0 ? ((size_t)max(km, 0) * a.dR + ir) * nphi : 0;
+        const size_t sz2 = kz2 >= 0 ? ((size_t)kz2 * nr + ic) * nphi : 0;
+        const AuxRows x2 = {a.mauxR + sr2, a.mauxZ + sz2, a.oauxR + sr2, a.oauxZ + sz2};
+        const bool store = own && km >= kb && km < ke;
+        if (h2_plane && sl >= 1 && sl <= nrow + 1 && row_ok) {
+            const int b = km & 1;
+            float2 ez_jp = sEz[b][t_jp], er_jp = sEr[b][t_jp];
+            if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+            float2 ez_ip = sEz[b][t_ip], ep_ip = sEp[b][t_ip];
+            if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+            float2 uu1 = zero2();
+            if (PR && ir1 >= 0) uu1 = sU[b][PR ? t_ip : 0];
+            h2r = h1r_p;
+            h2p = h1p_p;
+            h2z = h1z_p;
+            // E^{n+1} at km + 1 is the plane step one just finished (zero above the top)
+            h_cell(a, rc, zc2, i, km, ir, kz2, slabR, slabZ, x2, o, store, e1z_p, e1r_p, e1p_p, ez_jp, er_jp, e1r,
+                   e1p, ez_ip, ep_ip, (ir >= 0 && km > 0) ? u1_p : zero2(), uu1, h2r, h2p, h2z, v2);
+        }
+        s2z[t] = h2z;
+        s2r[t] = h2r;
+        s2p[t] = h2p;
+        if (PR) s2v[PR ? t : 0] = v2;
+        __syncthreads();
+        // ---- step two, E^{n+2} at plane km (owners), stores and DFT
+        if (store) {
+            float2 hz_jm = s2z[t_jm], hr_jm = s2r[t_jm];
+            if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+            const float2 hz_im = s2z[t_im], hp_im = s2p[t_im];
+            const float2 v_im = PR ? s2v[PR ? t_im : 0] : zero2();
+            float2 jr = zero2(), jph = zero2();
+            if (km == a.k_src) sheet_current(a, n + 1, plane, rowc, o, jr, jph);
+            float2 er2 = e1r_p, ep2 = e1p_p, ez2 = e1z_p, u2;
+            e_cell(a, rc, zc2, i, km, ir, kz2, slabR, slabZ, x2, o, ce_p, jr, jph, h2r, hr_jm, h2r_km, h2p, hp_im,
+                   h2p_km, h2z, hz_jm, hz_im, v2, v_im, er2, ep2, ez2, u2);
+            store_out(pto(a.oHr + c0m, o), h2r, nt);
+            store_out(pto(a.oHp + c0m, o), h2p, nt);
+            store_out(pto(a.oHz + c0m, o), h2z, nt);
+            store_out(pto(a.oEr + c0m, o), er2, nt);
+            store_out(pto(a.oEp + c0m, o), ep2, nt);
+            store_out(pto(a.oEz + c0m, o), ez2, nt);
+            if (a.dft_plane && km == a.k_mon) {
+                for (int f = 0; f < a.K; ++f) {
+                    const float2 tw0 = a.twiddle[(size_t)n * a.K + f], tw1 = a.twiddle[(size_t)(n + 1) * a.K + f];
+                    float2 *q0 = pto(a.dft_plane + (size_t)f * 2 * plane + rowc, o);
+                    float2 *q1 = pto(a.dft_plane + (size_t)f * 2 * plane + plane + rowc, o);
+                    *q0 = c_fma(c_fma(*q0, tw0, e1r_p), tw1, er2);
+                    *q1 = c_fma(c_fma(*q1, tw0, e1p_p), tw1, ep2);
+                }
+            }
+            if (a.dft_vol && km >= a.k0 && km < a.k1) {
+                const size_t vs = (size_t)nd * plane;
+                for (int f = 0; f < a.K; ++f) {
+                    const float2 tw0 = a.twiddle[(size_t)n * a.K + f], tw1 = a.twiddle[(size_t)(n + 1) * a.K + f];
+                    float2 *base = a.dft_vol + (size_t)f * 3 * vs + (size_t)(km - a.k0) * plane + rowc;
+                    float2 *q0 = pto(base, o), *q1 = pto(base + vs, o), *q2 = pto(base + 2 * vs, o);
+                    *q0 = c_fma(c_fma(*q0, tw0, e1r_p), tw1, er2);
+                    *q1 = c_fma(c_fma(*q1, tw0, e1p_p), tw1, ep2);
+                    *q2 = c_fma(c_fma(*q2, tw0, e1z_p), tw1, ez2);
+                }
+            }
+        }
+        er0 = er_kp;
+        ep0 = ep_kp;
+        h1r_p = h1r;
+        h1p_p = h1p;
+        h1z_p = h1z;
+        e1r_p = e1r;
+        e1p_p = e1p;
+        e1z_p = e1z;
+        u1_p = u1;
+        ce_p = ce;
+        h2r_km = h2r;
+        h2p_km = h2p;
+    }
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs; renumbering them so that
 // each XCD gets one contiguous range of tiles keeps the halo rows, columns and
 // chunk prologue planes that neighbouring tiles share in the same L2.
@@ -1028,6 +1243,12 @@ template <int TR, int LAY>
 __global__ __launch_bounds__(64 * (TR + 3)) void eh2_kernel(StepArgs a, int n)
 {
     eh2_body<TR, LAY>(a, n, a.tiles[blockIdx.x]);
+}
+
+template <int LAY>
+__global__ __launch_bounds__(FLAT_BLOCK) void eh2_flat_kernel(StepArgs a, int n)
+{
+    eh2_flat_body<LAY>(a, n, a.tiles[blockIdx.x]);
 }
 
 // Batched launches: one 1-D grid covers the tiles of many zones of uneven
@@ -1146,6 +1367,15 @@ __global__ __launch_bounds__(64 * (TR + 3)) void eh2_batch(BatchArgs b, int n_re
     const StepArgs a = zone_args(b.tab, (int)tile.w);
     const int n = n_rel + (b.n_base ? *b.n_base : 0);
     eh2_body<TR, LAY>(a, n, tile);
+}
+
+template <int LAY>
+__global__ __launch_bounds__(FLAT_BLOCK) void eh2_flat_batch(BatchArgs b, int n_rel)
+{
+    const uint4 tile = b.tiles[blockIdx.x];
+    const StepArgs a = zone_args(b.tab, (int)tile.w);
+    const int n = n_rel + (b.n_base ? *b.n_base : 0);
+    eh2_flat_body<LAY>(a, n, tile);
 }
 
 __global__ void advance_step_kernel(int *n_base, int by)
@@ -1303,7 +1533,10 @@ void launch_batch_two_tr(const BatchArgs &b, unsigned ntiles, int lay, int n_rel
 void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, int lay, int n_rel, hipStream_t s)
 {
     if (ntiles == 0) return;
-    if (tile_rows == 13) launch_batch_two_tr<13>(b, ntiles, lay, n_rel, s);
+    if (tile_rows == FLAT_TWO_ROWS) {
+        if (lay == 0) hipLaunchKernelGGL(eh2_flat_batch<0>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, b, n_rel);
+        else hipLaunchKernelGGL(eh2_flat_batch<3>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, b, n_rel);
+    } else if (tile_rows == 13) launch_batch_two_tr<13>(b, ntiles, lay, n_rel, s);
     else launch_batch_two_tr<5>(b, ntiles, lay, n_rel, s);
 }
 
@@ -1318,7 +1551,10 @@ void launch_two_tr(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream
 void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream_t s)
 {
     if (ntiles == 0) return;
-    if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, lay, s);
+    if (a.tile_rows == FLAT_TWO_ROWS) {
+        if (lay == 0) hipLaunchKernelGGL(eh2_flat_kernel<0>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, a, n);
+        else hipLaunchKernelGGL(eh2_flat_kernel<3>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, a, n);
+    } else if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, lay, s);
     else launch_two_tr<5>(a, n, ntiles, lay, s);
 }
 

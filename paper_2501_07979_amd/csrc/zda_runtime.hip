@@ -83,7 +83,7 @@ struct zda_zone {
     float2 *auxR[2] = {nullptr, nullptr}, *auxZ[2] = {nullptr, nullptr};
     int cur = 0;
     bool fused = true;
-    bool two = false;              // two leap-frog steps per launch (tile_rows 5 or 13)
+    bool two = false;              // two leap-frog steps per launch (tile_rows 5, 13 or 34)
     int xcd_remap = 0, nt_stores = 1, layer_stream = 0;
     int tile_patch = 0;            // (bands << 8) | columns of an XCD's patch of two-step tiles, 0 = off
     int layer_kchunk = -1;         // planes per chunk of the r-layer band tiles (-1: automatic)
@@ -546,16 +546,24 @@ int default_two_step_kchunk(const zda_zone_desc &d, int n_cu)
     return best;
 }
 
+// Owned rows of a two-step tile for a tile_rows code (the code itself, or
+// the rows a flat block holds less its halo)
+int two_step_rows(int tile_rows, int nphi)
+{
+    return tile_rows == FLAT_TWO_ROWS ? flat_two_rows(nphi) : tile_rows;
+}
+
 // The zone's own tile list (interior tiles first), rebuilt when the launch
 // shape, the source plane or the tile order changed.
 zda_status build_two_step_tiles(zda_zone *z)
 {
     const int TR = z->tile_rows, kc = z->kchunk;
+    const int rows = two_step_rows(TR, z->d.nphi);
     if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last &&
         z->tiles_xcd == tile_order(z) && z->tiles_lkc == z->layer_kchunk)
         return ZDA_OK;
     TwoStepTiles t;
-    two_step_tiles(z, TR, kc, z->k_src_last, tile_order(z), 0u, t);
+    two_step_tiles(z, rows, kc, z->k_src_last, tile_order(z), 0u, t);
     std::vector<uint4> all;
     for (int q = 0; q < 4; ++q) {
         z->n_lay[q] = (unsigned)t.v[q].size();
@@ -593,7 +601,7 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     auto one_step = [&](int n) {
         if (fused || two) {
             StepArgs b = ab[z->cur ^ ab_base];
-            if (two) b.tile_rows = 3;
+            if (two) b.tile_rows = z->tile_rows == FLAT_TWO_ROWS ? FLAT_FUSED_ROWS : 3;
             launch_fused_step(b, n, s);
             z->cur ^= 1;
         } else {
@@ -1248,16 +1256,18 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
     const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
                        tile_rows == FLAT_ROWS;
     const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15 || tile_rows == FLAT_FUSED_ROWS;
-    const bool two = tile_rows == 5 || tile_rows == 13;
+    const bool two = tile_rows == 5 || tile_rows == 13 || tile_rows == FLAT_TWO_ROWS;
     if (!split && !fused && !two)
-        return fail(ZDA_ERR_ARG,
-                    "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused) or 5, 13 (two-step)");
+        return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused) or 5, 13, "
+                                 "34 (two-step)");
     if ((fused || two) && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set");
     if ((fused || two) && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set");
     if (two && !z->has_m) return fail(ZDA_ERR_STATE, "no intermediate auxiliaries for the two-step kernel");
     if (two && (z->d.nr > 65535 || z->d.nz > 65535)) return fail(ZDA_ERR_ARG, "two-step tiles need nr, nz <= 65535");
     if (tile_rows == FLAT_FUSED_ROWS && z->d.nphi > FLAT_FUSED_MAX_PHI)
         return fail(ZDA_ERR_ARG, "the flat fused step needs nphi <= %d", FLAT_FUSED_MAX_PHI);
+    if (tile_rows == FLAT_TWO_ROWS && z->d.nphi > FLAT_TWO_MAX_PHI)
+        return fail(ZDA_ERR_ARG, "the flat two-step kernel needs nphi <= %d", FLAT_TWO_MAX_PHI);
     z->kchunk = kchunk;
     z->tile_rows = tile_rows;
     z->fused = fused;
@@ -1307,14 +1317,18 @@ zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kc
     if (d->pml_r_in < 0 || d->pml_r_out < 0 || d->pml_z_lo < 0 || d->pml_z_hi < 0 ||
         2 * std::max(d->pml_r_in, d->pml_r_out) > d->nr || 2 * std::max(d->pml_z_lo, d->pml_z_hi) > d->nz)
         return fail(ZDA_ERR_ARG, "layers must be >= 0 and at most half the extent");
-    if (tile_rows != 5 && tile_rows != 13) return fail(ZDA_ERR_ARG, "two-step tile_rows is 5 or 13");
+    if (tile_rows != 5 && tile_rows != 13 && tile_rows != FLAT_TWO_ROWS)
+        return fail(ZDA_ERR_ARG, "two-step tile_rows is 5, 13 or 34");
+    if (tile_rows == FLAT_TWO_ROWS && d->nphi > FLAT_TWO_MAX_PHI)
+        return fail(ZDA_ERR_ARG, "the flat two-step kernel needs nphi <= %d", FLAT_TWO_MAX_PHI);
     if (kchunk < 1) return fail(ZDA_ERR_ARG, "kchunk must be >= 1");
     if (order > 1 && ((order >> 8) < 1 || (order >> 8) > 255 || (order & 0xff) < 1))
         return fail(ZDA_ERR_ARG, "tile patch must be (bands << 8) | columns with both in [1, 255]");
     zda_zone z;
     z.d = *d;
     TwoStepTiles t;
-    two_step_tiles(&z, tile_rows, std::min(kchunk, d->nz), k_src, order < 0 ? 0 : order, 0u, t);
+    two_step_tiles(&z, two_step_rows(tile_rows, d->nphi), std::min(kchunk, d->nz), k_src, order < 0 ? 0 : order, 0u,
+                   t);
     *n_interior = t.v[0].size();
     *ntiles = t.v[0].size() + t.v[1].size() + t.v[2].size() + t.v[3].size();
     if (!out) return ZDA_OK;
@@ -1402,7 +1416,7 @@ struct zda_batch {
     int graph_steps = 32;         // steps per captured graph (even)
     std::vector<StepArgs> h_tab;
     std::vector<unsigned> h_prefix;
-    bool two = false;             // two-step kernel (tile_rows 5 or 13)
+    bool two = false;             // two-step kernel (tile_rows 5, 13 or 34)
     uint4 *tiles = nullptr;       // two-step: interior tiles of every zone, then layer tiles
     size_t cap_tiles = 0;
 };
@@ -1433,7 +1447,8 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
         TwoStepTiles t;
         for (int i = 0; i < nz; ++i) {
             const zda_zone *z = b->zones[i];
-            two_step_tiles(z, b->tile_rows, z->kchunk, ab[i][0].k_src, tile_order(z), (unsigned)i, t);
+            two_step_tiles(z, two_step_rows(b->tile_rows, z->d.nphi), z->kchunk, ab[i][0].k_src, tile_order(z),
+                           (unsigned)i, t);
         }
         std::vector<uint4> all;
         for (int q = 0; q < 4; ++q) {
@@ -1518,7 +1533,7 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
             // an odd last step: the fused step of each zone (absolute step index)
             for (int i = 0; i < nz; ++i) {
                 StepArgs a1 = ab[i][((nsteps - done) / 2) & 1];
-                a1.tile_rows = 3;
+                a1.tile_rows = b->tile_rows == FLAT_TWO_ROWS ? FLAT_FUSED_ROWS : 3;
                 launch_fused_step(a1, nsteps - 1, s);
             }
         }
@@ -1584,10 +1599,14 @@ zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk)
     const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
                        tile_rows == FLAT_ROWS;
     const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15 || tile_rows == FLAT_FUSED_ROWS;
-    const bool two = tile_rows == 5 || tile_rows == 13;
+    const bool two = tile_rows == 5 || tile_rows == 13 || tile_rows == FLAT_TWO_ROWS;
     if (!split && !fused && !two)
-        return fail(ZDA_ERR_ARG,
-                    "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused) or 5, 13 (two-step)");
+        return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused) or 5, 13, "
+                                 "34 (two-step)");
+    if (tile_rows == FLAT_TWO_ROWS)
+        for (auto z : b->zones)
+            if (z->d.nphi > FLAT_TWO_MAX_PHI)
+                return fail(ZDA_ERR_ARG, "the flat two-step kernel needs nphi <= %d", FLAT_TWO_MAX_PHI);
     if (fused)
         for (auto z : b->zones)
             if (!zone_has_second_set(z)) return fail(ZDA_ERR_STATE, "a zone has no second buffer set");
@@ -1696,13 +1715,15 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
     // (the time-block depth: 1 for the split and fused kernels, 2 for the
     // two-step kernel)
     std::vector<int> rows_c = {2, 4, 8, FLAT_ROWS};
-    bool can_fuse = true, can_two = true;
+    bool can_fuse = true, can_two = true, narrow = true;
     for (auto z : b->zones) {
         can_fuse = can_fuse && zone_has_second_set(z);
         can_two = can_two && zone_two_step_ok(z);
+        narrow = narrow && z->d.nphi <= FLAT_TWO_MAX_PHI;
     }
     if (can_fuse) rows_c.insert(rows_c.end(), {3, 7, 15});
     if (can_two) rows_c.insert(rows_c.end(), {5, 13});
+    if (can_two && narrow) rows_c.push_back(FLAT_TWO_ROWS);
     std::vector<int> kc(nz);
     for (size_t i = 0; i < nz; ++i) kc[i] = b->zones[i]->kchunk;
     double best = 1e300;
@@ -1724,7 +1745,7 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
         const size_t lo = nz * cl / nclass, hi = nz * (cl + 1) / nclass;
         const std::vector<int> kc0 = kc;
         int best_depth = 0;
-        const bool two_rows = best_rows == 5 || best_rows == 13;
+        const bool two_rows = best_rows == 5 || best_rows == 13 || best_rows == FLAT_TWO_ROWS;
         const std::vector<int> depths = two_rows ? std::vector<int>{16, 24, 32, 48, 96}
                                                  : std::vector<int>{6, 8, 12, 20, 40};
         for (int depth : depths) {

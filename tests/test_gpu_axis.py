@@ -7,13 +7,13 @@ Tolerances as for the wedge zones: fields and DFTs relative L2 <= 2e-5 /
 import numpy as np
 import pytest
 
-from test_gpu_parity import SHAPES, _objective, _rel
+from test_gpu_parity import SHAPES, _objective, _rel, skip_if_too_wide
 
 pytestmark = pytest.mark.gpu
 
 COMPS = ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz")
 FAMILIES = ["default", "fused_tr3_kc7", "split_r4_kc7", "split_r1", "two_tr13_kc9", "two_tr5_kc3", "flat_kc5",
-            "flatfused_kc5"]
+            "flatfused_kc5", "flattwo_kc5", "flattwo_kc16"]
 
 
 def _say(*a):
@@ -31,8 +31,7 @@ def zda():
 
 
 def _zones(zda, oracle_mod, wl, eps, shape):
-    if shape is not None and shape[1] == 33 and wl.nphi > 64:
-        pytest.skip("the flat fused step takes zones of at most 64 phi cells")
+    skip_if_too_wide(shape, wl.nphi)
     g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
     if shape is not None:
         kc, tr = shape
@@ -98,7 +97,7 @@ def test_first_band_zones_source_driven(zda, oracle_mod, case, shape):
 
 
 @pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr5_kc3", "flat_kc5",
-                                   "flatfused_kc5"])
+                                   "flatfused_kc5", "flattwo_kc5"])
 @pytest.mark.parametrize("case", ["axis_continuous", "axis_wedge", "narrow_wedge"])
 def test_axis_zone_random_state(zda, oracle_mod, case, shape):
     """Arbitrary fields on every cell that the axis zone updates (row 0
@@ -125,7 +124,8 @@ def test_axis_zone_random_state(zda, oracle_mod, case, shape):
     g.close()
 
 
-@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc3", "flat_kc5", "flatfused_kc5"])
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc3", "flat_kc5", "flatfused_kc5",
+                                   "flattwo_kc16"])
 def test_axis_zone_gradient_parity(zda, oracle_mod, shape):
     """Adjoint gradient over the design layer of a continuous zone containing
     the axis (the adjoint runs with -m: seams 1 -+ i m) against the oracle."""

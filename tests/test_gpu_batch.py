@@ -158,6 +158,52 @@ def test_batch_with_the_axis_zone(zda, oracle_mod, mode):
     b.close()
 
 
+@pytest.mark.parametrize("steps", [150, 151])
+def test_batch_of_narrow_zones_flat_two_step(zda, oracle_mod, steps):
+    """Narrow zones (the continuous axis zone, wedges of 11, 16 and 32 phi
+    cells) in one batch on the flat-mapped two-step kernel: each equals its
+    own run with the same launch bitwise and the oracle to 1e-5 (an odd step
+    count ends with one flat fused step)."""
+    from paper_2501_07979_amd.workloads import Workload
+    om = (0.28, 0.33, 0.39)
+    common = dict(nz=40, k_src=8, k_mon=30, design=(12, 16), k_sub=12, steps=steps, omegas=om, omega_c=0.33,
+                  width=6.0, density="smoothed")
+    wls = [Workload("axis", r_in=0.5, nr=40, nphi=1, n_fold=0, pml=(0, 5, 5, 5), axis=1, seed=87, **common),
+           Workload("ring11", r_in=600.5, nr=45, nphi=11, n_fold=360, pml=(5, 6, 4, 7), seed=88, **common),
+           Workload("ring16", r_in=645.5, nr=33, nphi=16, n_fold=270, pml=(5, 5, 5, 5), seed=89, **common),
+           Workload("ring32", r_in=678.5, nr=30, nphi=32, n_fold=140, pml=(5, 5, 5, 5), seed=90, **common)]
+    kcs = [16, 7, 12, 40]
+    eps = [w.eps() for w in wls]
+    singles = []
+    for w, e, kc in zip(wls, eps, kcs):
+        z = zda.Zone(zda.default_desc(**w.desc_kwargs()), e)
+        z.set_launch(kc, 34)
+        z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width)
+        singles.append(z.dft(zda.MON_PLANE).cpu().numpy())
+        z.close()
+    zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    b = zda.Batch(zones)
+    b.set_launch(34, kcs)
+    srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
+    _say("narrow zones, flat two-step batch", steps)
+    b.run(srcs, steps, om)
+    for w, e, z, pl in zip(wls, eps, zones, singles):
+        got = z.dft(zda.MON_PLANE).cpu().numpy()
+        o = oracle_mod.OracleZone(**w.desc_kwargs(), eps=e)
+        ref = o.forward(w.steps, np.array(om), omega_c=w.omega_c, width=w.width, k_src=w.k_src)["plane"]
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        _say(w.name, "flat two-step batch vs oracle rel L2 %.2e" % rel)
+        assert rel <= 1e-5
+        assert np.array_equal(got, pl)
+    b.close()
+    wide = zda.Zone(zda.default_desc(r_in=100.0, nr=20, nphi=33, nz=20, n_fold=16, m=1, pml=(3, 3, 3, 3),
+                                     k_mon=12, design=(8, 10)))
+    with pytest.raises(zda.ZdaError) as ex:
+        wide.set_launch(8, 34)
+    assert ex.value.status == zda.ZDA_ERR_ARG
+    wide.close()
+
+
 def test_lens_in_waves_equals_one_batch(zda):
     """A lens run in waves of zones (each wave one batch, released before the
     next) gives every zone's exit-plane DFT bitwise equal to one batch of all

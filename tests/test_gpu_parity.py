@@ -28,16 +28,23 @@ def _rel(a, b):
 # launch shapes: (kchunk, tile_rows); tile_rows 3/7/15 select the fused
 # double-buffered step, 5/13 the two-step kernel, 1/2/4/8/16 the split
 # in-place H and E kernels, 32 the in-place kernels with the flat (r, phi)
-# mapping, 33 the fused step with the flat mapping (nphi <= 64); None keeps
-# the zone's default
+# mapping, 33 the fused step with the flat mapping (nphi <= 64), 34 the
+# two-step kernel with the flat mapping (nphi <= 32); None keeps the zone's
+# default
 SHAPES = {"default": None, "fused_tr3_kc7": (7, 3), "fused_tr15_kc13": (13, 15), "split_r4_kc7": (7, 4),
           "split_r1": (0, 1), "two_tr13_kc9": (9, 13), "two_tr5_kc6": (6, 5), "two_tr5_kc3": (3, 5),
-          "flat_kc5": (5, 32), "flatfused_kc5": (5, 33)}
+          "flat_kc5": (5, 32), "flatfused_kc5": (5, 33), "flattwo_kc5": (5, 34), "flattwo_kc16": (16, 34)}
+# widest zone (phi cells) of the flat-mapped fused and two-step kernels
+FLAT_MAX_PHI = {33: 64, 34: 32}
+
+
+def skip_if_too_wide(shape, nphi):
+    if shape is not None and nphi > FLAT_MAX_PHI.get(shape[1], nphi):
+        pytest.skip("launch code %d takes zones of at most %d phi cells" % (shape[1], FLAT_MAX_PHI[shape[1]]))
 
 
 def _zone_pair(zda, oracle_mod, wl, eps, shape=None):
-    if shape is not None and shape[1] == 33 and wl.nphi > 64:
-        pytest.skip("the flat fused step takes zones of at most 64 phi cells")
+    skip_if_too_wide(shape, wl.nphi)
     g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
     if shape is not None:
         kc, tr = shape

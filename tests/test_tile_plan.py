@@ -3,7 +3,8 @@ of the zone exactly once; the interior tiles compute no layer cell (their
 rows i0-2 .. i0+rows and planes kb-2 .. ke, clipped to the zone, avoid both
 layers), so they may run the instantiation without layer recursions; the
 owned columns of interior tiles start on 64 B boundaries; every tile order
-is a permutation of the natural one."""
+is a permutation of the natural one.  The flat-mapped two-step plan (launch
+code 34) gives every tile all phi cells and at most 256 / nphi - 3 rows."""
 import numpy as np
 import pytest
 
@@ -71,3 +72,45 @@ def test_plan_rejects_bad_arguments():
         with pytest.raises(zda.ZdaError) as e:
             zda.plan_two_step_tiles(d, tr, kc, order=order)
         assert e.value.status == zda.ZDA_ERR_ARG
+
+
+NARROW = {
+    "continuous_axis": dict(nr=300, nphi=1, nz=41, pml=(0, 6, 4, 7)),
+    "wedge11": dict(nr=1250, nphi=11, nz=60, pml=(12, 12, 10, 10)),
+    "wedge16_ragged": dict(nr=37, nphi=16, nz=33, pml=(5, 6, 4, 7)),
+    "wedge32": dict(nr=29, nphi=32, nz=20, pml=(3, 3, 3, 3)),
+    "thin": dict(nr=3, nphi=5, nz=4, pml=(1, 1, 1, 1)),
+}
+
+
+@pytest.mark.parametrize("kchunk", [3, 16])
+@pytest.mark.parametrize("name", list(NARROW))
+def test_flat_two_step_tiles(name, kchunk):
+    from paper_2501_07979_amd import zda
+    z = NARROW[name]
+    d = _desc(zda, **z)
+    tiles, n_int = zda.plan_two_step_tiles(d, 34, kchunk, k_src=2)
+    nr, nphi, nz = z["nr"], z["nphi"], z["nz"]
+    pr0, pr1, pz0, pz1 = z["pml"]
+    rows_max = 256 // nphi - 3
+    own = np.zeros((nz, nr), np.int32)
+    for q, (bx, y, zz, kind) in enumerate(tiles):
+        i0, rows = int(y & 0xFFFF), int(y >> 16)
+        kb, ke = int(zz & 0xFFFF), int(zz >> 16)
+        assert bx == 0 and (kind == 0) == (q < n_int)
+        assert 1 <= rows <= rows_max and kb < ke and ke - kb <= kchunk
+        own[kb:ke, i0:i0 + rows] += 1
+        if kind == 0:
+            r_lo, r_hi = max(i0 - 2, 0), min(i0 + rows, nr - 1)
+            k_lo, k_hi = max(kb - 2, 0), min(ke, nz - 1)
+            assert pr0 <= r_lo and r_hi < nr - pr1, (i0, rows)
+            assert pz0 <= k_lo and k_hi < nz - pz1, (kb, ke)
+    assert own.min() == 1 and own.max() == 1
+
+
+def test_flat_two_step_plan_refuses_wide_zones():
+    from paper_2501_07979_amd import zda
+    d = _desc(zda, nr=20, nphi=33, nz=20, pml=(3, 3, 3, 3))
+    with pytest.raises(zda.ZdaError) as e:
+        zda.plan_two_step_tiles(d, 34, 8)
+    assert e.value.status == zda.ZDA_ERR_ARG
