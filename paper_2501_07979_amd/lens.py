@@ -33,13 +33,13 @@ class Lens:
         self.focal = objective.focal_length(self.radius, na)
         self.zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps()) for w in self.workloads]
         # one batch per kernel family: narrow wedges and the continuous zone on
-        # the flat-mapped fused step, the others on the two-step kernel
+        # the flat-mapped two-step kernel, the others on the two-step kernel
         self.groups = []
         for narrow in (True, False):
             idx = [q for q, w in enumerate(self.workloads) if is_narrow(w) == narrow]
             if idx:
                 b = zda.Batch([self.zones[q] for q in idx])
-                b.set_launch(FLAT if narrow else TWO_STEP)
+                set_family(b, FLAT if narrow else TWO_STEP, [self.workloads[q] for q in idx])
                 self.groups.append((idx, b))
         self.weights = [objective.focal_weights(w, w.omegas, self.focal) for w in self.workloads]
         self.run_kw = dict(nsteps=w0.steps, omegas=w0.omegas, k_src=w0.k_src, omega_c=w0.omega_c, width=w0.width)
@@ -65,11 +65,25 @@ class Lens:
 
 
 # batch launch codes: the two-step kernel (13 rows) and, for narrow zones,
-# the fused step with the flat (r, phi) mapping (whole rows per block): on a
-# 16-zone lens of narrow wedges it measured 32.1 Gcell-updates/s against 29.2
-# for the flat in-place kernels, which a single small zone prefers
-TWO_STEP, FLAT = 13, 33
+# the two-step kernel with the flat (r, phi) mapping (whole rows per block)
+# in 16-plane chunks: on a 16-zone lens of narrow wedges (37 M cells) it
+# measured 42.3 Gcell-updates/s against 28.0 for the flat fused step and
+# 25.9 for the flat in-place kernels (chunks of 12 to 64 planes: 39-42)
+TWO_STEP, FLAT = 13, 34
+FLAT_KCHUNK = 16
 NARROW_PHI = 16
+
+
+def family_kchunk(fam, w):
+    """Chunk depth a zone takes in a batch of launch family fam (None keeps
+    the zone's own)."""
+    return min(FLAT_KCHUNK, w.nz) if fam == FLAT else None
+
+
+def set_family(batch, fam, wls):
+    """Sets a batch of the zones described by wls to launch family fam."""
+    kcs = [family_kchunk(fam, w) for w in wls]
+    batch.set_launch(fam, None if any(k is None for k in kcs) else kcs)
 
 
 def is_narrow(w):
@@ -115,7 +129,7 @@ def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=None, warmup=0, keep
     two-step kernel applies) in waves: consecutive zones of one kernel family
     whose memory fits budget_bytes form one batch, which is created, run and
     released before the next (narrow wedges and the continuous zone run on the
-    flat-mapped fused step, the others on the two-step kernel, unless
+    flat-mapped two-step kernel, the others on the 13-row one, unless
     tile_rows fixes one launch for all).  Zones are independent, so this
     equals one batch of all of them.  Returns the exit-plane DFTs (complex64
     host arrays, in the order of workloads), the summed stepping time in ms
@@ -128,7 +142,7 @@ def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=None, warmup=0, keep
         wave = [workloads[q] for q in idx]
         zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps()) for w in wave]
         batch = zda.Batch(zones)
-        batch.set_launch(fam)
+        set_family(batch, fam, wave)
         srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wave]
         if warmup:
             batch.run(srcs, warmup, wave[0].omegas)

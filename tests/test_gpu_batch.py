@@ -229,7 +229,7 @@ def test_lens_in_waves_equals_one_batch(zda):
 
 
 def test_waves_group_zones_by_kernel_family(zda):
-    """A lens with the continuous axis zone (flat-mapped fused step) and
+    """A lens with the continuous axis zone (flat-mapped two-step kernel) and
     wedges (two-step kernel) in waves: each zone's exit-plane DFT is bitwise
     that of the zone run alone with the same kernel family."""
     from paper_2501_07979_amd import lens
@@ -244,7 +244,7 @@ def test_waves_group_zones_by_kernel_family(zda):
     for w in wls:
         z = zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps())
         if lens.is_narrow(w):
-            z.set_launch(z.info().kchunk, lens.FLAT)
+            z.set_launch(lens.family_kchunk(lens.FLAT, w), lens.FLAT)
         z.run(w.steps, w.omegas, k_src=w.k_src, omega_c=w.omega_c, width=w.width)
         ref.append(z.dft(zda.MON_PLANE).cpu().numpy())
         z.close()
