@@ -1724,17 +1724,25 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
     if (can_fuse) rows_c.insert(rows_c.end(), {3, 7, 15});
     if (can_two) rows_c.insert(rows_c.end(), {5, 13});
     if (can_two && narrow) rows_c.push_back(FLAT_TWO_ROWS);
-    std::vector<int> kc(nz);
-    for (size_t i = 0; i < nz; ++i) kc[i] = b->zones[i]->kchunk;
+    // the flat two-step kernel is probed with 16-plane chunks (the zones'
+    // own depth suits their default in-place kernels, 2 planes for narrow
+    // zones, and would hide it behind its chunk halo)
+    std::vector<int> kc(nz), kc_flat(nz);
+    for (size_t i = 0; i < nz; ++i) {
+        kc[i] = b->zones[i]->kchunk;
+        kc_flat[i] = std::min(16, b->zones[i]->d.nz);
+    }
+    auto depths_of = [&](int rr) { return rr == FLAT_TWO_ROWS ? kc_flat.data() : kc.data(); };
     double best = 1e300;
     int best_rows = b->tile_rows;
     zda_status st;
     for (int rr : rows_c) {
-        if ((st = zda_batch_set_launch(b, rr, kc.data())) != ZDA_OK) return st;
+        if ((st = zda_batch_set_launch(b, rr, depths_of(rr))) != ZDA_OK) return st;
         double ms;
         if ((st = probe(ms)) != ZDA_OK) return st;
         if (ms < best) { best = ms; best_rows = rr; }
     }
+    if (best_rows == FLAT_TWO_ROWS) kc = kc_flat;
     if ((st = zda_batch_set_launch(b, best_rows, kc.data())) != ZDA_OK) return st;
     // 2) z-chunk depth per size class (thirds of the zones by cell count)
     std::vector<size_t> order(nz);

@@ -119,6 +119,32 @@ def test_batch_autotune_keeps_results(zda):
     b.close()
 
 
+def test_autotune_on_narrow_zones_keeps_results(zda, oracle_mod):
+    """The autotuner on a batch of narrow wedges (where the flat two-step
+    kernel is a candidate, probed with its own chunk depth): whatever it
+    keeps, the zones' results match the oracle to 1e-5 afterwards."""
+    from paper_2501_07979_amd.workloads import Workload
+    om = (0.28, 0.33)
+    common = dict(nz=48, k_src=8, k_mon=36, design=(12, 16), k_sub=12, steps=100, omegas=om, omega_c=0.31,
+                  width=6.0, density="smoothed", nphi=11, n_fold=360, pml=(6, 6, 6, 6))
+    wls = [Workload("w%d" % q, r_in=600.5 + 200.0 * q, nr=200, seed=95 + q, **common) for q in range(4)]
+    eps = [w.eps() for w in wls]
+    zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    b = zda.Batch(zones)
+    srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
+    _say("autotune, narrow zones")
+    res = b.autotune(srcs, 8, om)
+    _say("autotune kept tile_rows", res.tile_rows, "%.4f ms/step" % res.ms_per_step)
+    assert res.probes >= 6 and res.ms_per_step > 0
+    b.run(srcs, wls[0].steps, om)
+    for w, e, z in zip(wls, eps, zones):
+        got = z.dft(zda.MON_PLANE).cpu().numpy()
+        o = oracle_mod.OracleZone(**w.desc_kwargs(), eps=e)
+        ref = o.forward(w.steps, np.array(om), omega_c=w.omega_c, width=w.width, k_src=w.k_src)["plane"]
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    b.close()
+
+
 @pytest.mark.parametrize("mode", ["fused", "two", "two_odd", "flatfused"])
 def test_batch_with_the_axis_zone(zda, oracle_mod, mode):
     """The first zones of a lens in one batch: the continuous zone that
