@@ -69,3 +69,43 @@ def test_lens_phasors_and_gradient(oracle_mod):
         _say("zone", z, "pixel", (l, i, j), "fd %.6e gpu %.6e |diff|/max|g| %.2e" % (fd, grads[z][l, i, j], e))
         assert e <= 1e-3
     lens.close()
+
+
+@pytest.mark.parametrize("zone", [0, 1, 15])
+def test_lwir_zone_full_size_in_the_lens_launch(oracle_mod, zone):
+    """Zones of the LWIR-shaped lens at full size (1250 x 11 x 180 cells; the
+    continuous axis zone 1250 x 1 x 180) in the launch that the lens batches
+    run (flat-mapped two-step kernel, 16-plane chunks): arbitrary fields on
+    every cell, stepped 21 times (an odd count: ten two-step launches and one
+    flat fused step), against the FP64 oracle, every field to 1e-5."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_07979_amd import lens, zda
+    from paper_2501_07979_amd.workloads import lwir_lens
+    w = lwir_lens()[zone]
+    eps = w.eps()
+    g = zda.Zone(zda.default_desc(**w.desc_kwargs()), eps)
+    g.set_launch(lens.family_kchunk(lens.FLAT, w), lens.FLAT)
+    o = oracle_mod.OracleZone(**w.desc_kwargs(), eps=eps)
+    rng = np.random.default_rng(64 + zone)
+    _say("full-size LWIR zone", w.name, "launch", g.info().tile_rows, g.info().kchunk)
+    for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz"):
+        f = (rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)).astype(np.complex64)
+        if c in ("Er", "Ephi", "Hz"):
+            f[0] = 0
+        if w.r_in >= w.dr and c in ("Ephi", "Ez", "Hr"):
+            f[:, 0] = 0
+        g.write_field(c, f)
+        o.set_field(c, f.astype(np.complex128))
+    steps = 21
+    zero = np.zeros((1, 2, w.nr, w.nphi), np.complex64)
+    g.run(steps, (), kind=zda.SRC_CUSTOM, k_src=w.k_src, patterns=zero, profiles=np.zeros((1, steps)), plane=False,
+          cont=True)
+    o.run(steps, m=w.m, reset=False)
+    for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz"):
+        got, ref = g.read_field(c).cpu().numpy(), o.get_field(c)
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        _say(w.name, c, "rel L2 %.2e" % e)
+        assert e <= 1e-5, (c, e)
+    g.close()
