@@ -327,7 +327,9 @@ zda_status zda_batch_adjoint_grad(zda_batch *b, const float *const *dF_dE, float
 
 /* Launch shape shared by the batched kernels (tile_rows as in
  * zda_zone_set_launch) and per-zone z-chunk depth kchunk[nzones] (NULL keeps
- * each zone's). */
+ * each zone's; the flat two-step kernel, 34, wants chunks of 12 to 64 planes,
+ * far deeper than the 2 that narrow zones keep for their default in-place
+ * kernels).  Errors as for zda_zone_set_launch, for any zone. */
 zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk);
 
 /* Autotuner: times short probe runs (probe_steps >= 2; the zones' state is
