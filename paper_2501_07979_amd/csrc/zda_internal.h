@@ -85,7 +85,8 @@ void launch_e_step(const StepArgs &a, int n, hipStream_t s);
 void launch_fused_step(const StepArgs &a, int n, hipStream_t s);
 // two leap-frog steps (n, n + 1) over the tiles listed in a.tiles; lay 0
 // runs the instantiation without layer recursions (tiles whose computed rows
-// and planes hold no layer cell), any other value the one with the r- and
+// and planes hold no layer cell), lay 2 with the flat mapping the one with
+// the z-layer recursions only, any other value the one with the r- and
 // z-layer recursions
 void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream_t s);
 // phi cells a tile owns.  56 (448 B) puts every tile's stores on 64 B

@@ -1535,6 +1535,7 @@ void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, int la
     if (ntiles == 0) return;
     if (tile_rows == FLAT_TWO_ROWS) {
         if (lay == 0) hipLaunchKernelGGL(eh2_flat_batch<0>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, b, n_rel);
+        else if (lay == 2) hipLaunchKernelGGL(eh2_flat_batch<2>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, b, n_rel);
         else hipLaunchKernelGGL(eh2_flat_batch<3>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, b, n_rel);
     } else if (tile_rows == 13) launch_batch_two_tr<13>(b, ntiles, lay, n_rel, s);
     else launch_batch_two_tr<5>(b, ntiles, lay, n_rel, s);
@@ -1553,6 +1554,7 @@ void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStre
     if (ntiles == 0) return;
     if (a.tile_rows == FLAT_TWO_ROWS) {
         if (lay == 0) hipLaunchKernelGGL(eh2_flat_kernel<0>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, a, n);
+        else if (lay == 2) hipLaunchKernelGGL(eh2_flat_kernel<2>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, a, n);
         else hipLaunchKernelGGL(eh2_flat_kernel<3>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, a, n);
     } else if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, lay, s);
     else launch_two_tr<5>(a, n, ntiles, lay, s);

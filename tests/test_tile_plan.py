@@ -4,7 +4,8 @@ rows i0-2 .. i0+rows and planes kb-2 .. ke, clipped to the zone, avoid both
 layers), so they may run the instantiation without layer recursions; the
 owned columns of interior tiles start on 64 B boundaries; every tile order
 is a permutation of the natural one.  The flat-mapped two-step plan (launch
-code 34) gives every tile all phi cells and at most 256 / nphi - 3 rows."""
+code 34) gives every tile all phi cells and at most 256 / nphi - 3 rows, and
+its z-layer-only tiles (kind 2) compute no r-layer row."""
 import numpy as np
 import pytest
 
@@ -97,9 +98,12 @@ def test_flat_two_step_tiles(name, kchunk):
     for q, (bx, y, zz, kind) in enumerate(tiles):
         i0, rows = int(y & 0xFFFF), int(y >> 16)
         kb, ke = int(zz & 0xFFFF), int(zz >> 16)
-        assert bx == 0 and (kind == 0) == (q < n_int)
+        assert bx == 0 and (kind == 0) == (q < n_int) and kind in (0, 2, 3)
         assert 1 <= rows <= rows_max and kb < ke and ke - kb <= kchunk
         own[kb:ke, i0:i0 + rows] += 1
+        if kind == 2:           # z-layer recursions only: no computed row in an r-layer
+            r_lo, r_hi = max(i0 - 2, 0), min(i0 + rows, nr - 1)
+            assert pr0 <= r_lo and r_hi < nr - pr1, (i0, rows)
         if kind == 0:
             r_lo, r_hi = max(i0 - 2, 0), min(i0 + rows, nr - 1)
             k_lo, k_hi = max(kb - 2, 0), min(ke, nz - 1)
