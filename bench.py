@@ -227,8 +227,9 @@ def main():
                     help="also run a plain 4 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs one zone on one GPU; --gpus %d is not supported "
-              "(zones shard one per GPU, see the design notes)" % args.gpus, file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only; --gpus %d is not supported "
+              "(a lens would shard its zones across GPUs, one zone per GPU; not built)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
