@@ -223,6 +223,8 @@ def main():
                     help="skip the gradient-zone design iteration reported beside the headline")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-vs-plain design comparison on the gradient zone's small copy")
+    ap.add_argument("--lens-iter-steps", type=int, default=2000,
+                    help="with --workload lwir: steps per run of the timed lens design iterations (0: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 4 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -248,13 +250,43 @@ def main():
         _, ms, nwaves = lens.run_in_waves(wls, args.steps, int(0.8 * free), warmup=args.warmup, keep_fields=False)
         gc = cells * args.steps / (ms / 1e3) / 1e9
         t_run = wls[0].steps * cells / (gc * 1e9)
+        design = None
+        if args.lens_iter_steps > 0:
+            # whole design iterations of the lens through its autograd path:
+            # batched forward runs with the design-layer DFT, the focal
+            # objective, batched adjoint runs and the overlap gradients
+            wl_it = lwir_lens(steps=args.lens_iter_steps)
+            ln = lens.Lens(wl_it)
+            rhos = [torch.tensor(w.rho(), device="cuda", requires_grad=True) for w in wl_it]
+            secs = []
+            for it in range(2):
+                print("bench: lens design iteration %d (%d steps per run)" % (it, args.lens_iter_steps),
+                      file=sys.stderr, flush=True)
+                for r in rhos:
+                    r.grad = None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F, _ = ln.objective(rhos)
+                F.backward()
+                torch.cuda.synchronize()
+                secs.append(time.perf_counter() - t0)
+            finite = all(bool(torch.isfinite(r.grad).all()) for r in rhos)
+            ln.close()
+            del ln, rhos
+            torch.cuda.empty_cache()
+            rate = 2 * cells * args.lens_iter_steps / secs[1] / 1e9
+            design = {"steps_per_run": args.lens_iter_steps, "runs_per_iter": 2, "s_per_iter": round(secs[1], 3),
+                      "s_first_iter": round(secs[0], 3), "gcell_updates_per_s": round(rate, 3),
+                      "finite_gradient": finite,
+                      "s_per_iter_at_%d_steps" % wls[0].steps: round(2 * wls[0].steps * cells / (rate * 1e9), 2)}
         print(json.dumps({"metric": METRIC, "value": round(gc, 4), "unit": "Gcell-updates/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
                           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
                           "data": "synthetic",
                           "config": {"workload": "lwir_shaped_lens_16_zones", "cells": cells, "frequencies": 1,
                                      "zones": [w.name for w in wls], "waves": nwaves,
-                                     "s_per_design_iteration_at_%d_steps" % wls[0].steps: round(2 * t_run, 2)}}),
+                                     "s_per_design_iteration_at_%d_steps" % wls[0].steps: round(2 * t_run, 2)},
+                          "design_iteration": design}),
               flush=True)
         return
     if args.workload == "c4":
