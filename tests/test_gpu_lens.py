@@ -1,5 +1,6 @@
 """A lens of three zones (the continuous zone containing the axis, then two
-wedges with growing n) stepped in one batch: its focal phasors equal the sum
+wedges with growing n; the first two on the flat-mapped kernel, the third
+on the 13-row one) stepped in batches: its focal phasors equal the sum
 of the zones' phasors from the FP64 oracle, and the gradient of the lens's
 focal intensity (one batched adjoint run) matches central finite differences
 of the same objective taken with the oracle, at a design pixel of each
@@ -20,7 +21,7 @@ def _zones():
                   omega_c=0.33, width=8.0, density="smoothed")
     return [Workload("axis", r_in=0.5, nr=24, nphi=1, n_fold=0, pml=(0, 4, 6, 6), axis=1, seed=91, **common),
             Workload("ring2", r_in=24.5, nr=24, nphi=32, n_fold=4, pml=(4, 4, 6, 6), seed=92, **common),
-            Workload("ring3", r_in=48.5, nr=24, nphi=32, n_fold=8, pml=(4, 4, 6, 6), seed=93, **common)]
+            Workload("ring3", r_in=48.5, nr=24, nphi=40, n_fold=8, pml=(4, 4, 6, 6), seed=93, **common)]
 
 
 def test_lens_phasors_and_gradient(oracle_mod):
