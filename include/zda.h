@@ -221,8 +221,9 @@ typedef struct {
  * block holds 256 / nphi whole rows and owns all but three, the radial halo;
  * nphi <= 32; an odd last step of a run takes the flat fused step; needs what
  * the two-step kernel needs).  Default: for zones of at most 16
- * phi cells (and the continuous zone) the flat in-place kernels; otherwise
- * the two-step kernel with 13 rows
+ * phi cells (and the continuous zone) the flat in-place kernels; for zones
+ * of 17 to 32 phi cells the flat two-step kernel in 4-plane chunks (where
+ * the two-step kernel fits); otherwise the two-step kernel with 13 rows
  * and the chunk depth (3 to 72 planes) whose launch is predicted to finish
  * first when tiles run in rounds of one per CU; the fused step (3 rows,
  * 12-plane chunks, fewer for small zones) where the intermediate set does not

@@ -57,13 +57,16 @@ def _workload(case):
     if case == "narrow_wedge":          # a wedge ~10 phi cells wide, as in the paper's lenses
         return Workload(case, r_in=600.0, nr=40, nphi=11, nz=50, n_fold=360, m=1, pml=(5, 6, 4, 7), steps=300,
                         **common)
+    if case == "wedge24":               # 24 phi cells: the flat two-step kernel is its default
+        return Workload(case, r_in=1400.0, nr=40, nphi=24, nz=50, n_fold=360, m=1, pml=(5, 6, 4, 7), steps=301,
+                        **common)
     if case == "continuous_annulus":    # continuous zone away from the axis, layers on both sides
         return Workload(case, r_in=30.0, nr=45, nphi=1, nz=50, n_fold=0, m=3, pml=(5, 6, 4, 7), steps=300,
                         **common)
     raise KeyError(case)
 
 
-CASES = ["axis_continuous", "axis_continuous_m2", "axis_wedge", "continuous_annulus", "narrow_wedge"]
+CASES = ["axis_continuous", "axis_continuous_m2", "axis_wedge", "continuous_annulus", "narrow_wedge", "wedge24"]
 
 
 @pytest.mark.parametrize("shape", FAMILIES)
@@ -151,6 +154,20 @@ def test_axis_zone_gradient_parity(zda, oracle_mod, shape):
     _say("axis gradient rel L2 = %.3e" % err)
     assert err <= 1e-4
     g.close()
+
+
+def test_default_launch_of_narrow_zones(zda):
+    """Default launch by width: the flat in-place kernels up to 16 phi cells
+    (and the continuous zone), the flat two-step kernel in 4-plane chunks
+    from 17 to 32, the 13-row two-step kernel above."""
+    for case, rows, kc in [("narrow_wedge", 32, None), ("axis_continuous", 32, None), ("wedge24", 34, 4),
+                           ("axis_wedge", 13, None)]:
+        wl = _workload(case)
+        g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), np.ones((wl.nz, wl.nr, wl.nphi), np.float32))
+        info = g.info()
+        _say("default launch", case, info.tile_rows, info.kchunk)
+        assert info.tile_rows == rows and (kc is None or info.kchunk == kc)
+        g.close()
 
 
 def test_first_band_zone_errors(zda):
