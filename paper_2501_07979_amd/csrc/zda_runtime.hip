@@ -1766,8 +1766,11 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
         const std::vector<int> kc0 = kc;
         int best_depth = 0;
         const bool two_rows = best_rows == 5 || best_rows == 13 || best_rows == FLAT_TWO_ROWS;
-        const std::vector<int> depths = two_rows ? std::vector<int>{16, 24, 32, 48, 96}
-                                                 : std::vector<int>{6, 8, 12, 20, 40};
+        // the flat two-step kernel measured best at 4-plane chunks on one
+        // narrow zone and at 16-24 on a 16-zone lens
+        const std::vector<int> depths = best_rows == FLAT_TWO_ROWS ? std::vector<int>{4, 8, 16, 24, 48}
+                                        : two_rows                 ? std::vector<int>{16, 24, 32, 48, 96}
+                                                                   : std::vector<int>{6, 8, 12, 20, 40};
         for (int depth : depths) {
             for (size_t q = lo; q < hi; ++q) kc[order[q]] = std::min(depth, b->zones[order[q]]->d.nz);
             if ((st = zda_batch_set_launch(b, best_rows, kc.data())) != ZDA_OK) return st;
