@@ -294,7 +294,9 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
  * row count << 16, first plane | end plane << 16, kind}, kind 0 for the
  * interior tiles (their computed rows i0-2 .. i0+rows and planes kb-2 .. ke
  * hold no layer cell; they own 56 phi cells) and 3 for the layer tiles (61
- * phi cells), interior tiles first; cap: capacity of out in tiles.
+ * phi cells; with tile_rows 34, 2 for the tiles whose computed rows hold no
+ * r-layer cell and 3 for the others), interior tiles first; cap: capacity
+ * of out in tiles.
  * *ntiles and *n_interior receive the counts.  Errors: ZDA_ERR_ARG (sizes
  * < 1, nr or nz > 65535, a layer wider than half the extent, tile_rows not 5,
  * 13 or 34, 34 with nphi > 32, kchunk < 1, a patch field of 0, out too
