@@ -245,8 +245,39 @@ def test_fused_launch_shapes_are_bitwise_identical(zda):
     for kc, tr, opt, val in [(41, 7, 0, 0), (5, 3, 0, 0), (13, 15, 0, 0), (1, 7, 0, 0), (9, 13, 0, 0), (41, 13, 0, 0),
                              (4, 5, 0, 0), (1, 5, 0, 0), (9, 13, zda.OPT_LAYER_STREAM, 1), (4, 5, zda.OPT_XCD_REMAP, 1),
                              (9, 13, zda.OPT_TILE_PATCH, (2 << 8) | 2), (4, 5, zda.OPT_TILE_PATCH, (3 << 8) | 1),
-                             (24, 13, zda.OPT_LAYER_KCHUNK, 0), (24, 13, zda.OPT_LAYER_KCHUNK, 5)]:
+                             (24, 13, zda.OPT_LAYER_KCHUNK, 0), (24, 13, zda.OPT_LAYER_KCHUNK, 5),
+                             (9, 13, zda.OPT_NT_STORES, 1), (5, 3, zda.OPT_NT_STORES, 1)]:
         _say("determinism", kc, tr, opt, val)
+        g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+        g.set_launch(kc, tr)
+        if opt:
+            g.set_option(opt, val)
+        g.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+        outs.append([g.read_field(c).cpu().numpy() for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz")] +
+                    [g.dft(zda.MON_PLANE).cpu().numpy()])
+        g.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nphi", [11, 24])
+def test_narrow_zone_launch_shapes_are_bitwise_identical(zda, nphi):
+    """A narrow wedge gives the same bits on the 13-row two-step kernel, the
+    flat-mapped fused step and the flat-mapped two-step kernel, with any
+    chunk depth, with non-temporal stores and with the XCD tile order (an
+    odd step count: the two-step runs end with one fused step)."""
+    from paper_2501_07979_amd.workloads import Workload
+    wl = Workload("narrow_determinism", r_in=600.0, nr=45, nphi=nphi, nz=41,
+                  n_fold=360 * 11 // nphi, m=1, pml=(5, 6, 4, 7), k_src=9, k_mon=30, design=(12, 17), k_sub=12,
+                  steps=121, omegas=(0.3,), omega_c=0.3, width=6.0)
+    rng = np.random.default_rng(42)
+    eps = (1.0 + 4.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
+    outs = []
+    for kc, tr, opt, val in [(9, 13, 0, 0), (5, 33, 0, 0), (16, 34, 0, 0), (4, 34, 0, 0), (41, 34, 0, 0),
+                             (16, 34, zda.OPT_NT_STORES, 1), (3, 33, zda.OPT_NT_STORES, 1),
+                             (8, 34, zda.OPT_XCD_REMAP, 1)]:
+        _say("narrow determinism", nphi, kc, tr, opt, val)
         g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
         g.set_launch(kc, tr)
         if opt:
