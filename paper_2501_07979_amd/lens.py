@@ -39,8 +39,7 @@ class Lens:
             idx = [q for q, w in enumerate(self.workloads) if is_narrow(w) == narrow]
             if idx:
                 b = zda.Batch([self.zones[q] for q in idx])
-                set_family(b, FLAT if narrow else TWO_STEP, [self.workloads[q] for q in idx],
-                           [self.zones[q] for q in idx])
+                set_family(b, FLAT if narrow else TWO_STEP, [self.workloads[q] for q in idx])
                 self.groups.append((idx, b))
         self.weights = [objective.focal_weights(w, w.omegas, self.focal) for w in self.workloads]
         self.run_kw = dict(nsteps=w0.steps, omegas=w0.omegas, k_src=w0.k_src, omega_c=w0.omega_c, width=w0.width)
@@ -84,15 +83,9 @@ def family_kchunk(fam, w):
     return min(FLAT_KCHUNK, w.nz) if fam == FLAT else None
 
 
-def set_family(batch, fam, wls, zones=()):
-    """Sets a batch of the zones described by wls to launch family fam; the
-    zones (when given) of the flat family store the next time level with
-    non-temporal stores (no block of a launch reads it back): on the 16-zone
-    LWIR-shaped lens 53.6 against 51.3 Gcell-updates/s over 400 steps, a
-    forward + adjoint iteration 2.94 against 3.08 s (same GPU)."""
+def set_family(batch, fam, wls):
+    """Sets a batch of the zones described by wls to launch family fam."""
     kcs = [family_kchunk(fam, w) for w in wls]
-    for z in zones:
-        z.set_option(zda.OPT_NT_STORES, 1 if fam == FLAT else 0)
     batch.set_launch(fam, None if any(k is None for k in kcs) else kcs)
 
 
@@ -152,7 +145,7 @@ def run_in_waves(workloads, nsteps, budget_bytes, tile_rows=None, warmup=0, keep
         wave = [workloads[q] for q in idx]
         zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps()) for w in wave]
         batch = zda.Batch(zones)
-        set_family(batch, fam, wave, zones)
+        set_family(batch, fam, wave)
         srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wave]
         if warmup:
             batch.run(srcs, warmup, wave[0].omegas)
