@@ -245,6 +245,12 @@ def main():
         from paper_2501_07979_amd.workloads import lwir_lens
         wls = lwir_lens()
         cells = sum(w.cells for w in wls)
+        if args.copy_calibration:
+            a = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            b.copy_(a)
+            torch.cuda.synchronize()
+            del a, b
         free, _ = torch.cuda.mem_get_info()
         print("bench: LWIR-shaped lens, %d zones, %d cells" % (len(wls), cells), file=sys.stderr, flush=True)
         _, ms, nwaves = lens.run_in_waves(wls, args.steps, int(0.8 * free), warmup=args.warmup, keep_fields=False)
