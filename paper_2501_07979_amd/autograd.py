@@ -2,13 +2,27 @@
 whose backward is the adjoint FDTD run and the permittivity-gradient overlap
 (hybrid time/frequency adjoint, section on the cylindrical solver of arXiv
 2501.07979; eq. 6 for the design interpolation).  No time history is kept:
-the backward needs only the forward design-volume DFT held by the zone.
+the backward needs only the forward design-volume DFT held by the zone, so a
+backward is refused once the zone has run, or had its design, permittivity
+or fields changed, since the forward it belongs to.
 """
 from __future__ import annotations
 
 import torch
 
 from . import zda
+
+
+class StaleForwardError(RuntimeError):
+    """The zone no longer holds the forward state this backward needs."""
+
+
+def _check_fresh(zone, serial):
+    if zone.state_serial != serial:
+        raise StaleForwardError(
+            "backward of a zone forward run after the zone ran or changed again (serial %d, now %d): the adjoint "
+            "would use the later run's design-volume DFT and permittivity; recompute the forward first"
+            % (serial, zone.state_serial))
 
 
 class ZoneFDTD(torch.autograd.Function):
@@ -21,10 +35,12 @@ class ZoneFDTD(torch.autograd.Function):
         zone.run(volume=True, **run_kw)
         plane = zone.dft(zda.MON_PLANE)
         ctx.zone = zone
+        ctx.serial = zone.state_serial
         return plane
 
     @staticmethod
     def backward(ctx, grad_plane):
+        _check_fresh(ctx.zone, ctx.serial)
         # torch passes 2 conj(dF/dEhat) for a real loss F; the ABI takes dF/dEhat
         g = (grad_plane.conj() * 0.5).to(torch.complex64).contiguous()
         grad_rho = ctx.zone.adjoint_grad(g)
@@ -48,14 +64,16 @@ class BatchFDTD(torch.autograd.Function):
                    for _ in batch.zones]
         batch.run(sources, run_kw["nsteps"], run_kw["omegas"], volume=True)
         ctx.batch = batch
+        ctx.serials = [z.state_serial for z in batch.zones]
         return tuple(z.dft(zda.MON_PLANE) for z in batch.zones)
 
     @staticmethod
     def backward(ctx, *grad_planes):
+        for z, s in zip(ctx.batch.zones, ctx.serials):
+            _check_fresh(z, s)
         gs = [(g.conj() * 0.5).to(torch.complex64).contiguous() for g in grad_planes]
         return (None, None, *ctx.batch.adjoint_grad(gs))
 
 
 def batch_fdtd(rhos, batch, **run_kw):
     return BatchFDTD.apply(batch, run_kw, *rhos)
-

@@ -171,6 +171,9 @@ class Zone:
         ptr, on_dev, keep = self._in_ptr(torch, eps, torch.float32)
         _check(lib.zda_zone_create(ctypes.byref(desc), ptr, on_dev, ctypes.byref(h)))
         self._h = h
+        # advanced by every call that changes what an adjoint run would use
+        # (permittivity, design, fields, forward monitors)
+        self.state_serial = 0
         del keep
 
     def close(self):
@@ -213,11 +216,13 @@ class Zone:
     def set_eps(self, eps):
         torch = _torch()
         ptr, dev, keep = self._in_ptr(torch, eps, torch.float32)
+        self.state_serial += 1
         _check(load().zda_zone_set_eps(self._h, ptr, dev))
 
     def set_design(self, rho):
         torch = _torch()
         ptr, dev, keep = self._in_ptr(torch, rho, torch.float32)
+        self.state_serial += 1
         _check(load().zda_zone_set_design(self._h, ptr, dev))
 
     def run(self, nsteps, omegas=(), *, kind=SRC_PLANE_CIRC, k_src=1, omega_c=0.0, width=1.0, n0=-1,
@@ -242,6 +247,7 @@ class Zone:
         om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, np.float64)))
         flags = (DFT_PLANE if plane else 0) | (DFT_VOLUME if volume else 0) | (RUN_CONTINUE if cont else 0) | \
             (RUN_TIMING if timing else 0)
+        self.state_serial += 1
         _check(load().zda_fdtd_run(self._h, ctypes.byref(s), int(nsteps), ctypes.c_void_p(om.ctypes.data),
                                    int(om.size), flags, _stream_ptr(torch, stream)))
         self._K = int(om.size)
@@ -286,6 +292,7 @@ class Zone:
         torch = _torch()
         t = value if isinstance(value, torch.Tensor) else torch.as_tensor(np.asarray(value, np.complex64))
         t = t.to(device="cuda", dtype=torch.complex64).contiguous()
+        self.state_serial += 1
         _check(load().zda_zone_write_field(self._h, COMP[name], ctypes.c_void_p(t.data_ptr()), 1))
 
 
@@ -328,6 +335,8 @@ class Batch:
         torch = _torch()
         om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, np.float64)))
         flags = (DFT_PLANE if plane else 0) | (DFT_VOLUME if volume else 0)
+        for z in self.zones:
+            z.state_serial += 1
         _check(load().zda_batch_run(self._h, self._sources(sources), int(nsteps), ctypes.c_void_p(om.ctypes.data),
                                     int(om.size), flags, _stream_ptr(torch, stream)))
         for z in self.zones:

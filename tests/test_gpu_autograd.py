@@ -45,3 +45,28 @@ def test_autograd_focal_objective_matches_oracle(oracle_mod):
     _say("autograd gradient rel L2 vs oracle = %.3e" % err)
     assert err <= 1e-4
     zone.close()
+
+
+def test_autograd_refuses_a_stale_forward():
+    """Two forward runs on one zone, then the first one's backward: the zone
+    holds only the second run's state, so the backward must raise."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_07979_amd import zda
+    from paper_2501_07979_amd.autograd import StaleForwardError, zone_fdtd
+    from paper_2501_07979_amd.workloads import c3_small
+
+    wl = c3_small()
+    zone = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps(wl.rho()))
+    kw = dict(nsteps=200, omegas=wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+    r1 = torch.tensor(wl.rho(), device="cuda", requires_grad=True)
+    r2 = torch.tensor(1.0 - wl.rho(), device="cuda", requires_grad=True)
+    _say("two forwards, then the first backward")
+    p1 = zone_fdtd(r1, zone, **kw)
+    p2 = zone_fdtd(r2, zone, **kw)
+    with pytest.raises(StaleForwardError):
+        p1.abs().pow(2).sum().backward()
+    p2.abs().pow(2).sum().backward()
+    assert r2.grad is not None and torch.isfinite(r2.grad).all()
+    zone.close()
