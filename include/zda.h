@@ -20,9 +20,16 @@
  *    device, otherwise host pointers.  Input buffers are copied; the caller
  *    keeps ownership of everything it passes.  The zone owns all its device
  *    memory and frees it in zda_zone_destroy.
- *  - Calls that take a `stream` (a hipStream_t, NULL = default stream) are
- *    asynchronous on it unless they read into host memory.  Calls on one
- *    zone must not overlap; different zones are independent.
+ *  - Every zone has a stream (a hipStream_t, NULL = the default stream):
+ *    the stream of its last zda_fdtd_run / zda_adjoint_grad, or the one given
+ *    to zda_zone_set_stream.  Calls that take a `stream` make it the zone's
+ *    stream.  All work of a zone is ordered on its stream and asynchronous;
+ *    a call waits for the stream only when it reads into host memory, takes
+ *    host input that it must copy before returning, or is zda_zone_sync.
+ *    Device inputs must stay valid until the stream has consumed them.
+ *    Calls on one zone must not overlap; different zones are independent.
+ *  - Device memory is allocated with hipMalloc, or through the functions
+ *    registered with zda_set_allocator.
  *  - Every call returns a zda_status; no exception or abort crosses the ABI.
  *    zda_last_error() gives a message for the last failure on the calling
  *    thread.
@@ -79,11 +86,35 @@ typedef struct {
 typedef struct zda_zone zda_zone;
 
 /* Fill *d with defaults (PML 8 cells everywhere, order 3, alpha 0.05,
- * courant 0.5, eps_bg 1, eps_hi 6.25); sizes are left zero. */
+ * courant 0.5, eps_bg 1, eps_hi 6.25); sizes are left zero.  The zone's
+ * parameters are those of the Fig. 2 caption (radii, wedge angle, height,
+ * steps); the PML constants are this library's reading of the section on
+ * the cylindrical solver, which says only that stretched-coordinate PMLs
+ * surround the zone in r and z. */
 void zda_zone_desc_default(zda_zone_desc *d);
 
 /*
- * Zones of the first radial band (the paper's zone 1 and its neighbours):
+ * Device allocator for zone and batch memory, so that a host framework's
+ * caching allocator can back it.  alloc_fn(bytes, device, ctx) returns a
+ * device pointer on `device` (the zone's device, current when it is called)
+ * or NULL (the call that needed it fails with ZDA_ERR_OOM); free_fn(ptr,
+ * bytes, device, ctx) takes back what alloc_fn gave.  Both NULL restores
+ * hipMalloc / hipFree; one NULL is ZDA_ERR_ARG.  Process-wide: zones and
+ * batches created afterwards use it (each keeps the pair it was created
+ * with and frees through it, in zda_zone_destroy or when a buffer grows; the
+ * library first waits for the zone's stream, so nothing in flight reads the
+ * memory it hands back).  Called on the thread that calls the library.
+ * Pinned host staging buffers, streams and events do not go through it.
+ */
+typedef void *(*zda_alloc_fn)(size_t bytes, int device, void *ctx);
+typedef void (*zda_free_fn)(void *ptr, size_t bytes, int device, void *ctx);
+zda_status zda_set_allocator(zda_alloc_fn alloc_fn, zda_free_fn free_fn, void *ctx);
+
+/*
+ * Create a zone (section "Zoned discrete axisymmetry"; Fig. 2 caption).
+ * Zones of the first radial band (the paper's zone 1 and its neighbours;
+ * the section on the cylindrical solver closes the lens centre with loop
+ * integrals and puts only an outer r-PML on the zone that holds r = 0):
  *  - axis = 1: the axis is the radial half-point r_{-1/2} = 0, so
  *    r_in = dr / 2 and nothing is stored on it.  The z components there are
  *    single-valued scalars, which the Bloch condition forces to zero unless
@@ -105,15 +136,37 @@ void zda_zone_desc_default(zda_zone_desc *d);
 zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_device,
                            zda_zone **out);
 
-/* NULL-safe; waits for the zone's work to finish. */
+/* NULL-safe; waits for the device to finish the zone's work, then frees its
+ * memory. */
 void zda_zone_destroy(zda_zone *z);
 
-/* Replace the permittivity (nz*nr*nphi FP32).  Synchronous. */
+/* Replace the permittivity map of the zone (Fig. 2 caption: a zone carries its
+ * eps map; one eps per cell, applied to the cell's three E samples):
+ * nz*nr*nphi FP32 [k][i][j] (NULL: eps = 1).  Ordered on the zone's stream;
+ * host input is copied before the call returns (it waits for the stream). */
 zda_status zda_zone_set_eps(zda_zone *z, const float *eps, int on_device);
 
 /* eq. (6) inside the design layer: rho is (design_k1-design_k0)*nr*nphi FP32
- * in [0, 1] (values are not clamped).  Synchronous. */
+ * in [0, 1] (values are not clamped), eps = eps_bg + rho (eps_hi - eps_bg).
+ * Ordered on the zone's stream; host input is copied before the call
+ * returns. */
 zda_status zda_zone_set_design(zda_zone *z, const float *rho, int on_device);
+
+/* Make `stream` the zone's stream (see the conventions above).  The next
+ * call that takes a stream replaces it. */
+zda_status zda_zone_set_stream(zda_zone *z, void *stream);
+
+/*
+ * Wait for the zone's stream.  Returns ZDA_ERR_DIVERGED if a divergence check
+ * since the last run that reset the zone found a field sample that is not
+ * finite or whose magnitude exceeds 1e18 (the regularised r-PML of the
+ * section on the cylindrical solver exists because unregularised layers
+ * diverge; the checks catch a run that does anyway).  Checks run inside the
+ * time loop every ZDA_OPT_WATCHDOG steps (all six fields) and on every
+ * monitor that zda_dft_fields reads; calls into host memory report the flag
+ * themselves.
+ */
+zda_status zda_zone_sync(zda_zone *z);
 
 /* Source presets (the normally incident plane wave decomposes into m = +-1,
  * section "Results and Discussion"). */
@@ -150,11 +203,20 @@ typedef struct {
 #define ZDA_RUN_TIMING   8    /* bracket every update kernel with HIP events (zda_zone_last_timing) */
 
 /*
- * Time-step nsteps leap-frog steps (H half-step then E half-step with the
- * source) and accumulate Ehat(w_k) = dt sum_{n=1..T} E^n e^{i w_k n dt} for
- * K <= ZDA_MAX_FREQ angular frequencies omega[] (host).  Resets fields,
- * auxiliaries and DFTs first unless ZDA_RUN_CONTINUE.  Asynchronous on
- * `stream`.  Errors: ZDA_ERR_ARG, ZDA_ERR_HIP.
+ * The time loop (section on the cylindrical solver: Yee leap-frog of eq. 3-5
+ * on the staggered grid, PMLs in r and z; the DTFT monitors of its adjoint
+ * paragraph, all frequencies extracted in one run).  Time-steps nsteps
+ * leap-frog steps (H half-step, then E half-step with the soft source sheet)
+ * and accumulates Ehat(w_k) = dt sum_{n=1..T} E^n e^{i w_k n dt} for
+ * K <= ZDA_MAX_FREQ angular frequencies omega[] (host) on the monitors that
+ * dft_flags selects.  Resets fields, auxiliaries, DFTs and the divergence
+ * flag first unless ZDA_RUN_CONTINUE (then the monitors keep accumulating and
+ * the pulse continues from the zone's step count).  Asynchronous on `stream`
+ * (the zone's stream from then on); host arrays (omega, profiles, host
+ * patterns) are copied before the call returns.  Errors: ZDA_ERR_ARG,
+ * ZDA_ERR_STATE (ZDA_DFT_VOLUME without a design layer), ZDA_ERR_UNSUPPORTED
+ * (preset and m disagree; axis zone with seam phase 1), ZDA_ERR_OOM,
+ * ZDA_ERR_HIP.  Divergence is reported by zda_zone_sync.
  */
 zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const double *omega, int K,
                         int dft_flags, void *stream);
@@ -164,13 +226,25 @@ zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const doub
 #define ZDA_MON_VOLUME 1      /* layout [K][3][design_k1-design_k0][nr][nphi] complex */
 #define ZDA_MON_ADJOINT_VOLUME 2  /* same layout, the adjoint run's volume DFT */
 
+/* component_mask bits of zda_dft_fields (0 selects every component) */
+#define ZDA_COMP_R   1        /* E_r */
+#define ZDA_COMP_PHI 2        /* E_phi */
+#define ZDA_COMP_Z   4        /* E_z (design-layer monitors only) */
+
 /*
- * Copy a DFT monitor into out (out_floats floats available; interleaved
- * complex on the native staggered points).  Synchronises if out is host
- * memory.  ZDA_ERR_ARG if out is too small, ZDA_ERR_STATE if the monitor was
- * not accumulated by the last run.
+ * Read a DFT monitor (the frequency-domain fields of the hybrid
+ * time/frequency adjoint, section on the cylindrical solver) into out:
+ * interleaved complex FP32 on the native staggered points, layout
+ * [K][selected components, in the order r, phi, z][plane or layer volume],
+ * out_floats floats available.  Ordered on the zone's stream; waits for it
+ * only if out is host memory, and then returns ZDA_ERR_DIVERGED (the data
+ * is still copied) if the divergence flag is set.  The monitor is scanned
+ * for non-finite values on the way (raising the flag).  ZDA_ERR_ARG if out
+ * is too small or the mask names a component the monitor lacks,
+ * ZDA_ERR_STATE if the monitor was not accumulated by the last run.
  */
-zda_status zda_dft_fields(zda_zone *z, int monitor, float *out, size_t out_floats, int out_on_device);
+zda_status zda_dft_fields(zda_zone *z, int monitor, int component_mask, float *out, size_t out_floats,
+                          int out_on_device);
 
 /*
  * Adjoint gradient (hybrid time/frequency adjoint with broadband adjoint
@@ -183,19 +257,24 @@ zda_status zda_dft_fields(zda_zone *z, int monitor, float *out, size_t out_float
  * grad_rho[(design_k1-design_k0)*nr*nphi] = dF/drho =
  * (eps_hi - eps_bg) sum_k sum_alpha 2 Re[wt_k^2 W Xhat Ehat].  adj_width <= 0
  * reuses the forward pulse width (and n0).  Requires a forward run with
- * ZDA_DFT_VOLUME (ZDA_ERR_STATE otherwise).  Synchronises if grad_rho is
- * host memory.
+ * ZDA_DFT_VOLUME (ZDA_ERR_STATE otherwise).  Asynchronous on `stream` (the
+ * zone's stream from then on); a host dF_dE is copied before the call
+ * returns; a host grad_rho makes the call wait and report ZDA_ERR_DIVERGED
+ * if the divergence flag is set.
  */
 zda_status zda_adjoint_grad(zda_zone *z, const float *dF_dE, int dF_on_device, float *grad_rho,
                             int grad_on_device, double adj_width, void *stream);
 
-/* Raw field access (testing and checkpoints).  comp: 0..5 = E_r, E_phi, E_z,
- * H_r, H_phi, H_z; buffer nz*nr*nphi complex.  Writing E_phi also seeds the
- * r-layer's integrated-field auxiliary as the first step expects.
- * Synchronous. */
+/* Raw access to the Yee fields of eq. (3)-(5) (testing and checkpoints).
+ * comp: 0..5 = E_r, E_phi, E_z, H_r, H_phi, H_z; buffer nz*nr*nphi complex.
+ * Writing E_phi also seeds the r-layer's integrated-field auxiliary as the
+ * first step expects.  Ordered on the zone's stream; waits for it when the
+ * buffer is host memory. */
 zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_device);
 zda_status zda_zone_write_field(zda_zone *z, int comp, const float *in, int in_on_device);
 
+/* Sizes and stability margin of a zone (the Courant bound of the Yee scheme,
+ * section on the cylindrical solver). */
 typedef struct {
     size_t cells;             /* nr*nphi*nz */
     size_t device_bytes;      /* owned device memory */
@@ -206,7 +285,9 @@ typedef struct {
     int tile_rows;            /* radial rows per thread block */
 } zda_zone_info;
 
-/* Launch shape of the update kernels: each thread marches kchunk z-planes of
+/* Launch shape of the update kernels of the leap-frog (eq. 3-5; the paper's
+ * own solver is a GPU FDTD, section on the cylindrical solver; shapes are
+ * this library's): each thread marches kchunk z-planes of
  * one (r, phi) column.  tile_rows in {3, 7, 15} selects the fused one-launch
  * step (a block owns tile_rows radial rows x 56 phi cells; needs the second
  * buffer set), tile_rows in {5, 13} the two-step kernel (two time steps per
@@ -260,11 +341,15 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
  * so that its long r-band tiles do not leave most CUs idle; 0: the zone's
  * kchunk. */
 #define ZDA_OPT_LAYER_KCHUNK 5
+/* ZDA_OPT_WATCHDOG: steps between the in-loop divergence checks of all six
+ * fields (default 1000; 0 = off; see zda_zone_sync). */
+#define ZDA_OPT_WATCHDOG 6
 zda_status zda_zone_set_option(zda_zone *z, int option, int value);
 
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);
 
-/* Per-kernel device time of the last zda_fdtd_run made with ZDA_RUN_TIMING
+/* Per-kernel device time of the leap-frog's update kernels (eq. 3-5) in the
+ * last zda_fdtd_run made with ZDA_RUN_TIMING
  * (HIP events on the run's stream around each launch).  Split kernels: h and
  * e per step; fused step: e per step; two-step kernel: e = the launch over
  * interior tiles (no layer cells), layer = the launch over the other tiles,
@@ -283,7 +368,8 @@ typedef struct {
 
 zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
 
-/* The two-step kernel's launch plan for a zone described by d, computed on
+/* The two-step kernel's launch plan (two leap-frog steps of eq. 3-5 per
+ * launch, temporal blocking of this library) for a zone described by d, computed on
  * the host (no device is touched; a zone created from d with the same
  * tile_rows, kchunk and tile order runs exactly these tiles).  tile_rows: 5,
  * 13 or 34 (flat mapping: tiles own 256 / nphi - 3 rows and every phi cell,
@@ -306,7 +392,8 @@ zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kc
 
 /*
  * Batches: many zones of uneven size (the lens-scale schedule in which n
- * grows with radius) stepped together -- one launch per time step (fused
+ * grows with radius: section "Zoned discrete axisymmetry", and the zone
+ * count of the section on the LWIR metalens) stepped together -- one launch per time step (fused
  * kernels, when every zone has its second buffer set) or two (split), whose
  * 1-D grid covers the tiles of every zone through a device zone table, with
  * the time loop captured once into a HIP graph and replayed.  A batch does
@@ -317,27 +404,33 @@ typedef struct zda_batch zda_batch;
 zda_status zda_batch_create(zda_zone *const *zones, int nzones, zda_batch **out);
 void zda_batch_destroy(zda_batch *b);
 
-/* Forward run of every zone: sources[i] is zone i's source; nsteps, omega[K]
- * and dft_flags (no ZDA_RUN_TIMING) are shared.  Same results as running the
- * zones one by one with zda_fdtd_run. */
+/* Forward run of every zone (the zones are independent simulations,
+ * section "Zoned discrete axisymmetry"): sources[i] is zone i's source;
+ * nsteps, omega[K] and dft_flags (no ZDA_RUN_TIMING) are shared.  Same
+ * results as running the zones one by one with zda_fdtd_run.  Waits for
+ * `stream` before it returns. */
 zda_status zda_batch_run(zda_batch *b, const zda_source *sources, int nsteps, const double *omega, int K,
                          int dft_flags, void *stream);
 
-/* Adjoint gradients of every zone in one batched adjoint run; dF_dE[i] and
- * grad_rho[i] are device pointers with the layouts of zda_adjoint_grad.
- * Every zone needs a forward run with ZDA_DFT_VOLUME of the same length. */
+/* Adjoint gradients of every zone in one batched adjoint run (one forward
+ * and one adjoint simulation per iteration, section on the poly-achromatic
+ * lenses); dF_dE[i] and grad_rho[i] are device pointers with the layouts of
+ * zda_adjoint_grad.  Every zone needs a forward run with ZDA_DFT_VOLUME of
+ * the same length.  Waits for `stream` before it returns. */
 zda_status zda_batch_adjoint_grad(zda_batch *b, const float *const *dF_dE, float *const *grad_rho, void *stream);
 
-/* Launch shape shared by the batched kernels (tile_rows as in
+/* Launch shape shared by the batched kernels of the leap-frog (eq. 3-5;
+ * tile_rows as in
  * zda_zone_set_launch) and per-zone z-chunk depth kchunk[nzones] (NULL keeps
  * each zone's; the flat two-step kernel, 34, wants chunks of 12 to 64 planes,
  * far deeper than the 2 that narrow zones keep for their default in-place
  * kernels).  Errors as for zda_zone_set_launch, for any zone. */
 zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk);
 
-/* Autotuner: times short probe runs (probe_steps >= 2; the zones' state is
- * reset) of every kernel family and tile shape, then of z-chunk depths per
- * size class of zones, keeps the fastest and reports it. */
+/* Autotuner of the batched leap-frog (eq. 3-5): times short probe runs
+ * (probe_steps >= 2; the zones' state is reset) of every kernel family and
+ * tile shape, then of z-chunk depths per size class of zones, keeps the
+ * fastest and reports it. */
 typedef struct {
     int tile_rows;
     double ms_per_step;
@@ -347,6 +440,8 @@ typedef struct {
 zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe_steps, const double *omega, int K,
                               void *stream, zda_tune_result *res);
 
+/* Text of a status code, and the message of the last failure on the calling
+ * thread (thread-local; valid until the next failing call on the thread). */
 const char *zda_status_str(int status);
 const char *zda_last_error(void);
 

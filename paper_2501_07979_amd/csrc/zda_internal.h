@@ -125,6 +125,7 @@ void launch_advance_step(int *n_base, int by, hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);
 void launch_design_dt(float *ceps, const float *rho, size_t n, double eps_bg, double eps_hi, double dt,
                       hipStream_t s);
+// ceps = dt / eps elementwise (eps may alias ceps; NULL eps means eps = 1)
 void launch_inv_eps(float *ceps, const float *eps, size_t n, double dt, hipStream_t s);
 void launch_seed_u(float2 *aux_u, const float2 *Ep, int nr, int nphi, int nz, int pr0, int pr1, float dt,
                    hipStream_t s);
@@ -133,5 +134,15 @@ void launch_adjoint_pattern(float2 *pat, const float2 *dFdE, const float2 *fac, 
 void launch_overlap(float *grad, const float2 *fwd, const float2 *adj, const float2 *wr, const float2 *wz,
                     int K, int nd, int nr, int nphi, float scale, hipStream_t s);
 void launch_nonfinite(const float2 *p, size_t n, int *flag, hipStream_t s);
+// Divergence watchdog over up to six field arrays of n samples each (NULL
+// entries skipped): *flag = 1 where a sample is not finite or |F|^2 is not
+// below bound2.  The flag is never cleared here.
+struct WatchArgs {
+    const float2 *f[6];
+    size_t n;
+    int *flag;
+    float bound2;
+};
+void launch_watch(const WatchArgs &w, hipStream_t s);
 
 }  // namespace zda

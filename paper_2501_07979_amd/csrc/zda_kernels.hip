@@ -1398,7 +1398,7 @@ __global__ void fill_kernel(float2 *p, size_t n)
 __global__ void inv_eps_kernel(float *ceps, const float *eps, size_t n, double dt)
 {
     size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) ceps[q] = (float)(dt / (double)eps[q]);
+    if (q < n) ceps[q] = (float)(dt / (eps ? (double)eps[q] : 1.0));
 }
 
 // eq. (6): eps = eps_bg + rho (eps_hi - eps_bg), rounded to FP32, then dt/eps
@@ -1463,6 +1463,24 @@ __global__ void nonfinite_kernel(const float2 *p, size_t n, int *flag)
     for (; q < n; q += stride) {
         float2 v = p[q];
         if (!isfinite(v.x) || !isfinite(v.y)) *flag = 1;
+    }
+}
+
+// every thread scans a grid-strided share of each array; the first sample out
+// of bounds (a NaN fails the comparison) raises the flag and ends the thread
+__global__ void watch_kernel(WatchArgs w)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (int c = 0; c < 6; ++c) {
+        const float2 *p = w.f[c];
+        if (!p) continue;
+        for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < w.n; q += stride) {
+            const float2 v = p[q];
+            if (!(v.x * v.x + v.y * v.y < w.bound2)) {
+                *w.flag = 1;
+                return;
+            }
+        }
     }
 }
 
@@ -1667,6 +1685,14 @@ void launch_overlap(float *grad, const float2 *fwd, const float2 *adj, const flo
 {
     hipLaunchKernelGGL(overlap_kernel, dim3((nphi + 63) / 64, nr, nd), dim3(64), 0, s, grad, fwd, adj, wr, wz, K,
                        nd, nr, nphi, scale);
+}
+
+void launch_watch(const WatchArgs &w, hipStream_t s)
+{
+    if (w.n == 0) return;
+    size_t blocks = (w.n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(watch_kernel, dim3((unsigned)blocks), dim3(256), 0, s, w);
 }
 
 void launch_nonfinite(const float2 *p, size_t n, int *flag, hipStream_t s)

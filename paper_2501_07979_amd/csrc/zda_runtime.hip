@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <array>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -63,6 +64,149 @@ double grade(double p, int n, int d0, int d1, double order, double smax)
     return rho > 0.0 ? smax * std::pow(rho, order) : 0.0;
 }
 
+// The device allocator registered with zda_set_allocator (NULL functions:
+// hipMalloc / hipFree).  Zones and batches copy it when they are created.
+struct Allocator {
+    zda_alloc_fn alloc = nullptr;
+    zda_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+Allocator current_allocator()
+{
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    return g_alloc;
+}
+
+// Device memory owned by one zone or batch: every buffer with its size,
+// returned through the allocator that made it.
+struct DevMem {
+    Allocator al;
+    int device = 0;
+    std::vector<std::pair<void *, size_t>> live;
+    size_t bytes = 0;
+
+    void *get(size_t n)
+    {
+        void *p = nullptr;
+        if (al.alloc) {
+            p = al.alloc(n, device, al.ctx);
+        } else if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        if (p) {
+            live.push_back({p, n});
+            bytes += n;
+        }
+        return p;
+    }
+    void release(void *p, size_t n)
+    {
+        if (al.free) al.free(p, n, device, al.ctx);
+        else (void)hipFree(p);
+    }
+    void put(void *p)
+    {
+        if (!p) return;
+        for (size_t q = 0; q < live.size(); ++q)
+            if (live[q].first == p) {
+                release(p, live[q].second);
+                bytes -= live[q].second;
+                live[q] = live.back();
+                live.pop_back();
+                return;
+            }
+    }
+    void put_all()
+    {
+        for (auto &e : live) release(e.first, e.second);
+        live.clear();
+        bytes = 0;
+    }
+};
+
+// Pinned host staging of one zone's (or batch's) uploads: a ring of slots,
+// each rewritten only after the copies that read it last (marked by its
+// event) have run, so a call never waits for the work of the call before.
+struct Stage {
+    static constexpr int N = 6;
+    void *buf[N] = {};
+    size_t cap[N] = {};
+    hipEvent_t ev[N] = {};
+    bool pending[N] = {};
+    int next = 0, cur = -1;
+
+    // a slot of at least n bytes that is free for writing
+    void *take(size_t n)
+    {
+        const int q = next;
+        next = (next + 1) % N;
+        if (pending[q]) {
+            if (hipEventSynchronize(ev[q]) != hipSuccess) return nullptr;
+            pending[q] = false;
+        }
+        if (!ev[q] && hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) != hipSuccess) return nullptr;
+        if (cap[q] < n) {
+            if (buf[q]) (void)hipHostFree(buf[q]);
+            buf[q] = nullptr;
+            cap[q] = 0;
+            const size_t want = std::max(n, (size_t)1 << 16);
+            if (hipHostMalloc(&buf[q], want, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                buf[q] = nullptr;
+                return nullptr;
+            }
+            cap[q] = want;
+        }
+        cur = q;
+        return buf[q];
+    }
+    // the copies just enqueued on s read the slot taken last
+    hipError_t issued(hipStream_t s)
+    {
+        if (cur < 0) return hipSuccess;
+        hipError_t e = hipEventRecord(ev[cur], s);
+        pending[cur] = e == hipSuccess;
+        cur = -1;
+        return e;
+    }
+    void destroy()
+    {
+        for (int q = 0; q < N; ++q) {
+            if (pending[q]) (void)hipEventSynchronize(ev[q]);
+            if (buf[q]) (void)hipHostFree(buf[q]);
+            if (ev[q]) (void)hipEventDestroy(ev[q]);
+            buf[q] = nullptr;
+            ev[q] = nullptr;
+            cap[q] = 0;
+            pending[q] = false;
+        }
+    }
+};
+
+// Tile counts of a two-step tile list (interior tiles first, then the layer
+// tiles by instantiation) and the cells the interior tiles own.
+struct TileCounts {
+    unsigned n_lay[4] = {0, 0, 0, 0};
+    size_t cells = 0, mon = 0, src = 0;
+};
+
+// Device buffers one run stages its inputs in: the zone's own (grown on
+// demand), or slices of the library's static scratch array for the entry
+// point that allocates nothing.
+struct RunBufs {
+    bool noalloc = false;
+    float2 *pattern = nullptr, *profile = nullptr, *twiddle = nullptr;
+    uint4 *tiles = nullptr;
+    size_t cap_pattern = 0, cap_profile = 0, cap_twiddle = 0, cap_tiles = 0;   // noalloc: slice sizes
+};
+
+// watchdog bound on |F|^2 (|F| = 1e18; FP32 squares overflow near 1.8e19)
+constexpr float WATCH_BOUND2 = 1e36f;
+
 }  // namespace
 
 struct zda_zone {
@@ -74,6 +218,11 @@ struct zda_zone {
     // FP64 layer constants: [0] integer points, [1] half points
     std::vector<double> sig_r[2], Sig_r[2], sgt_r[2], sig_z[2];
     double cr = 1, cz = 1;
+    DevMem mem;
+    Stage stage;
+    // the stream the zone's work is ordered on: the stream of its last run,
+    // or the one given to zda_zone_set_stream
+    hipStream_t stream = nullptr;
     // device memory
     // two buffer sets of the six fields and the PML auxiliaries: the split
     // kernels update set `cur` in place, the fused kernel steps cur -> cur^1
@@ -87,6 +236,7 @@ struct zda_zone {
     int xcd_remap = 0, nt_stores = 1, layer_stream = 0;
     int tile_patch = 0;            // (bands << 8) | columns of an XCD's patch of two-step tiles, 0 = off
     int layer_kchunk = -1;         // planes per chunk of the r-layer band tiles (-1: automatic)
+    int watch_every = 1000;        // steps between in-loop divergence checks (0: off)
     int tiles_lkc = -2;
     // second stream and join events for the concurrent layer-tile launch
     hipStream_t s2 = nullptr;
@@ -97,18 +247,19 @@ struct zda_zone {
     uint4 *tiles2 = nullptr;
     size_t cap_tiles2 = 0;
     bool has_m = false;
-    unsigned n_int = 0, n_pml = 0, n_lay[4] = {0, 0, 0, 0};
+    TileCounts tc;
     int tiles_tr = 0, tiles_kc = 0, tiles_src = -1, k_src_last = -1, tiles_xcd = -1;
-    size_t int_cells = 0, int_mon_cells = 0, int_src_cells = 0;
     RowCoef *rows = nullptr;
     ZCoef *zrows = nullptr;
     float2 *dft_plane = nullptr, *dft_vol = nullptr, *dft_vol_adj = nullptr;
     float2 *pattern = nullptr, *profile = nullptr, *twiddle = nullptr, *scratch = nullptr;
     size_t cap_pattern = 0, cap_profile = 0, cap_twiddle = 0, cap_scratch = 0;
-    int *flag = nullptr;
-    size_t bytes = 0;
-    // host staging (kept until the next call)
-    std::vector<float2> st_pat, st_prof, st_tw, st_misc;
+    int pattern_key = 0;           // preset pattern held in `pattern` (0: none)
+    int *flag = nullptr;           // sticky divergence flag (device)
+    int *flag_host = nullptr;      // pinned mirror, refreshed by the copies enqueued after runs and reads
+    // host staging of the entry point that allocates nothing (pageable)
+    std::vector<float2> st_pat, st_prof, st_tw;
+    std::vector<uint4> st_tiles;
     // state of the last forward run
     int n_done = 0;
     int last_K = 0;
@@ -122,6 +273,7 @@ struct zda_zone {
     int timed_steps = 0;
     bool timed_fused = false;
     bool timed_two = false;
+    TileCounts timed_tc;
 };
 
 namespace {
@@ -130,21 +282,37 @@ template <typename T>
 zda_status dev_alloc(zda_zone *z, T **p, size_t count)
 {
     if (count == 0) { *p = nullptr; return ZDA_OK; }
-    void *q = nullptr;
-    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ZDA_ERR_OOM, "hipMalloc of %zu bytes failed", count * sizeof(T));
-    }
+    void *q = z->mem.get(count * sizeof(T));
+    if (!q) return fail(ZDA_ERR_OOM, "device allocation of %zu bytes failed", count * sizeof(T));
     *p = (T *)q;
-    z->bytes += count * sizeof(T);
     return ZDA_OK;
+}
+
+template <typename T>
+void dev_free(zda_zone *z, T *&p)
+{
+    z->mem.put((void *)p);
+    p = nullptr;
+}
+
+// wait for everything the zone has enqueued (its stream and the layer stream)
+hipError_t zone_wait(zda_zone *z)
+{
+    hipError_t e = hipStreamSynchronize(z->stream);
+    if (e == hipSuccess && z->s2) e = hipStreamSynchronize(z->s2);
+    return e;
 }
 
 template <typename T>
 zda_status ensure(zda_zone *z, T **p, size_t *cap, size_t count)
 {
     if (count <= *cap) return ZDA_OK;
-    if (*p) { (void)hipFree(*p); z->bytes -= *cap * sizeof(T); *p = nullptr; *cap = 0; }
+    if (*p) {
+        // work already enqueued may still read the old buffer
+        HIP_TRY(zone_wait(z));
+        dev_free(z, *p);
+        *cap = 0;
+    }
     zda_status st = dev_alloc(z, p, count);
     if (st == ZDA_OK) *cap = count;
     return st;
@@ -157,12 +325,16 @@ void free_all(zda_zone *z)
     if (z->ev_fork) (void)hipEventDestroy(z->ev_fork);
     if (z->ev_join) (void)hipEventDestroy(z->ev_join);
     if (z->s2) (void)hipStreamDestroy(z->s2);
-    for (auto &set : z->F)
-        for (auto &f : set) if (f) (void)hipFree(f);
-    void *ptrs[] = {z->ceps, z->auxR[0], z->auxZ[0], z->auxR[1], z->auxZ[1], z->rows, z->zrows, z->dft_plane,
-                    z->dft_vol, z->dft_vol_adj, z->pattern, z->profile, z->twiddle, z->scratch, z->flag,
-                    z->mauxR, z->mauxZ, z->tiles2};
-    for (void *p : ptrs) if (p) (void)hipFree(p);
+    z->stage.destroy();
+    if (z->flag_host) (void)hipHostFree(z->flag_host);
+    z->flag_host = nullptr;
+    z->mem.put_all();
+}
+
+// refresh the pinned mirror of the divergence flag behind the work on s
+hipError_t post_flag(zda_zone *z, hipStream_t s)
+{
+    return hipMemcpyAsync(z->flag_host, z->flag, sizeof(int), hipMemcpyDeviceToHost, s);
 }
 
 // s(w) = 1 + sigma F(w), F = dt / (1 - c e^{i w dt})
@@ -292,6 +464,7 @@ zda_status reset_state(zda_zone *z, hipStream_t s)
     }
     if (z->mauxR) launch_fill(z->mauxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, s);
     if (z->mauxZ) launch_fill(z->mauxZ, (size_t)N_AUX_Z * z->dZ * z->plane, s);
+    if (z->flag) launch_set_int(z->flag, 0, s);
     z->cur = 0;
     HIP_TRY(hipGetLastError());
     z->n_done = 0;
@@ -308,53 +481,67 @@ double pulse_at(long n, double dt, double wc, double w, int n0)
 
 int default_n0(double w, double dt) { return (int)std::lround(6.0 * w / dt); }
 
-// Core time loop: P source patterns already on the device in z->pattern,
-// host complex profiles prof[p*nsteps + n], K frequencies.
 // Upload one run's source profiles and DFT twiddles (after the reset, if
 // asked) and fill the step arguments of the two buffer parities (ab[0] = the
-// zone's current set).
+// zone's current set).  P source patterns are already on the device at
+// rb.pattern; prof[p * nsteps + n] are the host complex profiles.
 zda_status prepare_run(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *prof, const double *omega, int K,
-                       float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, StepArgs ab[2])
+                       float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, StepArgs ab[2],
+                       const RunBufs &rb)
 {
     // next to the axis the z components there are single-valued scalars; they
     // vanish (and the scheme holds) only when the seam phase is not 1
     if (z->d.axis && (z->d.n_fold > 0 ? m % z->d.n_fold == 0 : m == 0))
         return fail(ZDA_ERR_UNSUPPORTED, "axis zone with seam phase 1 (m = %d): the axis scalars do not vanish", m);
     const size_t T = (size_t)std::max(nsteps, 1);
+    const size_t nprof = T * std::max(P, 1), ntw = T * std::max(K, 1);
     zda_status st;
-    if ((st = ensure(z, &z->profile, &z->cap_profile, T * std::max(P, 1))) != ZDA_OK) return st;
-    if ((st = ensure(z, &z->twiddle, &z->cap_twiddle, T * std::max(K, 1))) != ZDA_OK) return st;
+    float2 *dprof = rb.profile, *dtw = rb.twiddle;
+    if (rb.noalloc) {
+        if (nprof > rb.cap_profile || ntw > rb.cap_twiddle) return fail(ZDA_ERR_ARG, "scratch slices too small");
+    } else {
+        if ((st = ensure(z, &z->profile, &z->cap_profile, nprof)) != ZDA_OK) return st;
+        if ((st = ensure(z, &z->twiddle, &z->cap_twiddle, ntw)) != ZDA_OK) return st;
+        dprof = z->profile;
+        dtw = z->twiddle;
+    }
     if (reset) {
         if ((st = reset_state(z, s)) != ZDA_OK) return st;
         if (dft_plane) launch_fill(dft_plane, (size_t)K * 2 * z->plane, s);
         if (dft_vol) launch_fill(dft_vol, (size_t)K * 3 * z->nd * z->plane, s);
     }
-    z->st_prof.assign(T * std::max(P, 1), make_float2(0.f, 0.f));
+    float2 *hp = nullptr;
+    if (rb.noalloc) {
+        z->st_prof.assign(nprof + ntw, make_float2(0.f, 0.f));
+        hp = z->st_prof.data();
+    } else {
+        hp = (float2 *)z->stage.take((nprof + ntw) * sizeof(float2));
+        if (!hp) return fail(ZDA_ERR_HIP, "pinned staging allocation failed");
+        std::memset((void *)hp, 0, (nprof + ntw) * sizeof(float2));
+    }
     for (int n = 0; n < nsteps; ++n)
         for (int p = 0; p < P; ++p) {
             const cd g = prof[(size_t)p * nsteps + n];
-            z->st_prof[(size_t)n * P + p] = make_float2((float)g.real(), (float)g.imag());
+            hp[(size_t)n * P + p] = make_float2((float)g.real(), (float)g.imag());
         }
-    z->st_tw.assign(T * std::max(K, 1), make_float2(0.f, 0.f));
+    float2 *htw = hp + nprof;
     for (int n = 0; n < nsteps; ++n)
         for (int k = 0; k < K; ++k) {
             const double N = (double)(z->n_done + n + 1);
             const cd tw = z->dt * std::exp(cd(0.0, omega[k] * N * z->dt));
-            z->st_tw[(size_t)n * K + k] = make_float2((float)tw.real(), (float)tw.imag());
+            htw[(size_t)n * K + k] = make_float2((float)tw.real(), (float)tw.imag());
         }
-    HIP_TRY(hipMemcpyAsync(z->profile, z->st_prof.data(), z->st_prof.size() * sizeof(float2),
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(z->twiddle, z->st_tw.data(), z->st_tw.size() * sizeof(float2),
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpyAsync(dprof, hp, nprof * sizeof(float2), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dtw, htw, ntw * sizeof(float2), hipMemcpyHostToDevice, s));
+    if (!rb.noalloc) HIP_TRY(z->stage.issued(s));
     for (int b = 0; b < 2; ++b) {
         ab[b] = step_args(z, m);
         ab[b].k_src = k_src;
         ab[b].n_prof = P;
-        ab[b].pattern = z->pattern;
-        ab[b].profile = z->profile;
+        ab[b].pattern = rb.pattern;
+        ab[b].profile = dprof;
         ab[b].K = K;
-        ab[b].twiddle = z->twiddle;
+        ab[b].twiddle = dtw;
         ab[b].dft_plane = dft_plane;
         ab[b].dft_vol = dft_vol;
         z->cur ^= 1;
@@ -558,30 +745,42 @@ int two_step_rows(int tile_rows, int nphi)
     return tile_rows == FLAT_TWO_ROWS ? flat_two_rows(nphi) : tile_rows;
 }
 
-// The zone's own tile list (interior tiles first), rebuilt when the launch
-// shape, the source plane or the tile order changed.
-zda_status build_two_step_tiles(zda_zone *z)
+// A zone's two-step tile list (interior tiles first) and its counts.
+void plan_zone_tiles(const zda_zone *z, std::vector<uint4> &all, TileCounts &tc)
+{
+    const int TR = z->tile_rows;
+    TwoStepTiles t;
+    two_step_tiles(z, two_step_rows(TR, z->d.nphi), z->kchunk, z->k_src_last, tile_order(z), 0u, t,
+                   TR == FLAT_TWO_ROWS);
+    all.clear();
+    for (int q = 0; q < 4; ++q) {
+        tc.n_lay[q] = (unsigned)t.v[q].size();
+        all.insert(all.end(), t.v[q].begin(), t.v[q].end());
+    }
+    tc.cells = t.cells;
+    tc.mon = t.mon;
+    tc.src = t.src;
+}
+
+// The zone's own tile list, rebuilt when the launch shape, the source plane
+// or the tile order changed.
+zda_status build_two_step_tiles(zda_zone *z, hipStream_t s)
 {
     const int TR = z->tile_rows, kc = z->kchunk;
-    const int rows = two_step_rows(TR, z->d.nphi);
     if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last &&
         z->tiles_xcd == tile_order(z) && z->tiles_lkc == z->layer_kchunk)
         return ZDA_OK;
-    TwoStepTiles t;
-    two_step_tiles(z, rows, kc, z->k_src_last, tile_order(z), 0u, t, TR == FLAT_TWO_ROWS);
     std::vector<uint4> all;
-    for (int q = 0; q < 4; ++q) {
-        z->n_lay[q] = (unsigned)t.v[q].size();
-        all.insert(all.end(), t.v[q].begin(), t.v[q].end());
-    }
+    TileCounts tc;
+    plan_zone_tiles(z, all, tc);
     zda_status st = ensure(z, &z->tiles2, &z->cap_tiles2, all.size());
     if (st != ZDA_OK) return st;
-    HIP_TRY(hipMemcpy(z->tiles2, all.data(), all.size() * sizeof(uint4), hipMemcpyHostToDevice));
-    z->n_int = z->n_lay[0];
-    z->n_pml = z->n_lay[1] + z->n_lay[2] + z->n_lay[3];
-    z->int_cells = t.cells;
-    z->int_mon_cells = t.mon;
-    z->int_src_cells = t.src;
+    void *h = z->stage.take(all.size() * sizeof(uint4));
+    if (!h) return fail(ZDA_ERR_HIP, "pinned staging allocation failed");
+    std::memcpy(h, all.data(), all.size() * sizeof(uint4));
+    HIP_TRY(hipMemcpyAsync(z->tiles2, h, all.size() * sizeof(uint4), hipMemcpyHostToDevice, s));
+    HIP_TRY(z->stage.issued(s));
+    z->tc = tc;
     z->tiles_src = z->k_src_last;
     z->tiles_tr = TR;
     z->tiles_kc = kc;
@@ -590,17 +789,51 @@ zda_status build_two_step_tiles(zda_zone *z)
     return ZDA_OK;
 }
 
+// In-loop divergence check of the zone's newest fields
+void watch_fields(zda_zone *z, hipStream_t s)
+{
+    WatchArgs w{};
+    for (int c = 0; c < 6; ++c) w.f[c] = z->F[z->cur][c];
+    w.n = z->ncell;
+    w.flag = z->flag;
+    w.bound2 = WATCH_BOUND2;
+    launch_watch(w, s);
+}
+
+// rb: where the run's inputs are staged (rb.tiles / rb_tc: the two-step tile
+// list of the entry point that allocates nothing; otherwise the zone's own)
 zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *prof, const double *omega, int K,
-                    float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, bool timing = false)
+                    float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, const RunBufs &rb,
+                    bool timing = false, const TileCounts *rb_tc = nullptr)
 {
     StepArgs ab[2];
-    zda_status st = prepare_run(z, m, nsteps, k_src, P, prof, omega, K, dft_plane, dft_vol, reset, s, ab);
+    zda_status st = prepare_run(z, m, nsteps, k_src, P, prof, omega, K, dft_plane, dft_vol, reset, s, ab, rb);
     if (st != ZDA_OK) return st;
     const int ab_base = z->cur;
     const StepArgs &a = ab[0];
     const bool fused = z->fused, two = z->two;
     z->k_src_last = k_src;
-    if (two && (st = build_two_step_tiles(z)) != ZDA_OK) return st;
+    const uint4 *tiles = nullptr;
+    TileCounts tc;
+    if (two) {
+        if (rb.noalloc) {
+            tiles = rb.tiles;
+            tc = *rb_tc;
+        } else {
+            if ((st = build_two_step_tiles(z, s)) != ZDA_OK) return st;
+            tiles = z->tiles2;
+            tc = z->tc;
+        }
+    }
+    const unsigned n_pml = tc.n_lay[1] + tc.n_lay[2] + tc.n_lay[3];
+    // in-loop divergence watchdog every watch_every steps of the zone's clock
+    const long W = z->watch_every;
+    long next_watch = W > 0 ? ((long)z->n_done / W + 1) * W : -1;
+    auto watch = [&](int done) {
+        if (W <= 0 || (long)z->n_done + done < next_watch) return;
+        watch_fields(z, s);
+        while (next_watch <= (long)z->n_done + done) next_watch += W;
+    };
     // one step of the one-launch kernel (the fused step, or an odd last step
     // of a two-step run)
     auto one_step = [&](int n) {
@@ -616,7 +849,7 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     };
     // steps n and n + 1 by the two-step kernel; ev (if given) brackets the
     // interior-tile and the layer-tile launches
-    const bool conc = two && z->layer_stream && z->n_pml > 0;
+    const bool conc = two && z->layer_stream && n_pml > 0 && !rb.noalloc;
     if (conc && !z->s2) {
         HIP_TRY(hipStreamCreateWithFlags(&z->s2, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&z->ev_fork, hipEventDisableTiming));
@@ -625,11 +858,11 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     // the three layer-tile lists (r rows only, z planes only, both), each
     // with its own instantiation
     auto layer_launches = [&](StepArgs b, int n, hipStream_t st) {
-        size_t off = z->n_lay[0];
+        size_t off = tc.n_lay[0];
         for (int q = 1; q < 4; ++q) {
-            b.tiles = z->tiles2 + off;
-            launch_two_step(b, n, z->n_lay[q], q, st);
-            off += z->n_lay[q];
+            b.tiles = tiles + off;
+            launch_two_step(b, n, tc.n_lay[q], q, st);
+            off += tc.n_lay[q];
         }
     };
     auto two_steps = [&](int n, hipEvent_t *ev) -> zda_status {
@@ -643,9 +876,9 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
             layer_launches(b, n, sl);
             if (ev) HIP_TRY(hipEventRecord(ev[3], sl));
         }
-        b.tiles = z->tiles2;
+        b.tiles = tiles;
         if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-        launch_two_step(b, n, z->n_int, 0, s);
+        launch_two_step(b, n, tc.n_lay[0], 0, s);
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
         if (conc) {
             HIP_TRY(hipEventRecord(z->ev_join, sl));
@@ -669,9 +902,14 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
         int groups = 0;
         if (two) {
             int n = 0;
-            for (; n + 1 < nsteps; n += 2, ++groups)
+            for (; n + 1 < nsteps; n += 2, ++groups) {
                 if ((st = two_steps(n, &z->ev[4 * (size_t)groups])) != ZDA_OK) return st;
-            if (n < nsteps) one_step(n);
+                watch(n + 2);
+            }
+            if (n < nsteps) {
+                one_step(n);
+                watch(n + 1);
+            }
         } else {
             for (int n = 0; n < nsteps; ++n, ++groups) {
                 if (fused) {
@@ -686,20 +924,31 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
                     launch_e_step(a, n, s);
                     HIP_TRY(hipEventRecord(z->ev[4 * n + 3], s));
                 }
+                watch(n + 1);
             }
         }
         z->timed_steps = groups;
         z->timed_fused = fused || two;
         z->timed_two = two;
+        z->timed_tc = tc;
     } else if (two) {
         int n = 0;
-        for (; n + 1 < nsteps; n += 2)
+        for (; n + 1 < nsteps; n += 2) {
             if ((st = two_steps(n, nullptr)) != ZDA_OK) return st;
-        if (n < nsteps) one_step(n);
+            watch(n + 2);
+        }
+        if (n < nsteps) {
+            one_step(n);
+            watch(n + 1);
+        }
     } else {
-        for (int n = 0; n < nsteps; ++n) one_step(n);
+        for (int n = 0; n < nsteps; ++n) {
+            one_step(n);
+            watch(n + 1);
+        }
     }
     HIP_TRY(hipGetLastError());
+    HIP_TRY(post_flag(z, s));
     z->n_done += nsteps;
     return ZDA_OK;
 }
@@ -716,8 +965,36 @@ struct FwdPlan {
     bool reset = true;
 };
 
+// The plane-wave sheet of the presets on the host: J_r = -e^{i m phi_j}/dz,
+// J_phi = -i sgn(m) e^{i m phi_{j+1/2}}/dz (|m| = 1), or J_r = -1/dz (radial,
+// m = 0); the pulse multiplies it.  out: [2][nr][nphi].
+void preset_pattern_host(const zda_zone *z, int kind, float2 *out)
+{
+    const zda_zone_desc &d = z->d;
+    const double sgn = d.m > 0 ? 1.0 : (d.m < 0 ? -1.0 : 0.0);
+    for (int i = 0; i < d.nr; ++i)
+        for (int j = 0; j < d.nphi; ++j) {
+            cd jr, jp;
+            if (kind == ZDA_SRC_PLANE_CIRC) {
+                // sample points phi_j, phi_{j+1/2} (all at phi = 0 in a continuous zone)
+                const double pj = d.n_fold > 0 ? j * z->dphi : 0.0;
+                const double ph = d.n_fold > 0 ? (j + 0.5) * z->dphi : 0.0;
+                jr = -std::exp(cd(0.0, d.m * pj)) / d.dz;
+                jp = cd(0.0, -sgn) * std::exp(cd(0.0, d.m * ph)) / d.dz;
+            } else {
+                jr = -1.0 / d.dz;
+                jp = 0.0;
+            }
+            out[(size_t)i * d.nphi + j] = make_float2((float)jr.real(), (float)jr.imag());
+            out[z->plane + (size_t)i * d.nphi + j] = make_float2((float)jp.real(), (float)jp.imag());
+        }
+}
+
+// Patterns a source needs on the device (1 for the presets).
+int source_patterns(const zda_source *s) { return s->kind == ZDA_SRC_CUSTOM ? s->n_profiles : 1; }
+
 zda_status forward_setup(zda_zone *z, const zda_source *s, int nsteps, const double *omega, int K, int dft_flags,
-                         hipStream_t hs, FwdPlan &plan)
+                         hipStream_t hs, FwdPlan &plan, RunBufs &rb)
 {
     if (nsteps < 0) return fail(ZDA_ERR_ARG, "nsteps must be >= 0");
     if (K < 0 || K > ZDA_MAX_FREQ || (K > 0 && !omega)) return fail(ZDA_ERR_ARG, "K must be in [0, %d]", ZDA_MAX_FREQ);
@@ -726,7 +1003,6 @@ zda_status forward_setup(zda_zone *z, const zda_source *s, int nsteps, const dou
     if ((dft_flags & ZDA_DFT_VOLUME) && z->nd <= 0) return fail(ZDA_ERR_STATE, "zone has no design layer");
     const zda_zone_desc &d = z->d;
     if (s->k_src < 1 || s->k_src >= d.nz) return fail(ZDA_ERR_ARG, "k_src must be in [1, nz)");
-    HIP_TRY(hipStreamSynchronize(hs));   // staging buffers of the previous call are free
     plan.reset = !(dft_flags & ZDA_RUN_CONTINUE);
     if (plan.reset) z->n_done = 0;
     zda_status st;
@@ -737,35 +1013,55 @@ zda_status forward_setup(zda_zone *z, const zda_source *s, int nsteps, const dou
         plan.P = 1;
         plan.width = s->width;
         plan.n0 = s->n0 >= 0 ? s->n0 : default_n0(plan.width, z->dt);
-        if ((st = ensure(z, &z->pattern, &z->cap_pattern, 2 * z->plane)) != ZDA_OK) return st;
-        z->st_pat.assign(2 * z->plane, make_float2(0.f, 0.f));
-        const double sgn = d.m > 0 ? 1.0 : (d.m < 0 ? -1.0 : 0.0);
-        for (int i = 0; i < d.nr; ++i)
-            for (int j = 0; j < d.nphi; ++j) {
-                cd jr, jp;
-                if (s->kind == ZDA_SRC_PLANE_CIRC) {
-                    // sample points phi_j, phi_{j+1/2} (all at phi = 0 in a continuous zone)
-                    const double pj = d.n_fold > 0 ? j * z->dphi : 0.0;
-                    const double ph = d.n_fold > 0 ? (j + 0.5) * z->dphi : 0.0;
-                    jr = -std::exp(cd(0.0, d.m * pj)) / d.dz;
-                    jp = cd(0.0, -sgn) * std::exp(cd(0.0, d.m * ph)) / d.dz;
-                } else {
-                    jr = -1.0 / d.dz;
-                    jp = 0.0;
-                }
-                z->st_pat[(size_t)i * d.nphi + j] = make_float2((float)jr.real(), (float)jr.imag());
-                z->st_pat[z->plane + (size_t)i * d.nphi + j] = make_float2((float)jp.real(), (float)jp.imag());
+        const size_t bytes = 2 * z->plane * sizeof(float2);
+        if (rb.noalloc) {
+            if (2 * z->plane > rb.cap_pattern) return fail(ZDA_ERR_ARG, "scratch slice too small for the pattern");
+            z->st_pat.resize(2 * z->plane);
+            preset_pattern_host(z, s->kind, z->st_pat.data());
+            HIP_TRY(hipMemcpyAsync(rb.pattern, z->st_pat.data(), bytes, hipMemcpyHostToDevice, hs));
+        } else {
+            if ((st = ensure(z, &z->pattern, &z->cap_pattern, 2 * z->plane)) != ZDA_OK) return st;
+            // the sheet depends only on the zone and the preset: rebuilt and
+            // uploaded when the pattern buffer holds something else
+            const int key = 1 + s->kind;
+            if (z->pattern_key != key) {
+                float2 *h = (float2 *)z->stage.take(bytes);
+                if (!h) return fail(ZDA_ERR_HIP, "pinned staging allocation failed");
+                preset_pattern_host(z, s->kind, h);
+                HIP_TRY(hipMemcpyAsync(z->pattern, h, bytes, hipMemcpyHostToDevice, hs));
+                HIP_TRY(z->stage.issued(hs));
+                z->pattern_key = key;
             }
-        HIP_TRY(hipMemcpyAsync(z->pattern, z->st_pat.data(), 2 * z->plane * sizeof(float2), hipMemcpyHostToDevice, hs));
+            rb.pattern = z->pattern;
+        }
         plan.prof.resize(nsteps);
         for (int n = 0; n < nsteps; ++n) plan.prof[n] = pulse_at(z->n_done + n, z->dt, s->omega_c, plan.width, plan.n0);
     } else if (s->kind == ZDA_SRC_CUSTOM) {
         plan.P = s->n_profiles;
         if (plan.P < 1 || plan.P > ZDA_MAX_FREQ || !s->patterns || !s->profiles)
             return fail(ZDA_ERR_ARG, "CUSTOM needs 1..%d patterns and profiles", ZDA_MAX_FREQ);
-        if ((st = ensure(z, &z->pattern, &z->cap_pattern, (size_t)plan.P * 2 * z->plane)) != ZDA_OK) return st;
-        HIP_TRY(hipMemcpyAsync(z->pattern, s->patterns, (size_t)plan.P * 2 * z->plane * sizeof(float2),
-                               s->patterns_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
+        const size_t count = (size_t)plan.P * 2 * z->plane, bytes = count * sizeof(float2);
+        float2 *dst = rb.pattern;
+        if (rb.noalloc) {
+            if (count > rb.cap_pattern) return fail(ZDA_ERR_ARG, "scratch slice too small for the patterns");
+        } else {
+            if ((st = ensure(z, &z->pattern, &z->cap_pattern, count)) != ZDA_OK) return st;
+            dst = rb.pattern = z->pattern;
+            z->pattern_key = 0;
+        }
+        if (s->patterns_on_device) {
+            HIP_TRY(hipMemcpyAsync(dst, s->patterns, bytes, hipMemcpyDeviceToDevice, hs));
+        } else if (rb.noalloc) {
+            z->st_pat.resize(count);
+            std::memcpy((void *)z->st_pat.data(), s->patterns, bytes);
+            HIP_TRY(hipMemcpyAsync(dst, z->st_pat.data(), bytes, hipMemcpyHostToDevice, hs));
+        } else {
+            void *h = z->stage.take(bytes);
+            if (!h) return fail(ZDA_ERR_HIP, "pinned staging allocation failed");
+            std::memcpy(h, s->patterns, bytes);
+            HIP_TRY(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, hs));
+            HIP_TRY(z->stage.issued(hs));
+        }
         plan.prof.resize((size_t)plan.P * nsteps);
         for (size_t q = 0; q < plan.prof.size(); ++q) plan.prof[q] = cd(s->profiles[2 * q], s->profiles[2 * q + 1]);
     } else {
@@ -775,6 +1071,9 @@ zda_status forward_setup(zda_zone *z, const zda_source *s, int nsteps, const dou
     plan.dvol = nullptr;
     if ((dft_flags & ZDA_DFT_VOLUME) && K > 0) {
         if (!z->dft_vol) {
+            if (rb.noalloc)
+                return fail(ZDA_ERR_STATE, "the design-layer DFT buffer is allocated by a first zda_fdtd_run with "
+                                           "ZDA_DFT_VOLUME");
             if ((st = dev_alloc(z, &z->dft_vol, (size_t)ZDA_MAX_FREQ * 3 * z->nd * z->plane)) != ZDA_OK) return st;
             launch_fill(z->dft_vol, (size_t)ZDA_MAX_FREQ * 3 * z->nd * z->plane, hs);
         }
@@ -837,6 +1136,7 @@ struct AdjPlan {
     std::vector<cd> q;
     int K = 0, T = 0;
     float2 *wr_dev = nullptr, *wz_dev = nullptr;
+    float *gtmp = nullptr;         // the gradient before its copy into host memory
 };
 
 zda_status adjoint_setup(zda_zone *z, const float *dF_dE, int dF_on_device, double adj_width, hipStream_t hs,
@@ -848,17 +1148,26 @@ zda_status adjoint_setup(zda_zone *z, const float *dF_dE, int dF_on_device, doub
     double width = adj_width > 0 ? adj_width : z->last_width;
     if (!(width > 0)) return fail(ZDA_ERR_ARG, "adjoint pulse width unknown (custom forward source): pass adj_width");
     const int n0 = (adj_width > 0 || z->last_n0 < 0) ? default_n0(width, z->dt) : z->last_n0;
-    HIP_TRY(hipStreamSynchronize(hs));
     zda_status st;
     const size_t npl = (size_t)K * 2 * z->plane;
     const size_t nfac = (size_t)K * 2 * d.nr, nwr = (size_t)K * 3 * d.nr, nwz = (size_t)K * 3 * nd;
-    if ((st = ensure(z, &z->scratch, &z->cap_scratch, npl + nfac + nwr + nwz)) != ZDA_OK) return st;
+    const size_t ngt = ((size_t)nd * z->plane + 1) / 2;   // FP32 gradient in float2 units
+    if ((st = ensure(z, &z->scratch, &z->cap_scratch, npl + nfac + nwr + nwz + ngt)) != ZDA_OK) return st;
     if ((st = ensure(z, &z->pattern, &z->cap_pattern, npl)) != ZDA_OK) return st;
+    z->pattern_key = 0;
     if (!z->dft_vol_adj && (st = dev_alloc(z, &z->dft_vol_adj, (size_t)ZDA_MAX_FREQ * 3 * nd * z->plane)) != ZDA_OK)
         return st;
     float2 *g_dev = z->scratch, *fac_dev = g_dev + npl, *wr_dev = fac_dev + nfac, *wz_dev = wr_dev + nwr;
-    HIP_TRY(hipMemcpyAsync(g_dev, dF_dE, npl * sizeof(float2),
-                           dF_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
+    plan.gtmp = (float *)(wz_dev + nwz);
+    if (dF_on_device) {
+        HIP_TRY(hipMemcpyAsync(g_dev, dF_dE, npl * sizeof(float2), hipMemcpyDeviceToDevice, hs));
+    } else {
+        void *h = z->stage.take(npl * sizeof(float2));
+        if (!h) return fail(ZDA_ERR_HIP, "pinned staging allocation failed");
+        std::memcpy(h, dF_dE, npl * sizeof(float2));
+        HIP_TRY(hipMemcpyAsync(g_dev, h, npl * sizeof(float2), hipMemcpyHostToDevice, hs));
+        HIP_TRY(z->stage.issued(hs));
+    }
     // stretched volume W = R l_r l_z dphi and leap-frog frequency wt
     auto wt = [&](double w) { return 2.0 / z->dt * std::sin(w * z->dt / 2.0); };
     auto w_r = [&](int comp, int i, double w) {   // comp 0 = E_r (half point), 1, 2 = E_phi, E_z (integer)
@@ -871,26 +1180,29 @@ zda_status adjoint_setup(zda_zone *z, const float *dF_dE, int dF_on_device, doub
         const int h = comp == 2 ? 1 : 0;
         return stretch(z->sig_z[h][k], z->cz, w, z->dt);
     };
-    z->st_misc.assign(nfac + nwr + nwz, make_float2(0.f, 0.f));
+    float2 *misc = (float2 *)z->stage.take((nfac + nwr + nwz) * sizeof(float2));
+    if (!misc) return fail(ZDA_ERR_HIP, "pinned staging allocation failed");
+    std::memset((void *)misc, 0, (nfac + nwr + nwz) * sizeof(float2));
     for (int k = 0; k < K; ++k) {
         const double w = z->last_omega[k];
         for (int a = 0; a < 2; ++a)
             for (int i = 0; i < d.nr; ++i) {
                 const cd f = 1.0 / (w_r(a, i, w) * w_z(a, km, w) * cd(0.0, wt(w)));
-                z->st_misc[((size_t)k * 2 + a) * d.nr + i] = make_float2((float)f.real(), (float)f.imag());
+                misc[((size_t)k * 2 + a) * d.nr + i] = make_float2((float)f.real(), (float)f.imag());
             }
         for (int a = 0; a < 3; ++a) {
             for (int i = 0; i < d.nr; ++i) {
                 const cd v = wt(w) * wt(w) * w_r(a, i, w);
-                z->st_misc[nfac + ((size_t)k * 3 + a) * d.nr + i] = make_float2((float)v.real(), (float)v.imag());
+                misc[nfac + ((size_t)k * 3 + a) * d.nr + i] = make_float2((float)v.real(), (float)v.imag());
             }
             for (int kd = 0; kd < nd; ++kd) {
                 const cd v = w_z(a, d.design_k0 + kd, w);
-                z->st_misc[nfac + nwr + ((size_t)k * 3 + a) * nd + kd] = make_float2((float)v.real(), (float)v.imag());
+                misc[nfac + nwr + ((size_t)k * 3 + a) * nd + kd] = make_float2((float)v.real(), (float)v.imag());
             }
         }
     }
-    HIP_TRY(hipMemcpyAsync(fac_dev, z->st_misc.data(), (nfac + nwr + nwz) * sizeof(float2), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(fac_dev, misc, (nfac + nwr + nwz) * sizeof(float2), hipMemcpyHostToDevice, hs));
+    HIP_TRY(z->stage.issued(hs));
     launch_adjoint_pattern(z->pattern, g_dev, fac_dev, K, d.nr, d.nphi, hs);
     // broadband profiles: pulses p_l centred on w_l, mixed by P^{-1}, P_kl = phat_l(w_k)
     std::vector<double> p((size_t)K * T);
@@ -925,27 +1237,33 @@ zda_status adjoint_finish(zda_zone *z, const AdjPlan &plan, float *grad_rho, int
     const zda_zone_desc &d = z->d;
     const int nd = z->nd, K = plan.K;
     z->have_vol_adj = true;
-    float *gdst = grad_rho;
-    float *gtmp = nullptr;
-    if (!grad_on_device) {
-        HIP_TRY(hipMalloc((void **)&gtmp, (size_t)nd * z->plane * sizeof(float)));
-        gdst = gtmp;
-    }
+    float *gdst = grad_on_device ? grad_rho : plan.gtmp;
     launch_overlap(gdst, z->dft_vol, z->dft_vol_adj, plan.wr_dev, plan.wz_dev, K, nd, d.nr, d.nphi,
                    (float)(2.0 * (d.eps_hi - d.eps_bg)), hs);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && gtmp) {
-        e = hipMemcpyAsync(grad_rho, gtmp, (size_t)nd * z->plane * sizeof(float), hipMemcpyDeviceToHost, hs);
-        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    HIP_TRY(hipGetLastError());
+    if (!grad_on_device) {
+        HIP_TRY(hipMemcpyAsync(grad_rho, plan.gtmp, (size_t)nd * z->plane * sizeof(float), hipMemcpyDeviceToHost, hs));
+        HIP_TRY(post_flag(z, hs));
+        HIP_TRY(hipStreamSynchronize(hs));
+        if (*z->flag_host) return fail(ZDA_ERR_DIVERGED, "the watchdog found non-finite or exploding fields");
     }
-    if (gtmp) (void)hipFree(gtmp);
-    if (e != hipSuccess) return fail(ZDA_ERR_HIP, "overlap: %s", hipGetErrorString(e));
     return ZDA_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+zda_status zda_set_allocator(zda_alloc_fn alloc_fn, zda_free_fn free_fn, void *ctx)
+{
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+        return fail(ZDA_ERR_ARG, "give both allocator functions, or neither (hipMalloc / hipFree)");
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    g_alloc.alloc = alloc_fn;
+    g_alloc.free = free_fn;
+    g_alloc.ctx = alloc_fn ? ctx : nullptr;
+    return ZDA_OK;
+}
 
 void zda_zone_desc_default(zda_zone_desc *d)
 {
@@ -992,6 +1310,8 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     if (!z) return fail(ZDA_ERR_OOM, "host allocation failed");
     z->d = *d;
     if (hipGetDevice(&z->device) != hipSuccess) { delete z; return fail(ZDA_ERR_HIP, "no HIP device"); }
+    z->mem.al = current_allocator();
+    z->mem.device = z->device;
     z->dphi = dphi;
     z->tau = d->n_fold > 0 ? 2.0 * M_PI / d->n_fold : 1.0;
     z->dt = dt;
@@ -1034,17 +1354,9 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
         if (s1 == ZDA_OK) s1 = dev_alloc(z, &z->auxR[1], (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
         if (s1 == ZDA_OK) s1 = dev_alloc(z, &z->auxZ[1], (size_t)N_AUX_Z * z->dZ * z->plane);
         if (s1 != ZDA_OK) {
-            for (auto &f : z->F[1]) if (f) { (void)hipFree(f); z->bytes -= z->ncell * sizeof(float2); f = nullptr; }
-            if (z->auxR[1]) {
-                (void)hipFree(z->auxR[1]);
-                z->bytes -= (size_t)N_AUX_R * d->nz * z->dR * d->nphi * sizeof(float2);
-                z->auxR[1] = nullptr;
-            }
-            if (z->auxZ[1]) {
-                (void)hipFree(z->auxZ[1]);
-                z->bytes -= (size_t)N_AUX_Z * z->dZ * z->plane * sizeof(float2);
-                z->auxZ[1] = nullptr;
-            }
+            for (auto &f : z->F[1]) dev_free(z, f);
+            dev_free(z, z->auxR[1]);
+            dev_free(z, z->auxZ[1]);
             z->fused = false;
             z->tile_rows = 4;
         } else {
@@ -1065,12 +1377,8 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
             } else if (s2 == ZDA_OK) {
                 z->has_m = true;   // two-step tiles store rows and planes in 16 bits; not the default here
             } else {
-                if (z->mauxR) {
-                    (void)hipFree(z->mauxR);
-                    z->bytes -= (size_t)N_AUX_R * d->nz * z->dR * d->nphi * sizeof(float2);
-                    z->mauxR = nullptr;
-                }
-                z->mauxZ = nullptr;
+                dev_free(z, z->mauxR);
+                dev_free(z, z->mauxZ);
             }
             (void)hipGetLastError();
         }
@@ -1101,6 +1409,11 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     if (st == ZDA_OK) st = dev_alloc(z, &z->rows, (size_t)d->nr);
     if (st == ZDA_OK) st = dev_alloc(z, &z->zrows, (size_t)d->nz);
     if (st == ZDA_OK) st = dev_alloc(z, &z->flag, 1);
+    if (st == ZDA_OK && hipHostMalloc((void **)&z->flag_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        z->flag_host = nullptr;
+        st = fail(ZDA_ERR_OOM, "pinned host allocation failed");
+    }
     if (st == ZDA_OK) st = dev_alloc(z, &z->dft_plane, (size_t)ZDA_MAX_FREQ * 2 * z->plane);
     if (st != ZDA_OK) { free_all(z); delete z; return st; }
     if (hipMemcpy(z->rows, rows.data(), rows.size() * sizeof(RowCoef), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1111,7 +1424,8 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
     // a new zone starts from zero fields, auxiliaries and monitors
     if ((st = reset_state(z, nullptr)) != ZDA_OK) { free_all(z); delete z; return st; }
     launch_fill(z->dft_plane, (size_t)ZDA_MAX_FREQ * 2 * z->plane, nullptr);
-    if (hipDeviceSynchronize() != hipSuccess) { free_all(z); delete z; return fail(ZDA_ERR_HIP, "zone reset failed"); }
+    if (hipStreamSynchronize(nullptr) != hipSuccess) { free_all(z); delete z; return fail(ZDA_ERR_HIP, "zone reset failed"); }
+    *z->flag_host = 0;
     *out = z;
     if ((st = zda_zone_set_eps(z, eps, eps_on_device)) != ZDA_OK) { zda_zone_destroy(z); *out = nullptr; return st; }
     return ZDA_OK;
@@ -1130,25 +1444,13 @@ zda_status zda_zone_set_eps(zda_zone *z, const float *eps, int on_device)
 {
     if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
     DeviceGuard g(z->device);
-    if (!eps) {
-        std::vector<float> one(z->ncell, (float)z->dt);
-        HIP_TRY(hipMemcpy(z->ceps, one.data(), z->ncell * sizeof(float), hipMemcpyHostToDevice));
-        return ZDA_OK;
-    }
-    const float *src = eps;
-    float *tmp = nullptr;
-    if (!on_device) {
-        HIP_TRY(hipMalloc((void **)&tmp, z->ncell * sizeof(float)));
-        if (hipMemcpy(tmp, eps, z->ncell * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(tmp);
-            return fail(ZDA_ERR_HIP, "eps upload failed");
-        }
-        src = tmp;
-    }
-    launch_inv_eps(z->ceps, src, z->ncell, z->dt, nullptr);
-    hipError_t e = hipDeviceSynchronize();
-    if (tmp) (void)hipFree(tmp);
-    if (e != hipSuccess) return fail(ZDA_ERR_HIP, "eps kernel: %s", hipGetErrorString(e));
+    hipStream_t s = z->stream;
+    // the permittivity lands in the dt/eps array and is converted in place
+    if (eps && !on_device)
+        HIP_TRY(hipMemcpyAsync(z->ceps, eps, z->ncell * sizeof(float), hipMemcpyHostToDevice, s));
+    launch_inv_eps(z->ceps, eps ? (on_device ? eps : z->ceps) : nullptr, z->ncell, z->dt, s);
+    HIP_TRY(hipGetLastError());
+    if (eps && !on_device) HIP_TRY(hipStreamSynchronize(s));
     return ZDA_OK;
 }
 
@@ -1157,21 +1459,30 @@ zda_status zda_zone_set_design(zda_zone *z, const float *rho, int on_device)
     if (!z || !rho) return fail(ZDA_ERR_ARG, "NULL argument");
     if (z->nd <= 0) return fail(ZDA_ERR_STATE, "zone has no design layer");
     DeviceGuard g(z->device);
+    hipStream_t s = z->stream;
     const size_t n = (size_t)z->nd * z->plane;
-    const float *src = rho;
-    float *tmp = nullptr;
-    if (!on_device) {
-        HIP_TRY(hipMalloc((void **)&tmp, n * sizeof(float)));
-        if (hipMemcpy(tmp, rho, n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(tmp);
-            return fail(ZDA_ERR_HIP, "rho upload failed");
-        }
-        src = tmp;
-    }
-    launch_design_dt(z->ceps + (size_t)z->d.design_k0 * z->plane, src, n, z->d.eps_bg, z->d.eps_hi, z->dt, nullptr);
-    hipError_t e = hipDeviceSynchronize();
-    if (tmp) (void)hipFree(tmp);
-    if (e != hipSuccess) return fail(ZDA_ERR_HIP, "design kernel: %s", hipGetErrorString(e));
+    float *dst = z->ceps + (size_t)z->d.design_k0 * z->plane;
+    if (!on_device) HIP_TRY(hipMemcpyAsync(dst, rho, n * sizeof(float), hipMemcpyHostToDevice, s));
+    launch_design_dt(dst, on_device ? rho : dst, n, z->d.eps_bg, z->d.eps_hi, z->dt, s);
+    HIP_TRY(hipGetLastError());
+    if (!on_device) HIP_TRY(hipStreamSynchronize(s));
+    return ZDA_OK;
+}
+
+zda_status zda_zone_set_stream(zda_zone *z, void *stream)
+{
+    if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
+    z->stream = (hipStream_t)stream;
+    return ZDA_OK;
+}
+
+zda_status zda_zone_sync(zda_zone *z)
+{
+    if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
+    DeviceGuard g(z->device);
+    HIP_TRY(post_flag(z, z->stream));
+    HIP_TRY(zone_wait(z));
+    if (*z->flag_host) return fail(ZDA_ERR_DIVERGED, "the watchdog found non-finite or exploding fields");
     return ZDA_OK;
 }
 
@@ -1181,42 +1492,69 @@ zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const doub
     if (!z || !s) return fail(ZDA_ERR_ARG, "NULL zone or source");
     DeviceGuard g(z->device);
     hipStream_t hs = (hipStream_t)stream;
+    z->stream = hs;
     FwdPlan plan;
-    zda_status st = forward_setup(z, s, nsteps, omega, K, dft_flags, hs, plan);
+    RunBufs rb;
+    zda_status st = forward_setup(z, s, nsteps, omega, K, dft_flags, hs, plan, rb);
     if (st != ZDA_OK) return st;
     if ((st = run_loop(z, z->d.m, nsteps, s->k_src, plan.P, plan.prof.data(), omega, K, plan.dplane, plan.dvol,
-                       plan.reset, hs, (dft_flags & ZDA_RUN_TIMING) != 0)) != ZDA_OK)
+                       plan.reset, hs, rb, (dft_flags & ZDA_RUN_TIMING) != 0)) != ZDA_OK)
         return st;
     forward_finish(z, plan, nsteps, omega, K);
     return ZDA_OK;
 }
 
-zda_status zda_dft_fields(zda_zone *z, int monitor, float *out, size_t out_floats, int out_on_device)
+zda_status zda_dft_fields(zda_zone *z, int monitor, int component_mask, float *out, size_t out_floats,
+                          int out_on_device)
 {
     if (!z || !out) return fail(ZDA_ERR_ARG, "NULL argument");
     DeviceGuard g(z->device);
     const float2 *src = nullptr;
-    size_t n = 0;
+    size_t block = 0;     // samples of one component at one frequency
+    int ncomp = 0;
     if (monitor == ZDA_MON_PLANE) {
         if (!z->have_plane) return fail(ZDA_ERR_STATE, "no plane DFT in the last run");
         src = z->dft_plane;
-        n = (size_t)z->last_K * 2 * z->plane;
+        block = z->plane;
+        ncomp = 2;
     } else if (monitor == ZDA_MON_VOLUME || monitor == ZDA_MON_ADJOINT_VOLUME) {
         const bool adj = monitor == ZDA_MON_ADJOINT_VOLUME;
         if (!(adj ? z->have_vol_adj : z->have_vol)) return fail(ZDA_ERR_STATE, "volume DFT not available");
         src = adj ? z->dft_vol_adj : z->dft_vol;
-        n = (size_t)z->last_K * 3 * z->nd * z->plane;
+        block = (size_t)z->nd * z->plane;
+        ncomp = 3;
     } else {
         return fail(ZDA_ERR_ARG, "unknown monitor %d", monitor);
     }
+    const int all = (1 << ncomp) - 1;
+    const int mask = component_mask == 0 ? all : component_mask;
+    if (mask & ~all) return fail(ZDA_ERR_ARG, "component mask 0x%x names a component this monitor lacks", component_mask);
+    int nsel = 0;
+    for (int c = 0; c < ncomp; ++c) nsel += (mask >> c) & 1;
+    const int K = z->last_K;
+    const size_t n = (size_t)K * nsel * block;
     if (out_floats < 2 * n) return fail(ZDA_ERR_ARG, "output holds %zu floats, %zu needed", out_floats, 2 * n);
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemset(z->flag, 0, sizeof(int)));
-    launch_nonfinite(src, n, z->flag, nullptr);
-    int flag = 0;
-    HIP_TRY(hipMemcpy(&flag, z->flag, sizeof(int), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(out, src, n * sizeof(float2), out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
-    if (flag) return fail(ZDA_ERR_DIVERGED, "non-finite values in the DFT monitor (the run diverged)");
+    hipStream_t s = z->stream;
+    const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    float2 *o = (float2 *)out;
+    if (mask == all) {
+        HIP_TRY(hipMemcpyAsync(o, src, n * sizeof(float2), kind, s));
+    } else {
+        for (int k = 0; k < K; ++k)
+            for (int c = 0; c < ncomp; ++c)
+                if ((mask >> c) & 1) {
+                    HIP_TRY(hipMemcpyAsync(o, src + ((size_t)k * ncomp + c) * block, block * sizeof(float2), kind, s));
+                    o += block;
+                }
+    }
+    // a monitor that holds non-finite values raises the divergence flag too
+    launch_nonfinite(src, (size_t)K * ncomp * block, z->flag, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(post_flag(z, s));
+    if (!out_on_device) {
+        HIP_TRY(zone_wait(z));
+        if (*z->flag_host) return fail(ZDA_ERR_DIVERGED, "non-finite or exploding fields (the run diverged)");
+    }
     return ZDA_OK;
 }
 
@@ -1226,11 +1564,14 @@ zda_status zda_adjoint_grad(zda_zone *z, const float *dF_dE, int dF_on_device, f
     if (!z || !dF_dE || !grad_rho) return fail(ZDA_ERR_ARG, "NULL argument");
     DeviceGuard g(z->device);
     hipStream_t hs = (hipStream_t)stream;
+    z->stream = hs;
     AdjPlan plan;
     zda_status st = adjoint_setup(z, dF_dE, dF_on_device, adj_width, hs, plan);
     if (st != ZDA_OK) return st;
+    RunBufs rb;
+    rb.pattern = z->pattern;
     if ((st = run_loop(z, -z->d.m, plan.T, z->d.k_mon, plan.K, plan.q.data(), z->last_omega, plan.K, nullptr,
-                       z->dft_vol_adj, true, hs)) != ZDA_OK)
+                       z->dft_vol_adj, true, hs, rb)) != ZDA_OK)
         return st;
     return adjoint_finish(z, plan, grad_rho, grad_on_device, hs);
 }
@@ -1239,9 +1580,9 @@ zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_dev
 {
     if (!z || !out || comp < 0 || comp > 5) return fail(ZDA_ERR_ARG, "bad argument");
     DeviceGuard g(z->device);
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(out, z->F[z->cur][comp], z->ncell * sizeof(float2),
-                      out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(out, z->F[z->cur][comp], z->ncell * sizeof(float2),
+                           out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, z->stream));
+    if (!out_on_device) HIP_TRY(zone_wait(z));
     return ZDA_OK;
 }
 
@@ -1249,15 +1590,14 @@ zda_status zda_zone_write_field(zda_zone *z, int comp, const float *in, int in_o
 {
     if (!z || !in || comp < 0 || comp > 5) return fail(ZDA_ERR_ARG, "bad argument");
     DeviceGuard g(z->device);
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(z->F[z->cur][comp], in, z->ncell * sizeof(float2),
-                      in_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
-    if (comp == 1 && z->dR > 0) {
+    hipStream_t s = z->stream;
+    HIP_TRY(hipMemcpyAsync(z->F[z->cur][comp], in, z->ncell * sizeof(float2),
+                           in_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (comp == 1 && z->dR > 0)
         launch_seed_u(z->auxR[z->cur] + (size_t)AUX_U_EP * z->d.nz * z->dR * z->d.nphi, z->F[z->cur][1], z->d.nr,
-                      z->d.nphi,
-                      z->d.nz, z->d.pml_r_in, z->d.pml_r_out, (float)z->dt, nullptr);
-        HIP_TRY(hipDeviceSynchronize());
-    }
+                      z->d.nphi, z->d.nz, z->d.pml_r_in, z->d.pml_r_out, (float)z->dt, s);
+    HIP_TRY(hipGetLastError());
+    if (!in_on_device) HIP_TRY(hipStreamSynchronize(s));
     return ZDA_OK;
 }
 
@@ -1294,6 +1634,10 @@ zda_status zda_zone_set_option(zda_zone *z, int option, int value)
     case ZDA_OPT_XCD_REMAP: z->xcd_remap = value ? 1 : 0; return ZDA_OK;
     case ZDA_OPT_NT_STORES: z->nt_stores = value ? 1 : 0; return ZDA_OK;
     case ZDA_OPT_LAYER_STREAM: z->layer_stream = value ? 1 : 0; return ZDA_OK;
+    case ZDA_OPT_WATCHDOG:
+        if (value < 0) return fail(ZDA_ERR_ARG, "watchdog interval must be >= 0");
+        z->watch_every = value;
+        return ZDA_OK;
     case ZDA_OPT_LAYER_KCHUNK:
         if (value < -1) return fail(ZDA_ERR_ARG, "layer chunk depth must be >= -1");
         z->layer_kchunk = value;
@@ -1311,7 +1655,7 @@ zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info)
 {
     if (!z || !info) return fail(ZDA_ERR_ARG, "NULL argument");
     info->cells = z->ncell;
-    info->device_bytes = z->bytes;
+    info->device_bytes = z->mem.bytes;
     info->dt = z->dt;
     info->cfl = z->cfl;
     info->launch_chunks = (z->d.nz + z->kchunk - 1) / z->kchunk;
@@ -1381,12 +1725,12 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t)
     t->h_launches = z->timed_fused ? 0 : z->timed_steps;
     t->steps_per_launch = z->timed_two ? 2 : 1;
     t->layer_launches = z->timed_two ? z->timed_steps : 0;
-    t->e_cells = z->timed_two ? z->int_cells : z->ncell;
+    t->e_cells = z->timed_two ? z->timed_tc.cells : z->ncell;
     {
         const size_t mon = (z->d.k_mon >= 0 && z->d.k_mon < z->d.nz) ? z->plane : 0;
-        t->e_mon_cells = z->timed_two ? z->int_mon_cells : mon;
+        t->e_mon_cells = z->timed_two ? z->timed_tc.mon : mon;
         const size_t src = (z->k_src_last >= 0 && z->k_src_last < z->d.nz) ? z->plane : 0;
-        t->e_src_cells = z->timed_two ? z->int_src_cells : src;
+        t->e_src_cells = z->timed_two ? z->timed_tc.src : src;
     }
     t->e_launches = z->timed_steps;
     return ZDA_OK;
@@ -1431,6 +1775,7 @@ struct zda_batch {
     bool two = false;             // two-step kernel (tile_rows 5, 13 or 34)
     uint4 *tiles = nullptr;       // two-step: interior tiles of every zone, then layer tiles
     size_t cap_tiles = 0;
+    DevMem mem;
 };
 
 namespace {
@@ -1468,22 +1813,24 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
             all.insert(all.end(), t.v[q].begin(), t.v[q].end());
         }
         if (all.size() > b->cap_tiles) {
-            if (b->tiles) (void)hipFree(b->tiles);
-            b->tiles = nullptr;
+            HIP_TRY(hipStreamSynchronize(s));
+            b->mem.put(b->tiles);
             b->cap_tiles = 0;
-            HIP_TRY(hipMalloc((void **)&b->tiles, all.size() * sizeof(uint4)));
+            b->tiles = (uint4 *)b->mem.get(all.size() * sizeof(uint4));
+            if (!b->tiles) return fail(ZDA_ERR_OOM, "device allocation of the batch tile list failed");
             b->cap_tiles = all.size();
         }
         HIP_TRY(hipMemcpyAsync(b->tiles, all.data(), all.size() * sizeof(uint4), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));   // the staging vector goes out of scope
     }
     if ((size_t)nz > b->cap) {
-        if (b->tab) (void)hipFree(b->tab);
-        if (b->prefix) (void)hipFree(b->prefix);
-        b->tab = nullptr;
-        b->prefix = nullptr;
-        HIP_TRY(hipMalloc((void **)&b->tab, 2 * (size_t)nz * sizeof(StepArgs)));
-        HIP_TRY(hipMalloc((void **)&b->prefix, (size_t)nz * sizeof(unsigned)));
+        HIP_TRY(hipStreamSynchronize(s));
+        b->mem.put(b->tab);
+        b->mem.put(b->prefix);
+        b->cap = 0;
+        b->tab = (StepArgs *)b->mem.get(2 * (size_t)nz * sizeof(StepArgs));
+        b->prefix = (unsigned *)b->mem.get((size_t)nz * sizeof(unsigned));
+        if (!b->tab || !b->prefix) return fail(ZDA_ERR_OOM, "device allocation of the batch tables failed");
         b->cap = nz;
     }
     HIP_TRY(hipMemcpyAsync(b->tab, b->h_tab.data(), b->h_tab.size() * sizeof(StepArgs), hipMemcpyHostToDevice, s));
@@ -1530,7 +1877,29 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
             (void)hipGraphDestroy(graph);
             return fail(ZDA_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
         }
-        for (int q = 0; q < reps && e == hipSuccess; ++q) e = hipGraphLaunch(exec, s);
+        // after whole graphs every zone is back on the buffer set its run
+        // started from (each graph holds an even number of steps); the
+        // watchdog checks those fields every watch_every steps
+        const long W = b->zones[0]->watch_every;
+        long next_watch = W > 0 ? ((long)b->zones[0]->n_done / W + 1) * W : -1;
+        for (int q = 0; q < reps && e == hipSuccess; ++q) {
+            e = hipGraphLaunch(exec, s);
+            const long at = (long)b->zones[0]->n_done + (long)(q + 1) * S;
+            if (e == hipSuccess && W > 0 && at >= next_watch) {
+                for (int i = 0; i < nz; ++i) {
+                    WatchArgs w{};
+                    const StepArgs &a0 = ab[i][0];
+                    w.f[0] = a0.Er; w.f[1] = a0.Ep; w.f[2] = a0.Ez;
+                    w.f[3] = a0.Hr; w.f[4] = a0.Hp; w.f[5] = a0.Hz;
+                    w.n = b->zones[i]->ncell;
+                    w.flag = b->zones[i]->flag;
+                    w.bound2 = WATCH_BOUND2;
+                    launch_watch(w, s);
+                }
+                while (next_watch <= at) next_watch += W;
+                e = hipGetLastError();
+            }
+        }
         hipError_t e2 = hipStreamSynchronize(s);
         (void)hipGraphExecDestroy(exec);
         (void)hipGraphDestroy(graph);
@@ -1558,6 +1927,7 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
     for (auto z : b->zones) {
         z->n_done += nsteps;
         z->cur ^= (flips & 1);
+        HIP_TRY(post_flag(z, s));
     }
     return ZDA_OK;
 }
@@ -1583,8 +1953,10 @@ zda_status zda_batch_create(zda_zone *const *zones, int nzones, zda_batch **out)
     for (auto z : b->zones) b->fused = b->fused && zone_has_second_set(z);
     b->tile_rows = b->fused ? 3 : 4;
     DeviceGuard g(dev);
-    if (hipMalloc((void **)&b->n_base, sizeof(int)) != hipSuccess ||
-        hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    b->mem.al = current_allocator();
+    b->mem.device = dev;
+    b->n_base = (int *)b->mem.get(sizeof(int));
+    if (!b->n_base || hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         zda_batch_destroy(b);
         return fail(ZDA_ERR_HIP, "batch setup failed");
     }
@@ -1597,10 +1969,7 @@ void zda_batch_destroy(zda_batch *b)
     if (!b) return;
     DeviceGuard g(b->device);
     (void)hipDeviceSynchronize();
-    if (b->tab) (void)hipFree(b->tab);
-    if (b->prefix) (void)hipFree(b->prefix);
-    if (b->tiles) (void)hipFree(b->tiles);
-    if (b->n_base) (void)hipFree(b->n_base);
+    b->mem.put_all();
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
 }
@@ -1649,13 +2018,16 @@ zda_status zda_batch_run(zda_batch *b, const zda_source *sources, int nsteps, co
     hipStream_t hs = (hipStream_t)stream;
     const size_t nz = b->zones.size();
     std::vector<FwdPlan> plans(nz);
+    std::vector<RunBufs> rbs(nz);
     std::vector<std::array<StepArgs, 2>> ab(nz);
     zda_status st;
     for (size_t i = 0; i < nz; ++i) {
         zda_zone *z = b->zones[i];
-        if ((st = forward_setup(z, &sources[i], nsteps, omega, K, dft_flags, hs, plans[i])) != ZDA_OK) return st;
+        z->stream = hs;
+        if ((st = forward_setup(z, &sources[i], nsteps, omega, K, dft_flags, hs, plans[i], rbs[i])) != ZDA_OK)
+            return st;
         if ((st = prepare_run(z, z->d.m, nsteps, sources[i].k_src, plans[i].P, plans[i].prof.data(), omega, K,
-                              plans[i].dplane, plans[i].dvol, plans[i].reset, hs, ab[i].data())) != ZDA_OK)
+                              plans[i].dplane, plans[i].dvol, plans[i].reset, hs, ab[i].data(), rbs[i])) != ZDA_OK)
             return st;
     }
     if ((st = batch_loop(b, ab, nsteps, hs)) != ZDA_OK) return st;
@@ -1681,9 +2053,12 @@ zda_status zda_batch_adjoint_grad(zda_batch *b, const float *const *dF_dE, float
     for (size_t i = 0; i < nz; ++i) {
         zda_zone *z = b->zones[i];
         if (!dF_dE[i] || !grad_rho[i]) return fail(ZDA_ERR_ARG, "NULL pointer for zone %zu", i);
+        z->stream = hs;
         if ((st = adjoint_setup(z, dF_dE[i], 1, 0.0, hs, plans[i])) != ZDA_OK) return st;
+        RunBufs rb;
+        rb.pattern = z->pattern;
         if ((st = prepare_run(z, -z->d.m, plans[i].T, z->d.k_mon, plans[i].K, plans[i].q.data(), z->last_omega,
-                              plans[i].K, nullptr, z->dft_vol_adj, true, hs, ab[i].data())) != ZDA_OK)
+                              plans[i].K, nullptr, z->dft_vol_adj, true, hs, ab[i].data(), rb)) != ZDA_OK)
             return st;
     }
     if ((st = batch_loop(b, ab, T, hs)) != ZDA_OK) return st;

@@ -20,11 +20,13 @@ ZDA_MAX_FREQ = 8
 SRC_PLANE_CIRC, SRC_RADIAL, SRC_CUSTOM = 0, 1, 2
 DFT_PLANE, DFT_VOLUME, RUN_CONTINUE, RUN_TIMING = 1, 2, 4, 8
 MON_PLANE, MON_VOLUME, MON_ADJOINT_VOLUME = 0, 1, 2
-OPT_XCD_REMAP, OPT_NT_STORES, OPT_LAYER_STREAM, OPT_TILE_PATCH, OPT_LAYER_KCHUNK = 1, 2, 3, 4, 5
+OPT_XCD_REMAP, OPT_NT_STORES, OPT_LAYER_STREAM, OPT_TILE_PATCH, OPT_LAYER_KCHUNK, OPT_WATCHDOG = 1, 2, 3, 4, 5, 6
+COMP_R, COMP_PHI, COMP_Z = 1, 2, 4
 COMP = {"Er": 0, "Ephi": 1, "Ez": 2, "Hr": 3, "Hphi": 4, "Hz": 5}
 
-EXPORTS = ["zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_zone_set_eps",
-           "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields", "zda_adjoint_grad",
+EXPORTS = ["zda_set_allocator", "zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_zone_set_eps",
+           "zda_zone_set_design", "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_dft_fields",
+           "zda_adjoint_grad",
            "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_set_launch",
            "zda_zone_set_option",
            "zda_zone_last_timing", "zda_plan_two_step_tiles", "zda_batch_create", "zda_batch_destroy", "zda_batch_run",
@@ -73,7 +75,13 @@ class ZdaError(RuntimeError):
         self.status = status
 
 
+# zda_set_allocator's callback types: alloc(bytes, device, ctx) -> ptr,
+# free(ptr, bytes, device, ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)
+
 _lib = None
+_allocator = None     # keeps the registered callbacks alive
 
 
 def load():
@@ -92,8 +100,11 @@ def load():
     lib.zda_zone_destroy.restype = None
     lib.zda_zone_set_eps.argtypes = [P, P, I]
     lib.zda_zone_set_design.argtypes = [P, P, I]
+    lib.zda_zone_set_stream.argtypes = [P, P]
+    lib.zda_zone_sync.argtypes = [P]
+    lib.zda_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
     lib.zda_fdtd_run.argtypes = [P, ctypes.POINTER(Source), I, P, I, I, P]
-    lib.zda_dft_fields.argtypes = [P, I, P, ctypes.c_size_t, I]
+    lib.zda_dft_fields.argtypes = [P, I, I, P, ctypes.c_size_t, I]
     lib.zda_adjoint_grad.argtypes = [P, P, I, P, I, D, P]
     lib.zda_zone_read_field.argtypes = [P, I, P, I]
     lib.zda_zone_write_field.argtypes = [P, I, P, I]
@@ -114,13 +125,39 @@ def load():
     lib.zda_status_str.restype = ctypes.c_char_p
     lib.zda_last_error.argtypes = []
     lib.zda_last_error.restype = ctypes.c_char_p
-    for name in ("zda_zone_create", "zda_zone_set_eps", "zda_zone_set_design", "zda_fdtd_run", "zda_dft_fields",
+    for name in ("zda_set_allocator", "zda_zone_create", "zda_zone_set_eps", "zda_zone_set_design",
+                 "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_dft_fields",
                  "zda_adjoint_grad", "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info",
                  "zda_zone_last_timing", "zda_zone_set_launch", "zda_zone_set_option", "zda_batch_create",
                  "zda_batch_run", "zda_batch_adjoint_grad", "zda_batch_set_launch", "zda_batch_autotune"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
+
+
+def use_torch_allocator(on=True):
+    """Back the device memory of zones and batches created from now on with
+    torch's caching allocator (on=False restores hipMalloc / hipFree)."""
+    global _allocator
+    lib = load()
+    if not on:
+        _check(lib.zda_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _allocator = None
+        return
+    torch = _torch()
+
+    def _alloc(nbytes, device, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), int(device))
+        except RuntimeError:
+            return None
+
+    def _free(ptr, nbytes, device, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _check(lib.zda_set_allocator(cbs[0], cbs[1], None))
+    _allocator = cbs
 
 
 def _status_name(st):
@@ -257,18 +294,44 @@ class Zone:
         _check(load().zda_zone_last_timing(self._h, ctypes.byref(t)))
         return t
 
-    def dft(self, monitor=MON_PLANE, K=None):
-        """Monitor as a complex64 CUDA tensor ([K][2][nr][nphi] or [K][3][nd][nr][nphi])."""
+    def dft(self, monitor=MON_PLANE, K=None, components=0):
+        """Monitor as a complex64 CUDA tensor ([K][C][nr][nphi] or
+        [K][C][nd][nr][nphi]; C = every component of the monitor, or those
+        whose COMP_* bits `components` sets).  Ordered on the zone's stream."""
         torch = _torch()
         K = self._K if K is None else K
         d = self.desc
+        ncomp = 2 if monitor == MON_PLANE else 3
+        C = ncomp if components == 0 else bin(int(components)).count("1")
         if monitor == MON_PLANE:
-            shape = (K, 2, d.nr, d.nphi)
+            shape = (K, C, d.nr, d.nphi)
         else:
-            shape = (K, 3, d.design_k1 - d.design_k0, d.nr, d.nphi)
+            shape = (K, C, d.design_k1 - d.design_k0, d.nr, d.nphi)
         out = torch.empty(shape, dtype=torch.complex64, device="cuda")
-        _check(load().zda_dft_fields(self._h, monitor, ctypes.c_void_p(out.data_ptr()), 2 * out.numel(), 1))
+        _check(load().zda_dft_fields(self._h, monitor, int(components), ctypes.c_void_p(out.data_ptr()),
+                                     2 * out.numel(), 1))
         return out
+
+    def dft_host(self, monitor=MON_PLANE, K=None, components=0):
+        """The monitor copied into host memory (complex64 numpy array); waits
+        for the zone and raises ZdaError (ZDA_ERR_DIVERGED) after a divergence."""
+        K = self._K if K is None else K
+        d = self.desc
+        ncomp = 2 if monitor == MON_PLANE else 3
+        C = ncomp if components == 0 else bin(int(components)).count("1")
+        shape = (K, C, d.nr, d.nphi) if monitor == MON_PLANE else (K, C, d.design_k1 - d.design_k0, d.nr, d.nphi)
+        out = np.empty(shape, np.complex64)
+        _check(load().zda_dft_fields(self._h, monitor, int(components), ctypes.c_void_p(out.ctypes.data),
+                                     2 * out.size, 0))
+        return out
+
+    def sync(self):
+        """Wait for the zone's stream; raises ZdaError (ZDA_ERR_DIVERGED) if
+        the divergence watchdog fired since the last resetting run."""
+        _check(load().zda_zone_sync(self._h))
+
+    def set_stream(self, stream):
+        _check(load().zda_zone_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
 
     def adjoint_grad(self, dF_dE, adj_width=0.0, stream=None):
         torch = _torch()

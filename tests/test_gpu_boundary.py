@@ -1,0 +1,172 @@
+"""The C ABI's boundary semantics on the GPU: monitor component selection,
+the divergence watchdog, stream ordering of reads, host and device inputs,
+and zone memory from a caller's allocator (torch's caching allocator)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-boundary]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def zda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_07979_amd import zda as Z
+    Z.load()
+    return Z
+
+
+def _small():
+    from paper_2501_07979_amd.workloads import Workload
+    return Workload("boundary_30x64x40", r_in=200.0, nr=30, nphi=64, nz=40, n_fold=16, pml=(4, 4, 4, 4), k_src=8,
+                    k_mon=30, design=(14, 18), k_sub=14, steps=120, omegas=(0.28, 0.31, 0.34), omega_c=0.31,
+                    width=8.0, seed=13)
+
+
+def _run(zone, wl, **kw):
+    zone.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width, **kw)
+
+
+def test_component_mask(zda):
+    wl = _small()
+    z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    _run(z, wl, volume=True)
+    plane = z.dft(zda.MON_PLANE).cpu().numpy()
+    vol = z.dft(zda.MON_VOLUME).cpu().numpy()
+    assert np.array_equal(z.dft(zda.MON_PLANE, components=zda.COMP_PHI).cpu().numpy(), plane[:, 1:2])
+    assert np.array_equal(z.dft(zda.MON_PLANE, components=zda.COMP_R | zda.COMP_PHI).cpu().numpy(), plane)
+    assert np.array_equal(z.dft(zda.MON_VOLUME, components=zda.COMP_R | zda.COMP_Z).cpu().numpy(), vol[:, [0, 2]])
+    assert np.array_equal(z.dft_host(zda.MON_VOLUME, components=zda.COMP_Z), vol[:, 2:3])
+    with pytest.raises(zda.ZdaError) as e:
+        z.dft(zda.MON_PLANE, components=zda.COMP_Z)
+    assert e.value.status == zda.ZDA_ERR_ARG
+    z.close()
+
+
+@pytest.mark.parametrize("bad", ["nan", "huge"])
+def test_watchdog_reports_divergence(zda, bad):
+    """A non-finite (or beyond-bound) field sample written into a running zone
+    is found by the in-loop check; zda_zone_sync and host reads report it; the
+    next resetting run clears the flag."""
+    import torch
+    wl = _small()
+    z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    z.set_option(zda.OPT_WATCHDOG, 10)
+    _run(z, wl)
+    z.sync()
+    er = z.read_field("Er").cpu().numpy()
+    er[20, 15, 30] = np.nan if bad == "nan" else 1e20
+    z.write_field("Er", er)
+    _say("watchdog", bad)
+    # continue from the planted state: the check after 10 steps sees it
+    z.run(12, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width, cont=True)
+    with pytest.raises(zda.ZdaError) as e:
+        z.sync()
+    assert e.value.status == zda.ZDA_ERR_DIVERGED
+    with pytest.raises(zda.ZdaError) as e:
+        z.dft_host(zda.MON_PLANE)
+    assert e.value.status == zda.ZDA_ERR_DIVERGED
+    _run(z, wl)
+    z.sync()
+    assert np.isfinite(z.dft_host(zda.MON_PLANE)).all()
+    z.close()
+    del torch
+
+
+def test_watchdog_off_and_clean_runs(zda):
+    wl = _small()
+    z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    z.set_option(zda.OPT_WATCHDOG, 1)
+    _run(z, wl)
+    z.sync()
+    ref = z.dft_host(zda.MON_PLANE)
+    z.set_option(zda.OPT_WATCHDOG, 0)
+    _run(z, wl)
+    z.sync()
+    # the checks read the fields only: results are identical with and without
+    assert np.array_equal(z.dft_host(zda.MON_PLANE), ref)
+    z.close()
+
+
+def test_run_on_a_side_stream(zda):
+    """Work and device reads are ordered on the zone's stream (a non-default
+    torch stream here); the result equals a run on the default stream."""
+    import torch
+    wl = _small()
+    z0 = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    _run(z0, wl)
+    ref = z0.dft(zda.MON_PLANE).cpu().numpy()
+    z0.close()
+    z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        _run(z, wl)
+        out = z.dft(zda.MON_PLANE)
+        got = out.cpu().numpy()
+    z.sync()
+    assert np.array_equal(got, ref)
+    z.close()
+
+
+def test_host_and_device_inputs_agree(zda):
+    import torch
+    wl = _small()
+    eps = wl.eps()
+    a = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+    b = zda.Zone(zda.default_desc(**wl.desc_kwargs()), torch.from_numpy(eps).cuda())
+    rho = wl.rho()
+    a.set_design(rho)
+    b.set_design(torch.from_numpy(rho).cuda())
+    for z in (a, b):
+        _run(z, wl, volume=True)
+    assert np.array_equal(a.dft_host(zda.MON_PLANE), b.dft_host(zda.MON_PLANE))
+    rng = np.random.default_rng(3)
+    dF = (rng.standard_normal((3, 2, wl.nr, wl.nphi)) + 1j * rng.standard_normal((3, 2, wl.nr, wl.nphi)))
+    dF = dF.astype(np.complex64)
+    ga = a.adjoint_grad(dF).cpu().numpy()
+    # host dF and host gradient through the C ABI
+    gb = np.empty_like(ga)
+    lib = zda.load()
+    d = np.ascontiguousarray(dF)
+    st = lib.zda_adjoint_grad(b._h, ctypes.c_void_p(d.ctypes.data), 0, ctypes.c_void_p(gb.ctypes.data), 0, 0.0,
+                              None)
+    assert st == zda.ZDA_OK, lib.zda_last_error()
+    assert np.array_equal(ga, gb)
+    a.close()
+    b.close()
+
+
+def test_zone_memory_from_torch_allocator(zda):
+    """With torch's caching allocator registered, a zone's device memory comes
+    from it (torch counts it) and goes back on destroy; results are bitwise
+    those of a zone on hipMalloc."""
+    import torch
+    wl = _small()
+    ref_zone = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    _run(ref_zone, wl, volume=True)
+    ref = ref_zone.dft_host(zda.MON_PLANE)
+    ref_zone.close()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    zda.use_torch_allocator(True)
+    try:
+        z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+        during = torch.cuda.memory_allocated()
+        nbytes = z.info().device_bytes
+        _say("torch allocator: %d bytes counted, zone reports %d" % (during - before, nbytes))
+        assert during - before >= nbytes > 0
+        _run(z, wl, volume=True)
+        grown = z.info().device_bytes
+        assert np.array_equal(z.dft_host(zda.MON_PLANE), ref)
+        z.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == before, (torch.cuda.memory_allocated(), before, grown)
+    finally:
+        zda.use_torch_allocator(False)
