@@ -3,12 +3,21 @@
 A step is one leap-frog time step of the whole forward hot path over the
 production zone (n = 512 wedge, 512 x 1024 x 400 cells): the H half-step, the
 E half-step with the soft source sheet and the 3-frequency exit-plane DFT.
-K timed steps run inside one zda_fdtd_run after W warm-up steps; the value is
-cell-updates per second.  The default kernel advances two steps per launch
-(one launch over the tiles without layer cells, one over the rest); the
-dominant kernel's roofline uses its algorithmic bytes per launch over its
-average duration, both measured live with HIP events on the run's stream;
-the FP64 oracle is timed on the host cores on a few steps of the same zone.
+A warm-up run of W steps (which resets fields, auxiliaries and monitors)
+is followed by the timed run of K more steps that continues from it, so the
+per-run reset is outside the timed region and timed separately; every
+per-step piece (source profile and twiddle staging, the update launches,
+the divergence checks) is inside.  The value is cell-updates per second.
+The default kernel advances two steps per launch (one launch over the tiles
+without layer cells, one over the rest).  The dominant kernel's roofline
+takes its algorithmic bytes per launch -- 100 B per cell-update (six complex
+fields read and written once per step, dt/eps read) plus 2 x 8 B per DFT
+accumulator per step, times the cell-updates of one launch -- over its
+average launch duration, both measured live with HIP events on the run's
+stream; the least HBM traffic the launch can have (every field crosses HBM
+once per two steps) is reported beside it.  The FP64 oracle is timed on the
+host cores on a bounded sample of the same zone and on the small parity and
+gradient zones.
 """
 from __future__ import annotations
 
@@ -63,6 +72,24 @@ def two_step_interior_bytes(tm, K):
     return 100 * tm.e_cells + K * 32 * tm.e_mon_cells + 16 * tm.e_src_cells
 
 
+def interior_b_alg_per_launch(tm, K):
+    """Algorithmic bytes of one launch over interior tiles counted per
+    cell-update: 100 B per cell-update (read and write the six complex fields,
+    read dt/eps), 2 x 8 B per DFT accumulator per step (2 K on an exit-plane
+    cell), 2 x 8 B per source cell per step, times the steps of one launch."""
+    return tm.steps_per_launch * (100 * tm.e_cells + K * 32 * tm.e_mon_cells + 16 * tm.e_src_cells)
+
+
+def zone_b_alg_per_step(wl, K):
+    """Whole-zone algorithmic bytes per time step counted per cell-update:
+    100 B per cell, 2 x 8 B per stretched-coordinate auxiliary (8 terms in an
+    r-layer cell, 4 in a z-layer cell), the exit-plane DFT and the source."""
+    plane = wl.nr * wl.nphi
+    r_cells = (wl.pml[0] + wl.pml[1]) * wl.nphi * wl.nz
+    z_cells = (wl.pml[2] + wl.pml[3]) * plane
+    return 100 * wl.cells + 128 * r_cells + 64 * z_cells + K * 32 * plane + 16 * plane
+
+
 def two_step_zone_bytes(wl, K):
     """Whole-zone minimum per two-step launch pair (interior and layer tiles):
     100 B per cell, r-layer cells 10 auxiliaries x 16 B, z-layer cells 4 x 16
@@ -88,11 +115,29 @@ def load_traffic(kernel, wl_name, launch=None):
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s=12.0, max_steps=12):
-    """The FP64 oracle on the same zone for a few steps (whole zone, full
-    source and DFT work), timed after one untimed step."""
+def host_info():
+    """Host CPU model, logical CPU count and the oracle's thread count."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     from oracle import oracle
-    eps = wl.eps()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "oracle_threads": oracle.num_threads()}
+
+
+def cpu_baseline(wl, eps=None, budget_s=12.0, max_steps=12):
+    """The FP64 oracle on a bounded sample of the same zone (whole zone, full
+    source and DFT work, a few steps after one untimed step), and in full on
+    the parity zone (64 x 64 x 96, 1000 steps) and on the gradient zone's
+    small copy (64 x 64 x 96, 2500 steps forward with the design-layer DFT
+    plus the adjoint run and overlap)."""
+    from oracle import oracle
+    if eps is None:
+        eps = wl.eps()
     oz = oracle.OracleZone(**wl.desc_kwargs(), eps=eps)
     del eps
     g, n0 = oracle.pulse(max_steps + 1, oz.dt, wl.omega_c, wl.width)
@@ -105,10 +150,32 @@ def cpu_baseline(wl, budget_s=12.0, max_steps=12):
                n_start=steps + 1)
         steps += 1
     dt = time.perf_counter() - t0
-    return {"value": round(wl.cells * steps / dt / 1e9, 5), "unit": "Gcell-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d time steps of the full %s zone (FP64, whole-zone H+E updates, source, 3-frequency "
-                      "exit-plane DFT), after one untimed step, %.1f s" % (steps, wl.name, dt)}
+    del oz
+    out = {"value": round(wl.cells * steps / dt / 1e9, 5), "unit": "Gcell-updates/s",
+           "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": "%d time steps of the full %s zone (FP64, whole-zone H+E updates, source, 3-frequency "
+                     "exit-plane DFT), after one untimed step, %.1f s" % (steps, wl.name, dt),
+           "host": host_info()}
+    from paper_2501_07979_amd.workloads import c1, c3_small
+    w1 = c1()
+    o1 = oracle.OracleZone(**w1.desc_kwargs(), eps=w1.eps())
+    t0 = time.perf_counter()
+    o1.forward(w1.steps, np.array(w1.omegas), omega_c=w1.omega_c, width=w1.width, k_src=w1.k_src)
+    t1 = time.perf_counter() - t0
+    out["c1_parity_full"] = {"workload": w1.name, "steps": w1.steps, "s": round(t1, 3),
+                             "gcell_updates_per_s": round(w1.cells * w1.steps / t1 / 1e9, 5)}
+    w3 = c3_small()
+    o3 = oracle.OracleZone(**w3.desc_kwargs(), eps=w3.eps())
+    t0 = time.perf_counter()
+    fwd = o3.forward(w3.steps, np.array(w3.omegas), omega_c=w3.omega_c, width=w3.width, k_src=w3.k_src,
+                     volume=True)
+    rng = np.random.default_rng(5)
+    wts = rng.standard_normal(fwd["plane"].shape) + 1j * rng.standard_normal(fwd["plane"].shape)
+    o3.adjoint_grad(np.conj(np.sum(wts * fwd["plane"])) * wts)
+    t3 = time.perf_counter() - t0
+    out["c3_small_forward_adjoint"] = {"workload": w3.name, "steps_per_run": w3.steps, "runs": 2, "s": round(t3, 3),
+                                       "gcell_updates_per_s": round(2 * w3.cells * w3.steps / t3 / 1e9, 5)}
+    return out
 
 
 def design_iteration(steps=None):
@@ -322,7 +389,8 @@ def main():
     wl = WORKLOADS[args.workload]()
     K = len(wl.omegas)
     print("bench: building %s (%d cells)" % (wl.name, wl.cells), file=sys.stderr, flush=True)
-    eps = torch.from_numpy(wl.eps()).cuda()
+    eps_host = wl.eps()
+    eps = torch.from_numpy(eps_host).cuda()
     zone = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
     del eps
     run_kw = dict(k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
@@ -332,16 +400,24 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    stream = torch.cuda.current_stream()
+    # the run's reset (fills of both buffer sets, auxiliaries, monitors), timed on its own
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    zone.run(0, wl.omegas, **run_kw)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    reset_ms = r0.elapsed_time(r1)
     print("bench: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
     zone.run(args.warmup, wl.omegas, **run_kw)
     torch.cuda.synchronize()
     print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
-    stream = torch.cuda.current_stream()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    zone.run(args.steps, wl.omegas, timing=True, **run_kw)
+    # continues the warmed-up run: no reset inside the timed region
+    zone.run(args.steps, wl.omegas, timing=True, cont=True, **run_kw)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -349,17 +425,21 @@ def main():
     tm = zone.last_timing()
     info = zone.info()
     launch = {"tile_rows": info.tile_rows, "kchunk": info.kchunk}
-    # sanity: the run produced finite monitors
+    # sanity: the run produced finite monitors, and no divergence was flagged
     plane = zone.dft(zda.MON_PLANE)
     assert torch.isfinite(torch.view_as_real(plane)).all().item()
+    zone.sync()
     zone.close()
 
     gcells = wl.cells * args.steps / (ms / 1e3) / 1e9
     hb, eb, fused = algorithmic_bytes(wl, K)
     e_avg = tm.e_ms / tm.e_launches
     kernel_ms = {}
+    min_bytes = None
     if tm.steps_per_launch == 2:   # two-step kernel: interior tiles + tiles with layer cells
-        kernel, kbytes = "eh2_kernel_interior", two_step_interior_bytes(tm, K)
+        kernel = "eh2_kernel_interior"
+        kbytes = interior_b_alg_per_launch(tm, K)
+        min_bytes = two_step_interior_bytes(tm, K)
         kernel_ms = {"eh2_kernel_interior": round(e_avg, 5),
                      "eh2_kernel_layer": round(tm.layer_ms / tm.layer_launches, 5)}
         zone_min = two_step_zone_bytes(wl, K) / 2
@@ -376,6 +456,20 @@ def main():
         family = "split"
     achieved = kbytes / (e_avg / 1e3) / 1e9
     traffic = load_traffic(kernel, wl.name, launch)
+    zone_balg = zone_b_alg_per_step(wl, K) / wl.cells
+    roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes_per_launch": kbytes,
+            "algorithmic_bytes": "per cell-update: 100 B + 2 x 8 B per DFT accumulator and source sample",
+            "cell_updates_per_launch": tm.e_cells * tm.steps_per_launch,
+            "cells_per_launch": tm.e_cells, "steps_per_launch": tm.steps_per_launch,
+            "avg_launch_ms": round(e_avg, 5)}
+    if min_bytes is not None:
+        # the least HBM traffic of the launch: each field read and written
+        # once per two steps; its rate against peak is what HBM delivers
+        roof["min_traffic_bytes_per_launch"] = min_bytes
+        roof["min_traffic_achieved"] = round(min_bytes / (e_avg / 1e3) / 1e9, 1)
+        roof["min_traffic_frac"] = round(min_bytes / (e_avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     out = {
         "metric": METRIC,
         "value": round(gcells, 4),
@@ -400,14 +494,15 @@ def main():
             "launch": launch,
             "steps_per_launch": tm.steps_per_launch,
             "kernel_ms_per_launch": kernel_ms,
+            "timed_region": "continues the warm-up run (no reset inside); per-run reset timed apart",
+            "reset_ms_per_run": round(reset_ms, 3),
             "wall_s": round(wall, 3),
+            "zone_b_alg_bytes_per_cell_update": round(zone_balg, 2),
+            "zone_b_alg_roofline_frac": round(gcells * 1e9 * zone_balg / (HBM_PEAK_GBS * 1e9), 4),
             "min_hbm_bytes_per_cell_update": round(zone_min / wl.cells, 2),
             "zone_min_bytes_roofline_frac": round(gcells * 1e9 * (zone_min / wl.cells) / (HBM_PEAK_GBS * 1e9), 4),
         },
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": kbytes,
-                     "cells_per_launch": tm.e_cells, "steps_per_launch": tm.steps_per_launch},
+        "roofline": roof,
     }
     if not args.no_design_iter and args.workload == "c2":
         print("bench: one design iteration on the gradient zone", file=sys.stderr, flush=True)
@@ -417,7 +512,8 @@ def main():
         out["surrogate_design"] = surrogate_design()
     if not args.no_cpu_baseline:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, eps_host)
+    del eps_host
     print(json.dumps(out), flush=True)
 
 
