@@ -221,6 +221,35 @@ typedef struct {
 zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const double *omega, int K,
                         int dft_flags, void *stream);
 
+/*
+ * zda_fdtd_run for callers that cannot allocate (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same run with
+ * the same kernels and results, whose per-run staging (source patterns,
+ * pulse profiles, DFT twiddles, the two-step tile list) goes to a fixed
+ * device scratch array of the library, ZDA_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from the first call on that GPU until the process ends.  It calls no
+ * hipMalloc / hipFree, no pinned-host allocation and no allocator registered
+ * with zda_set_allocator; the zone (created beforehand) brings its own field
+ * memory, and a ZDA_DFT_VOLUME run needs the design-layer buffer that a
+ * first zda_fdtd_run with ZDA_DFT_VOLUME allocates (ZDA_ERR_STATE
+ * otherwise).  Limits, each refused with ZDA_ERR_ARG before any work is
+ * enqueued: source patterns * 2 * nr * nphi <= ZDA_NOALLOC_PATTERN complex
+ * samples, nsteps * patterns <= ZDA_NOALLOC_STEPS and nsteps * K <=
+ * ZDA_NOALLOC_STEPS, at most ZDA_NOALLOC_TILES two-step tiles; ZDA_RUN_TIMING
+ * is refused.  The staging is written from the zone's pageable host vectors,
+ * and the call waits for `stream` before it returns so that the next call
+ * may rewrite them.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (on different streams or threads) race and must
+ * not be made.  The concurrent layer-tile stream option is not used here.
+ */
+#define ZDA_NOALLOC_PATTERN (1u << 20)   /* complex samples (8 MiB) */
+#define ZDA_NOALLOC_STEPS (1u << 17)     /* complex samples each for profiles and twiddles (1 MiB each) */
+#define ZDA_NOALLOC_TILES (1u << 16)     /* 16-byte two-step tile descriptors (1 MiB) */
+#define ZDA_NOALLOC_SCRATCH_BYTES \
+    (8u * (ZDA_NOALLOC_PATTERN + 2u * ZDA_NOALLOC_STEPS) + 16u * ZDA_NOALLOC_TILES)
+zda_status zda_fdtd_run_noalloc(zda_zone *z, const zda_source *s, int nsteps, const double *omega, int K,
+                                int dft_flags, void *stream);
+
 /* monitor ids */
 #define ZDA_MON_PLANE  0      /* layout [K][2][nr][nphi] complex (E_r, E_phi at k_mon) */
 #define ZDA_MON_VOLUME 1      /* layout [K][3][design_k1-design_k0][nr][nphi] complex */

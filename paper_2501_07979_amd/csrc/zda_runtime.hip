@@ -1504,6 +1504,99 @@ zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const doub
     return ZDA_OK;
 }
 
+namespace {
+
+// Device scratch of zda_fdtd_run_noalloc: [pattern | profiles | twiddles |
+// tile list], one copy per GPU for the life of the process.  Host code never
+// passes `scratch` itself (in host code it is a stand-in, not a device
+// address): it uses the address hipGetSymbolAddress returns on each device.
+constexpr size_t NA_PATTERN = ZDA_NOALLOC_PATTERN, NA_STEPS = ZDA_NOALLOC_STEPS, NA_TILES = ZDA_NOALLOC_TILES;
+constexpr size_t NA_F2 = NA_PATTERN + 2 * NA_STEPS + 2 * NA_TILES;   // float2 units (a tile is two)
+static_assert(NA_F2 * sizeof(float2) == ZDA_NOALLOC_SCRATCH_BYTES, "scratch size");
+
+}  // namespace
+
+static __device__ __align__(256) float2 scratch[NA_F2];
+
+namespace {
+
+constexpr int NA_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+float2 *g_scratch_dev[NA_MAX_DEV] = {};
+
+// the scratch array's address on `dev` (the current device), looked up once
+zda_status scratch_on(int dev, float2 **out)
+{
+    if (dev < 0 || dev >= NA_MAX_DEV) return fail(ZDA_ERR_UNSUPPORTED, "device %d beyond %d", dev, NA_MAX_DEV);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ZDA_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = (float2 *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return ZDA_OK;
+}
+
+}  // namespace
+
+zda_status zda_fdtd_run_noalloc(zda_zone *z, const zda_source *s, int nsteps, const double *omega, int K,
+                                int dft_flags, void *stream)
+{
+    if (!z || !s) return fail(ZDA_ERR_ARG, "NULL zone or source");
+    if (dft_flags & ZDA_RUN_TIMING) return fail(ZDA_ERR_ARG, "ZDA_RUN_TIMING is not available without allocation");
+    if (nsteps < 0 || K < 0 || K > ZDA_MAX_FREQ) return fail(ZDA_ERR_ARG, "bad nsteps or K");
+    if (s->k_src < 1 || s->k_src >= z->d.nz) return fail(ZDA_ERR_ARG, "k_src must be in [1, nz)");
+    if (s->kind == ZDA_SRC_CUSTOM && (s->n_profiles < 1 || s->n_profiles > ZDA_MAX_FREQ))
+        return fail(ZDA_ERR_ARG, "CUSTOM needs 1..%d patterns and profiles", ZDA_MAX_FREQ);
+    const size_t P = (size_t)source_patterns(s), T = (size_t)std::max(nsteps, 1);
+    if (P * 2 * z->plane > NA_PATTERN)
+        return fail(ZDA_ERR_ARG, "%zu pattern samples exceed the no-allocation limit %zu", P * 2 * z->plane,
+                    NA_PATTERN);
+    if (T * P > NA_STEPS || T * (size_t)std::max(K, 1) > NA_STEPS)
+        return fail(ZDA_ERR_ARG, "nsteps %d with %zu profiles and %d frequencies exceeds the no-allocation limit %zu",
+                    nsteps, P, K, NA_STEPS);
+    DeviceGuard g(z->device);
+    float2 *base = nullptr;
+    zda_status st = scratch_on(z->device, &base);
+    if (st != ZDA_OK) return st;
+    RunBufs rb;
+    rb.noalloc = true;
+    rb.pattern = base;
+    rb.cap_pattern = NA_PATTERN;
+    rb.profile = base + NA_PATTERN;
+    rb.cap_profile = NA_STEPS;
+    rb.twiddle = rb.profile + NA_STEPS;
+    rb.cap_twiddle = NA_STEPS;
+    rb.tiles = (uint4 *)(rb.twiddle + NA_STEPS);
+    rb.cap_tiles = NA_TILES;
+    TileCounts tc;
+    if (z->two) {
+        // the tile list depends on the source plane, known before the run
+        z->k_src_last = s->k_src;
+        plan_zone_tiles(z, z->st_tiles, tc);
+        if (z->st_tiles.size() > NA_TILES)
+            return fail(ZDA_ERR_ARG, "%zu two-step tiles exceed the no-allocation limit %zu", z->st_tiles.size(),
+                        NA_TILES);
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    z->stream = hs;
+    FwdPlan plan;
+    if ((st = forward_setup(z, s, nsteps, omega, K, dft_flags, hs, plan, rb)) != ZDA_OK) return st;
+    if (z->two)
+        HIP_TRY(hipMemcpyAsync(rb.tiles, z->st_tiles.data(), z->st_tiles.size() * sizeof(uint4),
+                               hipMemcpyHostToDevice, hs));
+    if ((st = run_loop(z, z->d.m, nsteps, s->k_src, plan.P, plan.prof.data(), omega, K, plan.dplane, plan.dvol,
+                       plan.reset, hs, rb, false, &tc)) != ZDA_OK)
+        return st;
+    // the next call rewrites the pageable host staging these copies read
+    HIP_TRY(hipStreamSynchronize(hs));
+    forward_finish(z, plan, nsteps, omega, K);
+    return ZDA_OK;
+}
+
 zda_status zda_dft_fields(zda_zone *z, int monitor, int component_mask, float *out, size_t out_floats,
                           int out_on_device)
 {

@@ -25,7 +25,8 @@ COMP_R, COMP_PHI, COMP_Z = 1, 2, 4
 COMP = {"Er": 0, "Ephi": 1, "Ez": 2, "Hr": 3, "Hphi": 4, "Hz": 5}
 
 EXPORTS = ["zda_set_allocator", "zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_zone_set_eps",
-           "zda_zone_set_design", "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_dft_fields",
+           "zda_zone_set_design", "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_fdtd_run_noalloc",
+           "zda_dft_fields",
            "zda_adjoint_grad",
            "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_set_launch",
            "zda_zone_set_option",
@@ -104,6 +105,7 @@ def load():
     lib.zda_zone_sync.argtypes = [P]
     lib.zda_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
     lib.zda_fdtd_run.argtypes = [P, ctypes.POINTER(Source), I, P, I, I, P]
+    lib.zda_fdtd_run_noalloc.argtypes = [P, ctypes.POINTER(Source), I, P, I, I, P]
     lib.zda_dft_fields.argtypes = [P, I, I, P, ctypes.c_size_t, I]
     lib.zda_adjoint_grad.argtypes = [P, P, I, P, I, D, P]
     lib.zda_zone_read_field.argtypes = [P, I, P, I]
@@ -126,8 +128,9 @@ def load():
     lib.zda_last_error.argtypes = []
     lib.zda_last_error.restype = ctypes.c_char_p
     for name in ("zda_set_allocator", "zda_zone_create", "zda_zone_set_eps", "zda_zone_set_design",
-                 "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_dft_fields",
-                 "zda_adjoint_grad", "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info",
+                 "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_fdtd_run_noalloc",
+                 "zda_dft_fields", "zda_adjoint_grad", "zda_zone_read_field", "zda_zone_write_field",
+                 "zda_zone_get_info",
                  "zda_zone_last_timing", "zda_zone_set_launch", "zda_zone_set_option", "zda_batch_create",
                  "zda_batch_run", "zda_batch_adjoint_grad", "zda_batch_set_launch", "zda_batch_autotune"):
         getattr(lib, name).restype = I
@@ -263,8 +266,11 @@ class Zone:
         _check(load().zda_zone_set_design(self._h, ptr, dev))
 
     def run(self, nsteps, omegas=(), *, kind=SRC_PLANE_CIRC, k_src=1, omega_c=0.0, width=1.0, n0=-1,
-            patterns=None, profiles=None, plane=True, volume=False, cont=False, timing=False, stream=None):
-        """Time-step (asynchronous on the current torch stream)."""
+            patterns=None, profiles=None, plane=True, volume=False, cont=False, timing=False, stream=None,
+            noalloc=False):
+        """Time-step (asynchronous on the current torch stream).  noalloc:
+        through zda_fdtd_run_noalloc (staging in the library's fixed device
+        scratch; waits for the stream before it returns)."""
         torch = _torch()
         s = Source()
         s.kind, s.k_src, s.omega_c, s.width, s.n0 = kind, k_src, omega_c, width, n0
@@ -285,8 +291,9 @@ class Zone:
         flags = (DFT_PLANE if plane else 0) | (DFT_VOLUME if volume else 0) | (RUN_CONTINUE if cont else 0) | \
             (RUN_TIMING if timing else 0)
         self.state_serial += 1
-        _check(load().zda_fdtd_run(self._h, ctypes.byref(s), int(nsteps), ctypes.c_void_p(om.ctypes.data),
-                                   int(om.size), flags, _stream_ptr(torch, stream)))
+        fn = load().zda_fdtd_run_noalloc if noalloc else load().zda_fdtd_run
+        _check(fn(self._h, ctypes.byref(s), int(nsteps), ctypes.c_void_p(om.ctypes.data), int(om.size), flags,
+                  _stream_ptr(torch, stream)))
         self._K = int(om.size)
 
     def last_timing(self) -> Timing:
