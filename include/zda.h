@@ -242,6 +242,25 @@ zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const doub
  * that overlap on one GPU (on different streams or threads) race and must
  * not be made.  The concurrent layer-tile stream option is not used here.
  */
+/*
+ * The forward leap-frog of zda_fdtd_run (section on the cylindrical solver:
+ * eq. 3-5 with the zone's PMLs, the soft source sheet, the exit-plane DTFT)
+ * in FP64: fields, layer auxiliaries, coefficients, source and DFT all in
+ * double precision, stepped by the in-place H and E kernel pair.  It exists
+ * for finite-difference checks of the FP32 adjoint gradient (eq. 6 overlap):
+ * the objective change from one design pixel lies below FP32 rounding, not
+ * below FP64's.  eps: nz*nr*nphi FP64 permittivity [k][i][j] (host or device;
+ * the zone's own FP32 map is not used, so a check can move a pixel by less
+ * than an FP32 ulp); the zone supplies geometry, layers and k_mon.  Preset
+ * sources only (ZDA_ERR_UNSUPPORTED otherwise); 1 <= K <= ZDA_MAX_FREQ.
+ * plane_out: [K][2][nr][nphi] complex FP64 (2*K*2*nr*nphi doubles), host or
+ * device.  The first call allocates the FP64 state (six complex FP64 fields,
+ * dt/eps, auxiliaries: about 104 B per cell), kept until zda_zone_destroy;
+ * the zone's FP32 state is untouched.  Waits for `stream` before it returns.
+ */
+zda_status zda_fdtd_run_fp64(zda_zone *z, const double *eps, int eps_on_device, const zda_source *s, int nsteps,
+                             const double *omega, int K, double *plane_out, int out_on_device, void *stream);
+
 #define ZDA_NOALLOC_PATTERN (1u << 20)   /* complex samples (8 MiB) */
 #define ZDA_NOALLOC_STEPS (1u << 17)     /* complex samples each for profiles and twiddles (1 MiB each) */
 #define ZDA_NOALLOC_TILES (1u << 16)     /* 16-byte two-step tile descriptors (1 MiB) */
@@ -373,6 +392,14 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 /* ZDA_OPT_WATCHDOG: steps between the in-loop divergence checks of all six
  * fields (default 1000; 0 = off; see zda_zone_sync). */
 #define ZDA_OPT_WATCHDOG 6
+/* ZDA_OPT_LAYER_CARRY: 1 = the two-step kernel's tiles with layer cells keep
+ * the level-(n+1) recursion auxiliaries of step one in registers for step
+ * two (tiles with r-layer rows in blocks of 7 owned rows, z-layer-only tiles
+ * in their own launch) instead of passing them through the intermediate set
+ * in device memory; 0 = through the intermediate set; -1 (default) = 1 when
+ * the zone has at least 1024 layer tiles (its layer launch fills the CUs
+ * several times over).  Same results either way. */
+#define ZDA_OPT_LAYER_CARRY 7
 zda_status zda_zone_set_option(zda_zone *z, int option, int value);
 
 zda_status zda_zone_get_info(const zda_zone *z, zda_zone_info *info);
@@ -404,18 +431,21 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
  * 13 or 34 (flat mapping: tiles own 256 / nphi - 3 rows and every phi cell,
  * nphi <= 32); kchunk >= 1 planes per chunk; k_src: the source plane (only the
  * cell counts depend on it); order: 0 natural, 1 contiguous range per XCD
- * (ZDA_OPT_XCD_REMAP), else a patch code (ZDA_OPT_TILE_PATCH).  out (may be
+ * (ZDA_OPT_XCD_REMAP), else a patch code (ZDA_OPT_TILE_PATCH), with
+ * ZDA_PLAN_CARRY or-ed in for the plan of ZDA_OPT_LAYER_CARRY.  out (may be
  * NULL to query the count): 4 uint32 per tile, {phi block, first owned row |
  * row count << 16, first plane | end plane << 16, kind}, kind 0 for the
  * interior tiles (their computed rows i0-2 .. i0+rows and planes kb-2 .. ke
  * hold no layer cell; they own 56 phi cells) and 3 for the layer tiles (61
- * phi cells; with tile_rows 34, 2 for the tiles whose computed rows hold no
- * r-layer cell and 3 for the others), interior tiles first; cap: capacity
- * of out in tiles.
+ * phi cells; with tile_rows 34 or ZDA_PLAN_CARRY, 2 for the tiles whose
+ * computed rows hold no r-layer cell; with ZDA_PLAN_CARRY, 1 for the others,
+ * which own at most 7 rows), interior tiles first; cap: capacity of out in
+ * tiles.
  * *ntiles and *n_interior receive the counts.  Errors: ZDA_ERR_ARG (sizes
  * < 1, nr or nz > 65535, a layer wider than half the extent, tile_rows not 5,
  * 13 or 34, 34 with nphi > 32, kchunk < 1, a patch field of 0, out too
  * small). */
+#define ZDA_PLAN_CARRY (1 << 16)
 zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kchunk, int k_src, int order,
                                    uint32_t *out, size_t cap, size_t *ntiles, size_t *n_interior);
 

@@ -8,62 +8,77 @@
 
 namespace zda {
 
-// Per-radial-row constants (index i, FP32, computed in FP64 on the host).
-// "int" = at r_i, "half" = at r_{i+1/2}.
-struct RowCoef {
-    float inv_rdphi_int, inv_rdphi_half;   // 1/(r dphi)
-    float inv_2r_int, inv_2r_half;         // 1/(2 r)
+// Complex sample type of a real type (interleaved re, im).
+template <typename R> struct CplxOf;
+template <> struct CplxOf<float> { using T = float2; };
+template <> struct CplxOf<double> { using T = double2; };
+
+// Per-radial-row constants (index i, computed in FP64 on the host, rounded
+// to R).  "int" = at r_i, "half" = at r_{i+1/2}.
+template <typename R>
+struct RowCoefT {
+    R inv_rdphi_int, inv_rdphi_half;   // 1/(r dphi)
+    R inv_2r_int, inv_2r_half;         // 1/(2 r)
     // divide-by-stretch recursions y = g1 x - g2 u, u <- c u + dt y
-    float g1_s_int, g2_s_int, g1_s_half, g2_s_half;   // radial lengths l = dr (1 + sigma F)
-    float g1_t_int, g2_t_int, g1_t_half, g2_t_half;   // radius ratio R / r = 1 + (Sigma/r) F
-    float hz_c1, hz_c0;                    // Sigma_{i+1}/(r_{i+1/2} dr), Sigma_i/(r_{i+1/2} dr)
-    float ez_c1, ez_c0;                    // Sigma_{i+1/2}/(r_i dr), Sigma_{i-1/2}/(r_i dr)
+    R g1_s_int, g2_s_int, g1_s_half, g2_s_half;   // radial lengths l = dr (1 + sigma F)
+    R g1_t_int, g2_t_int, g1_t_half, g2_t_half;   // radius ratio R / r = 1 + (Sigma/r) F
+    R hz_c1, hz_c0;                    // Sigma_{i+1}/(r_{i+1/2} dr), Sigma_i/(r_{i+1/2} dr)
+    R ez_c1, ez_c0;                    // Sigma_{i+1/2}/(r_i dr), Sigma_{i-1/2}/(r_i dr)
 };
+using RowCoef = RowCoefT<float>;
 
-struct ZCoef {
-    float g1_int, g2_int, g1_half, g2_half;   // axial lengths dz (1 + sigma_z F)
+template <typename R>
+struct ZCoefT {
+    R g1_int, g2_int, g1_half, g2_half;   // axial lengths dz (1 + sigma_z F)
 };
+using ZCoef = ZCoefT<float>;
 
-// Arguments of the update kernels (passed by value).
-struct StepArgs {
+// Arguments of the update kernels (passed by value).  R = float is the
+// production path; R = double instantiates the in-place kernel pair for the
+// FP64 verification runs.
+template <typename R>
+struct StepArgsT {
+    using C = typename CplxOf<R>::T;
     int nr, nphi, nz;
     int pr0, pr1, pz0, pz1;        // layer widths
     int dR, dZ;                    // slab thicknesses
-    float dt, inv_dr, inv_dz;
-    float cr, cz;                  // exp(-alpha dt)
-    float2 seam_p, seam_m;         // exp(+i m tau), exp(-i m tau); 1 +- i m in a continuous zone
+    R dt, inv_dr, inv_dz;
+    R cr, cz;                      // exp(-alpha dt)
+    C seam_p, seam_m;              // exp(+i m tau), exp(-i m tau); 1 +- i m in a continuous zone
     int axis;                      // 1: row 0 is next to the axis (updated, no wall)
     // fields [nz][nr][nphi]
-    float2 *Er, *Ep, *Ez, *Hr, *Hp, *Hz;
-    const float *ceps;             // dt/eps per cell
-    float2 *auxR;                  // [10][nz][dR][nphi]
-    float2 *auxZ;                  // [4][dZ][nr][nphi]
-    const RowCoef *rows;           // [nr]
-    const ZCoef *zrows;            // [nz]
+    C *Er, *Ep, *Ez, *Hr, *Hp, *Hz;
+    const R *ceps;                 // dt/eps per cell
+    C *auxR;                       // [10][nz][dR][nphi]
+    C *auxZ;                       // [4][dZ][nr][nphi]
+    const RowCoefT<R> *rows;       // [nr]
+    const ZCoefT<R> *zrows;        // [nz]
     // source
     int k_src, n_prof;
-    const float2 *pattern;         // [P][2][nr][nphi]
-    const float2 *profile;         // [T][P]
+    const C *pattern;              // [P][2][nr][nphi]
+    const C *profile;              // [T][P]
     // DFT
     int K;
-    const float2 *twiddle;         // [T][K]: dt e^{i w_k (n+1) dt}
+    const C *twiddle;              // [T][K]: dt e^{i w_k (n+1) dt}
     int k_mon;
-    float2 *dft_plane;             // [K][2][nr][nphi] or null
+    C *dft_plane;                  // [K][2][nr][nphi] or null
     int k0, k1;
-    float2 *dft_vol;               // [K][3][k1-k0][nr][nphi] or null
+    C *dft_vol;                    // [K][3][k1-k0][nr][nphi] or null
     int kchunk;                    // planes per z-chunk
     int tile_rows;                 // radial rows per block (1, 2, 4, 8, 16 split; 3, 7, 15 fused; 5, 13 two-step),
                                    // or a flat-mapping code (32, 33, 34)
     // fused step: fields and auxiliaries read from the set above, written here
-    float2 *oEr, *oEp, *oEz, *oHr, *oHp, *oHz;
-    float2 *oauxR, *oauxZ;
+    C *oEr, *oEp, *oEz, *oHr, *oHp, *oHz;
+    C *oauxR, *oauxZ;
     int xcd_remap;                 // fused: contiguous tile ranges per XCD
     int nt_stores;                 // fused: non-temporal stores of the next buffer set
     // two-step launch: auxiliaries at the intermediate time level and the
     // linear indices of the tiles this launch covers
-    float2 *mauxR, *mauxZ;
+    C *mauxR, *mauxZ;
     const uint4 *tiles;            // {phi block, first row | rows << 16, kb | ke << 16, 0}
 };
+using StepArgs = StepArgsT<float>;
+using StepArgs64 = StepArgsT<double>;
 
 // Batched launch over many zones: per-zone argument blocks in device memory
 // and the first block index of each zone (prefix sums of tile counts).
@@ -82,6 +97,13 @@ enum { ZAUX_HR, ZAUX_HP, ZAUX_ER, ZAUX_EP, N_AUX_Z };
 
 void launch_h_step(const StepArgs &a, int n, hipStream_t s);
 void launch_e_step(const StepArgs &a, int n, hipStream_t s);
+// the in-place H and E kernels (4 rows x 64 phi cells per block) in FP64:
+// fields, auxiliaries, coefficients, source and exit-plane DFT all double
+void launch_h_step64(const StepArgs64 &a, int n, hipStream_t s);
+void launch_e_step64(const StepArgs64 &a, int n, hipStream_t s);
+void launch_fill64(double2 *p, size_t n, hipStream_t s);
+// ceps = dt / eps elementwise in FP64
+void launch_inv_eps64(double *ceps, const double *eps, size_t n, double dt, hipStream_t s);
 void launch_fused_step(const StepArgs &a, int n, hipStream_t s);
 // two leap-frog steps (n, n + 1) over the tiles listed in a.tiles; lay 0
 // runs the instantiation without layer recursions (tiles whose computed rows
@@ -97,6 +119,9 @@ void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStre
 // layer tiles (dearer per cell) 61; a two-step tile owns its phi cells, up to
 // TR rows and a range of planes.
 constexpr int two_step_cols(int lay) { return lay == 0 ? 56 : 61; }
+// owned rows of the two-step tiles with r-layer rows whose step-one
+// auxiliaries stay in registers (launch code lay = 1)
+constexpr int TWO_CARRY_ROWS = 7;
 // a fused-step tile owns FUSED_COLS phi cells and TR rows
 constexpr int FUSED_COLS = 56;
 // tile_rows code of the in-place kernels with the flat (r, phi) mapping, its

@@ -12,6 +12,8 @@
 // and axial lengths; each stretched term x is divided by its stretch with one
 // auxiliary recursion y = g1 x - g2 u, u <- c u + dt y (F is the causal
 // one-pole filter dt / (1 - c e^{i w dt})).
+#include <type_traits>
+
 #include "zda_internal.h"
 
 namespace zda {
@@ -31,12 +33,36 @@ __device__ __forceinline__ float2 c_fma(float2 acc, float2 a, float2 b)   // acc
 }
 __device__ __forceinline__ float2 zero2() { return make_float2(0.f, 0.f); }
 
-// y = x / (1 + s F) with the auxiliary u = F y
-__device__ __forceinline__ float2 div_stretch(float2 x, float2 *aux, float g1, float g2, float c, float dt)
+// the same complex helpers in FP64 (the in-place kernels' verification instantiation)
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b)
 {
-    float2 u = *aux;
-    float2 y = make_float2(g1 * x.x - g2 * u.x, g1 * x.y - g2 * u.y);
-    *aux = make_float2(c * u.x + dt * y.x, c * u.y + dt * y.y);
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 c_fma(double2 acc, double2 a, double2 b)
+{
+    return make_double2(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 mk(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ double2 mk(double x, double y) { return make_double2(x, y); }
+template <typename C>
+__device__ __forceinline__ C czero()
+{
+    C c;
+    c.x = 0;
+    c.y = 0;
+    return c;
+}
+
+// y = x / (1 + s F) with the auxiliary u = F y
+template <typename C, typename R>
+__device__ __forceinline__ C div_stretch(C x, C *aux, R g1, R g2, R c, R dt)
+{
+    C u = *aux;
+    C y = mk(g1 * x.x - g2 * u.x, g1 * x.y - g2 * u.y);
+    *aux = mk(c * u.x + dt * y.x, c * u.y + dt * y.y);
     return y;
 }
 
@@ -54,8 +80,8 @@ constexpr int BX = 64;   // one wavefront along phi
 constexpr int FLAT_BLOCK = FLAT_BLOCK_HOST;
 
 // (i, j) of this thread in the in-place kernels, false if outside the zone
-template <int BY, bool FLAT>
-__device__ __forceinline__ bool split_cell(const StepArgs &a, int bx, int by, int &i, int &j)
+template <int BY, bool FLAT, typename A>
+__device__ __forceinline__ bool split_cell(const A &a, int bx, int by, int &i, int &j)
 {
     if constexpr (FLAT) {
         const unsigned q = (unsigned)bx * FLAT_BLOCK + threadIdx.x;
@@ -71,9 +97,10 @@ __device__ __forceinline__ bool split_cell(const StepArgs &a, int bx, int by, in
 }
 
 // H^{n+1/2} = H^{n-1/2} - dt curlE(E^n); also advances V = F H_phi in the r-layer.
-template <int BY, bool FLAT = false>
-__device__ __forceinline__ void h_step_body(const StepArgs &a, int n, int bx, int by, int bz)
+template <int BY, bool FLAT = false, typename R = float>
+__device__ __forceinline__ void h_step_body(const StepArgsT<R> &a, int n, int bx, int by, int bz)
 {
+    using C = typename CplxOf<R>::T;
     int i, j;
     if (!split_cell<BY, FLAT>(a, bx, by, i, j)) return;
     const int kb = bz * a.kchunk;
@@ -82,67 +109,67 @@ __device__ __forceinline__ void h_step_body(const StepArgs &a, int n, int bx, in
     const size_t plane = (size_t)nr * nphi;
     const int ir = slab_row(i, nr, a.pr0, a.pr1);
     const int ir1 = (i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
-    const RowCoef rc = a.rows[i];
+    const RowCoefT<R> rc = a.rows[i];
     const int jp = (j + 1 < nphi) ? j + 1 : 0;
     const bool wrap = (j + 1 >= nphi);
     const size_t slabR = (size_t)nz * a.dR * nphi;
     const size_t slabZ = (size_t)a.dZ * plane;
-    const float dt = a.dt;
+    const R dt = a.dt;
 
     size_t c = ((size_t)kb * nr + i) * nphi + j;
-    float2 er = a.Er[c], ep = a.Ep[c];
+    C er = a.Er[c], ep = a.Ep[c];
     for (int k = kb; k < ke; ++k, c += plane) {
         const size_t row = c - j;
-        const float2 ez = a.Ez[c];
-        float2 er_kp = zero2(), ep_kp = zero2();
+        const C ez = a.Ez[c];
+        C er_kp = czero<C>(), ep_kp = czero<C>();
         if (k + 1 < nz) { er_kp = a.Er[c + plane]; ep_kp = a.Ep[c + plane]; }
-        float2 ez_jp = a.Ez[row + jp], er_jp = a.Er[row + jp];
+        C ez_jp = a.Ez[row + jp], er_jp = a.Er[row + jp];
         if (wrap) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
-        float2 ez_ip = zero2(), ep_ip = zero2();
+        C ez_ip = czero<C>(), ep_ip = czero<C>();
         if (i + 1 < nr) { ez_ip = a.Ez[c + nphi]; ep_ip = a.Ep[c + nphi]; }
         const int kz = slab_row(k, nz, a.pz0, a.pz1);
         const size_t sr = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi + j : 0;
         const size_t sz = kz >= 0 ? ((size_t)kz * nr + i) * nphi + j : 0;
-        const ZCoef zc = a.zrows[k];
+        const ZCoefT<R> zc = a.zrows[k];
 
         // H_r at (i, j+1/2, k+1/2); row 0 is a wall unless it borders the axis
         if (i > 0 || a.axis) {
-            float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
-            float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
+            C t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
+            C t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
             if (ir >= 0) t1 = div_stretch(t1, a.auxR + AUX_HR_T * slabR + sr, rc.g1_t_int, rc.g2_t_int, a.cr, dt);
             if (kz >= 0) t2 = div_stretch(t2, a.auxZ + ZAUX_HR * slabZ + sz, zc.g1_half, zc.g2_half, a.cz, dt);
-            float2 h = a.Hr[c];
-            a.Hr[c] = make_float2(h.x - dt * (t1.x - t2.x), h.y - dt * (t1.y - t2.y));
+            C h = a.Hr[c];
+            a.Hr[c] = mk(h.x - dt * (t1.x - t2.x), h.y - dt * (t1.y - t2.y));
         }
         // H_phi at (i+1/2, j, k+1/2)
         {
-            float2 t1 = c_scale(c_sub(er_kp, er), a.inv_dz);
-            float2 t2 = c_scale(c_sub(ez_ip, ez), a.inv_dr);
+            C t1 = c_scale(c_sub(er_kp, er), a.inv_dz);
+            C t2 = c_scale(c_sub(ez_ip, ez), a.inv_dr);
             if (kz >= 0) t1 = div_stretch(t1, a.auxZ + ZAUX_HP * slabZ + sz, zc.g1_half, zc.g2_half, a.cz, dt);
             if (ir >= 0) t2 = div_stretch(t2, a.auxR + AUX_HP_S * slabR + sr, rc.g1_s_half, rc.g2_s_half, a.cr, dt);
-            float2 h = a.Hp[c];
-            h = make_float2(h.x - dt * (t1.x - t2.x), h.y - dt * (t1.y - t2.y));
+            C h = a.Hp[c];
+            h = mk(h.x - dt * (t1.x - t2.x), h.y - dt * (t1.y - t2.y));
             a.Hp[c] = h;
             if (ir >= 0) {
-                float2 *v = a.auxR + AUX_V_HP * slabR + sr;
-                float2 vv = *v;
-                *v = make_float2(a.cr * vv.x + dt * h.x, a.cr * vv.y + dt * h.y);
+                C *v = a.auxR + AUX_V_HP * slabR + sr;
+                C vv = *v;
+                *v = mk(a.cr * vv.x + dt * h.x, a.cr * vv.y + dt * h.y);
             }
         }
         // H_z at (i+1/2, j+1/2, k)
         if (k > 0) {
-            float2 t = c_add(c_scale(c_sub(ep_ip, ep), a.inv_dr), c_scale(c_add(ep_ip, ep), rc.inv_2r_half));
+            C t = c_add(c_scale(c_sub(ep_ip, ep), a.inv_dr), c_scale(c_add(ep_ip, ep), rc.inv_2r_half));
             if (ir >= 0) {
-                const float2 *U = a.auxR + AUX_U_EP * slabR;
-                float2 u0 = U[sr];
-                float2 u1 = ir1 >= 0 ? U[((size_t)k * a.dR + ir1) * nphi + j] : zero2();
+                const C *U = a.auxR + AUX_U_EP * slabR;
+                C u0 = U[sr];
+                C u1 = ir1 >= 0 ? U[((size_t)k * a.dR + ir1) * nphi + j] : czero<C>();
                 t = c_add(t, c_sub(c_scale(u1, rc.hz_c1), c_scale(u0, rc.hz_c0)));
                 t = div_stretch(t, a.auxR + AUX_HZ_S * slabR + sr, rc.g1_s_half, rc.g2_s_half, a.cr, dt);
             }
             t = c_sub(t, c_scale(c_sub(er_jp, er), rc.inv_rdphi_half));
             if (ir >= 0) t = div_stretch(t, a.auxR + AUX_HZ_T * slabR + sr, rc.g1_t_half, rc.g2_t_half, a.cr, dt);
-            float2 h = a.Hz[c];
-            a.Hz[c] = make_float2(h.x - dt * t.x, h.y - dt * t.y);
+            C h = a.Hz[c];
+            a.Hz[c] = mk(h.x - dt * t.x, h.y - dt * t.y);
         }
         er = er_kp;
         ep = ep_kp;
@@ -151,9 +178,10 @@ __device__ __forceinline__ void h_step_body(const StepArgs &a, int n, int bx, in
 
 // E^{n+1} = E^n + (dt/eps)(curlH(H^{n+1/2}) - J^{n+1/2}); source sheet, DFT
 // accumulation and U = F E_phi in the r-layer fused.
-template <int BY, bool FLAT = false>
-__device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, int by, int bz)
+template <int BY, bool FLAT = false, typename R = float>
+__device__ __forceinline__ void e_step_body(const StepArgsT<R> &a, int n, int bx, int by, int bz)
 {
+    using C = typename CplxOf<R>::T;
     int i, j;
     if (!split_cell<BY, FLAT>(a, bx, by, i, j)) return;
     const int kb = bz * a.kchunk;
@@ -162,83 +190,83 @@ __device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, in
     const size_t plane = (size_t)nr * nphi;
     const int ir = slab_row(i, nr, a.pr0, a.pr1);
     const int irm = (i > 0) ? slab_row(i - 1, nr, a.pr0, a.pr1) : -1;
-    const RowCoef rc = a.rows[i];
+    const RowCoefT<R> rc = a.rows[i];
     const int jm = (j > 0) ? j - 1 : nphi - 1;
     const bool wrap = (j == 0);
     const size_t slabR = (size_t)nz * a.dR * nphi;
     const size_t slabZ = (size_t)a.dZ * plane;
-    const float dt = a.dt;
+    const R dt = a.dt;
     const int nd = a.k1 - a.k0;
 
     size_t c = ((size_t)kb * nr + i) * nphi + j;
-    float2 hp_km = zero2(), hr_km = zero2();
+    C hp_km = czero<C>(), hr_km = czero<C>();
     if (kb > 0) { hp_km = a.Hp[c - plane]; hr_km = a.Hr[c - plane]; }
     for (int k = kb; k < ke; ++k, c += plane) {
         const size_t row = c - j;
-        const float2 hr = a.Hr[c], hp = a.Hp[c], hz = a.Hz[c];
-        float2 hz_jm = a.Hz[row + jm], hr_jm = a.Hr[row + jm];
+        const C hr = a.Hr[c], hp = a.Hp[c], hz = a.Hz[c];
+        C hz_jm = a.Hz[row + jm], hr_jm = a.Hr[row + jm];
         if (wrap) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
-        float2 hz_im = zero2(), hp_im = zero2();
+        C hz_im = czero<C>(), hp_im = czero<C>();
         if (i > 0) { hz_im = a.Hz[c - nphi]; hp_im = a.Hp[c - nphi]; }
-        const float ce = a.ceps[c];
+        const R ce = a.ceps[c];
         const int kz = slab_row(k, nz, a.pz0, a.pz1);
         const size_t sr = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi + j : 0;
         const size_t sz = kz >= 0 ? ((size_t)kz * nr + i) * nphi + j : 0;
-        const ZCoef zc = a.zrows[k];
-        float2 jr = zero2(), jp = zero2();
+        const ZCoefT<R> zc = a.zrows[k];
+        C jr = czero<C>(), jp = czero<C>();
         if (k == a.k_src) {
             for (int p = 0; p < a.n_prof; ++p) {
-                const float2 g = a.profile[(size_t)n * a.n_prof + p];
-                const float2 *pat = a.pattern + (size_t)p * 2 * plane + (size_t)i * nphi + j;
+                const C g = a.profile[(size_t)n * a.n_prof + p];
+                const C *pat = a.pattern + (size_t)p * 2 * plane + (size_t)i * nphi + j;
                 jr = c_fma(jr, pat[0], g);
                 jp = c_fma(jp, pat[plane], g);
             }
         }
-        float2 er = a.Er[c], ep = a.Ep[c], ez = a.Ez[c];
+        C er = a.Er[c], ep = a.Ep[c], ez = a.Ez[c];
         // E_r at (i+1/2, j, k)
         if (k > 0) {
-            float2 t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
-            float2 t2 = c_scale(c_sub(hp, hp_km), a.inv_dz);
+            C t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
+            C t2 = c_scale(c_sub(hp, hp_km), a.inv_dz);
             if (ir >= 0) t1 = div_stretch(t1, a.auxR + AUX_ER_T * slabR + sr, rc.g1_t_half, rc.g2_t_half, a.cr, dt);
             if (kz >= 0) t2 = div_stretch(t2, a.auxZ + ZAUX_ER * slabZ + sz, zc.g1_int, zc.g2_int, a.cz, dt);
-            er = make_float2(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
+            er = mk(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
             a.Er[c] = er;
         }
         // E_phi at (i, j+1/2, k) (H_z on the axis is zero)
         if (k > 0 && (i > 0 || a.axis)) {
-            float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
-            float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
+            C t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
+            C t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
             if (kz >= 0) t1 = div_stretch(t1, a.auxZ + ZAUX_EP * slabZ + sz, zc.g1_int, zc.g2_int, a.cz, dt);
             if (ir >= 0) t2 = div_stretch(t2, a.auxR + AUX_EP_S * slabR + sr, rc.g1_s_int, rc.g2_s_int, a.cr, dt);
-            ep = make_float2(ep.x + ce * (t1.x - t2.x - jp.x), ep.y + ce * (t1.y - t2.y - jp.y));
+            ep = mk(ep.x + ce * (t1.x - t2.x - jp.x), ep.y + ce * (t1.y - t2.y - jp.y));
             a.Ep[c] = ep;
         }
         // U = F E_phi advances on every r-layer cell (also where E_phi is held)
         if (ir >= 0) {
-            float2 *u = a.auxR + AUX_U_EP * slabR + sr;
-            float2 uu = *u;
-            *u = make_float2(a.cr * uu.x + dt * ep.x, a.cr * uu.y + dt * ep.y);
+            C *u = a.auxR + AUX_U_EP * slabR + sr;
+            C uu = *u;
+            *u = mk(a.cr * uu.x + dt * ep.x, a.cr * uu.y + dt * ep.y);
         }
         // E_z at (i, j, k+1/2) (next to the axis the H_phi term at r = 0 has weight 0)
         if (i > 0 || a.axis) {
-            float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
+            C t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
             if (ir >= 0) {
-                const float2 *V = a.auxR + AUX_V_HP * slabR;
-                float2 v1 = V[sr];
-                float2 v0 = irm >= 0 ? V[((size_t)k * a.dR + irm) * nphi + j] : zero2();
+                const C *V = a.auxR + AUX_V_HP * slabR;
+                C v1 = V[sr];
+                C v0 = irm >= 0 ? V[((size_t)k * a.dR + irm) * nphi + j] : czero<C>();
                 t = c_add(t, c_sub(c_scale(v1, rc.ez_c1), c_scale(v0, rc.ez_c0)));
                 t = div_stretch(t, a.auxR + AUX_EZ_S * slabR + sr, rc.g1_s_int, rc.g2_s_int, a.cr, dt);
             }
             t = c_sub(t, c_scale(c_sub(hr, hr_jm), rc.inv_rdphi_int));
             if (ir >= 0) t = div_stretch(t, a.auxR + AUX_EZ_T * slabR + sr, rc.g1_t_int, rc.g2_t_int, a.cr, dt);
-            ez = make_float2(ez.x + ce * t.x, ez.y + ce * t.y);
+            ez = mk(ez.x + ce * t.x, ez.y + ce * t.y);
             a.Ez[c] = ez;
         }
         // DFT monitors: Ehat += dt e^{i w (n+1) dt} E^{n+1}
         if (a.dft_plane && k == a.k_mon) {
             for (int f = 0; f < a.K; ++f) {
-                const float2 tw = a.twiddle[(size_t)n * a.K + f];
-                float2 *o = a.dft_plane + (size_t)f * 2 * plane + (size_t)i * nphi + j;
+                const C tw = a.twiddle[(size_t)n * a.K + f];
+                C *o = a.dft_plane + (size_t)f * 2 * plane + (size_t)i * nphi + j;
                 o[0] = c_fma(o[0], tw, er);
                 o[plane] = c_fma(o[plane], tw, ep);
             }
@@ -246,8 +274,8 @@ __device__ __forceinline__ void e_step_body(const StepArgs &a, int n, int bx, in
         if (a.dft_vol && k >= a.k0 && k < a.k1) {
             const size_t vs = (size_t)nd * plane;
             for (int f = 0; f < a.K; ++f) {
-                const float2 tw = a.twiddle[(size_t)n * a.K + f];
-                float2 *o = a.dft_vol + (size_t)f * 3 * vs + (size_t)(k - a.k0) * plane + (size_t)i * nphi + j;
+                const C tw = a.twiddle[(size_t)n * a.K + f];
+                C *o = a.dft_vol + (size_t)f * 3 * vs + (size_t)(k - a.k0) * plane + (size_t)i * nphi + j;
                 o[0] = c_fma(o[0], tw, er);
                 o[vs] = c_fma(o[vs], tw, ep);
                 o[2 * vs] = c_fma(o[2 * vs], tw, ez);
@@ -298,11 +326,61 @@ __device__ __forceinline__ float2 div_stretch2(float2 x, const float2 *src, floa
 }
 
 // Auxiliary row bases of one cell row for the recursions: r-layer slab row
-// (k, ir) and z-layer slab row (kz, i) of one auxiliary set.
+// (k, ir) and z-layer slab row (kz, i) of one auxiliary set.  Slot q of a
+// cell is the r-layer auxiliary q (q < N_AUX_R) or the z-layer auxiliary
+// q - N_AUX_R.
 struct AuxRows {
     const float2 *sR, *sZ;   // read (time level before the half-step)
     float2 *dR, *dZ;         // written (time level after it)
+    __device__ __forceinline__ float2 ld(int q, size_t slabR, size_t slabZ, unsigned o) const
+    {
+        return q < N_AUX_R ? ldo(sR + q * slabR, o) : ldo(sZ + (q - N_AUX_R) * slabZ, o);
+    }
+    __device__ __forceinline__ void st(int q, float2 v, size_t slabR, size_t slabZ, unsigned o) const
+    {
+        *(q < N_AUX_R ? pto(dR + q * slabR, o) : pto(dZ + (q - N_AUX_R) * slabZ, o)) = v;
+    }
 };
+
+// a cell's auxiliaries at one time level held in registers (slots as above)
+constexpr int N_SLOT = N_AUX_R + N_AUX_Z;
+struct AuxCarry {
+    float2 v[N_SLOT];
+};
+
+// read from memory (the level before the half-step), write to registers
+struct AuxToReg {
+    const float2 *sR, *sZ;
+    AuxCarry *r;
+    __device__ __forceinline__ float2 ld(int q, size_t slabR, size_t slabZ, unsigned o) const
+    {
+        return q < N_AUX_R ? ldo(sR + q * slabR, o) : ldo(sZ + (q - N_AUX_R) * slabZ, o);
+    }
+    __device__ __forceinline__ void st(int q, float2 v, size_t, size_t, unsigned) const { r->v[q] = v; }
+};
+
+// read from registers, write to memory (the level after the half-step)
+struct AuxFromReg {
+    const AuxCarry *r;
+    float2 *dR, *dZ;
+    __device__ __forceinline__ float2 ld(int q, size_t, size_t, unsigned) const { return r->v[q]; }
+    __device__ __forceinline__ void st(int q, float2 v, size_t slabR, size_t slabZ, unsigned o) const
+    {
+        *(q < N_AUX_R ? pto(dR + q * slabR, o) : pto(dZ + (q - N_AUX_R) * slabZ, o)) = v;
+    }
+};
+
+// y = x / (1 + s F) with the auxiliary of slot q read through io and, when
+// store, its update written through io
+template <class X>
+__device__ __forceinline__ float2 div_stretch_io(float2 x, const X &io, int q, size_t slabR, size_t slabZ, unsigned o,
+                                                 bool store, float g1, float g2, float c, float dt)
+{
+    const float2 u = io.ld(q, slabR, slabZ, o);
+    const float2 y = make_float2(g1 * x.x - g2 * u.x, g1 * x.y - g2 * u.y);
+    if (store) io.st(q, make_float2(c * u.x + dt * y.x, c * u.y + dt * y.y), slabR, slabZ, o);
+    return y;
+}
 
 // H half-step of one cell, H^{n+1/2} = H^{n-1/2} - dt curl E^n, with the PML
 // divide-by-stretch recursions.  E^n at the cell and its +phi (jp), +r (ip)
@@ -311,8 +389,9 @@ struct AuxRows {
 // updated V = F H_phi (r-layer; zero elsewhere).  Inner boundary (i = 0):
 // H_r is not updated unless the row borders the axis; bottom plane (k = 0):
 // H_z is not updated.
+template <class X>
 __device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, const ZCoef &zc, int i, int k, int ir,
-                                       int kz, size_t slabR, size_t slabZ, const AuxRows &x, unsigned o, bool wr,
+                                       int kz, size_t slabR, size_t slabZ, const X &x, unsigned o, bool wr,
                                        float2 ez, float2 er, float2 ep, float2 ez_jp, float2 er_jp, float2 er_kp,
                                        float2 ep_kp, float2 ez_ip, float2 ep_ip, float2 u0, float2 u1, float2 &hr,
                                        float2 &hp, float2 &hz, float2 &v)
@@ -323,10 +402,10 @@ __device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, con
         float2 t1 = c_scale(c_sub(ez_jp, ez), rc.inv_rdphi_int);
         float2 t2 = c_scale(c_sub(ep_kp, ep), a.inv_dz);
         if (ir >= 0)
-            t1 = div_stretch2(t1, pco(x.sR + AUX_HR_T * slabR, o), pto(x.dR + AUX_HR_T * slabR, o), wr,
+            t1 = div_stretch_io(t1, x, AUX_HR_T, slabR, slabZ, o, wr,
                               rc.g1_t_int, rc.g2_t_int, a.cr, dt);
         if (kz >= 0)
-            t2 = div_stretch2(t2, pco(x.sZ + ZAUX_HR * slabZ, o), pto(x.dZ + ZAUX_HR * slabZ, o), wr, zc.g1_half,
+            t2 = div_stretch_io(t2, x, N_AUX_R + ZAUX_HR, slabR, slabZ, o, wr, zc.g1_half,
                               zc.g2_half, a.cz, dt);
         hr = make_float2(hr.x - dt * (t1.x - t2.x), hr.y - dt * (t1.y - t2.y));
     }
@@ -335,17 +414,17 @@ __device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, con
         float2 t1 = c_scale(c_sub(er_kp, er), a.inv_dz);
         float2 t2 = c_scale(c_sub(ez_ip, ez), a.inv_dr);
         if (kz >= 0)
-            t1 = div_stretch2(t1, pco(x.sZ + ZAUX_HP * slabZ, o), pto(x.dZ + ZAUX_HP * slabZ, o), wr, zc.g1_half,
+            t1 = div_stretch_io(t1, x, N_AUX_R + ZAUX_HP, slabR, slabZ, o, wr, zc.g1_half,
                               zc.g2_half, a.cz, dt);
         if (ir >= 0)
-            t2 = div_stretch2(t2, pco(x.sR + AUX_HP_S * slabR, o), pto(x.dR + AUX_HP_S * slabR, o), wr,
+            t2 = div_stretch_io(t2, x, AUX_HP_S, slabR, slabZ, o, wr,
                               rc.g1_s_half, rc.g2_s_half, a.cr, dt);
         hp = make_float2(hp.x - dt * (t1.x - t2.x), hp.y - dt * (t1.y - t2.y));
         v = zero2();
         if (ir >= 0) {
-            const float2 vo = ldo(x.sR + AUX_V_HP * slabR, o);
+            const float2 vo = x.ld(AUX_V_HP, slabR, slabZ, o);
             v = make_float2(a.cr * vo.x + dt * hp.x, a.cr * vo.y + dt * hp.y);
-            if (wr) *pto(x.dR + AUX_V_HP * slabR, o) = v;
+            if (wr) x.st(AUX_V_HP, v, slabR, slabZ, o);
         }
     }
     // H_z at (i+1/2, j+1/2, k)
@@ -353,12 +432,12 @@ __device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, con
         float2 t = c_add(c_scale(c_sub(ep_ip, ep), a.inv_dr), c_scale(c_add(ep_ip, ep), rc.inv_2r_half));
         if (ir >= 0) {
             t = c_add(t, c_sub(c_scale(u1, rc.hz_c1), c_scale(u0, rc.hz_c0)));
-            t = div_stretch2(t, pco(x.sR + AUX_HZ_S * slabR, o), pto(x.dR + AUX_HZ_S * slabR, o), wr, rc.g1_s_half,
+            t = div_stretch_io(t, x, AUX_HZ_S, slabR, slabZ, o, wr, rc.g1_s_half,
                              rc.g2_s_half, a.cr, dt);
         }
         t = c_sub(t, c_scale(c_sub(er_jp, er), rc.inv_rdphi_half));
         if (ir >= 0)
-            t = div_stretch2(t, pco(x.sR + AUX_HZ_T * slabR, o), pto(x.dR + AUX_HZ_T * slabR, o), wr, rc.g1_t_half,
+            t = div_stretch_io(t, x, AUX_HZ_T, slabR, slabZ, o, wr, rc.g1_t_half,
                              rc.g2_t_half, a.cr, dt);
         hz = make_float2(hz.x - dt * t.x, hz.y - dt * t.y);
     }
@@ -372,8 +451,9 @@ __device__ __forceinline__ void h_cell(const StepArgs &a, const RowCoef &rc, con
 // boundary: E_phi and E_z are not updated, except next to the axis, where the
 // -r neighbours (H_z on the axis, H_phi at r = 0) count as zero whatever the
 // caller passes; bottom plane: E_r and E_phi are not updated.
+template <class X>
 __device__ __forceinline__ void e_cell(const StepArgs &a, const RowCoef &rc, const ZCoef &zc, int i, int k, int ir,
-                                       int kz, size_t slabR, size_t slabZ, const AuxRows &x, unsigned o, float ce,
+                                       int kz, size_t slabR, size_t slabZ, const X &x, unsigned o, float ce,
                                        float2 jr, float2 jph, float2 hr, float2 hr_jm, float2 hr_km, float2 hp,
                                        float2 hp_im, float2 hp_km, float2 hz, float2 hz_jm, float2 hz_im, float2 v,
                                        float2 v_im, float2 &er, float2 &ep, float2 &ez, float2 &u)
@@ -385,10 +465,10 @@ __device__ __forceinline__ void e_cell(const StepArgs &a, const RowCoef &rc, con
         float2 t1 = c_scale(c_sub(hz, hz_jm), rc.inv_rdphi_half);
         float2 t2 = c_scale(c_sub(hp, hp_km), a.inv_dz);
         if (ir >= 0)
-            t1 = div_stretch2(t1, pco(x.sR + AUX_ER_T * slabR, o), pto(x.dR + AUX_ER_T * slabR, o), true,
+            t1 = div_stretch_io(t1, x, AUX_ER_T, slabR, slabZ, o, true,
                               rc.g1_t_half, rc.g2_t_half, a.cr, dt);
         if (kz >= 0)
-            t2 = div_stretch2(t2, pco(x.sZ + ZAUX_ER * slabZ, o), pto(x.dZ + ZAUX_ER * slabZ, o), true, zc.g1_int,
+            t2 = div_stretch_io(t2, x, N_AUX_R + ZAUX_ER, slabR, slabZ, o, true, zc.g1_int,
                               zc.g2_int, a.cz, dt);
         er = make_float2(er.x + ce * (t1.x - t2.x - jr.x), er.y + ce * (t1.y - t2.y - jr.y));
     }
@@ -398,30 +478,30 @@ __device__ __forceinline__ void e_cell(const StepArgs &a, const RowCoef &rc, con
         float2 t1 = c_scale(c_sub(hr, hr_km), a.inv_dz);
         float2 t2 = c_scale(c_sub(hz, hz_im), a.inv_dr);
         if (kz >= 0)
-            t1 = div_stretch2(t1, pco(x.sZ + ZAUX_EP * slabZ, o), pto(x.dZ + ZAUX_EP * slabZ, o), true, zc.g1_int,
+            t1 = div_stretch_io(t1, x, N_AUX_R + ZAUX_EP, slabR, slabZ, o, true, zc.g1_int,
                               zc.g2_int, a.cz, dt);
         if (ir >= 0)
-            t2 = div_stretch2(t2, pco(x.sR + AUX_EP_S * slabR, o), pto(x.dR + AUX_EP_S * slabR, o), true,
+            t2 = div_stretch_io(t2, x, AUX_EP_S, slabR, slabZ, o, true,
                               rc.g1_s_int, rc.g2_s_int, a.cr, dt);
         ep = make_float2(ep.x + ce * (t1.x - t2.x - jph.x), ep.y + ce * (t1.y - t2.y - jph.y));
     }
     // U = F E_phi advances on every r-layer cell (also where E_phi is held)
     if (ir >= 0) {
-        const float2 uo = ldo(x.sR + AUX_U_EP * slabR, o);
+        const float2 uo = x.ld(AUX_U_EP, slabR, slabZ, o);
         u = make_float2(a.cr * uo.x + dt * ep.x, a.cr * uo.y + dt * ep.y);
-        *pto(x.dR + AUX_U_EP * slabR, o) = u;
+        x.st(AUX_U_EP, u, slabR, slabZ, o);
     }
     // E_z at (i, j, k+1/2)
     if (i > 0 || a.axis) {
         float2 t = c_add(c_scale(c_sub(hp, hp_im), a.inv_dr), c_scale(c_add(hp, hp_im), rc.inv_2r_int));
         if (ir >= 0) {
             t = c_add(t, c_sub(c_scale(v, rc.ez_c1), c_scale(v_im, rc.ez_c0)));
-            t = div_stretch2(t, pco(x.sR + AUX_EZ_S * slabR, o), pto(x.dR + AUX_EZ_S * slabR, o), true,
+            t = div_stretch_io(t, x, AUX_EZ_S, slabR, slabZ, o, true,
                              rc.g1_s_int, rc.g2_s_int, a.cr, dt);
         }
         t = c_sub(t, c_scale(c_sub(hr, hr_jm), rc.inv_rdphi_int));
         if (ir >= 0)
-            t = div_stretch2(t, pco(x.sR + AUX_EZ_T * slabR, o), pto(x.dR + AUX_EZ_T * slabR, o), true,
+            t = div_stretch_io(t, x, AUX_EZ_T, slabR, slabZ, o, true,
                              rc.g1_t_int, rc.g2_t_int, a.cr, dt);
         ez = make_float2(ez.x + ce * t.x, ez.y + ce * t.y);
     }
@@ -762,7 +842,14 @@ __device__ __forceinline__ PlaneIn load_plane(const StepArgs &a, int k, size_t p
 // block computes halo cells with the same inputs and the same arithmetic as
 // their owner, so the level-(n+1) auxiliaries that step one writes to the
 // intermediate set are identical whichever block writes them.
-template <int TR, int LAY>
+//
+// CARRY: the level-(n+1) auxiliaries stay in registers from step one at
+// plane k to step two at the same plane (the next iteration) instead of
+// going through the intermediate set: each thread reads back only what it
+// wrote itself, so the values and the arithmetic are the same.  It costs two
+// sets of the cell's auxiliaries in registers, which the layer tiles of a
+// narrower block (or with the z-layer recursions only) can hold.
+template <int TR, int LAY, bool CARRY = false>
 __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
 {
     // LAY bit 0: the tile's rows include r-layer rows; bit 1: its planes include z-layer planes
@@ -814,7 +901,10 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
     float ce_p = 0.f;
     // the next plane's loads are issued one plane ahead (where the registers
     // allow), so they are in flight through this plane's barriers and updates
-    constexpr bool PF = !PR;
+    constexpr bool PF = !PR && !CARRY;
+    using X1 = std::conditional_t<CARRY, AuxToReg, AuxRows>;
+    using X2 = std::conditional_t<CARRY, AuxFromReg, AuxRows>;
+    AuxCarry car_c, car_p;   // CARRY: step one's auxiliaries of planes k and k - 1
     PlaneIn cur = load_plane(a, k_lo, plane, rowc, dip, o, ojp, oc);
     for (int k = k_lo; k <= ke; ++k) {
         const int km = k - 1;
@@ -833,14 +923,20 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
         // ---- step one, H^{n+1/2} at plane k (every lane and wave)
         int kz = -1;
         ZCoef zc = {};
-        AuxRows x1 = {};
+        X1 x1 = {};
+        if constexpr (CARRY) x1.r = &car_c;   // set on every path, so the carry stays in registers
         float2 ez0 = zero2();
         if (step1 && active) {
             kz = PZ ? slab_row(k, nz, a.pz0, a.pz1) : -1;
             if (kz >= 0) zc = a.zrows[k];
             const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
             const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
-            x1 = {a.auxR + sr0, a.auxZ + sz0, a.mauxR + sr0, a.mauxZ + sz0};
+            x1.sR = a.auxR + sr0;
+            x1.sZ = a.auxZ + sz0;
+            if constexpr (!CARRY) {
+                x1.dR = a.mauxR + sr0;
+                x1.dZ = a.mauxZ + sz0;
+            }
             const bool kp_ok = k + 1 < nz;
             ez0 = in.ez;
             er_kp = in.er_kp;
@@ -900,7 +996,9 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
         const size_t c0m = (size_t)max(km, 0) * plane + rowc;
         const size_t sr2 = ir >= 0 ? ((size_t)max(km, 0) * a.dR + ir) * nphi : 0;
         const size_t sz2 = kz2 >= 0 ? ((size_t)kz2 * nr + ic) * nphi : 0;
-        const AuxRows x2 = {a.mauxR + sr2, a.mauxZ + sz2, a.oauxR + sr2, a.oauxZ + sz2};
+        X2 x2;
+        if constexpr (CARRY) x2 = X2{&car_p, a.oauxR + sr2, a.oauxZ + sz2};
+        else x2 = X2{a.mauxR + sr2, a.mauxZ + sz2, a.oauxR + sr2, a.oauxZ + sz2};
         const bool store = own && km >= kb && km < ke;
         // lanes 0 and 63 feed no owned cell: without layer recursions they
         // compute from clamped neighbours instead of being masked off
@@ -975,6 +1073,7 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
         ce_p = ce;
         h2r_km = h2r;
         h2p_km = h2p;
+        if constexpr (CARRY) car_p = car_c;
     }
 }
 
@@ -1215,6 +1314,19 @@ __global__ __launch_bounds__(BX * BY) void e_step_kernel(StepArgs a, int n)
     e_step_body<BY>(a, n, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// FP64 instantiation of the in-place pair (verification runs)
+template <int BY>
+__global__ __launch_bounds__(BX * BY) void h_step_kernel64(StepArgs64 a, int n)
+{
+    h_step_body<BY, false, double>(a, n, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int BY>
+__global__ __launch_bounds__(BX * BY) void e_step_kernel64(StepArgs64 a, int n)
+{
+    e_step_body<BY, false, double>(a, n, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 __global__ __launch_bounds__(FLAT_BLOCK) void h_step_flat(StepArgs a, int n)
 {
     h_step_body<1, true>(a, n, blockIdx.x, 0, blockIdx.z);
@@ -1239,10 +1351,10 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int
     eh_fused_body<TR>(a, n, p, gx, gy);
 }
 
-template <int TR, int LAY>
+template <int TR, int LAY, bool CARRY = false>
 __global__ __launch_bounds__(64 * (TR + 3)) void eh2_kernel(StepArgs a, int n)
 {
-    eh2_body<TR, LAY>(a, n, a.tiles[blockIdx.x]);
+    eh2_body<TR, LAY, CARRY>(a, n, a.tiles[blockIdx.x]);
 }
 
 template <int LAY>
@@ -1395,6 +1507,19 @@ __global__ void fill_kernel(float2 *p, size_t n)
     for (; q < n; q += stride) p[q] = zero2();
 }
 
+__global__ void fill64_kernel(double2 *p, size_t n)
+{
+    size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; q < n; q += stride) p[q] = make_double2(0.0, 0.0);
+}
+
+__global__ void inv_eps64_kernel(double *ceps, const double *eps, size_t n, double dt)
+{
+    size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) ceps[q] = dt / eps[q];
+}
+
 __global__ void inv_eps_kernel(float *ceps, const float *eps, size_t n, double dt)
 {
     size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1515,6 +1640,24 @@ void launch_step(const StepArgs &a, int n, hipStream_t s, bool h)
 
 void launch_h_step(const StepArgs &a, int n, hipStream_t s) { launch_step(a, n, s, true); }
 
+namespace {
+constexpr int BY64 = 4;
+dim3 grid64(const StepArgs64 &a)
+{
+    return dim3((a.nphi + BX - 1) / BX, (a.nr + BY64 - 1) / BY64, (a.nz + a.kchunk - 1) / a.kchunk);
+}
+}  // namespace
+
+void launch_h_step64(const StepArgs64 &a, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(h_step_kernel64<BY64>, grid64(a), dim3(BX, BY64, 1), 0, s, a, n);
+}
+
+void launch_e_step64(const StepArgs64 &a, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(e_step_kernel64<BY64>, grid64(a), dim3(BX, BY64, 1), 0, s, a, n);
+}
+
 template <int TR>
 void launch_fused_tr(const StepArgs &a, int n, hipStream_t s)
 {
@@ -1564,6 +1707,7 @@ void launch_two_tr(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream
 {
     dim3 block(64, TR + 3, 1);
     if (lay == 0) hipLaunchKernelGGL((eh2_kernel<TR, 0>), dim3(ntiles), block, 0, s, a, n);
+    else if (lay == 2) hipLaunchKernelGGL((eh2_kernel<TR, 2, true>), dim3(ntiles), block, 0, s, a, n);
     else hipLaunchKernelGGL((eh2_kernel<TR, 3>), dim3(ntiles), block, 0, s, a, n);
 }
 
@@ -1574,6 +1718,11 @@ void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStre
         if (lay == 0) hipLaunchKernelGGL(eh2_flat_kernel<0>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, a, n);
         else if (lay == 2) hipLaunchKernelGGL(eh2_flat_kernel<2>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, a, n);
         else hipLaunchKernelGGL(eh2_flat_kernel<3>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, a, n);
+    } else if (lay == 1) {
+        // tiles with r-layer rows, auxiliaries carried in registers: a
+        // narrower block (TWO_CARRY_ROWS owned rows) leaves room for them
+        hipLaunchKernelGGL((eh2_kernel<TWO_CARRY_ROWS, 3, true>), dim3(ntiles), dim3(64, TWO_CARRY_ROWS + 3, 1), 0, s,
+                           a, n);
     } else if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, lay, s);
     else launch_two_tr<5>(a, n, ntiles, lay, s);
 }
@@ -1652,6 +1801,20 @@ void launch_fill(float2 *p, size_t n, hipStream_t s)
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+}
+
+void launch_fill64(double2 *p, size_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+}
+
+void launch_inv_eps64(double *ceps, const double *eps, size_t n, double dt, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(inv_eps64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ceps, eps, n, dt);
 }
 
 void launch_inv_eps(float *ceps, const float *eps, size_t n, double dt, hipStream_t s)

@@ -217,6 +217,20 @@ struct zda_zone {
     int dR = 0, dZ = 0, nd = 0, kchunk = 1, tile_rows = 7;
     // FP64 layer constants: [0] integer points, [1] half points
     std::vector<double> sig_r[2], Sig_r[2], sgt_r[2], sig_z[2];
+    // FP64 per-row and per-plane coefficients (the FP32 ones are these rounded)
+    std::vector<RowCoefT<double>> rows64;
+    std::vector<ZCoefT<double>> zrows64;
+    // device state of the FP64 verification runs (allocated by the first one)
+    struct F64 {
+        double2 *F[6] = {};
+        double *ceps = nullptr;
+        double2 *auxR = nullptr, *auxZ = nullptr;
+        RowCoefT<double> *rows = nullptr;
+        ZCoefT<double> *zrows = nullptr;
+        double2 *pattern = nullptr, *dft = nullptr, *prof = nullptr, *tw = nullptr;
+        size_t cap_steps = 0;
+        bool ready = false;
+    } f64;
     double cr = 1, cz = 1;
     DevMem mem;
     Stage stage;
@@ -236,8 +250,9 @@ struct zda_zone {
     int xcd_remap = 0, nt_stores = 1, layer_stream = 0;
     int tile_patch = 0;            // (bands << 8) | columns of an XCD's patch of two-step tiles, 0 = off
     int layer_kchunk = -1;         // planes per chunk of the r-layer band tiles (-1: automatic)
+    int layer_carry = -1;          // 1: layer tiles keep step one's auxiliaries in registers; -1: automatic
     int watch_every = 1000;        // steps between in-loop divergence checks (0: off)
-    int tiles_lkc = -2;
+    int tiles_lkc = -2, tiles_carry = -1;
     // second stream and join events for the concurrent layer-tile launch
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -384,16 +399,18 @@ void setup_layers(zda_zone *z, std::vector<RowCoef> &rows, std::vector<ZCoef> &z
     const double dt = z->dt;
     z->cr = std::exp(-(d.pml_alpha + 2.0 * worst) * dt);
     z->cz = std::exp(-d.pml_alpha * dt);
-    auto g1 = [&](double s) { return (float)(1.0 / (1.0 + s * dt)); };
-    auto g2 = [&](double s, double c) { return (float)(s * c / (1.0 + s * dt)); };
-    rows.resize(nr);
+    auto g1 = [&](double s) { return 1.0 / (1.0 + s * dt); };
+    auto g2 = [&](double s, double c) { return s * c / (1.0 + s * dt); };
+    // FP64 rows (kept for the FP64 verification runs), rounded to FP32 for the kernels
+    auto &r64 = z->rows64;
+    r64.resize(nr);
     for (int i = 0; i < nr; ++i) {
         const double ri = d.r_in + i * d.dr, rh = ri + 0.5 * d.dr;
-        RowCoef &rc = rows[i];
-        rc.inv_rdphi_int = (float)(1.0 / (ri * z->dphi));
-        rc.inv_rdphi_half = (float)(1.0 / (rh * z->dphi));
-        rc.inv_2r_int = (float)(0.5 / ri);
-        rc.inv_2r_half = (float)(0.5 / rh);
+        RowCoefT<double> &rc = r64[i];
+        rc.inv_rdphi_int = 1.0 / (ri * z->dphi);
+        rc.inv_rdphi_half = 1.0 / (rh * z->dphi);
+        rc.inv_2r_int = 0.5 / ri;
+        rc.inv_2r_half = 0.5 / rh;
         rc.g1_s_int = g1(z->sig_r[0][i]);
         rc.g2_s_int = g2(z->sig_r[0][i], z->cr);
         rc.g1_s_half = g1(z->sig_r[1][i]);
@@ -402,17 +419,46 @@ void setup_layers(zda_zone *z, std::vector<RowCoef> &rows, std::vector<ZCoef> &z
         rc.g2_t_int = g2(z->sgt_r[0][i], z->cr);
         rc.g1_t_half = g1(z->sgt_r[1][i]);
         rc.g2_t_half = g2(z->sgt_r[1][i], z->cr);
-        rc.hz_c1 = (float)((i + 1 < nr ? z->Sig_r[0][i + 1] : 0.0) / (rh * d.dr));
-        rc.hz_c0 = (float)(z->Sig_r[0][i] / (rh * d.dr));
-        rc.ez_c1 = (float)(z->Sig_r[1][i] / (ri * d.dr));
-        rc.ez_c0 = (float)((i > 0 ? z->Sig_r[1][i - 1] : 0.0) / (ri * d.dr));
+        rc.hz_c1 = (i + 1 < nr ? z->Sig_r[0][i + 1] : 0.0) / (rh * d.dr);
+        rc.hz_c0 = z->Sig_r[0][i] / (rh * d.dr);
+        rc.ez_c1 = z->Sig_r[1][i] / (ri * d.dr);
+        rc.ez_c0 = (i > 0 ? z->Sig_r[1][i - 1] : 0.0) / (ri * d.dr);
+    }
+    auto &z64 = z->zrows64;
+    z64.resize(nz);
+    for (int k = 0; k < nz; ++k) {
+        z64[k].g1_int = g1(z->sig_z[0][k]);
+        z64[k].g2_int = g2(z->sig_z[0][k], z->cz);
+        z64[k].g1_half = g1(z->sig_z[1][k]);
+        z64[k].g2_half = g2(z->sig_z[1][k], z->cz);
+    }
+    rows.resize(nr);
+    for (int i = 0; i < nr; ++i) {
+        const RowCoefT<double> &q = r64[i];
+        RowCoef &rc = rows[i];
+        rc.inv_rdphi_int = (float)q.inv_rdphi_int;
+        rc.inv_rdphi_half = (float)q.inv_rdphi_half;
+        rc.inv_2r_int = (float)q.inv_2r_int;
+        rc.inv_2r_half = (float)q.inv_2r_half;
+        rc.g1_s_int = (float)q.g1_s_int;
+        rc.g2_s_int = (float)q.g2_s_int;
+        rc.g1_s_half = (float)q.g1_s_half;
+        rc.g2_s_half = (float)q.g2_s_half;
+        rc.g1_t_int = (float)q.g1_t_int;
+        rc.g2_t_int = (float)q.g2_t_int;
+        rc.g1_t_half = (float)q.g1_t_half;
+        rc.g2_t_half = (float)q.g2_t_half;
+        rc.hz_c1 = (float)q.hz_c1;
+        rc.hz_c0 = (float)q.hz_c0;
+        rc.ez_c1 = (float)q.ez_c1;
+        rc.ez_c0 = (float)q.ez_c0;
     }
     zr.resize(nz);
     for (int k = 0; k < nz; ++k) {
-        zr[k].g1_int = g1(z->sig_z[0][k]);
-        zr[k].g2_int = g2(z->sig_z[0][k], z->cz);
-        zr[k].g1_half = g1(z->sig_z[1][k]);
-        zr[k].g2_half = g2(z->sig_z[1][k], z->cz);
+        zr[k].g1_int = (float)z64[k].g1_int;
+        zr[k].g2_int = (float)z64[k].g2_int;
+        zr[k].g1_half = (float)z64[k].g1_half;
+        zr[k].g2_half = (float)z64[k].g2_half;
     }
 }
 
@@ -566,9 +612,11 @@ void split_range(int lo, int hi, int len, std::vector<std::pair<int, int>> &out)
 // the layers.  The fourth word of each descriptor is `tag` (the zone's index
 // in a batch).
 struct TwoStepTiles {
-    // by the layer recursions a tile runs: [0] none, [2] the z-layer
-    // recursions only (flat-mapped kernel: tiles whose computed rows hold no
-    // r-layer cell), [3] the r- and z-layer recursions ([1] stays empty)
+    // by the layer recursions a tile runs: [0] none, [1] the r- and z-layer
+    // recursions with the auxiliaries carried in registers (TWO_CARRY_ROWS
+    // owned rows), [2] the z-layer recursions only (tiles whose computed rows
+    // hold no r-layer cell: the flat-mapped kernel, or carried in registers),
+    // [3] the r- and z-layer recursions through the intermediate set
     std::vector<uint4> v[4];
     size_t cells = 0, mon = 0, src = 0;   // owned by the interior tiles
 };
@@ -582,19 +630,23 @@ int tile_order(const zda_zone *z)
 }
 
 void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, unsigned tag, TwoStepTiles &t,
-                    bool split_z = false)
+                    bool split_z = false, bool carry = false)
 {
+    // carry: the r-layer bands are cut into tiles of TWO_CARRY_ROWS rows for
+    // the carrying instantiation, and the z-only tiles get their own launch
+    if (split_z) carry = false;
+    const int TRr = carry ? TWO_CARRY_ROWS : TR;
     const zda_zone_desc &d = z->d;
     const int rA = d.pml_r_in > 0 ? std::min(d.pml_r_in + 2, d.nr) : 0;
     const int rB = d.pml_r_out > 0 ? std::max(d.nr - d.pml_r_out - 1, rA) : d.nr;
     const int zA = d.pml_z_lo > 0 ? std::min(d.pml_z_lo + 2, d.nz) : 0;
     const int zB = d.pml_z_hi > 0 ? std::max(d.nz - d.pml_z_hi - 1, zA) : d.nz;
     std::vector<std::pair<int, int>> rows, planes;
-    split_range(0, rA, TR, rows);
+    split_range(0, rA, TRr, rows);
     const size_t r_in0 = rows.size();
     split_range(rA, rB, TR, rows);
     const size_t r_in1 = rows.size();
-    split_range(rB, d.nr, TR, rows);
+    split_range(rB, d.nr, TRr, rows);
     split_range(0, zA, kc, planes);
     const size_t z_in0 = planes.size();
     split_range(zA, zB, kc, planes);
@@ -628,7 +680,7 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
             // With split_z (the flat-mapped kernel, whose lens batches hold
             // many small tiles) the z-only tiles get their own launch: 2 %
             // faster on the 16-zone LWIR-shaped lens
-            const int lay = rl ? 3 : (zl ? (split_z ? 2 : 3) : 0);
+            const int lay = rl ? (carry ? 1 : 3) : (zl ? (split_z || carry ? 2 : 3) : 0);
             const int cw = two_step_cols(lay);
             // r-layer band tiles carry ten recursions per cell: where they
             // are few, shorter chunks spread them over more blocks
@@ -745,13 +797,27 @@ int two_step_rows(int tile_rows, int nphi)
     return tile_rows == FLAT_TWO_ROWS ? flat_two_rows(nphi) : tile_rows;
 }
 
+// Layer tiles at and above which the automatic choice keeps step one's
+// auxiliaries in registers: four per CU.  Measured on one MI355X, the layer
+// launch of the 512 x 1024 x 400 zone (1802 tiles) runs 2.59 -> 2.21 ms with
+// them, that of the 256 x 512 x 300 zone (486 tiles, whose r-band tiles
+// already leave CUs idle) 0.71 -> 0.86 ms.
+constexpr size_t CARRY_MIN_LAYER_TILES = 1024;
+
 // A zone's two-step tile list (interior tiles first) and its counts.
 void plan_zone_tiles(const zda_zone *z, std::vector<uint4> &all, TileCounts &tc)
 {
     const int TR = z->tile_rows;
     TwoStepTiles t;
+    bool carry = z->layer_carry > 0;
+    if (z->layer_carry < 0 && TR != FLAT_TWO_ROWS) {
+        TwoStepTiles plain;
+        two_step_tiles(z, two_step_rows(TR, z->d.nphi), z->kchunk, z->k_src_last, tile_order(z), 0u, plain, false,
+                       false);
+        carry = plain.v[1].size() + plain.v[2].size() + plain.v[3].size() >= CARRY_MIN_LAYER_TILES;
+    }
     two_step_tiles(z, two_step_rows(TR, z->d.nphi), z->kchunk, z->k_src_last, tile_order(z), 0u, t,
-                   TR == FLAT_TWO_ROWS);
+                   TR == FLAT_TWO_ROWS, carry);
     all.clear();
     for (int q = 0; q < 4; ++q) {
         tc.n_lay[q] = (unsigned)t.v[q].size();
@@ -768,7 +834,7 @@ zda_status build_two_step_tiles(zda_zone *z, hipStream_t s)
 {
     const int TR = z->tile_rows, kc = z->kchunk;
     if (z->tiles2 && z->tiles_tr == TR && z->tiles_kc == kc && z->tiles_src == z->k_src_last &&
-        z->tiles_xcd == tile_order(z) && z->tiles_lkc == z->layer_kchunk)
+        z->tiles_xcd == tile_order(z) && z->tiles_lkc == z->layer_kchunk && z->tiles_carry == z->layer_carry)
         return ZDA_OK;
     std::vector<uint4> all;
     TileCounts tc;
@@ -786,6 +852,7 @@ zda_status build_two_step_tiles(zda_zone *z, hipStream_t s)
     z->tiles_kc = kc;
     z->tiles_xcd = tile_order(z);
     z->tiles_lkc = z->layer_kchunk;
+    z->tiles_carry = z->layer_carry;
     return ZDA_OK;
 }
 
@@ -968,8 +1035,10 @@ struct FwdPlan {
 // The plane-wave sheet of the presets on the host: J_r = -e^{i m phi_j}/dz,
 // J_phi = -i sgn(m) e^{i m phi_{j+1/2}}/dz (|m| = 1), or J_r = -1/dz (radial,
 // m = 0); the pulse multiplies it.  out: [2][nr][nphi].
-void preset_pattern_host(const zda_zone *z, int kind, float2 *out)
+template <typename V>
+void preset_pattern_host(const zda_zone *z, int kind, V *out)
 {
+    using R = decltype(out->x);
     const zda_zone_desc &d = z->d;
     const double sgn = d.m > 0 ? 1.0 : (d.m < 0 ? -1.0 : 0.0);
     for (int i = 0; i < d.nr; ++i)
@@ -985,8 +1054,11 @@ void preset_pattern_host(const zda_zone *z, int kind, float2 *out)
                 jr = -1.0 / d.dz;
                 jp = 0.0;
             }
-            out[(size_t)i * d.nphi + j] = make_float2((float)jr.real(), (float)jr.imag());
-            out[z->plane + (size_t)i * d.nphi + j] = make_float2((float)jp.real(), (float)jp.imag());
+            V &a = out[(size_t)i * d.nphi + j], &b = out[z->plane + (size_t)i * d.nphi + j];
+            a.x = (R)jr.real();
+            a.y = (R)jr.imag();
+            b.x = (R)jp.real();
+            b.y = (R)jp.imag();
         }
 }
 
@@ -1597,6 +1669,131 @@ zda_status zda_fdtd_run_noalloc(zda_zone *z, const zda_source *s, int nsteps, co
     return ZDA_OK;
 }
 
+namespace {
+
+// The FP64 state of a zone: one in-place set of the six fields, the layer
+// auxiliaries, dt/eps, the coefficient rows, the source sheet and the
+// exit-plane DFT.
+zda_status f64_setup(zda_zone *z, hipStream_t s)
+{
+    auto &f = z->f64;
+    if (f.ready) return ZDA_OK;
+    zda_status st;
+    for (auto &p : f.F)
+        if ((st = dev_alloc(z, &p, z->ncell)) != ZDA_OK) return st;
+    if ((st = dev_alloc(z, &f.ceps, z->ncell)) != ZDA_OK) return st;
+    if (z->dR > 0 && (st = dev_alloc(z, &f.auxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi)) != ZDA_OK)
+        return st;
+    if (z->dZ > 0 && (st = dev_alloc(z, &f.auxZ, (size_t)N_AUX_Z * z->dZ * z->plane)) != ZDA_OK) return st;
+    if ((st = dev_alloc(z, &f.rows, z->rows64.size())) != ZDA_OK) return st;
+    if ((st = dev_alloc(z, &f.zrows, z->zrows64.size())) != ZDA_OK) return st;
+    if ((st = dev_alloc(z, &f.pattern, 2 * z->plane)) != ZDA_OK) return st;
+    if ((st = dev_alloc(z, &f.dft, (size_t)ZDA_MAX_FREQ * 2 * z->plane)) != ZDA_OK) return st;
+    HIP_TRY(hipMemcpyAsync(f.rows, z->rows64.data(), z->rows64.size() * sizeof(RowCoefT<double>),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(f.zrows, z->zrows64.data(), z->zrows64.size() * sizeof(ZCoefT<double>),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    f.ready = true;
+    return ZDA_OK;
+}
+
+}  // namespace
+
+zda_status zda_fdtd_run_fp64(zda_zone *z, const double *eps, int eps_on_device, const zda_source *s, int nsteps,
+                             const double *omega, int K, double *plane_out, int out_on_device, void *stream)
+{
+    if (!z || !eps || !s || !plane_out || (K > 0 && !omega)) return fail(ZDA_ERR_ARG, "NULL argument");
+    if (nsteps < 0 || K < 1 || K > ZDA_MAX_FREQ) return fail(ZDA_ERR_ARG, "bad nsteps or K (1..%d)", ZDA_MAX_FREQ);
+    const zda_zone_desc &d = z->d;
+    if (s->kind != ZDA_SRC_PLANE_CIRC && s->kind != ZDA_SRC_RADIAL)
+        return fail(ZDA_ERR_UNSUPPORTED, "FP64 runs take the preset sources only");
+    if (s->kind == ZDA_SRC_PLANE_CIRC && std::abs(d.m) != 1) return fail(ZDA_ERR_UNSUPPORTED, "PLANE_CIRC needs |m| = 1");
+    if (s->kind == ZDA_SRC_RADIAL && d.m != 0) return fail(ZDA_ERR_UNSUPPORTED, "RADIAL needs m = 0");
+    if (!(s->width > 0)) return fail(ZDA_ERR_ARG, "pulse width must be > 0");
+    if (s->k_src < 1 || s->k_src >= d.nz) return fail(ZDA_ERR_ARG, "k_src must be in [1, nz)");
+    if (d.axis && (d.n_fold > 0 ? d.m % d.n_fold == 0 : d.m == 0))
+        return fail(ZDA_ERR_UNSUPPORTED, "axis zone with seam phase 1");
+    DeviceGuard g(z->device);
+    hipStream_t hs = (hipStream_t)stream;
+    z->stream = hs;
+    HIP_TRY(zone_wait(z));
+    zda_status st = f64_setup(z, hs);
+    if (st != ZDA_OK) return st;
+    auto &f = z->f64;
+    const size_t T = (size_t)std::max(nsteps, 1);
+    if (f.cap_steps < T * K || f.cap_steps < T) {
+        z->mem.put(f.prof);
+        z->mem.put(f.tw);
+        f.prof = f.tw = nullptr;
+        f.cap_steps = 0;
+        if ((st = dev_alloc(z, &f.prof, T * K)) != ZDA_OK) return st;
+        if ((st = dev_alloc(z, &f.tw, T * K)) != ZDA_OK) return st;
+        f.cap_steps = T * K;
+    }
+    // dt / eps from the FP64 permittivity
+    HIP_TRY(hipMemcpyAsync(f.ceps, eps, z->ncell * sizeof(double),
+                           eps_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, hs));
+    launch_inv_eps64(f.ceps, f.ceps, z->ncell, z->dt, hs);
+    // reset
+    for (auto p : f.F) launch_fill64(p, z->ncell, hs);
+    if (f.auxR) launch_fill64(f.auxR, (size_t)N_AUX_R * d.nz * z->dR * d.nphi, hs);
+    if (f.auxZ) launch_fill64(f.auxZ, (size_t)N_AUX_Z * z->dZ * z->plane, hs);
+    launch_fill64(f.dft, (size_t)K * 2 * z->plane, hs);
+    // source sheet, pulse and twiddles in FP64 (pageable staging, consumed
+    // before the call returns)
+    std::vector<double2> pat(2 * z->plane), prof(T), tw(T * K);
+    preset_pattern_host(z, s->kind, pat.data());
+    const int n0 = s->n0 >= 0 ? s->n0 : default_n0(s->width, z->dt);
+    for (size_t n = 0; n < T; ++n) prof[n] = make_double2(n < (size_t)nsteps ? pulse_at((long)n, z->dt, s->omega_c, s->width, n0) : 0.0, 0.0);
+    for (size_t n = 0; n < T; ++n)
+        for (int k = 0; k < K; ++k) {
+            const cd t = z->dt * std::exp(cd(0.0, omega[k] * (double)(n + 1) * z->dt));
+            tw[n * K + k] = make_double2(t.real(), t.imag());
+        }
+    HIP_TRY(hipMemcpyAsync(f.pattern, pat.data(), pat.size() * sizeof(double2), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(f.prof, prof.data(), prof.size() * sizeof(double2), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(f.tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, hs));
+    StepArgs64 a{};
+    a.nr = d.nr; a.nphi = d.nphi; a.nz = d.nz;
+    a.pr0 = d.pml_r_in; a.pr1 = d.pml_r_out; a.pz0 = d.pml_z_lo; a.pz1 = d.pml_z_hi;
+    a.dR = z->dR; a.dZ = z->dZ;
+    a.dt = z->dt;
+    a.inv_dr = 1.0 / d.dr;
+    a.inv_dz = 1.0 / d.dz;
+    a.cr = z->cr; a.cz = z->cz;
+    if (d.n_fold > 0) {
+        const double ph = d.m * z->tau;
+        a.seam_p = make_double2(std::cos(ph), std::sin(ph));
+        a.seam_m = make_double2(std::cos(ph), -std::sin(ph));
+    } else {
+        a.seam_p = make_double2(1.0, (double)d.m);
+        a.seam_m = make_double2(1.0, (double)-d.m);
+    }
+    a.axis = d.axis ? 1 : 0;
+    a.Er = f.F[0]; a.Ep = f.F[1]; a.Ez = f.F[2]; a.Hr = f.F[3]; a.Hp = f.F[4]; a.Hz = f.F[5];
+    a.ceps = f.ceps;
+    a.auxR = f.auxR; a.auxZ = f.auxZ;
+    a.rows = f.rows; a.zrows = f.zrows;
+    a.k_src = s->k_src; a.n_prof = 1;
+    a.pattern = f.pattern; a.profile = f.prof;
+    a.K = K; a.twiddle = f.tw;
+    a.k_mon = d.k_mon; a.dft_plane = f.dft;
+    a.k0 = d.design_k0; a.k1 = d.design_k1; a.dft_vol = nullptr;
+    a.kchunk = std::min(d.nz, 16);
+    a.tile_rows = 4;
+    for (int n = 0; n < nsteps; ++n) {
+        launch_h_step64(a, n, hs);
+        launch_e_step64(a, n, hs);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(plane_out, f.dft, (size_t)K * 2 * z->plane * sizeof(double2),
+                           out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, hs));
+    // the pageable staging above (and a host eps) must be read before it goes
+    HIP_TRY(hipStreamSynchronize(hs));
+    return ZDA_OK;
+}
+
 zda_status zda_dft_fields(zda_zone *z, int monitor, int component_mask, float *out, size_t out_floats,
                           int out_on_device)
 {
@@ -1735,6 +1932,10 @@ zda_status zda_zone_set_option(zda_zone *z, int option, int value)
         if (value < -1) return fail(ZDA_ERR_ARG, "layer chunk depth must be >= -1");
         z->layer_kchunk = value;
         return ZDA_OK;
+    case ZDA_OPT_LAYER_CARRY:
+        if (value < -1 || value > 1) return fail(ZDA_ERR_ARG, "layer carry is -1 (automatic), 0 or 1");
+        z->layer_carry = value;
+        return ZDA_OK;
     case ZDA_OPT_TILE_PATCH:
         if (value < 0 || (value != 0 && ((value >> 8) < 1 || (value >> 8) > 255 || (value & 0xff) < 1)))
             return fail(ZDA_ERR_ARG, "tile patch must be 0 or (bands << 8) | columns with both in [1, 255]");
@@ -1771,13 +1972,15 @@ zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kc
     if (tile_rows == FLAT_TWO_ROWS && d->nphi > FLAT_TWO_MAX_PHI)
         return fail(ZDA_ERR_ARG, "the flat two-step kernel needs nphi <= %d", FLAT_TWO_MAX_PHI);
     if (kchunk < 1) return fail(ZDA_ERR_ARG, "kchunk must be >= 1");
+    const bool carry = order >= 0 && (order & ZDA_PLAN_CARRY) != 0;
+    if (order >= 0) order &= ~ZDA_PLAN_CARRY;
     if (order > 1 && ((order >> 8) < 1 || (order >> 8) > 255 || (order & 0xff) < 1))
         return fail(ZDA_ERR_ARG, "tile patch must be (bands << 8) | columns with both in [1, 255]");
     zda_zone z;
     z.d = *d;
     TwoStepTiles t;
     two_step_tiles(&z, two_step_rows(tile_rows, d->nphi), std::min(kchunk, d->nz), k_src, order < 0 ? 0 : order, 0u,
-                   t, tile_rows == FLAT_TWO_ROWS);
+                   t, tile_rows == FLAT_TWO_ROWS, carry);
     *n_interior = t.v[0].size();
     *ntiles = t.v[0].size() + t.v[1].size() + t.v[2].size() + t.v[3].size();
     if (!out) return ZDA_OK;

@@ -21,12 +21,13 @@ SRC_PLANE_CIRC, SRC_RADIAL, SRC_CUSTOM = 0, 1, 2
 DFT_PLANE, DFT_VOLUME, RUN_CONTINUE, RUN_TIMING = 1, 2, 4, 8
 MON_PLANE, MON_VOLUME, MON_ADJOINT_VOLUME = 0, 1, 2
 OPT_XCD_REMAP, OPT_NT_STORES, OPT_LAYER_STREAM, OPT_TILE_PATCH, OPT_LAYER_KCHUNK, OPT_WATCHDOG = 1, 2, 3, 4, 5, 6
+OPT_LAYER_CARRY = 7
 COMP_R, COMP_PHI, COMP_Z = 1, 2, 4
 COMP = {"Er": 0, "Ephi": 1, "Ez": 2, "Hr": 3, "Hphi": 4, "Hz": 5}
 
 EXPORTS = ["zda_set_allocator", "zda_zone_desc_default", "zda_zone_create", "zda_zone_destroy", "zda_zone_set_eps",
            "zda_zone_set_design", "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_fdtd_run_noalloc",
-           "zda_dft_fields",
+           "zda_fdtd_run_fp64", "zda_dft_fields",
            "zda_adjoint_grad",
            "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_set_launch",
            "zda_zone_set_option",
@@ -106,6 +107,7 @@ def load():
     lib.zda_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
     lib.zda_fdtd_run.argtypes = [P, ctypes.POINTER(Source), I, P, I, I, P]
     lib.zda_fdtd_run_noalloc.argtypes = [P, ctypes.POINTER(Source), I, P, I, I, P]
+    lib.zda_fdtd_run_fp64.argtypes = [P, P, I, ctypes.POINTER(Source), I, P, I, P, I, P]
     lib.zda_dft_fields.argtypes = [P, I, I, P, ctypes.c_size_t, I]
     lib.zda_adjoint_grad.argtypes = [P, P, I, P, I, D, P]
     lib.zda_zone_read_field.argtypes = [P, I, P, I]
@@ -129,8 +131,8 @@ def load():
     lib.zda_last_error.restype = ctypes.c_char_p
     for name in ("zda_set_allocator", "zda_zone_create", "zda_zone_set_eps", "zda_zone_set_design",
                  "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_fdtd_run_noalloc",
-                 "zda_dft_fields", "zda_adjoint_grad", "zda_zone_read_field", "zda_zone_write_field",
-                 "zda_zone_get_info",
+                 "zda_fdtd_run_fp64", "zda_dft_fields", "zda_adjoint_grad", "zda_zone_read_field",
+                 "zda_zone_write_field", "zda_zone_get_info",
                  "zda_zone_last_timing", "zda_zone_set_launch", "zda_zone_set_option", "zda_batch_create",
                  "zda_batch_run", "zda_batch_adjoint_grad", "zda_batch_set_launch", "zda_batch_autotune"):
         getattr(lib, name).restype = I
@@ -295,6 +297,31 @@ class Zone:
         _check(fn(self._h, ctypes.byref(s), int(nsteps), ctypes.c_void_p(om.ctypes.data), int(om.size), flags,
                   _stream_ptr(torch, stream)))
         self._K = int(om.size)
+
+    def run_fp64(self, eps, nsteps, omegas, *, kind=SRC_PLANE_CIRC, k_src=1, omega_c=0.0, width=1.0, n0=-1,
+                 stream=None):
+        """The same forward run in FP64 (zda_fdtd_run_fp64) with the FP64
+        permittivity eps [nz][nr][nphi] (numpy or a CUDA float64 tensor);
+        returns the exit-plane DFT as complex128 numpy [K][2][nr][nphi]."""
+        torch = _torch()
+        s = Source()
+        s.kind, s.k_src, s.omega_c, s.width, s.n0 = kind, k_src, omega_c, width, n0
+        if isinstance(eps, torch.Tensor):
+            e = eps.to(torch.float64).contiguous()
+            eptr, edev = e.data_ptr(), int(e.is_cuda)
+        else:
+            e = np.ascontiguousarray(np.asarray(eps, np.float64))
+            eptr, edev = e.ctypes.data, 0
+        nr, nphi, nz = self.desc.nr, self.desc.nphi, self.desc.nz
+        if (e.numel() if isinstance(e, torch.Tensor) else e.size) != nr * nphi * nz:
+            raise ValueError("eps must hold nz * nr * nphi values")
+        om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, np.float64)))
+        out = np.empty((om.size, 2, nr, nphi), np.complex128)
+        _check(load().zda_fdtd_run_fp64(self._h, ctypes.c_void_p(eptr), edev, ctypes.byref(s), int(nsteps),
+                                        ctypes.c_void_p(om.ctypes.data), int(om.size),
+                                        ctypes.c_void_p(out.ctypes.data), 0, _stream_ptr(torch, stream)))
+        del e
+        return out
 
     def last_timing(self) -> Timing:
         t = Timing()

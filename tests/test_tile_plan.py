@@ -118,3 +118,41 @@ def test_flat_two_step_plan_refuses_wide_zones():
     with pytest.raises(zda.ZdaError) as e:
         zda.plan_two_step_tiles(d, 34, 8)
     assert e.value.status == zda.ZDA_ERR_ARG
+
+
+PLAN_CARRY = 1 << 16
+
+
+@pytest.mark.parametrize("tile_rows", [5, 13])
+@pytest.mark.parametrize("kchunk", [3, 48])
+@pytest.mark.parametrize("name", list(ZONES))
+def test_carry_plan_tiles(name, kchunk, tile_rows):
+    """The plan of ZDA_OPT_LAYER_CARRY: every cell owned once; kind 1 tiles
+    (r-layer rows, auxiliaries carried in registers) own at most 7 rows;
+    kind 2 tiles compute no r-layer row; the interior tiles are those of the
+    plain plan."""
+    from paper_2501_07979_amd import zda
+    z = ZONES[name]
+    d = _desc(zda, **z)
+    tiles, n_int = zda.plan_two_step_tiles(d, tile_rows, kchunk, k_src=2, order=PLAN_CARRY)
+    plain, n_plain = zda.plan_two_step_tiles(d, tile_rows, kchunk, k_src=2)
+    assert n_int == n_plain
+    assert sorted(map(tuple, tiles[:n_int].tolist())) == sorted(map(tuple, plain[:n_plain].tolist()))
+    nr, nphi, nz = z["nr"], z["nphi"], z["nz"]
+    pr0, pr1, pz0, pz1 = z["pml"]
+    own = np.zeros((nz, nr, nphi), np.int32)
+    for q, (bx, y, zz, kind) in enumerate(tiles):
+        i0, rows = int(y & 0xFFFF), int(y >> 16)
+        kb, ke = int(zz & 0xFFFF), int(zz >> 16)
+        assert (kind == 0) == (q < n_int) and kind in (0, 1, 2)
+        cols = 56 if kind == 0 else 61
+        assert 1 <= rows <= (7 if kind == 1 else tile_rows) and kb < ke
+        j0 = int(bx) * cols
+        assert j0 < nphi
+        own[kb:ke, i0:i0 + rows, j0:min(j0 + cols, nphi)] += 1
+        r_lo, r_hi = max(i0 - 2, 0), min(i0 + rows, nr - 1)
+        if kind == 2:
+            assert pr0 <= r_lo and r_hi < nr - pr1, (i0, rows)
+        if kind == 1:
+            assert r_lo < pr0 or r_hi >= nr - pr1, (i0, rows)
+    assert own.min() == 1 and own.max() == 1
