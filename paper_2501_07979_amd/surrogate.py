@@ -530,3 +530,241 @@ if __name__ == "__main__":
     ap.add_argument("--batch", type=int, default=16)
     args = ap.parse_args()
     print(json.dumps(bench_train(args.bench_train, args.batch)))
+
+
+# ---- surrogate-assisted design against plain FDTD-adjoint design at equal
+# final focusing efficiency
+
+def adam_update(x, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam ascent step on x along g (torch, in place), clipped to [0, 1]."""
+    import torch
+    m.mul_(b1).add_(g, alpha=1 - b1)
+    v.mul_(b2).addcmul_(g, g, value=1 - b2)
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    x.add_(lr * mh / (torch.sqrt(vh) + eps)).clamp_(0.0, 1.0)
+
+
+def checked_loop(fdtd, sur, rho0, outer, inner, lr, stop=None, log=None):
+    """Surrogate-assisted ascent with the FDTD as fallback and judge.
+
+    fdtd(rho) -> (F, dF/drho) is the plain FDTD-adjoint evaluation and
+    sur(rho) -> dF/drho the surrogate's gradient.  Each outer step re-checks
+    the current pattern with the FDTD.  After a block of surrogate steps the
+    re-check accepts the pattern only if F did not fall below the last
+    accepted one; otherwise the block is rejected: the loop returns to the
+    last accepted pattern (and its Adam moments) and falls back to plain
+    FDTD-adjoint steps for 1, 2, 4, ... outer steps (doubling while blocks
+    keep failing).  A pattern reached by a plain step is always accepted, as
+    in plain design.  Every outer step takes one Adam step along the FDTD
+    gradient, then (outside the fall-back) `inner` along the surrogate's.
+    stop(step, rho, F) is asked after each accepted re-check.  Returns the
+    last accepted pattern, its F and the per-outer-step history."""
+    import torch
+    rho = rho0.clone()
+    m, v = torch.zeros_like(rho), torch.zeros_like(rho)
+    t = 0
+    best = None          # (rho, F, grad, m, v, t) of the last accepted re-check
+    hist = []
+    block = False        # the steps since the last re-check include surrogate steps
+    wait, gap = 0, 1
+    for s in range(outer):
+        F, g = fdtd(rho)
+        accepted = best is None or not block or F >= best[1]
+        if accepted:
+            best = (rho.clone(), F, g, m.clone(), v.clone(), t)
+            if block:
+                gap = 1
+        else:
+            rho, F, g = best[0].clone(), best[1], best[2]
+            m, v, t = best[3].clone(), best[4].clone(), best[5]
+            wait, gap = gap, gap * 2
+        hist.append({"step": s, "F_fdtd": float(F), "surrogate_block": bool(block), "accepted": bool(accepted)})
+        if log:
+            log("outer %d F %.5e %s" % (s, F, ("accept" if accepted else "reject, back to the last accepted") +
+                                           (" (surrogate block)" if block else "")))
+        if accepted and stop is not None and stop(s, rho, F):
+            break
+        t += 1
+        adam_update(rho, g, m, v, t, lr)
+        if wait > 0 or inner == 0:
+            wait = max(wait - 1, 0)
+            block = False
+        else:
+            for _ in range(inner):
+                t += 1
+                adam_update(rho, sur(rho), m, v, t, lr)
+            block = True
+    return best[0], best[1], hist
+
+
+def incident_power(wl):
+    """Incident power of the preset source per frequency: the power its plane
+    wave carries through the active ring, from a run of the zone filled with
+    the substrate everywhere (nothing reflects it)."""
+    from . import objective, zda
+    eps = np.full((wl.nz, wl.nr, wl.nphi), wl.eps_sub, np.float32)
+    z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+    z.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+    plane = z.dft(zda.MON_PLANE).cpu().numpy()
+    z.close()
+    return objective.exit_plane_power(plane, wl, index=float(np.sqrt(wl.eps_sub)))
+
+
+def mean_efficiency(plane, wl, focal, p_inc):
+    """Absolute focusing efficiency averaged over the frequencies."""
+    from . import objective
+    return float(np.mean(objective.focusing_efficiency(plane, wl, wl.omegas, focal, p_inc, n_rho=64,
+                                                       n_phi=4)["absolute"]))
+
+
+def fdtd_value_and_grad(zone, wl, weights):
+    """fdtd(rho2d) for checked_loop: forward run, focal objective, adjoint
+    run (torch.autograd through the zone) -> (F, dF/drho2d, exit plane)."""
+    import torch
+    from .autograd import zone_fdtd
+    nd = wl.design[1] - wl.design[0]
+    Wt = torch.as_tensor(weights, dtype=torch.complex64, device="cuda")
+
+    def f(rho2d):
+        r = rho2d.detach().clone().requires_grad_(True)
+        plane = zone_fdtd(r[None].expand(nd, wl.nr, wl.nphi).contiguous(), zone, nsteps=wl.steps,
+                          omegas=wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+        a = (Wt * plane).sum(dim=(1, 2, 3))
+        F = (a.abs() ** 2).sum()
+        F.backward()
+        f.last_plane = plane.detach()
+        return float(F.item()), r.grad.detach()
+    f.last_plane = None
+    return f
+
+
+def surrogate_grad(net, wl, weights, scale):
+    """sur(rho2d) for checked_loop: dF/drho2d of the focal objective on the
+    network's predicted fields (network backward on its own kernels)."""
+    import torch
+    Wt = torch.as_tensor(weights, dtype=torch.complex64, device="cuda")
+    pr, pp = bloch_phases(wl)
+    ph = torch.as_tensor(np.stack([1 / pr, 1 / pp]), dtype=torch.complex64, device="cuda")
+    K = len(wl.omegas)
+
+    def g(rho2d):
+        x = features(rho2d[None], wl.nr)
+        y = net.forward(x, keep=True)
+        yv = y[:, 0].detach().clone().requires_grad_(True)
+        u = torch.complex(yv[0::2], yv[1::2]).view(K, 2, wl.nr, wl.nphi) * scale
+        a = (Wt * (u * ph[None, :, None, :])).sum(dim=(1, 2, 3))
+        (a.abs() ** 2).sum().backward()
+        dx = net.backward(yv.grad.contiguous()[:, None], need_dx=True)
+        return dx[0, 0].detach().clone()
+    return g
+
+
+def equal_efficiency_comparison(wl, plain_iters=24, outer_max=48, inner=9, lr=0.02, n_train=256, train_iters=1500,
+                                width=160, batch=8, seed=7, log=None):
+    """Plain FDTD-adjoint design against surrogate-assisted design from the
+    same start, compared at equal final focusing efficiency.
+
+    Plain: `plain_iters` Adam iterations on the 2-D pattern (one forward and
+    one adjoint run each); its final absolute focusing efficiency is the
+    target.  Surrogate: the network (about 2M parameters at width 160) is
+    trained once on n_train seeded random patterns and their FDTD fields,
+    then checked_loop runs from the same start (FDTD re-check and gradient
+    every inner + 1 iterations) until an accepted pattern's efficiency
+    reaches the target within 1 % or outer_max re-checks pass.  Wall-clock
+    times exclude the efficiency evaluations (measurement only).  Returns a
+    dict of both runs."""
+    import torch
+    from . import objective, zda
+    focal = objective.focal_length(wl.r_in + 0.5 * wl.nr * wl.dr)
+    W = objective.focal_weights(wl, np.array(wl.omegas), focal).cpu().numpy()
+    p_inc = incident_power(wl)
+    rho0 = random_patterns(1, wl.nr, wl.nphi, seed=seed)[0]
+    zone = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    fd = fdtd_value_and_grad(zone, wl, W)
+    # ---- plain
+    rho = torch.tensor(rho0, device="cuda")
+    m, v = torch.zeros_like(rho), torch.zeros_like(rho)
+    planes, Fs, t_plain = [], [], 0.0
+    for it in range(1, plain_iters + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F, g = fd(rho)
+        adam_update(rho, g, m, v, it, lr)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        planes.append(fd.last_plane.cpu())
+        Fs.append(F)
+    F_end, g = fd(rho)
+    plane_end = fd.last_plane.cpu()
+    eff_plain = mean_efficiency(plane_end, wl, focal, p_inc)
+    eff_start = mean_efficiency(planes[0], wl, focal, p_inc)
+    target = eff_plain
+    if log:
+        log("plain: %d iterations, %.2f s, efficiency %.4f -> %.4f" % (plain_iters, t_plain, eff_start, eff_plain))
+    # ---- offline training set and training
+    t0 = time.perf_counter()
+    pats = random_patterns(n_train, wl.nr, wl.nphi, seed=seed + 1)
+    T = generate_samples(wl, pats)
+    t_gen = time.perf_counter() - t0
+    scale = float(np.abs(T).std())
+    nh = max(8, n_train // 8)
+    X = features(pats, wl.nr)
+    Tt = torch.tensor(np.ascontiguousarray(np.moveaxis(T / scale, 0, 1)), device="cuda")
+    net = Surrogate(in_ch=2, width=width, out_ch=4 * len(wl.omegas), seed=seed)
+    t0 = time.perf_counter()
+    losses = train(net, X[:, :-nh].contiguous(), Tt[:, :-nh].contiguous(), train_iters, batch=batch, seed=seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    errs = field_errors(net, X[:, -nh:].contiguous(), Tt[:, -nh:].contiguous(), wl, scale)
+    if log:
+        log("surrogate: %d params, %d samples (%.1f s), trained %.1f s, held-out field error median %.3f p90 %.3f"
+            % (net.n_params(), n_train, t_gen, t_train, np.median(errs), np.percentile(errs, 90)))
+    # ---- assisted
+    sur = surrogate_grad(net, wl, W, scale)
+    state = {"t": 0.0, "eff": eff_start, "reached": False, "checks": 0}
+    clock = [time.perf_counter()]
+
+    def stop(step, r, F):
+        torch.cuda.synchronize()
+        state["t"] += time.perf_counter() - clock[0]
+        state["checks"] = step + 1
+        e = mean_efficiency(fd.last_plane.cpu(), wl, focal, p_inc)
+        state["eff"] = e
+        done = e >= 0.99 * target
+        state["reached"] = state["reached"] or done
+        if log:
+            log("assisted re-check %d: F %.4e efficiency %.4f (target %.4f)" % (step, F, e, target))
+        clock[0] = time.perf_counter()
+        return done
+
+    torch.cuda.synchronize()
+    clock[0] = time.perf_counter()
+    best, F_best, hist = checked_loop(fd, sur, torch.tensor(rho0, device="cuda"), outer_max, inner, lr, stop=stop)
+    torch.cuda.synchronize()
+    if not state["reached"]:
+        state["t"] += time.perf_counter() - clock[0]
+    zone.close()
+    n_sur = sum(inner for h in hist if h["surrogate_block"])
+    n_fd = len(hist)
+    return {
+        "workload": wl.name, "steps_per_run": wl.steps,
+        "efficiency_definition": "absolute: focal-plane power within 3 FWHM of the spot centre / incident power",
+        "plain": {"iterations": plain_iters, "s": round(t_plain, 3), "iters_per_s": round(plain_iters / t_plain, 4),
+                  "efficiency_start": round(eff_start, 5), "efficiency_end": round(eff_plain, 5),
+                  "F_end": round(F_end, 5)},
+        "surrogate": {"params": net.n_params(), "patch": [wl.nr, wl.nphi], "train_samples": n_train - nh,
+                      "held_out": nh, "sample_s": round(t_gen, 2), "train_s": round(t_train, 2),
+                      "train_loss_end": losses[-1][1],
+                      "field_err_median": round(float(np.median(errs)), 4),
+                      "field_err_p90": round(float(np.percentile(errs, 90)), 4)},
+        "assisted": {"fdtd_rechecks": n_fd, "surrogate_iterations": n_sur,
+                     "iterations": n_fd + n_sur, "s": round(state["t"], 3),
+                     "iters_per_s": round((n_fd + n_sur) / max(state["t"], 1e-9), 4),
+                     "efficiency_end": round(state["eff"], 5), "F_end": round(F_best, 5),
+                     "reached_target_within_1pct": bool(state["reached"]),
+                     "accepted_surrogate_blocks": sum(1 for h in hist if h["surrogate_block"] and h["accepted"]),
+                     "rejected_surrogate_blocks": sum(1 for h in hist if h["surrogate_block"] and not h["accepted"])},
+        "wall_clock_ratio_plain_over_assisted": round(t_plain / max(state["t"], 1e-9), 4)
+                                               if state["reached"] else None,
+    }

@@ -91,3 +91,47 @@ def test_continuous_zone_weights_equal_wedge_weights_on_a_pure_mode():
         plane = E0[..., None] * phase[None, :, None, :]
         a_w = np.einsum("kaij,kaij->k", Ww, plane)
         assert np.allclose(a_w, a_c, rtol=1e-6, atol=0), (n, nphi, a_w, a_c)
+
+
+def test_ring_focal_field_on_axis_is_the_focal_phasor():
+    """On the axis the co-polarised amplitude (E_x - i E_y)/2 of the ring
+    projection equals the focal objective's phasor a_k (two independent
+    routes: full-ring Cartesian quadrature and the wedge weights)."""
+    rng = np.random.default_rng(6)
+    wl = Workload("obj", r_in=60.0, nr=20, nphi=12, nz=10, n_fold=9, m=1, pml=(3, 4, 2, 2))
+    om = (0.3, 0.41)
+    F = 140.0
+    W = objective.focal_weights(wl, om, F, device="cpu").numpy().astype(np.complex128)
+    plane = rng.standard_normal((2, 2, wl.nr, wl.nphi)) + 1j * rng.standard_normal((2, 2, wl.nr, wl.nphi))
+    a = np.einsum("kaij,kaij->k", W, plane)
+    E = objective.ring_focal_field(torch.tensor(plane), wl, om, F, [0.0], [0.0])
+    co = 0.5 * (E[:, 0, 0] - 1j * E[:, 1, 0])
+    assert np.allclose(co, a, rtol=1e-6, atol=0)
+
+
+def test_thin_ring_lens_focuses_to_the_bessel_spot():
+    """A narrow ring carrying the ideal converging wave e^{-i k sqrt(r^2 + F^2)}
+    (x + i y polarised, the m = +1 preset's field) focuses to the J0^2 spot of
+    an annular aperture: FWHM = 2 x 1.1264 / (k sin theta), sin theta =
+    r / sqrt(r^2 + F^2), within 3 %; the focusing efficiency against the
+    ring's own transmitted power is below 1 and positive."""
+    r0, width, n, nphi = 400.0, 8, 24, 6
+    wl = Workload("ring", r_in=r0, nr=width, nphi=nphi, nz=10, n_fold=n, m=1, pml=(0, 0, 2, 2))
+    w = 2 * np.pi / 20
+    F = 400.0
+    dphi = 2 * np.pi / (n * nphi)
+    ri = r0 + np.arange(width)
+    rh = ri + 0.5
+    pj, ph = np.arange(nphi) * dphi, (np.arange(nphi) + 0.5) * dphi
+    # x + i y = e^{i phi} (r + i phi): E_r = e^{i phi} u, E_phi = i e^{i phi} u
+    u_r = np.exp(-1j * w * np.sqrt(rh ** 2 + F ** 2))[:, None]
+    u_p = np.exp(-1j * w * np.sqrt(ri ** 2 + F ** 2))[:, None]
+    plane = np.stack([u_r * np.exp(1j * pj)[None], 1j * u_p * np.exp(1j * ph)[None]])[None]
+    P_t = objective.exit_plane_power(plane, wl)
+    eff = objective.focusing_efficiency(torch.tensor(plane), wl, (w,), F, incident_power=P_t, transmitted_power=P_t,
+                                        n_rho=160, n_phi=4, rho_max=120.0)
+    rm = r0 + width / 2
+    sin_t = rm / np.sqrt(rm ** 2 + F ** 2)
+    expect = 2 * 1.1264 / (w * sin_t)
+    assert abs(eff["fwhm"][0] - expect) < 0.03 * expect, (eff["fwhm"], expect)
+    assert 0.0 < eff["relative"][0] < 1.0
