@@ -270,11 +270,14 @@ def main():
                     help="skip the gradient-zone design iteration reported beside the headline")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-assisted vs plain design comparison on the surrogate zone")
-    ap.add_argument("--lens-iter-steps", type=int, default=2000,
-                    help="with --workload lwir: steps per run of the timed lens design iterations (0: none)")
+    ap.add_argument("--lens-iter-steps", type=int, default=None,
+                    help="with --workload lwir or c4: steps per run of the timed lens design iterations "
+                         "(0: none; default 2000 for lwir, 200 for c4)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 4 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
+    if args.lens_iter_steps is None:
+        args.lens_iter_steps = 200 if args.workload == "c4" else 2000
     if args.gpus != 1:
         print("bench.py: the benchmark runs on one GPU only; --gpus %d is not supported "
               "(a lens would shard its zones across GPUs, one zone per GPU; not built)" % args.gpus,
@@ -354,6 +357,37 @@ def main():
                                             keep_fields=False)
         gw = cells * args.steps / (ms_w / 1e3) / 1e9
         best_waves = gw > gc
+        fa = None
+        if args.lens_iter_steps > 0:
+            # one optimizer step of the whole lens: batched forward runs with
+            # the design-layer DFT, the lens focal objective (all 48 zones'
+            # phasors summed), one batched adjoint run and the overlaps; the
+            # zones hold one field set so that all of them fit at once
+            from paper_2501_07979_amd.workloads import c4 as c4_lens
+            T = args.lens_iter_steps
+            wl_it = c4_lens(steps=T)
+            print("bench: lens forward + adjoint iteration (%d steps per run)" % T, file=sys.stderr, flush=True)
+            ln = lens.Lens(wl_it, single_buffer=True)
+            rhos = [torch.tensor(w.rho(), device="cuda", requires_grad=True) for w in wl_it]
+            secs = []
+            for it in range(2):
+                for r in rhos:
+                    r.grad = None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F, _ = ln.objective(rhos)
+                F.backward()
+                torch.cuda.synchronize()
+                secs.append(time.perf_counter() - t0)
+            finite = all(bool(torch.isfinite(r.grad).all()) for r in rhos)
+            ln.close()
+            del ln, rhos
+            torch.cuda.empty_cache()
+            rate = 2 * cells * T / secs[1] / 1e9
+            fa = {"steps_per_run": T, "runs_per_iter": 2, "s_per_iter": round(secs[1], 3),
+                  "s_first_iter": round(secs[0], 3), "gcell_updates_per_s": round(rate, 3), "finite_gradient": finite,
+                  "kernels": "batched in-place kernels, one field set per zone, every zone at once",
+                  "s_per_iter_at_%d_steps" % wls[0].steps: round(2 * cells * wls[0].steps / (rate * 1e9), 1)}
         print(json.dumps({"metric": METRIC, "value": round(max(gc, gw), 4), "unit": "Gcell-updates/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": round((ms_w if best_waves else ms) / args.steps, 4),
@@ -364,7 +398,8 @@ def main():
                                      "one_batch_single_buffer": {"gcell_updates_per_s": round(gc, 4),
                                                                  "autotune": tune},
                                      "waves_two_step": {"gcell_updates_per_s": round(gw, 4), "waves": nwaves,
-                                                        "budget_bytes": int(0.8 * free)}}}), flush=True)
+                                                        "budget_bytes": int(0.8 * free)}},
+                          "forward_adjoint_iteration": fa}), flush=True)
         return
     wl = WORKLOADS[args.workload]()
     K = len(wl.omegas)

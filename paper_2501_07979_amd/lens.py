@@ -22,7 +22,7 @@ class Lens:
     pulse, frequencies and step count) of one lens; focal length from the
     numerical aperture at the lens's outer radius."""
 
-    def __init__(self, workloads, na=0.3):
+    def __init__(self, workloads, na=0.3, single_buffer=False):
         self.workloads = list(workloads)
         w0 = self.workloads[0]
         for w in self.workloads[1:]:
@@ -31,16 +31,25 @@ class Lens:
                     raise ValueError("zones of one lens share %s (%r != %r)" % (f, getattr(w, f), getattr(w0, f)))
         self.radius = max(w.r_in + w.nr * w.dr for w in self.workloads)
         self.focal = objective.focal_length(self.radius, na)
-        self.zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), w.eps()) for w in self.workloads]
+        sb = 1 if single_buffer else 0
+        self.zones = [zda.Zone(zda.default_desc(single_buffer=sb, **w.desc_kwargs()), w.eps())
+                      for w in self.workloads]
         # one batch per kernel family: narrow wedges and the continuous zone on
-        # the flat-mapped two-step kernel, the others on the two-step kernel
+        # the flat-mapped two-step kernel, the others on the two-step kernel;
+        # single-buffer zones (half the field memory, so that a lens larger
+        # than half the HBM fits at once) all on the in-place kernels
         self.groups = []
-        for narrow in (True, False):
-            idx = [q for q, w in enumerate(self.workloads) if is_narrow(w) == narrow]
-            if idx:
-                b = zda.Batch([self.zones[q] for q in idx])
-                set_family(b, FLAT if narrow else TWO_STEP, [self.workloads[q] for q in idx])
-                self.groups.append((idx, b))
+        if single_buffer:
+            b = zda.Batch(self.zones)
+            set_family(b, IN_PLACE, self.workloads)
+            self.groups.append((list(range(len(self.zones))), b))
+        else:
+            for narrow in (True, False):
+                idx = [q for q, w in enumerate(self.workloads) if is_narrow(w) == narrow]
+                if idx:
+                    b = zda.Batch([self.zones[q] for q in idx])
+                    set_family(b, FLAT if narrow else TWO_STEP, [self.workloads[q] for q in idx])
+                    self.groups.append((idx, b))
         self.weights = [objective.focal_weights(w, w.omegas, self.focal) for w in self.workloads]
         self.run_kw = dict(nsteps=w0.steps, omegas=w0.omegas, k_src=w0.k_src, omega_c=w0.omega_c, width=w0.width)
 
@@ -72,7 +81,7 @@ class Lens:
 # Zones up to 32 phi cells (the kernel's limit) take it: in batches of eight
 # 1250 x nphi x 180 wedges it ran 47.2, 44.7, 46.1 Gcell-updates/s at
 # nphi = 16, 22, 32 against 9.8, 22.7, 31.2 on the 13-row kernel
-TWO_STEP, FLAT = 13, 34
+TWO_STEP, FLAT, IN_PLACE = 13, 34, 4
 FLAT_KCHUNK = 16
 NARROW_PHI = 32
 

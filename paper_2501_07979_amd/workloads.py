@@ -168,9 +168,9 @@ def c4_zone(l, steps=4000):
                     width=w, seed=4000 + l, density="smoothed")
 
 
-def c4(nzones=48):
+def c4(nzones=48, steps=4000):
     """The batched lens: 48 uneven zones (2.89e9 cells in total)."""
-    return [c4_zone(l) for l in range(1, nzones + 1)]
+    return [c4_zone(l, steps) for l in range(1, nzones + 1)]
 
 
 def lwir_lens(nz=180, steps=10000):
