@@ -398,7 +398,9 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
  * in their own launch) instead of passing them through the intermediate set
  * in device memory; 0 = through the intermediate set; -1 (default) = 1 when
  * the zone has at least 1024 layer tiles (its layer launch fills the CUs
- * several times over).  Same results either way. */
+ * several times over).  A batch of two-step zones carries them when its
+ * first zone's option is 1 (its default is not to).  Same results either
+ * way. */
 #define ZDA_OPT_LAYER_CARRY 7
 zda_status zda_zone_set_option(zda_zone *z, int option, int value);
 

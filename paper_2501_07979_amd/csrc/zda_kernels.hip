@@ -1472,13 +1472,13 @@ __global__ __launch_bounds__(FLAT_BLOCK) void eh_flat_batch(BatchArgs b, int n_r
     eh_flat_body(a, n, local % gq, local / gq);
 }
 
-template <int TR, int LAY>
+template <int TR, int LAY, bool CARRY = false>
 __global__ __launch_bounds__(64 * (TR + 3)) void eh2_batch(BatchArgs b, int n_rel)
 {
     const uint4 tile = b.tiles[blockIdx.x];
     const StepArgs a = zone_args(b.tab, (int)tile.w);
     const int n = n_rel + (b.n_base ? *b.n_base : 0);
-    eh2_body<TR, LAY>(a, n, tile);
+    eh2_body<TR, LAY, CARRY>(a, n, tile);
 }
 
 template <int LAY>
@@ -1688,6 +1688,7 @@ void launch_batch_two_tr(const BatchArgs &b, unsigned ntiles, int lay, int n_rel
 {
     dim3 block(64, TR + 3, 1);
     if (lay == 0) hipLaunchKernelGGL((eh2_batch<TR, 0>), dim3(ntiles), block, 0, s, b, n_rel);
+    else if (lay == 2) hipLaunchKernelGGL((eh2_batch<TR, 2, true>), dim3(ntiles), block, 0, s, b, n_rel);
     else hipLaunchKernelGGL((eh2_batch<TR, 3>), dim3(ntiles), block, 0, s, b, n_rel);
 }
 
@@ -1698,6 +1699,9 @@ void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, int la
         if (lay == 0) hipLaunchKernelGGL(eh2_flat_batch<0>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, b, n_rel);
         else if (lay == 2) hipLaunchKernelGGL(eh2_flat_batch<2>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, b, n_rel);
         else hipLaunchKernelGGL(eh2_flat_batch<3>, dim3(ntiles), dim3(FLAT_BLOCK), 0, s, b, n_rel);
+    } else if (lay == 1) {
+        hipLaunchKernelGGL((eh2_batch<TWO_CARRY_ROWS, 3, true>), dim3(ntiles), dim3(64, TWO_CARRY_ROWS + 3, 1), 0, s,
+                           b, n_rel);
     } else if (tile_rows == 13) launch_batch_two_tr<13>(b, ntiles, lay, n_rel, s);
     else launch_batch_two_tr<5>(b, ntiles, lay, n_rel, s);
 }

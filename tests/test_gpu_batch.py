@@ -35,10 +35,12 @@ def zda():
     return Z
 
 
-@pytest.mark.parametrize("mode", ["fused", "split", "flat", "two", "two_odd"])
+@pytest.mark.parametrize("mode", ["fused", "split", "flat", "two", "two_odd", "two_carry"])
 def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
+    """two_carry: the batched layer tiles keep step one's auxiliaries in
+    registers (the single-zone runs do not: same bits either way)."""
     wls = _zones()
-    if mode == "two_odd":            # an odd step count ends with one fused step
+    if mode in ("two_odd", "two_carry"):   # an odd step count ends with one fused step
         for w in wls:
             w.steps = 151
     eps = [w.eps() for w in wls]
@@ -54,8 +56,11 @@ def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
                         z.dft(zda.MON_VOLUME).cpu().numpy()))
         z.close()
     zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    if mode == "two_carry":
+        for z in zones:
+            z.set_option(zda.OPT_LAYER_CARRY, 1)
     b = zda.Batch(zones)
-    b.set_launch({"fused": 7, "split": 4, "flat": 32, "two": 13, "two_odd": 5}[mode])
+    b.set_launch({"fused": 7, "split": 4, "flat": 32, "two": 13, "two_odd": 5, "two_carry": 13}[mode])
     srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
     _say("batch run", mode)
     b.run(srcs, wls[0].steps, wls[0].omegas, volume=True)    # graph replays + eager tail
@@ -71,7 +76,8 @@ def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
     b.close()
 
 
-def test_batch_adjoint_equals_single_zone_adjoint(zda):
+@pytest.mark.parametrize("carry", [0, 1])
+def test_batch_adjoint_equals_single_zone_adjoint(zda, carry):
     import torch
     wls = _zones(seed=71)
     for w in wls:
@@ -88,9 +94,12 @@ def test_batch_adjoint_equals_single_zone_adjoint(zda):
         single.append(z.adjoint_grad(g).cpu().numpy())
         z.close()
     zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
+    for z in zones:
+        z.set_option(zda.OPT_LAYER_CARRY, carry)
     b = zda.Batch(zones)
+    b.set_launch(13)
     srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
-    _say("batch forward + adjoint")
+    _say("batch forward + adjoint, carry", carry)
     b.run(srcs, wls[0].steps, wls[0].omegas, volume=True)
     grads = b.adjoint_grad(dFs)
     for gb, gs in zip(grads, single):

@@ -144,19 +144,24 @@ def test_training_learns_a_teacher_network(sur):
 
 def test_surrogate_gain_at_equal_efficiency(sur):
     """What the trained network gains: on the 128 x 128 x 96 surrogate zone,
-    surrogate-assisted design (the network trained on FDTD samples; FDTD
-    re-check and gradient every 10 iterations) reaches the final focusing
-    efficiency of 24 plain FDTD-adjoint iterations within 1 % with fewer
-    FDTD-adjoint evaluations than the plain path needs for it."""
+    surrogate-assisted design (the network trained once on FDTD samples; FDTD
+    re-check and gradient every 10 iterations) and plain FDTD-adjoint design,
+    both from the same start and each at learning rates 0.02, 0.05, 0.1, to
+    the focusing efficiency that 24 plain iterations at 0.02 reach (within
+    1 %): at every learning rate the assisted path needs fewer FDTD-adjoint
+    evaluations, and its best run fewer than the best plain run."""
     from paper_2501_07979_amd.workloads import c5_zone
     res = sur.equal_efficiency_comparison(c5_zone(), log=lambda m: _say(m))
     p, a, n = res["plain"], res["assisted"], res["surrogate"]
-    _say("plain: %d evaluations / %.2f s to the target; assisted: %d re-checks + %d surrogate iterations / %.2f s; "
-         "speedup online %s, with training %s" % (p["fdtd_evaluations_to_target"], p["s_to_target"],
-                                                   a["fdtd_rechecks"], a["surrogate_iterations"], a["s"],
-                                                   res["speedup_online"], res["speedup_with_training"]))
+    for pr, ar in zip(p["to_target"], a["to_target"]):
+        _say("lr %.3f: plain %d evaluations / %.2f s; assisted %d re-checks + %d surrogate iterations / %.2f s"
+             % (pr["lr"], pr["fdtd_evaluations_to_target"], pr["s_to_target"], ar["fdtd_rechecks"],
+                ar["surrogate_iterations"], ar["s"]))
+    _say("best against best: online speedup %s, with the one-off training %s"
+         % (res["speedup_online_best"], res["speedup_with_training_best"]))
     assert p["efficiency_end"] > 10 * p["efficiency_start"]
     assert np.isfinite(n["field_err_median"]) and n["params"] > 1_500_000
-    assert a["reached_target_within_1pct"]
-    assert a["fdtd_rechecks"] < p["fdtd_evaluations_to_target"]
-    assert a["F_accepted"][-1] > a["F_accepted"][0]
+    for pr, ar in zip(p["to_target"], a["to_target"]):
+        assert pr["lr"] == ar["lr"] and pr["reached"] and ar["reached_target_within_1pct"]
+        assert ar["fdtd_rechecks"] < pr["fdtd_evaluations_to_target"]
+    assert a["best"]["fdtd_rechecks"] < p["best"]["fdtd_evaluations_to_target"]
