@@ -120,8 +120,10 @@ void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStre
 // TR rows and a range of planes.
 constexpr int two_step_cols(int lay) { return lay == 0 ? 56 : 61; }
 // owned rows of the two-step tiles with r-layer rows whose step-one
-// auxiliaries stay in registers (launch code lay = 1)
-constexpr int TWO_CARRY_ROWS = 7;
+// auxiliaries stay in registers (launch code lay = 1): 8-wavefront blocks
+// of 195 VGPRs, two waves per SIMD (7 rows without the grouped loads of
+// the level-n auxiliaries: 166 VGPRs, 3 waves per SIMD, 19 % slower)
+constexpr int TWO_CARRY_ROWS = 5;
 // a fused-step tile owns FUSED_COLS phi cells and TR rows
 constexpr int FUSED_COLS = 56;
 // tile_rows code of the in-place kernels with the flat (r, phi) mapping, its

@@ -348,17 +348,6 @@ struct AuxCarry {
     float2 v[N_SLOT];
 };
 
-// read from memory (the level before the half-step), write to registers
-struct AuxToReg {
-    const float2 *sR, *sZ;
-    AuxCarry *r;
-    __device__ __forceinline__ float2 ld(int q, size_t slabR, size_t slabZ, unsigned o) const
-    {
-        return q < N_AUX_R ? ldo(sR + q * slabR, o) : ldo(sZ + (q - N_AUX_R) * slabZ, o);
-    }
-    __device__ __forceinline__ void st(int q, float2 v, size_t, size_t, unsigned) const { r->v[q] = v; }
-};
-
 // read from registers, write to memory (the level after the half-step)
 struct AuxFromReg {
     const AuxCarry *r;
@@ -368,6 +357,15 @@ struct AuxFromReg {
     {
         *(q < N_AUX_R ? pto(dR + q * slabR, o) : pto(dZ + (q - N_AUX_R) * slabZ, o)) = v;
     }
+};
+
+// read from registers loaded together beforehand (the level before the
+// half-step), write to registers
+struct AuxPreToReg {
+    const AuxCarry *p;
+    AuxCarry *r;
+    __device__ __forceinline__ float2 ld(int q, size_t, size_t, unsigned) const { return p->v[q]; }
+    __device__ __forceinline__ void st(int q, float2 v, size_t, size_t, unsigned) const { r->v[q] = v; }
 };
 
 // y = x / (1 + s F) with the auxiliary of slot q read through io and, when
@@ -846,9 +844,11 @@ __device__ __forceinline__ PlaneIn load_plane(const StepArgs &a, int k, size_t p
 // CARRY: the level-(n+1) auxiliaries stay in registers from step one at
 // plane k to step two at the same plane (the next iteration) instead of
 // going through the intermediate set: each thread reads back only what it
-// wrote itself, so the values and the arithmetic are the same.  It costs two
-// sets of the cell's auxiliaries in registers, which the layer tiles of a
-// narrower block (or with the z-layer recursions only) can hold.
+// wrote itself, so the values and the arithmetic are the same.  The level-n
+// auxiliaries that step one reads are loaded together at the start of the
+// plane, so their latencies overlap.  It costs three sets of the cell's
+// auxiliaries in registers, which the layer tiles of a narrower block (or
+// with the z-layer recursions only) can hold.
 template <int TR, int LAY, bool CARRY = false>
 __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
 {
@@ -902,9 +902,10 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
     // the next plane's loads are issued one plane ahead (where the registers
     // allow), so they are in flight through this plane's barriers and updates
     constexpr bool PF = !PR && !CARRY;
-    using X1 = std::conditional_t<CARRY, AuxToReg, AuxRows>;
+    using X1 = std::conditional_t<CARRY, AuxPreToReg, AuxRows>;
     using X2 = std::conditional_t<CARRY, AuxFromReg, AuxRows>;
     AuxCarry car_c, car_p;   // CARRY: step one's auxiliaries of planes k and k - 1
+    AuxCarry pre;            // CARRY: the level-n auxiliaries of plane k, all loads issued together
     PlaneIn cur = load_plane(a, k_lo, plane, rowc, dip, o, ojp, oc);
     for (int k = k_lo; k <= ke; ++k) {
         const int km = k - 1;
@@ -925,14 +926,22 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
         ZCoef zc = {};
         X1 x1 = {};
         if constexpr (CARRY) x1.r = &car_c;   // set on every path, so the carry stays in registers
+        if constexpr (CARRY) x1.p = &pre;
         float2 ez0 = zero2();
         if (step1 && active) {
             kz = PZ ? slab_row(k, nz, a.pz0, a.pz1) : -1;
             if (kz >= 0) zc = a.zrows[k];
             const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
             const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
-            x1.sR = a.auxR + sr0;
-            x1.sZ = a.auxZ + sz0;
+            if constexpr (CARRY) {
+                if (ir >= 0)
+                    for (int q = 0; q < N_AUX_R; ++q) pre.v[q] = ldo(a.auxR + sr0 + q * slabR, o);
+                if (kz >= 0)
+                    for (int q = 0; q < N_AUX_Z; ++q) pre.v[N_AUX_R + q] = ldo(a.auxZ + sz0 + q * slabZ, o);
+            } else {
+                x1.sR = a.auxR + sr0;
+                x1.sZ = a.auxZ + sz0;
+            }
             if constexpr (!CARRY) {
                 x1.dR = a.mauxR + sr0;
                 x1.dZ = a.mauxZ + sz0;
@@ -952,7 +961,8 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
             if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
             float2 u0 = zero2(), uu1 = zero2();
             if (ir >= 0 && k > 0) {
-                u0 = ldo(x1.sR + AUX_U_EP * slabR, o);
+                if constexpr (CARRY) u0 = pre.v[AUX_U_EP];
+                else u0 = ldo(a.auxR + sr0 + AUX_U_EP * slabR, o);
                 if (ir1 >= 0) uu1 = ldo(a.auxR + AUX_U_EP * slabR + ((size_t)k * a.dR + ir1) * nphi, o);
             }
             h_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x1, o, row_ok, ez0, er0, ep0, ez_jp, er_jp, er_kp, ep_kp,

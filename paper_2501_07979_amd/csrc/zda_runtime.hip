@@ -250,7 +250,7 @@ struct zda_zone {
     int xcd_remap = 0, nt_stores = 1, layer_stream = 0;
     int tile_patch = 0;            // (bands << 8) | columns of an XCD's patch of two-step tiles, 0 = off
     int layer_kchunk = -1;         // planes per chunk of the r-layer band tiles (-1: automatic)
-    int layer_carry = -1;          // 1: layer tiles keep step one's auxiliaries in registers; -1: automatic
+    int layer_carry = 1;           // 1: layer tiles keep step one's auxiliaries in registers
     int watch_every = 1000;        // steps between in-loop divergence checks (0: off)
     int tiles_lkc = -2, tiles_carry = -1;
     // second stream and join events for the concurrent layer-tile launch
@@ -797,27 +797,13 @@ int two_step_rows(int tile_rows, int nphi)
     return tile_rows == FLAT_TWO_ROWS ? flat_two_rows(nphi) : tile_rows;
 }
 
-// Layer tiles at and above which the automatic choice keeps step one's
-// auxiliaries in registers: four per CU.  Measured on one MI355X, the layer
-// launch of the 512 x 1024 x 400 zone (1802 tiles) runs 2.59 -> 2.21 ms with
-// them, that of the 256 x 512 x 300 zone (486 tiles, whose r-band tiles
-// already leave CUs idle) 0.71 -> 0.86 ms.
-constexpr size_t CARRY_MIN_LAYER_TILES = 1024;
-
 // A zone's two-step tile list (interior tiles first) and its counts.
 void plan_zone_tiles(const zda_zone *z, std::vector<uint4> &all, TileCounts &tc)
 {
     const int TR = z->tile_rows;
     TwoStepTiles t;
-    bool carry = z->layer_carry > 0;
-    if (z->layer_carry < 0 && TR != FLAT_TWO_ROWS) {
-        TwoStepTiles plain;
-        two_step_tiles(z, two_step_rows(TR, z->d.nphi), z->kchunk, z->k_src_last, tile_order(z), 0u, plain, false,
-                       false);
-        carry = plain.v[1].size() + plain.v[2].size() + plain.v[3].size() >= CARRY_MIN_LAYER_TILES;
-    }
     two_step_tiles(z, two_step_rows(TR, z->d.nphi), z->kchunk, z->k_src_last, tile_order(z), 0u, t,
-                   TR == FLAT_TWO_ROWS, carry);
+                   TR == FLAT_TWO_ROWS, z->layer_carry != 0);
     all.clear();
     for (int q = 0; q < 4; ++q) {
         tc.n_lay[q] = (unsigned)t.v[q].size();
@@ -1933,7 +1919,7 @@ zda_status zda_zone_set_option(zda_zone *z, int option, int value)
         z->layer_kchunk = value;
         return ZDA_OK;
     case ZDA_OPT_LAYER_CARRY:
-        if (value < -1 || value > 1) return fail(ZDA_ERR_ARG, "layer carry is -1 (automatic), 0 or 1");
+        if (value < 0 || value > 1) return fail(ZDA_ERR_ARG, "layer carry is 0 or 1");
         z->layer_carry = value;
         return ZDA_OK;
     case ZDA_OPT_TILE_PATCH:
@@ -2097,12 +2083,9 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
     }
     unsigned n_lay[4] = {0, 0, 0, 0};
     if (b->two) {
-        // layer tiles with carried auxiliaries only when the first zone asks
-        // for them (ZDA_OPT_LAYER_CARRY = 1): on the 48-zone lens, in two
-        // waves of 24 zones, they measured 53.2 against 53.9 Gcell-updates/s
-        // without, so the automatic choice of single zones is not applied
+        // layer tiles with carried auxiliaries as the first zone's option says
         const bool flat = b->tile_rows == FLAT_TWO_ROWS;
-        const bool carry = !flat && b->zones[0]->layer_carry > 0;
+        const bool carry = !flat && b->zones[0]->layer_carry != 0;
         TwoStepTiles t;
         for (int i = 0; i < nz; ++i) {
             const zda_zone *z = b->zones[i];

@@ -7,8 +7,10 @@ if the library is missing -- there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -83,7 +85,9 @@ ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctyp
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)
 
 _lib = None
-_allocator = None     # keeps the registered callbacks alive
+# every callback pair ever registered stays alive: zones created while it was
+# registered free their memory through it until they are destroyed
+_allocators = []
 
 
 def load():
@@ -143,11 +147,9 @@ def load():
 def use_torch_allocator(on=True):
     """Back the device memory of zones and batches created from now on with
     torch's caching allocator (on=False restores hipMalloc / hipFree)."""
-    global _allocator
     lib = load()
     if not on:
         _check(lib.zda_set_allocator(ALLOC_FN(), FREE_FN(), None))
-        _allocator = None
         return
     torch = _torch()
 
@@ -162,7 +164,7 @@ def use_torch_allocator(on=True):
 
     cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
     _check(lib.zda_set_allocator(cbs[0], cbs[1], None))
-    _allocator = cbs
+    _allocators.append(cbs)
 
 
 def _status_name(st):
@@ -189,6 +191,36 @@ def default_desc(**kw) -> ZoneDesc:
     return d
 
 
+# zones and batches not yet closed, destroyed at interpreter exit while torch
+# (whose caching allocator may back their memory) is still whole
+_live_zones = weakref.WeakSet()
+_live_batches = weakref.WeakSet()
+_exit_hook = False
+
+
+def _close_live():
+    for b in list(_live_batches):
+        try:
+            b.close()
+        except Exception:
+            pass
+    for z in list(_live_zones):
+        try:
+            z.close()
+        except Exception:
+            pass
+
+
+def _track(obj, live):
+    """Registers obj for destruction at exit; the hook is registered after
+    torch is imported, so that it runs before torch's own exit handlers."""
+    global _exit_hook
+    live.add(obj)
+    if not _exit_hook:
+        atexit.register(_close_live)
+        _exit_hook = True
+
+
 def _torch():
     import torch
     if not torch.cuda.is_available():
@@ -213,6 +245,7 @@ class Zone:
         ptr, on_dev, keep = self._in_ptr(torch, eps, torch.float32)
         _check(lib.zda_zone_create(ctypes.byref(desc), ptr, on_dev, ctypes.byref(h)))
         self._h = h
+        _track(self, _live_zones)
         # advanced by every call that changes what an adjoint run would use
         # (permittivity, design, fields, forward monitors)
         self.state_serial = 0
@@ -222,6 +255,7 @@ class Zone:
         if getattr(self, "_h", None):
             load().zda_zone_destroy(self._h)
             self._h = None
+        _live_zones.discard(self)
 
     def __del__(self):
         try:
@@ -410,11 +444,13 @@ class Batch:
         h = ctypes.c_void_p()
         _check(load().zda_batch_create(arr, len(self.zones), ctypes.byref(h)))
         self._h = h
+        _track(self, _live_batches)
 
     def close(self):
         if getattr(self, "_h", None):
             load().zda_batch_destroy(self._h)
             self._h = None
+        _live_batches.discard(self)
 
     def __del__(self):
         try:

@@ -35,12 +35,13 @@ def zda():
     return Z
 
 
-@pytest.mark.parametrize("mode", ["fused", "split", "flat", "two", "two_odd", "two_carry"])
+@pytest.mark.parametrize("mode", ["fused", "split", "flat", "two", "two_odd", "two_nocarry"])
 def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
-    """two_carry: the batched layer tiles keep step one's auxiliaries in
-    registers (the single-zone runs do not: same bits either way)."""
+    """two_nocarry: the batched layer tiles pass step one's auxiliaries
+    through the intermediate set (the single-zone runs keep them in
+    registers: same bits either way)."""
     wls = _zones()
-    if mode in ("two_odd", "two_carry"):   # an odd step count ends with one fused step
+    if mode in ("two_odd", "two_nocarry"):   # an odd step count ends with one fused step
         for w in wls:
             w.steps = 151
     eps = [w.eps() for w in wls]
@@ -56,11 +57,11 @@ def test_batch_equals_single_zone_runs(zda, oracle_mod, mode):
                         z.dft(zda.MON_VOLUME).cpu().numpy()))
         z.close()
     zones = [zda.Zone(zda.default_desc(**w.desc_kwargs()), e) for w, e in zip(wls, eps)]
-    if mode == "two_carry":
+    if mode == "two_nocarry":
         for z in zones:
-            z.set_option(zda.OPT_LAYER_CARRY, 1)
+            z.set_option(zda.OPT_LAYER_CARRY, 0)
     b = zda.Batch(zones)
-    b.set_launch({"fused": 7, "split": 4, "flat": 32, "two": 13, "two_odd": 5, "two_carry": 13}[mode])
+    b.set_launch({"fused": 7, "split": 4, "flat": 32, "two": 13, "two_odd": 5, "two_nocarry": 13}[mode])
     srcs = [zda.preset_source(k_src=w.k_src, omega_c=w.omega_c, width=w.width) for w in wls]
     _say("batch run", mode)
     b.run(srcs, wls[0].steps, wls[0].omegas, volume=True)    # graph replays + eager tail

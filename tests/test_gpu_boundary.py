@@ -147,15 +147,20 @@ def test_zone_memory_from_torch_allocator(zda):
     """With torch's caching allocator registered, a zone's device memory comes
     from it (torch counts it) and goes back on destroy; results are bitwise
     those of a zone on hipMalloc."""
+    import gc
     import torch
     wl = _small()
     ref_zone = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
     _run(ref_zone, wl, volume=True)
     ref = ref_zone.dft_host(zda.MON_PLANE)
     ref_zone.close()
+    # tensors of earlier tests that only the cycle collector frees would
+    # otherwise be freed (uncounted) while the zone allocates
+    gc.collect()
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated()
     zda.use_torch_allocator(True)
+    z = None
     try:
         z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
         during = torch.cuda.memory_allocated()
@@ -169,4 +174,25 @@ def test_zone_memory_from_torch_allocator(zda):
         torch.cuda.synchronize()
         assert torch.cuda.memory_allocated() == before, (torch.cuda.memory_allocated(), before, grown)
     finally:
+        if z is not None:
+            z.close()         # frees through the torch allocator while it is registered and alive
         zda.use_torch_allocator(False)
+
+
+def test_zone_outlives_its_allocator_registration(zda):
+    """A zone created while torch's allocator was registered frees its memory
+    through those callbacks even after the registration is undone and the
+    caller dropped every reference to them."""
+    import gc
+    import torch
+    wl = _small()
+    zda.use_torch_allocator(True)
+    try:
+        z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    finally:
+        zda.use_torch_allocator(False)
+    gc.collect()
+    _run(z, wl)
+    assert np.isfinite(z.dft_host(zda.MON_PLANE)).all()
+    z.close()
+    torch.cuda.synchronize()

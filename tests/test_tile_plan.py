@@ -128,7 +128,7 @@ PLAN_CARRY = 1 << 16
 @pytest.mark.parametrize("name", list(ZONES))
 def test_carry_plan_tiles(name, kchunk, tile_rows):
     """The plan of ZDA_OPT_LAYER_CARRY: every cell owned once; kind 1 tiles
-    (r-layer rows, auxiliaries carried in registers) own at most 7 rows;
+    (r-layer rows, auxiliaries carried in registers) own at most 5 rows;
     kind 2 tiles compute no r-layer row; the interior tiles are those of the
     plain plan."""
     from paper_2501_07979_amd import zda
@@ -146,7 +146,7 @@ def test_carry_plan_tiles(name, kchunk, tile_rows):
         kb, ke = int(zz & 0xFFFF), int(zz >> 16)
         assert (kind == 0) == (q < n_int) and kind in (0, 1, 2)
         cols = 56 if kind == 0 else 61
-        assert 1 <= rows <= (7 if kind == 1 else tile_rows) and kb < ke
+        assert 1 <= rows <= (5 if kind == 1 else tile_rows) and kb < ke
         j0 = int(bx) * cols
         assert j0 < nphi
         own[kb:ke, i0:i0 + rows, j0:min(j0 + cols, nphi)] += 1
