@@ -383,11 +383,11 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 #define ZDA_OPT_LAYER_STREAM 3
 #define ZDA_OPT_TILE_PATCH 4
 /* ZDA_OPT_LAYER_KCHUNK: planes per chunk of the two-step tiles of the r-layer
- * bands (outside the z-layers).  -1 (default): the zone's kchunk (at most
- * 48), halved (down to 12) while the layer-tile launch would hold fewer than
- * 512 tiles,
- * so that its long r-band tiles do not leave most CUs idle; 0: the zone's
- * kchunk. */
+ * bands (outside the z-layers).  -1 (default): the zone's kchunk, at most 24
+ * when the layer tiles carry their auxiliaries in registers (48 otherwise),
+ * halved (down to 12) while the layer-tile launch would hold fewer than 512
+ * tiles, so that its long r-band tiles do not leave most CUs idle; 0: the
+ * zone's kchunk. */
 #define ZDA_OPT_LAYER_KCHUNK 5
 /* ZDA_OPT_WATCHDOG: steps between the in-loop divergence checks of all six
  * fields (default 1000; 0 = off; see zda_zone_sync). */

@@ -653,10 +653,13 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
     const size_t z_in1 = planes.size();
     split_range(zB, d.nz, kc, planes);
     auto gx_of = [&](int lay) { return (d.nphi + two_step_cols(lay) - 1) / two_step_cols(lay); };
-    // chunk depth of the r-layer band tiles: given, or at most 48 and halved
-    // (down to 12 planes) while the layer launch would hold fewer than 512
-    // tiles (two blocks per CU)
-    int lkc = z->layer_kchunk > 0 ? std::min(z->layer_kchunk, kc) : std::min(kc, 48);
+    // chunk depth of the r-layer band tiles: given, or at most 48 (24 for
+    // the tiles that carry their auxiliaries in registers) and halved (down
+    // to 12 planes) while the layer launch would hold fewer than 512 tiles
+    // (two blocks per CU).  With carried auxiliaries 24 planes measured best
+    // of 8-96 on the 512 x 1024 x 400 zone (layer launches 1.772 -> 1.748
+    // ms against 48) and on the 256 x 512 x 300 zone (0.564 -> 0.464 ms)
+    int lkc = z->layer_kchunk > 0 ? std::min(z->layer_kchunk, kc) : std::min(kc, carry ? 24 : 48);
     if (z->layer_kchunk < 0) {
         const size_t r_bands = r_in0 + (rows.size() - r_in1), z_chunks = z_in0 + (planes.size() - z_in1);
         const size_t z_tiles = z_chunks * (r_in1 - r_in0) * (size_t)gx_of(3);
