@@ -64,11 +64,11 @@ def algorithmic_bytes(wl, K):
 
 
 def two_step_interior_bytes(tm, K):
-    """Bytes the two-step kernel's launch over interior tiles must move: it
+    """Bytes a multi-step kernel's launch over interior tiles must move: it
     reads E, H (48 B) and dt/eps (4 B) of every owned cell once and writes E,
-    H (48 B) once for two time steps (no layer cells in these tiles); exit
-    plane cells add K x 2 x 16 B (DFT read+write, both steps folded into one
-    update), source cells 2 x 8 B (pattern)."""
+    H (48 B) once for the launch's two (three) time steps (no layer cells in
+    these tiles); exit plane cells add K x 2 x 16 B (DFT read+write, the
+    steps folded into one update), source cells 2 x 8 B (pattern)."""
     return 100 * tm.e_cells + K * 32 * tm.e_mon_cells + 16 * tm.e_src_cells
 
 
@@ -273,6 +273,9 @@ def main():
     ap.add_argument("--lens-iter-steps", type=int, default=None,
                     help="with --workload lwir or c4: steps per run of the timed lens design iterations "
                          "(0: none; default 2000 for lwir, 200 for c4)")
+    ap.add_argument("--launch", default=None, metavar="KCHUNK,TILE_ROWS",
+                    help="launch shape of the timed zone (zda_zone_set_launch), e.g. 64,11 for the three-step "
+                         "kernel; default: the zone's own")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 4 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -410,6 +413,9 @@ def main():
     eps = torch.from_numpy(eps_host).cuda()
     zone = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
     del eps
+    if args.launch:
+        kc, tr = (int(v) for v in args.launch.split(","))
+        zone.set_launch(kc, tr)
     run_kw = dict(k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
@@ -453,14 +459,15 @@ def main():
     e_avg = tm.e_ms / tm.e_launches
     kernel_ms = {}
     min_bytes = None
-    if tm.steps_per_launch == 2:   # two-step kernel: interior tiles + tiles with layer cells
-        kernel = "eh2_kernel_interior"
+    if tm.steps_per_launch >= 2:   # multi-step kernel: interior tiles + tiles with layer cells
+        depth = tm.steps_per_launch
+        kernel = "eh%d_kernel_interior" % depth
         kbytes = interior_b_alg_per_launch(tm, K)
         min_bytes = two_step_interior_bytes(tm, K)
-        kernel_ms = {"eh2_kernel_interior": round(e_avg, 5),
-                     "eh2_kernel_layer": round(tm.layer_ms / tm.layer_launches, 5)}
-        zone_min = two_step_zone_bytes(wl, K) / 2
-        family = "two-step"
+        kernel_ms = {kernel: round(e_avg, 5),
+                     "eh%d_kernel_layer" % depth: round(tm.layer_ms / tm.layer_launches, 5)}
+        zone_min = two_step_zone_bytes(wl, K) / depth
+        family = "two-step" if depth == 2 else "three-step"
     elif tm.h_launches == 0:      # fused step: one kernel per time step
         kernel, kbytes = "eh_fused_kernel", fused
         kernel_ms = {"eh_fused_kernel": round(e_avg, 5)}

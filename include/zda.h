@@ -349,7 +349,12 @@ typedef struct {
  * nphi <= 64), tile_rows = 34 the two-step kernel with a flat mapping (a
  * block holds 256 / nphi whole rows and owns all but three, the radial halo;
  * nphi <= 32; an odd last step of a run takes the flat fused step; needs what
- * the two-step kernel needs).  Default: for zones of at most 16
+ * the two-step kernel needs), tile_rows = 11 the three-step kernel (three
+ * time steps per launch, a block owns 11 rows x 56 phi cells, r-layer band
+ * tiles 7 rows x 59 cells, tiles with z-layer planes only 11 x 59; the last
+ * nsteps mod 3 steps of a run take the fused step; needs what the two-step
+ * kernel needs, and allocates a second intermediate set of the layer
+ * auxiliaries when first selected: ZDA_ERR_OOM if that fails).  Default: for zones of at most 16
  * phi cells (and the continuous zone) the flat in-place kernels; for zones
  * of 17 to 32 phi cells the flat two-step kernel in 4-plane chunks (where
  * the two-step kernel fits); otherwise the two-step kernel with 13 rows
@@ -429,7 +434,11 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
  * the host (no device is touched; a zone created from d with the same
  * tile_rows, kchunk and tile order runs exactly these tiles).  tile_rows: 5,
  * 13 or 34 (flat mapping: tiles own 256 / nphi - 3 rows and every phi cell,
- * nphi <= 32); kchunk >= 1 planes per chunk; k_src: the source plane (only the
+ * nphi <= 32), or 11 for the three-step kernel's plan (interior tiles own
+ * 11 rows and 56 phi cells and compute rows i0-3 .. i0+rows+1 and planes
+ * kb-3 .. ke+1; kind 2 for the tiles whose computed rows hold no r-layer
+ * cell, kind 3 for the r-layer band tiles of at most 7 rows; layer tiles own
+ * 59 phi cells); kchunk >= 1 planes per chunk; k_src: the source plane (only the
  * cell counts depend on it); order: 0 natural, 1 contiguous range per XCD
  * (ZDA_OPT_XCD_REMAP), else a patch code (ZDA_OPT_TILE_PATCH), with
  * ZDA_PLAN_CARRY or-ed in for the plan of ZDA_OPT_LAYER_CARRY.  out (may be
@@ -443,7 +452,7 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
  * tiles.
  * *ntiles and *n_interior receive the counts.  Errors: ZDA_ERR_ARG (sizes
  * < 1, nr or nz > 65535, a layer wider than half the extent, tile_rows not 5,
- * 13 or 34, 34 with nphi > 32, kchunk < 1, a patch field of 0, out too
+ * 13, 34 or 11, 34 with nphi > 32, kchunk < 1, a patch field of 0, out too
  * small). */
 #define ZDA_PLAN_CARRY (1 << 16)
 zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kchunk, int k_src, int order,

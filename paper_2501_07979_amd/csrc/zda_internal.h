@@ -76,6 +76,8 @@ struct StepArgsT {
     // linear indices of the tiles this launch covers
     C *mauxR, *mauxZ;
     const uint4 *tiles;            // {phi block, first row | rows << 16, kb | ke << 16, 0}
+    // three-step launch: auxiliaries at the second intermediate time level
+    C *m2auxR, *m2auxZ;
 };
 using StepArgs = StepArgsT<float>;
 using StepArgs64 = StepArgsT<double>;
@@ -124,6 +126,19 @@ constexpr int two_step_cols(int lay) { return lay == 0 ? 56 : 61; }
 // of 195 VGPRs, two waves per SIMD (7 rows without the grouped loads of
 // the level-n auxiliaries: 166 VGPRs, 3 waves per SIMD, 19 % slower)
 constexpr int TWO_CARRY_ROWS = 5;
+// Three-step kernel (three leap-frog steps per launch): the tile_rows code
+// that selects it, the owned rows of its tiles without r-layer rows (16
+// wavefronts, three halo rows below and two above) and of its r-layer band
+// tiles (12 wavefronts), and its owned phi cells (56 on 64 B boundaries
+// without layer cells; 59, all exact lanes, with them)
+constexpr int THREE_STEP_ROWS = 11;
+constexpr int THREE_LAYER_ROWS = 7;
+constexpr int three_step_cols(int lay) { return lay == 0 ? 56 : 59; }
+// three leap-frog steps (n, n + 1, n + 2) over the tiles listed in a.tiles;
+// lay 0: no layer cell in the tile's computed rows and planes, lay 2: the
+// z-layer recursions only, lay 3: r- and z-layer recursions (r-layer band
+// tiles of THREE_LAYER_ROWS rows)
+void launch_three_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream_t s);
 // a fused-step tile owns FUSED_COLS phi cells and TR rows
 constexpr int FUSED_COLS = 56;
 // tile_rows code of the in-place kernels with the flat (r, phi) mapping, its

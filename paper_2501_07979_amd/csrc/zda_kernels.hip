@@ -1087,6 +1087,313 @@ __device__ __forceinline__ void eh2_body(const StepArgs &a, int n, uint4 tile)
     }
 }
 
+// The value a float2 holds in lane l - 1 (shr) or l + 1 (shl) of the wave,
+// moved by DPP wave shifts (lane 0, resp. 63, gets zero).  Every lane of the
+// wave must execute it.
+__device__ __forceinline__ float dpp_f(float x, int ctrl_shl)
+{
+    const int v = __float_as_int(x);
+    return __int_as_float(ctrl_shl ? __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true)
+                                   : __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float2 from_lane_below(float2 x) { return make_float2(dpp_f(x.x, 0), dpp_f(x.y, 0)); }
+__device__ __forceinline__ float2 from_lane_above(float2 x) { return make_float2(dpp_f(x.x, 1), dpp_f(x.y, 1)); }
+
+// Three whole leap-frog steps (n, n + 1, n + 2) per launch: the two-step
+// schedule above one step deeper.  The launch reads level n from one buffer
+// set and writes level n + 3 to the other, so each cell's six fields cross
+// HBM once per three steps.  Block = (TR + 5) wavefronts x 64 lanes marching
+// a z-chunk: wave w on row i0 - 3 + w, lane l on phi cell j0 - 3 + l (j0 =
+// three_step_cols(LAY) x tile column), modulo nphi as before.  Step s + 1
+// lags step s by one plane; per plane the H half-steps of the three steps
+// hand their -r neighbours to the E half-steps through LDS, the E half-steps
+// of steps one and two hand their +r neighbours to the next H half-step
+// through LDS (double-buffered, the H half-step reads the plane below), and
+// the +-phi neighbours move between lanes by DPP shifts.  Exact cells: step
+// one H everywhere, E on lanes >= 1 and waves >= 1; step two H on lanes
+// 1..62, waves 1..nrow + 3, E on lanes 2..62, waves 2..nrow + 3; step three
+// H on lanes 2..61, waves 2..nrow + 2, E (owners) on lanes 3..3 + COLS - 1,
+// waves 3..nrow + 2.  A chunk starts three planes early; step one runs two
+// planes past its end.  Layer auxiliaries: level n + 1 goes to the
+// intermediate set m, level n + 2 to the second intermediate set m2 (written
+// only by exact cells, so every block that writes one writes the same
+// value), level n + 3 (owners) to the other set.
+template <int TR, int LAY>
+__device__ __forceinline__ void eh3_body(const StepArgs &a, int n, uint4 tile)
+{
+    constexpr bool PR = (LAY & 1) != 0, PZ = (LAY & 2) != 0;
+    constexpr bool LAYERS = PR || PZ;
+    constexpr int NW = TR + 5;
+    constexpr int NV = PR ? NW : 1;
+    __shared__ float2 s1z[NW][64], s1p[NW][64], s1v[NV][64];
+    __shared__ float2 sE1z[2][NW][64], sE1p[2][NW][64], sU1[2][NV][64];
+    __shared__ float2 s2z[NW][64], s2p[NW][64], s2v[NV][64];
+    __shared__ float2 sE2z[2][NW][64], sE2p[2][NW][64], sU2[2][NV][64];
+    __shared__ float2 s3z[NW][64], s3p[NW][64], s3v[NV][64];
+    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int nphi = a.nphi, nr = a.nr, nz = a.nz;
+    const size_t plane = (size_t)nr * nphi;
+    const int bx = (int)tile.x, i0 = (int)(tile.y & 0xffffu), nrow = (int)(tile.y >> 16);
+    const int kb = (int)(tile.z & 0xffffu), ke = (int)(tile.z >> 16);
+    const int i = i0 + w - 3;
+    const bool active = w <= nrow + 4;                      // waves above the top halo row idle
+    const bool row_ok = active && i >= 0 && i < nr;
+    constexpr int COLS = three_step_cols(LAY);
+    const int jj = bx * COLS - 3 + lane;
+    const int pc = (jj % nphi + nphi) % nphi;               // physical column
+    const bool cross_m = pc == 0;                           // lane - 1 holds column nphi - 1
+    const bool cross_p = pc == nphi - 1;                    // lane + 1 holds column 0
+    const bool own = lane >= 3 && lane < 3 + COLS && jj < nphi && w >= 3 && w <= nrow + 2 && row_ok;
+    const int k_lo = max(kb - 3, 0);
+    const bool nt = a.nt_stores;
+    const int ir = (PR && row_ok) ? slab_row(i, nr, a.pr0, a.pr1) : -1;
+    const int ir1 = (PR && row_ok && i + 1 < nr) ? slab_row(i + 1, nr, a.pr0, a.pr1) : -1;
+    const RowCoef rc = a.rows[row_ok ? i : 0];
+    const int ic = min(max(i, 0), nr - 1);
+    const unsigned o = (unsigned)pc * 8u;
+    const unsigned ojp = cross_p ? 0u : o + 8u;
+    const unsigned oc = (unsigned)pc * 4u;
+    const size_t rowc = (size_t)ic * nphi;
+    const bool ip_ok = ic + 1 < nr;
+    const size_t dip = ip_ok ? (size_t)nphi : 0;
+    const size_t slabR = (size_t)nz * a.dR * nphi;
+    const size_t slabZ = (size_t)a.dZ * plane;
+    const int nd = a.k1 - a.k0;
+    // exact lanes of the E and H half-steps of steps one to three (all lanes
+    // without layer recursions: inexact cells then only feed inexact cells)
+    const bool l_e1 = !LAYERS || lane >= 1, l_h2 = !LAYERS || (lane >= 1 && lane <= 62);
+    const bool l_e2 = !LAYERS || (lane >= 2 && lane <= 62), l_h3 = !LAYERS || (lane >= 2 && lane <= 61);
+
+    // carried along z (level: plane): E^n (k); H, E, U, dt/eps of step one
+    // (k - 1) and E of step one at k - 2 (DFT); H, E, U of step two (k - 2);
+    // H of step three (k - 3)
+    float2 er0 = ldo(a.Er + (size_t)k_lo * plane + rowc, o);
+    float2 ep0 = ldo(a.Ep + (size_t)k_lo * plane + rowc, o);
+    float2 h1r_p = zero2(), h1p_p = zero2(), h1z_p = zero2();
+    float2 e1r_p = zero2(), e1p_p = zero2(), e1z_p = zero2(), u1_p = zero2();
+    float2 e1r_pp = zero2(), e1p_pp = zero2(), e1z_pp = zero2();
+    float2 h2r_p = zero2(), h2p_p = zero2(), h2z_p = zero2();
+    float2 e2r_p = zero2(), e2p_p = zero2(), e2z_p = zero2(), u2_p = zero2();
+    float2 h3r_km = zero2(), h3p_km = zero2();
+    float ce_p = 0.f, ce_pp = 0.f;
+    for (int k = k_lo; k <= ke + 1; ++k) {
+        const int km = k - 1, km2 = k - 2;
+        const PlaneIn in = load_plane(a, min(k, nz - 1), plane, rowc, dip, o, ojp, oc);
+        float2 h1r = zero2(), h1p = zero2(), h1z = zero2(), v1 = zero2();
+        float2 e1r = zero2(), e1p = zero2(), e1z = zero2(), u1 = zero2();
+        float2 er_kp = zero2(), ep_kp = zero2();
+        float ce = 0.f;
+        const bool step1 = k < nz;
+        // ---- step one, H at plane k
+        int kz = -1;
+        ZCoef zc = {};
+        AuxRows x1 = {};
+        float2 ez0 = zero2();
+        if (step1 && active) {
+            kz = PZ ? slab_row(k, nz, a.pz0, a.pz1) : -1;
+            if (kz >= 0) zc = a.zrows[k];
+            const size_t sr0 = ir >= 0 ? ((size_t)k * a.dR + ir) * nphi : 0;
+            const size_t sz0 = kz >= 0 ? ((size_t)kz * nr + ic) * nphi : 0;
+            x1 = AuxRows{a.auxR + sr0, a.auxZ + sz0, a.mauxR + sr0, a.mauxZ + sz0};
+            const bool kp_ok = k + 1 < nz;
+            ez0 = in.ez;
+            er_kp = in.er_kp;
+            ep_kp = in.ep_kp;
+            float2 ez_jp = in.ez_jp, er_jp = in.er_jp;
+            float2 ez_ip = in.ez_ip, ep_ip = in.ep_ip;
+            h1r = in.hr;
+            h1p = in.hp;
+            h1z = in.hz;
+            ce = in.ce;
+            if (!kp_ok) { er_kp = zero2(); ep_kp = zero2(); }
+            if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+            if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+            float2 u0 = zero2(), uu1 = zero2();
+            if (ir >= 0 && k > 0) {
+                u0 = ldo(a.auxR + sr0 + AUX_U_EP * slabR, o);
+                if (ir1 >= 0) uu1 = ldo(a.auxR + AUX_U_EP * slabR + ((size_t)k * a.dR + ir1) * nphi, o);
+            }
+            h_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x1, o, row_ok, ez0, er0, ep0, ez_jp, er_jp, er_kp, ep_kp,
+                   ez_ip, ep_ip, u0, uu1, h1r, h1p, h1z, v1);
+            s1z[w][lane] = h1z;
+            s1p[w][lane] = h1p;
+            if (PR) s1v[w][lane] = v1;
+        }
+        __syncthreads();
+        // ---- step one, E at plane k
+        {
+            float2 hz_jm = from_lane_below(h1z), hr_jm = from_lane_below(h1r);
+            if (step1 && (k != k_lo || k == 0) && w >= 1 && row_ok) {
+                if (l_e1) {
+                    if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+                    const float2 hz_im = s1z[w - 1][lane], hp_im = s1p[w - 1][lane];
+                    const float2 v_im = PR ? s1v[PR ? w - 1 : 0][lane] : zero2();
+                    float2 jr = zero2(), jph = zero2();
+                    if (k == a.k_src) sheet_current(a, n, plane, rowc, o, jr, jph);
+                    e1r = er0;
+                    e1p = ep0;
+                    e1z = ez0;
+                    e_cell(a, rc, zc, i, k, ir, kz, slabR, slabZ, x1, o, ce, jr, jph, h1r, hr_jm, h1r_p, h1p, hp_im,
+                           h1p_p, h1z, hz_jm, hz_im, v1, v_im, e1r, e1p, e1z, u1);
+                }
+                sE1z[k & 1][w][lane] = e1z;
+                sE1p[k & 1][w][lane] = e1p;
+                if (PR) sU1[k & 1][PR ? w : 0][lane] = u1;
+            }
+        }
+        // ---- step two, H at plane km
+        float2 h2r = zero2(), h2p = zero2(), h2z = zero2(), v2 = zero2();
+        const int kz2 = (PZ && km >= 0 && km < nz) ? slab_row(km, nz, a.pz0, a.pz1) : -1;
+        ZCoef zc2 = {};
+        if (kz2 >= 0) zc2 = a.zrows[km];
+        const size_t sr2 = ir >= 0 ? ((size_t)min(max(km, 0), nz - 1) * a.dR + ir) * nphi : 0;
+        const size_t sz2 = kz2 >= 0 ? ((size_t)kz2 * nr + ic) * nphi : 0;
+        const AuxRows x2 = {a.mauxR + sr2, a.mauxZ + sz2, a.m2auxR + sr2, a.m2auxZ + sz2};
+        {
+            float2 ez_jp = from_lane_above(e1z_p), er_jp = from_lane_above(e1r_p);
+            if (km >= 0 && km < nz && (km > k_lo || k_lo == 0) && w >= 1 && w <= nrow + 3 && row_ok && l_h2) {
+                const int b = km & 1;
+                if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+                float2 ez_ip = sE1z[b][w + 1][lane], ep_ip = sE1p[b][w + 1][lane];
+                if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+                float2 uu1 = zero2();
+                if (PR && ir1 >= 0) uu1 = sU1[b][PR ? w + 1 : 0][lane];
+                h2r = h1r_p;
+                h2p = h1p_p;
+                h2z = h1z_p;
+                // E of step one at km + 1 is the plane just finished (zero above the top)
+                h_cell(a, rc, zc2, i, km, ir, kz2, slabR, slabZ, x2, o, true, e1z_p, e1r_p, e1p_p, ez_jp, er_jp, e1r,
+                       e1p, ez_ip, ep_ip, (ir >= 0 && km > 0) ? u1_p : zero2(), uu1, h2r, h2p, h2z, v2);
+            }
+        }
+        s2z[w][lane] = h2z;
+        s2p[w][lane] = h2p;
+        if (PR) s2v[w][lane] = v2;
+        __syncthreads();
+        // ---- step two, E at plane km
+        float2 e2r = zero2(), e2p = zero2(), e2z = zero2(), u2 = zero2();
+        {
+            float2 hz_jm = from_lane_below(h2z), hr_jm = from_lane_below(h2r);
+            if (km >= 0 && km < nz && (km > k_lo + 1 || k_lo == 0) && w >= 2 && w <= nrow + 3 && row_ok) {
+                if (l_e2) {
+                    if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+                    const float2 hz_im = s2z[w - 1][lane], hp_im = s2p[w - 1][lane];
+                    const float2 v_im = PR ? s2v[PR ? w - 1 : 0][lane] : zero2();
+                    float2 jr = zero2(), jph = zero2();
+                    if (km == a.k_src) sheet_current(a, n + 1, plane, rowc, o, jr, jph);
+                    e2r = e1r_p;
+                    e2p = e1p_p;
+                    e2z = e1z_p;
+                    e_cell(a, rc, zc2, i, km, ir, kz2, slabR, slabZ, x2, o, ce_p, jr, jph, h2r, hr_jm, h2r_p, h2p,
+                           hp_im, h2p_p, h2z, hz_jm, hz_im, v2, v_im, e2r, e2p, e2z, u2);
+                }
+                sE2z[km & 1][w][lane] = e2z;
+                sE2p[km & 1][w][lane] = e2p;
+                if (PR) sU2[km & 1][PR ? w : 0][lane] = u2;
+            }
+        }
+        // ---- step three, H at plane km2
+        float2 h3r = zero2(), h3p = zero2(), h3z = zero2(), v3 = zero2();
+        const int kz3 = (PZ && km2 >= 0) ? slab_row(km2, nz, a.pz0, a.pz1) : -1;
+        ZCoef zc3 = {};
+        if (kz3 >= 0) zc3 = a.zrows[km2];
+        const size_t c0m = (size_t)max(km2, 0) * plane + rowc;
+        const size_t sr3 = ir >= 0 ? ((size_t)max(km2, 0) * a.dR + ir) * nphi : 0;
+        const size_t sz3 = kz3 >= 0 ? ((size_t)kz3 * nr + ic) * nphi : 0;
+        const AuxRows x3 = {a.m2auxR + sr3, a.m2auxZ + sz3, a.oauxR + sr3, a.oauxZ + sz3};
+        const bool store = own && km2 >= kb && km2 < ke;
+        {
+            float2 ez_jp = from_lane_above(e2z_p), er_jp = from_lane_above(e2r_p);
+            if (km2 >= 0 && (km2 > k_lo + 1 || k_lo == 0) && w >= 2 && w <= nrow + 2 && row_ok && l_h3) {
+                const int b = km2 & 1;
+                if (cross_p) { ez_jp = c_mul(a.seam_p, ez_jp); er_jp = c_mul(a.seam_p, er_jp); }
+                float2 ez_ip = sE2z[b][w + 1][lane], ep_ip = sE2p[b][w + 1][lane];
+                if (!ip_ok) { ez_ip = zero2(); ep_ip = zero2(); }
+                float2 uu1 = zero2();
+                if (PR && ir1 >= 0) uu1 = sU2[b][PR ? w + 1 : 0][lane];
+                h3r = h2r_p;
+                h3p = h2p_p;
+                h3z = h2z_p;
+                // E of step two at km2 + 1 is the plane step two just finished
+                h_cell(a, rc, zc3, i, km2, ir, kz3, slabR, slabZ, x3, o, store, e2z_p, e2r_p, e2p_p, ez_jp, er_jp,
+                       e2r, e2p, ez_ip, ep_ip, (ir >= 0 && km2 > 0) ? u2_p : zero2(), uu1, h3r, h3p, h3z, v3);
+            }
+        }
+        s3z[w][lane] = h3z;
+        s3p[w][lane] = h3p;
+        if (PR) s3v[w][lane] = v3;
+        __syncthreads();
+        // ---- step three, E at plane km2 (owners), stores and DFT
+        {
+            float2 hz_jm = from_lane_below(h3z), hr_jm = from_lane_below(h3r);
+            if (store) {
+                if (cross_m) { hz_jm = c_mul(a.seam_m, hz_jm); hr_jm = c_mul(a.seam_m, hr_jm); }
+                const float2 hz_im = s3z[w - 1][lane], hp_im = s3p[w - 1][lane];
+                const float2 v_im = PR ? s3v[PR ? w - 1 : 0][lane] : zero2();
+                float2 jr = zero2(), jph = zero2();
+                if (km2 == a.k_src) sheet_current(a, n + 2, plane, rowc, o, jr, jph);
+                float2 er3 = e2r_p, ep3 = e2p_p, ez3 = e2z_p, u3;
+                e_cell(a, rc, zc3, i, km2, ir, kz3, slabR, slabZ, x3, o, ce_pp, jr, jph, h3r, hr_jm, h3r_km, h3p,
+                       hp_im, h3p_km, h3z, hz_jm, hz_im, v3, v_im, er3, ep3, ez3, u3);
+                store_out(pto(a.oHr + c0m, o), h3r, nt);
+                store_out(pto(a.oHp + c0m, o), h3p, nt);
+                store_out(pto(a.oHz + c0m, o), h3z, nt);
+                store_out(pto(a.oEr + c0m, o), er3, nt);
+                store_out(pto(a.oEp + c0m, o), ep3, nt);
+                store_out(pto(a.oEz + c0m, o), ez3, nt);
+                if (a.dft_plane && km2 == a.k_mon) {
+                    for (int f = 0; f < a.K; ++f) {
+                        const float2 tw0 = a.twiddle[(size_t)n * a.K + f];
+                        const float2 tw1 = a.twiddle[(size_t)(n + 1) * a.K + f];
+                        const float2 tw2 = a.twiddle[(size_t)(n + 2) * a.K + f];
+                        float2 *q0 = pto(a.dft_plane + (size_t)f * 2 * plane + rowc, o);
+                        float2 *q1 = pto(a.dft_plane + (size_t)f * 2 * plane + plane + rowc, o);
+                        *q0 = c_fma(c_fma(c_fma(*q0, tw0, e1r_pp), tw1, e2r_p), tw2, er3);
+                        *q1 = c_fma(c_fma(c_fma(*q1, tw0, e1p_pp), tw1, e2p_p), tw2, ep3);
+                    }
+                }
+                if (a.dft_vol && km2 >= a.k0 && km2 < a.k1) {
+                    const size_t vs = (size_t)nd * plane;
+                    for (int f = 0; f < a.K; ++f) {
+                        const float2 tw0 = a.twiddle[(size_t)n * a.K + f];
+                        const float2 tw1 = a.twiddle[(size_t)(n + 1) * a.K + f];
+                        const float2 tw2 = a.twiddle[(size_t)(n + 2) * a.K + f];
+                        float2 *base = a.dft_vol + (size_t)f * 3 * vs + (size_t)(km2 - a.k0) * plane + rowc;
+                        float2 *q0 = pto(base, o), *q1 = pto(base + vs, o), *q2 = pto(base + 2 * vs, o);
+                        *q0 = c_fma(c_fma(c_fma(*q0, tw0, e1r_pp), tw1, e2r_p), tw2, er3);
+                        *q1 = c_fma(c_fma(c_fma(*q1, tw0, e1p_pp), tw1, e2p_p), tw2, ep3);
+                        *q2 = c_fma(c_fma(c_fma(*q2, tw0, e1z_pp), tw1, e2z_p), tw2, ez3);
+                    }
+                }
+            }
+        }
+        er0 = er_kp;
+        ep0 = ep_kp;
+        e1r_pp = e1r_p;
+        e1p_pp = e1p_p;
+        e1z_pp = e1z_p;
+        h1r_p = h1r;
+        h1p_p = h1p;
+        h1z_p = h1z;
+        e1r_p = e1r;
+        e1p_p = e1p;
+        e1z_p = e1z;
+        u1_p = u1;
+        ce_pp = ce_p;
+        ce_p = ce;
+        h3r_km = h3r;
+        h3p_km = h3p;
+        h2r_p = h2r;
+        h2p_p = h2p;
+        h2z_p = h2z;
+        e2r_p = e2r;
+        e2p_p = e2p;
+        e2z_p = e2z;
+        u2_p = u2;
+    }
+}
+
 // The two-step schedule above with the flat (r, phi) mapping, for narrow
 // zones (nphi <= FLAT_TWO_MAX_PHI): a block of FLAT_BLOCK threads holds
 // RB = FLAT_BLOCK / nphi whole rows, thread t on row slot s = t / nphi
@@ -1359,6 +1666,12 @@ __global__ __launch_bounds__(64 * (TR + 1)) void eh_fused_kernel(StepArgs a, int
     const unsigned nblk = gx * gy * gridDim.z;
     const unsigned p = xcd_order(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), nblk, a.xcd_remap);
     eh_fused_body<TR>(a, n, p, gx, gy);
+}
+
+template <int TR, int LAY>
+__global__ __launch_bounds__(64 * (TR + 5)) void eh3_kernel(StepArgs a, int n)
+{
+    eh3_body<TR, LAY>(a, n, a.tiles[blockIdx.x]);
 }
 
 template <int TR, int LAY, bool CARRY = false>
@@ -1739,6 +2052,15 @@ void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStre
                            a, n);
     } else if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, lay, s);
     else launch_two_tr<5>(a, n, ntiles, lay, s);
+}
+
+void launch_three_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStream_t s)
+{
+    if (ntiles == 0) return;
+    constexpr int TR = THREE_STEP_ROWS, TL = THREE_LAYER_ROWS;
+    if (lay == 0) hipLaunchKernelGGL((eh3_kernel<TR, 0>), dim3(ntiles), dim3(64, TR + 5), 0, s, a, n);
+    else if (lay == 2) hipLaunchKernelGGL((eh3_kernel<TR, 2>), dim3(ntiles), dim3(64, TR + 5), 0, s, a, n);
+    else hipLaunchKernelGGL((eh3_kernel<TL, 3>), dim3(ntiles), dim3(64, TL + 5), 0, s, a, n);
 }
 
 unsigned tiles_split(const StepArgs &a, int BY)

@@ -259,6 +259,10 @@ struct zda_zone {
     // two-step launches: auxiliaries at the intermediate time level, and the
     // tile lists (interior tiles without layer cells first, then layer tiles)
     float2 *mauxR = nullptr, *mauxZ = nullptr;
+    // three-step launches (tile_rows THREE_STEP_ROWS): the second
+    // intermediate time level, allocated when the zone first selects them
+    float2 *m2auxR = nullptr, *m2auxZ = nullptr;
+    bool has_m2 = false, three = false;
     uint4 *tiles2 = nullptr;
     size_t cap_tiles2 = 0;
     bool has_m = false;
@@ -288,6 +292,7 @@ struct zda_zone {
     int timed_steps = 0;
     bool timed_fused = false;
     bool timed_two = false;
+    int timed_depth = 2;
     TileCounts timed_tc;
 };
 
@@ -491,6 +496,7 @@ StepArgs step_args(zda_zone *z, int m)
     a.auxR = z->auxR[s0]; a.auxZ = z->auxZ[s0];
     a.oauxR = z->auxR[s1]; a.oauxZ = z->auxZ[s1];
     a.mauxR = z->mauxR; a.mauxZ = z->mauxZ;
+    a.m2auxR = z->m2auxR; a.m2auxZ = z->m2auxZ;
     a.rows = z->rows; a.zrows = z->zrows;
     a.k_mon = d.k_mon;
     a.k0 = d.design_k0; a.k1 = d.design_k1;
@@ -510,6 +516,8 @@ zda_status reset_state(zda_zone *z, hipStream_t s)
     }
     if (z->mauxR) launch_fill(z->mauxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, s);
     if (z->mauxZ) launch_fill(z->mauxZ, (size_t)N_AUX_Z * z->dZ * z->plane, s);
+    if (z->m2auxR) launch_fill(z->m2auxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, s);
+    if (z->m2auxZ) launch_fill(z->m2auxZ, (size_t)N_AUX_Z * z->dZ * z->plane, s);
     if (z->flag) launch_set_int(z->flag, 0, s);
     z->cur = 0;
     HIP_TRY(hipGetLastError());
@@ -630,17 +638,22 @@ int tile_order(const zda_zone *z)
 }
 
 void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, unsigned tag, TwoStepTiles &t,
-                    bool split_z = false, bool carry = false)
+                    bool split_z = false, bool carry = false, bool three = false)
 {
     // carry: the r-layer bands are cut into tiles of TWO_CARRY_ROWS rows for
-    // the carrying instantiation, and the z-only tiles get their own launch
-    if (split_z) carry = false;
-    const int TRr = carry ? TWO_CARRY_ROWS : TR;
+    // the carrying instantiation, and the z-only tiles get their own launch.
+    // three: the three-step kernel's tiles (interior rows in bands of TR,
+    // r-layer bands in THREE_LAYER_ROWS, z-only tiles in their own launch),
+    // whose computed rows and planes reach one further below and above
+    if (split_z || three) carry = false;
+    const int TRr = three ? THREE_LAYER_ROWS : carry ? TWO_CARRY_ROWS : TR;
+    const int lo = three ? 3 : 2, hi = three ? 2 : 1;   // computed rows (planes) below and above a tile's own
     const zda_zone_desc &d = z->d;
-    const int rA = d.pml_r_in > 0 ? std::min(d.pml_r_in + 2, d.nr) : 0;
-    const int rB = d.pml_r_out > 0 ? std::max(d.nr - d.pml_r_out - 1, rA) : d.nr;
-    const int zA = d.pml_z_lo > 0 ? std::min(d.pml_z_lo + 2, d.nz) : 0;
-    const int zB = d.pml_z_hi > 0 ? std::max(d.nz - d.pml_z_hi - 1, zA) : d.nz;
+    const int rA = d.pml_r_in > 0 ? std::min(d.pml_r_in + lo, d.nr) : 0;
+    const int rB = d.pml_r_out > 0 ? std::max(d.nr - d.pml_r_out - hi, rA) : d.nr;
+    const int zA = d.pml_z_lo > 0 ? std::min(d.pml_z_lo + lo, d.nz) : 0;
+    const int zB = d.pml_z_hi > 0 ? std::max(d.nz - d.pml_z_hi - hi, zA) : d.nz;
+    auto cols_of = [three](int lay) { return three ? three_step_cols(lay) : two_step_cols(lay); };
     std::vector<std::pair<int, int>> rows, planes;
     split_range(0, rA, TRr, rows);
     const size_t r_in0 = rows.size();
@@ -652,7 +665,7 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
     split_range(zA, zB, kc, planes);
     const size_t z_in1 = planes.size();
     split_range(zB, d.nz, kc, planes);
-    auto gx_of = [&](int lay) { return (d.nphi + two_step_cols(lay) - 1) / two_step_cols(lay); };
+    auto gx_of = [&](int lay) { return (d.nphi + cols_of(lay) - 1) / cols_of(lay); };
     // chunk depth of the r-layer band tiles: given, or at most 48 (24 for
     // the tiles that carry their auxiliaries in registers) and halved (down
     // to 12 planes) while the layer launch would hold fewer than 512 tiles
@@ -683,8 +696,8 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
             // With split_z (the flat-mapped kernel, whose lens batches hold
             // many small tiles) the z-only tiles get their own launch: 2 %
             // faster on the 16-zone LWIR-shaped lens
-            const int lay = rl ? (carry ? 1 : 3) : (zl ? (split_z || carry ? 2 : 3) : 0);
-            const int cw = two_step_cols(lay);
+            const int lay = rl ? (carry ? 1 : 3) : (zl ? (split_z || carry || three ? 2 : 3) : 0);
+            const int cw = cols_of(lay);
             // r-layer band tiles carry ten recursions per cell: where they
             // are few, shorter chunks spread them over more blocks
             std::vector<std::pair<int, int>> sub;
@@ -806,7 +819,7 @@ void plan_zone_tiles(const zda_zone *z, std::vector<uint4> &all, TileCounts &tc)
     const int TR = z->tile_rows;
     TwoStepTiles t;
     two_step_tiles(z, two_step_rows(TR, z->d.nphi), z->kchunk, z->k_src_last, tile_order(z), 0u, t,
-                   TR == FLAT_TWO_ROWS, z->layer_carry != 0);
+                   TR == FLAT_TWO_ROWS, z->layer_carry != 0, z->three);
     all.clear();
     for (int q = 0; q < 4; ++q) {
         tc.n_lay[q] = (unsigned)t.v[q].size();
@@ -868,6 +881,10 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     const int ab_base = z->cur;
     const StepArgs &a = ab[0];
     const bool fused = z->fused, two = z->two;
+    // steps per launch of the multi-step kernels (the two-step family, or
+    // the three-step kernel); a run's last nsteps mod depth steps take the
+    // fused one-step kernel
+    const int depth = z->three ? 3 : 2;
     z->k_src_last = k_src;
     const uint4 *tiles = nullptr;
     TileCounts tc;
@@ -903,8 +920,8 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
             launch_e_step(a, n, s);
         }
     };
-    // steps n and n + 1 by the two-step kernel; ev (if given) brackets the
-    // interior-tile and the layer-tile launches
+    // steps n .. n + depth - 1 by the multi-step kernel; ev (if given)
+    // brackets the interior-tile and the layer-tile launches
     const bool conc = two && z->layer_stream && n_pml > 0 && !rb.noalloc;
     if (conc && !z->s2) {
         HIP_TRY(hipStreamCreateWithFlags(&z->s2, hipStreamNonBlocking));
@@ -917,7 +934,8 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
         size_t off = tc.n_lay[0];
         for (int q = 1; q < 4; ++q) {
             b.tiles = tiles + off;
-            launch_two_step(b, n, tc.n_lay[q], q, st);
+            if (depth == 3) launch_three_step(b, n, tc.n_lay[q], q, st);
+            else launch_two_step(b, n, tc.n_lay[q], q, st);
             off += tc.n_lay[q];
         }
     };
@@ -934,7 +952,8 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
         }
         b.tiles = tiles;
         if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-        launch_two_step(b, n, tc.n_lay[0], 0, s);
+        if (depth == 3) launch_three_step(b, n, tc.n_lay[0], 0, s);
+        else launch_two_step(b, n, tc.n_lay[0], 0, s);
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
         if (conc) {
             HIP_TRY(hipEventRecord(z->ev_join, sl));
@@ -958,11 +977,11 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
         int groups = 0;
         if (two) {
             int n = 0;
-            for (; n + 1 < nsteps; n += 2, ++groups) {
+            for (; n + depth - 1 < nsteps; n += depth, ++groups) {
                 if ((st = two_steps(n, &z->ev[4 * (size_t)groups])) != ZDA_OK) return st;
-                watch(n + 2);
+                watch(n + depth);
             }
-            if (n < nsteps) {
+            for (; n < nsteps; ++n) {
                 one_step(n);
                 watch(n + 1);
             }
@@ -986,14 +1005,15 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
         z->timed_steps = groups;
         z->timed_fused = fused || two;
         z->timed_two = two;
+        z->timed_depth = depth;
         z->timed_tc = tc;
     } else if (two) {
         int n = 0;
-        for (; n + 1 < nsteps; n += 2) {
+        for (; n + depth - 1 < nsteps; n += depth) {
             if ((st = two_steps(n, nullptr)) != ZDA_OK) return st;
-            watch(n + 2);
+            watch(n + depth);
         }
-        if (n < nsteps) {
+        for (; n < nsteps; ++n) {
             one_step(n);
             watch(n + 1);
         }
@@ -1887,10 +1907,11 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
     const bool split = tile_rows == 1 || tile_rows == 2 || tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
                        tile_rows == FLAT_ROWS;
     const bool fused = tile_rows == 3 || tile_rows == 7 || tile_rows == 15 || tile_rows == FLAT_FUSED_ROWS;
-    const bool two = tile_rows == 5 || tile_rows == 13 || tile_rows == FLAT_TWO_ROWS;
+    const bool three = tile_rows == THREE_STEP_ROWS;
+    const bool two = tile_rows == 5 || tile_rows == 13 || tile_rows == FLAT_TWO_ROWS || three;
     if (!split && !fused && !two)
-        return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused) or 5, 13, "
-                                 "34 (two-step)");
+        return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused), 5, 13, "
+                                 "34 (two-step) or 11 (three-step)");
     if ((fused || two) && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set");
     if ((fused || two) && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set");
     if (two && !z->has_m) return fail(ZDA_ERR_STATE, "no intermediate auxiliaries for the two-step kernel");
@@ -1899,10 +1920,23 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
         return fail(ZDA_ERR_ARG, "the flat fused step needs nphi <= %d", FLAT_FUSED_MAX_PHI);
     if (tile_rows == FLAT_TWO_ROWS && z->d.nphi > FLAT_TWO_MAX_PHI)
         return fail(ZDA_ERR_ARG, "the flat two-step kernel needs nphi <= %d", FLAT_TWO_MAX_PHI);
+    if (three && !z->has_m2) {
+        // the second intermediate time level of the layer auxiliaries
+        DeviceGuard g(z->device);
+        zda_status st = dev_alloc(z, &z->m2auxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi);
+        if (st == ZDA_OK) st = dev_alloc(z, &z->m2auxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
+        if (st != ZDA_OK) {
+            dev_free(z, z->m2auxR);
+            dev_free(z, z->m2auxZ);
+            return st;
+        }
+        z->has_m2 = true;
+    }
     z->kchunk = kchunk;
     z->tile_rows = tile_rows;
     z->fused = fused;
     z->two = two;
+    z->three = three;
     return ZDA_OK;
 }
 
@@ -1956,8 +1990,8 @@ zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kc
     if (d->pml_r_in < 0 || d->pml_r_out < 0 || d->pml_z_lo < 0 || d->pml_z_hi < 0 ||
         2 * std::max(d->pml_r_in, d->pml_r_out) > d->nr || 2 * std::max(d->pml_z_lo, d->pml_z_hi) > d->nz)
         return fail(ZDA_ERR_ARG, "layers must be >= 0 and at most half the extent");
-    if (tile_rows != 5 && tile_rows != 13 && tile_rows != FLAT_TWO_ROWS)
-        return fail(ZDA_ERR_ARG, "two-step tile_rows is 5, 13 or 34");
+    if (tile_rows != 5 && tile_rows != 13 && tile_rows != FLAT_TWO_ROWS && tile_rows != THREE_STEP_ROWS)
+        return fail(ZDA_ERR_ARG, "multi-step tile_rows is 5, 13, 34 or 11 (three-step)");
     if (tile_rows == FLAT_TWO_ROWS && d->nphi > FLAT_TWO_MAX_PHI)
         return fail(ZDA_ERR_ARG, "the flat two-step kernel needs nphi <= %d", FLAT_TWO_MAX_PHI);
     if (kchunk < 1) return fail(ZDA_ERR_ARG, "kchunk must be >= 1");
@@ -1969,7 +2003,7 @@ zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kc
     z.d = *d;
     TwoStepTiles t;
     two_step_tiles(&z, two_step_rows(tile_rows, d->nphi), std::min(kchunk, d->nz), k_src, order < 0 ? 0 : order, 0u,
-                   t, tile_rows == FLAT_TWO_ROWS, carry);
+                   t, tile_rows == FLAT_TWO_ROWS, carry, tile_rows == THREE_STEP_ROWS);
     *n_interior = t.v[0].size();
     *ntiles = t.v[0].size() + t.v[1].size() + t.v[2].size() + t.v[3].size();
     if (!out) return ZDA_OK;
@@ -2008,7 +2042,7 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t)
         }
     }
     t->h_launches = z->timed_fused ? 0 : z->timed_steps;
-    t->steps_per_launch = z->timed_two ? 2 : 1;
+    t->steps_per_launch = z->timed_two ? z->timed_depth : 1;
     t->layer_launches = z->timed_two ? z->timed_steps : 0;
     t->e_cells = z->timed_two ? z->timed_tc.cells : z->ncell;
     {

@@ -29,11 +29,12 @@ def _rel(a, b):
 # double-buffered step, 5/13 the two-step kernel, 1/2/4/8/16 the split
 # in-place H and E kernels, 32 the in-place kernels with the flat (r, phi)
 # mapping, 33 the fused step with the flat mapping (nphi <= 64), 34 the
-# two-step kernel with the flat mapping (nphi <= 32); None keeps the zone's
-# default
+# two-step kernel with the flat mapping (nphi <= 32), 11 the three-step
+# kernel; None keeps the zone's default
 SHAPES = {"default": None, "fused_tr3_kc7": (7, 3), "fused_tr15_kc13": (13, 15), "split_r4_kc7": (7, 4),
           "split_r1": (0, 1), "two_tr13_kc9": (9, 13), "two_tr5_kc6": (6, 5), "two_tr5_kc3": (3, 5),
-          "flat_kc5": (5, 32), "flatfused_kc5": (5, 33), "flattwo_kc5": (5, 34), "flattwo_kc16": (16, 34)}
+          "flat_kc5": (5, 32), "flatfused_kc5": (5, 33), "flattwo_kc5": (5, 34), "flattwo_kc16": (16, 34),
+          "three_kc9": (9, 11), "three_kc4": (4, 11)}
 # widest zone (phi cells) of the flat-mapped fused and two-step kernels
 FLAT_MAX_PHI = {33: 64, 34: 32}
 
@@ -53,7 +54,7 @@ def _zone_pair(zda, oracle_mod, wl, eps, shape=None):
     return g, o
 
 
-@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr13_kc9"])
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr13_kc9", "three_kc9"])
 def test_c1_parity_exit_plane_dft(zda, oracle_mod, shape):
     from paper_2501_07979_amd.workloads import c1
     wl = c1()
@@ -73,7 +74,7 @@ def test_c1_parity_exit_plane_dft(zda, oracle_mod, shape):
 
 
 @pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "fused_tr15_kc13", "split_r4_kc7", "two_tr13_kc9",
-                                   "two_tr5_kc6", "two_tr5_kc3", "flat_kc5"])
+                                   "two_tr5_kc6", "two_tr5_kc3", "flat_kc5", "three_kc9"])
 @pytest.mark.parametrize("case", ["ragged_m1", "ragged_m0", "ragged_mneg", "no_pml"])
 def test_ragged_shapes_all_fields(zda, oracle_mod, case, shape):
     """Shapes that are not multiples of the tile (nphi 70, nr 37) with uneven
@@ -99,7 +100,7 @@ def test_ragged_shapes_all_fields(zda, oracle_mod, case, shape):
 
 
 @pytest.mark.parametrize("shape", ["default", "fused_tr3_kc7", "split_r4_kc7", "two_tr13_kc9", "two_tr5_kc3",
-                                   "flat_kc5", "flatfused_kc5"])
+                                   "flat_kc5", "flatfused_kc5", "three_kc9", "three_kc4"])
 def test_random_state_steps_with_pml(zda, oracle_mod, shape):
     """Arbitrary initial fields (written through the ABI) stepped without
     reset: every update term, PML auxiliary and the seam act from step 1
@@ -161,7 +162,7 @@ def _objective(wts, plane):
     return np.sum(np.abs(s) ** 2), np.conj(s)[:, None, None, None] * wts
 
 
-@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc6"])
+@pytest.mark.parametrize("shape", ["default", "split_r4_kc7", "two_tr5_kc6", "three_kc4"])
 def test_gradient_parity_small_copy(zda, oracle_mod, shape):
     """Adjoint gradient over the design layer of the gradient zone's small
     copy (64 x 64 x 96, three frequencies) against the oracle's gradient."""

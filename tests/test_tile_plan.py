@@ -156,3 +156,38 @@ def test_carry_plan_tiles(name, kchunk, tile_rows):
         if kind == 1:
             assert r_lo < pr0 or r_hi >= nr - pr1, (i0, rows)
     assert own.min() == 1 and own.max() == 1
+
+
+@pytest.mark.parametrize("kchunk", [3, 9, 48])
+@pytest.mark.parametrize("name", list(ZONES))
+def test_three_step_tiles_cover_each_cell_once(name, kchunk):
+    """The three-step plan (tile_rows 11): every cell owned once; interior
+    tiles (kind 0) own at most 11 rows and 56 phi cells starting on 64 B
+    boundaries, and their computed rows i0-3 .. i0+rows+1 and planes kb-3 ..
+    ke+1 hold no layer cell; kind 2 tiles (z-layer recursions only) compute
+    no r-layer row; kind 3 tiles (r-layer bands) own at most 7 rows; layer
+    tiles own 59 phi cells."""
+    from paper_2501_07979_amd import zda
+    z = ZONES[name]
+    d = _desc(zda, **z)
+    tiles, n_int = zda.plan_two_step_tiles(d, 11, kchunk, k_src=2)
+    nr, nphi, nz = z["nr"], z["nphi"], z["nz"]
+    pr0, pr1, pz0, pz1 = z["pml"]
+    own = np.zeros((nz, nr, nphi), np.int32)
+    for q, (bx, y, zz, kind) in enumerate(tiles):
+        i0, rows = int(y & 0xFFFF), int(y >> 16)
+        kb, ke = int(zz & 0xFFFF), int(zz >> 16)
+        assert kind in (0, 2, 3) and (kind == 0) == (q < n_int)
+        assert 1 <= rows <= (7 if kind == 3 else 11) and kb < ke
+        cols = 56 if kind == 0 else 59
+        j0 = int(bx) * cols
+        assert j0 < nphi
+        own[kb:ke, i0:i0 + rows, j0:min(j0 + cols, nphi)] += 1
+        r_lo, r_hi = max(i0 - 3, 0), min(i0 + rows + 1, nr - 1)
+        if kind in (0, 2):
+            assert pr0 <= r_lo and r_hi < nr - pr1, (i0, rows)
+        if kind == 0:
+            assert (j0 * 8) % 64 == 0
+            k_lo, k_hi = max(kb - 3, 0), min(ke + 1, nz - 1)
+            assert pz0 <= k_lo and k_hi < nz - pz1, (kb, ke)
+    assert own.min() == 1 and own.max() == 1
