@@ -399,8 +399,10 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows);
 #define ZDA_OPT_WATCHDOG 6
 /* ZDA_OPT_LAYER_CARRY: 1 (default) = the two-step kernel's tiles with layer
  * cells keep the level-(n+1) recursion auxiliaries of step one in registers
- * for step two (tiles with r-layer rows in blocks of 5 owned rows, z-layer-
- * only tiles in their own launch, the level-n auxiliaries loaded together at
+ * for step two (tiles with r-layer rows in blocks of 5 owned rows, or of 7
+ * rows with the r-layer recursions only in the plane chunks without z-layer
+ * planes of a band that 7-row tiles cover with fewer wavefront rows; z-layer-
+ * only tiles in their own launch; the level-n auxiliaries loaded together at
  * the start of each plane); 0 = through the intermediate set in device
  * memory.  A batch follows its first zone's option.  Same results either
  * way. */
@@ -448,7 +450,9 @@ zda_status zda_zone_last_timing(zda_zone *z, zda_timing *t);
  * hold no layer cell; they own 56 phi cells) and 3 for the layer tiles (61
  * phi cells; with tile_rows 34 or ZDA_PLAN_CARRY, 2 for the tiles whose
  * computed rows hold no r-layer cell; with ZDA_PLAN_CARRY, 1 for the others,
- * which own at most 5 rows), interior tiles first; cap: capacity of out in
+ * which own at most 5 rows, and 4 for the r-layer band tiles of at most 7
+ * rows whose computed planes hold no z-layer plane, in the bands that 7-row
+ * tiles cover with fewer wavefront rows), interior tiles first; cap: capacity of out in
  * tiles.
  * *ntiles and *n_interior receive the counts.  Errors: ZDA_ERR_ARG (sizes
  * < 1, nr or nz > 65535, a layer wider than half the extent, tile_rows not 5,

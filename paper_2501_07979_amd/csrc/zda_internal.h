@@ -126,6 +126,13 @@ constexpr int two_step_cols(int lay) { return lay == 0 ? 56 : 61; }
 // of 195 VGPRs, two waves per SIMD (7 rows without the grouped loads of
 // the level-n auxiliaries: 166 VGPRs, 3 waves per SIMD, 19 % slower)
 constexpr int TWO_CARRY_ROWS = 5;
+// owned rows of the carried two-step tiles of an r-layer band whose chunk
+// holds no z-layer plane (launch code lay = 4): the r-layer recursions only,
+// 10-wavefront blocks of 166 VGPRs, 3 waves per SIMD; taken for the bands
+// that this cuts into fewer wavefront rows than TWO_CARRY_ROWS does
+constexpr int TWO_RBAND_ROWS = 7;
+// kinds of two-step tiles (lay codes 0..4)
+constexpr int N_LAY = 5;
 // Three-step kernel (three leap-frog steps per launch): the tile_rows code
 // that selects it, the owned rows of its tiles without r-layer rows (16
 // wavefronts, three halo rows below and two above) and of its r-layer band

@@ -2025,6 +2025,9 @@ void launch_batch_two(const BatchArgs &b, unsigned ntiles, int tile_rows, int la
     } else if (lay == 1) {
         hipLaunchKernelGGL((eh2_batch<TWO_CARRY_ROWS, 3, true>), dim3(ntiles), dim3(64, TWO_CARRY_ROWS + 3, 1), 0, s,
                            b, n_rel);
+    } else if (lay == 4) {
+        hipLaunchKernelGGL((eh2_batch<TWO_RBAND_ROWS, 1, true>), dim3(ntiles), dim3(64, TWO_RBAND_ROWS + 3, 1), 0, s,
+                           b, n_rel);
     } else if (tile_rows == 13) launch_batch_two_tr<13>(b, ntiles, lay, n_rel, s);
     else launch_batch_two_tr<5>(b, ntiles, lay, n_rel, s);
 }
@@ -2049,6 +2052,11 @@ void launch_two_step(const StepArgs &a, int n, unsigned ntiles, int lay, hipStre
         // tiles with r-layer rows, auxiliaries carried in registers: a
         // narrower block (TWO_CARRY_ROWS owned rows) leaves room for them
         hipLaunchKernelGGL((eh2_kernel<TWO_CARRY_ROWS, 3, true>), dim3(ntiles), dim3(64, TWO_CARRY_ROWS + 3, 1), 0, s,
+                           a, n);
+    } else if (lay == 4) {
+        // r-layer band tiles without z-layer planes, auxiliaries carried:
+        // the r-layer recursions only fit TWO_RBAND_ROWS rows at 3 waves per SIMD
+        hipLaunchKernelGGL((eh2_kernel<TWO_RBAND_ROWS, 1, true>), dim3(ntiles), dim3(64, TWO_RBAND_ROWS + 3, 1), 0, s,
                            a, n);
     } else if (a.tile_rows == 13) launch_two_tr<13>(a, n, ntiles, lay, s);
     else launch_two_tr<5>(a, n, ntiles, lay, s);

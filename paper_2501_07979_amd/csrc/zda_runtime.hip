@@ -190,7 +190,7 @@ struct Stage {
 // Tile counts of a two-step tile list (interior tiles first, then the layer
 // tiles by instantiation) and the cells the interior tiles own.
 struct TileCounts {
-    unsigned n_lay[4] = {0, 0, 0, 0};
+    unsigned n_lay[N_LAY] = {};
     size_t cells = 0, mon = 0, src = 0;
 };
 
@@ -625,7 +625,7 @@ struct TwoStepTiles {
     // owned rows), [2] the z-layer recursions only (tiles whose computed rows
     // hold no r-layer cell: the flat-mapped kernel, or carried in registers),
     // [3] the r- and z-layer recursions through the intermediate set
-    std::vector<uint4> v[4];
+    std::vector<uint4> v[N_LAY];
     size_t cells = 0, mon = 0, src = 0;   // owned by the interior tiles
 };
 
@@ -654,12 +654,30 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
     const int zA = d.pml_z_lo > 0 ? std::min(d.pml_z_lo + lo, d.nz) : 0;
     const int zB = d.pml_z_hi > 0 ? std::max(d.nz - d.pml_z_hi - hi, zA) : d.nz;
     auto cols_of = [three](int lay) { return three ? three_step_cols(lay) : two_step_cols(lay); };
-    std::vector<std::pair<int, int>> rows, planes;
+    std::vector<std::pair<int, int>> rows, rows2, planes;
     split_range(0, rA, TRr, rows);
     const size_t r_in0 = rows.size();
     split_range(rA, rB, TR, rows);
     const size_t r_in1 = rows.size();
     split_range(rB, d.nr, TRr, rows);
+    // with carried auxiliaries, the chunks without z-layer planes cut an
+    // r-layer band into TWO_RBAND_ROWS-row tiles of the r-layer-only
+    // instantiation (lay 4) where that takes fewer wavefront rows than
+    // TWO_CARRY_ROWS-row tiles: the 14- and 13-row bands of the 512 x 1024 x
+    // 400 zone (layer launches 1.757 -> 1.597 ms), not the 10- and 9-row bands
+    // of the 256 x 512 x 300 zone (0.462 -> 0.502 ms with 7-row tiles there)
+    auto rband_rows = [&](int h) {
+        if (!carry || h <= 0) return TRr;
+        const int w7 = (h + TWO_RBAND_ROWS - 1) / TWO_RBAND_ROWS * (TWO_RBAND_ROWS + 3);
+        const int w5 = (h + TWO_CARRY_ROWS - 1) / TWO_CARRY_ROWS * (TWO_CARRY_ROWS + 3);
+        return w7 < w5 ? TWO_RBAND_ROWS : TRr;
+    };
+    const int TRq0 = rband_rows(rA), TRq1 = rband_rows(d.nr - rB);
+    split_range(0, rA, TRq0, rows2);
+    const size_t r2_in0 = rows2.size();
+    split_range(rA, rB, TR, rows2);
+    const size_t r2_in1 = rows2.size();
+    split_range(rB, d.nr, TRq1, rows2);
     split_range(0, zA, kc, planes);
     const size_t z_in0 = planes.size();
     split_range(zA, zB, kc, planes);
@@ -674,7 +692,7 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
     // ms against 48) and on the 256 x 512 x 300 zone (0.564 -> 0.464 ms)
     int lkc = z->layer_kchunk > 0 ? std::min(z->layer_kchunk, kc) : std::min(kc, carry ? 24 : 48);
     if (z->layer_kchunk < 0) {
-        const size_t r_bands = r_in0 + (rows.size() - r_in1), z_chunks = z_in0 + (planes.size() - z_in1);
+        const size_t r_bands = r2_in0 + (rows2.size() - r2_in1), z_chunks = z_in0 + (planes.size() - z_in1);
         const size_t z_tiles = z_chunks * (r_in1 - r_in0) * (size_t)gx_of(3);
         const size_t in_planes = (size_t)(z_in1 > z_in0 ? planes[z_in1 - 1].second - planes[z_in0].first : 0);
         auto layer_tiles = [&](int c) {
@@ -682,21 +700,27 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
         };
         while (r_bands > 0 && lkc / 2 >= 12 && layer_tiles(lkc) < 512) lkc /= 2;
     }
-    std::vector<uint4> v[4];
+    std::vector<uint4> v[N_LAY];
     for (size_t pz = 0; pz < planes.size(); ++pz) {
         const int kb = planes[pz].first, ke = planes[pz].second;
         const bool zl = !(pz >= z_in0 && pz < z_in1);
-        for (size_t pr = 0; pr < rows.size(); ++pr) {
-            const int i0 = rows[pr].first, nrow = rows[pr].second - rows[pr].first;
-            const bool rl = !(pr >= r_in0 && pr < r_in1);
-            // every tile with layer cells goes to one launch of the full
-            // instantiation: separate launches for the z-only and r-only tiles
-            // (leaner instantiations) measured slower on the 512 x 1024 x 400
-            // zone, their partly filled last rounds outweighing the gain.
-            // With split_z (the flat-mapped kernel, whose lens batches hold
-            // many small tiles) the z-only tiles get their own launch: 2 %
-            // faster on the 16-zone LWIR-shaped lens
-            const int lay = rl ? (carry ? 1 : 3) : (zl ? (split_z || carry || three ? 2 : 3) : 0);
+        const auto &R = zl ? rows : rows2;
+        const size_t a0 = zl ? r_in0 : r2_in0, a1 = zl ? r_in1 : r2_in1;
+        for (size_t pr = 0; pr < R.size(); ++pr) {
+            const int i0 = R[pr].first, nrow = R[pr].second - R[pr].first;
+            const bool rl = !(pr >= a0 && pr < a1);
+            // without carried auxiliaries every tile with layer cells goes
+            // to one launch of the full instantiation (lay 3): separate
+            // launches for the z-only and r-only tiles measured slower there
+            // on the 512 x 1024 x 400 zone, their partly filled last rounds
+            // outweighing the gain.  With carried auxiliaries the r-layer
+            // band tiles (lay 1, lay 4 as above) and the z-only tiles (lay 2)
+            // take one launch each; so do the z-only tiles with split_z (the
+            // flat-mapped kernel, whose lens batches hold many small tiles:
+            // 2 % faster on the 16-zone LWIR-shaped lens)
+            const int band_rows = pr < a0 ? TRq0 : TRq1;
+            const int lay = rl ? (carry ? (!zl && band_rows == TWO_RBAND_ROWS ? 4 : 1) : 3)
+                               : (zl ? (split_z || carry || three ? 2 : 3) : 0);
             const int cw = cols_of(lay);
             // r-layer band tiles carry ten recursions per cell: where they
             // are few, shorter chunks spread them over more blocks
@@ -769,7 +793,7 @@ void two_step_tiles(const zda_zone *z, int TR, int kc, int k_src, int order, uns
                 if (s < seq[x].size()) o.push_back(seq[x][s]);
         u.swap(o);
     };
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < N_LAY; ++q) {
         if (order == 1) xcd_order(v[q]);
         else if (order > 1) patch_order(v[q], gx_of(q), order >> 8, order & 0xff);
         t.v[q].insert(t.v[q].end(), v[q].begin(), v[q].end());
@@ -821,7 +845,7 @@ void plan_zone_tiles(const zda_zone *z, std::vector<uint4> &all, TileCounts &tc)
     two_step_tiles(z, two_step_rows(TR, z->d.nphi), z->kchunk, z->k_src_last, tile_order(z), 0u, t,
                    TR == FLAT_TWO_ROWS, z->layer_carry != 0, z->three);
     all.clear();
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < N_LAY; ++q) {
         tc.n_lay[q] = (unsigned)t.v[q].size();
         all.insert(all.end(), t.v[q].begin(), t.v[q].end());
     }
@@ -898,7 +922,8 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
             tc = z->tc;
         }
     }
-    const unsigned n_pml = tc.n_lay[1] + tc.n_lay[2] + tc.n_lay[3];
+    unsigned n_pml = 0;
+    for (int q = 1; q < N_LAY; ++q) n_pml += tc.n_lay[q];
     // in-loop divergence watchdog every watch_every steps of the zone's clock
     const long W = z->watch_every;
     long next_watch = W > 0 ? ((long)z->n_done / W + 1) * W : -1;
@@ -932,7 +957,7 @@ zda_status run_loop(zda_zone *z, int m, int nsteps, int k_src, int P, const cd *
     // with its own instantiation
     auto layer_launches = [&](StepArgs b, int n, hipStream_t st) {
         size_t off = tc.n_lay[0];
-        for (int q = 1; q < 4; ++q) {
+        for (int q = 1; q < N_LAY; ++q) {
             b.tiles = tiles + off;
             if (depth == 3) launch_three_step(b, n, tc.n_lay[q], q, st);
             else launch_two_step(b, n, tc.n_lay[q], q, st);
@@ -2005,11 +2030,12 @@ zda_status zda_plan_two_step_tiles(const zda_zone_desc *d, int tile_rows, int kc
     two_step_tiles(&z, two_step_rows(tile_rows, d->nphi), std::min(kchunk, d->nz), k_src, order < 0 ? 0 : order, 0u,
                    t, tile_rows == FLAT_TWO_ROWS, carry, tile_rows == THREE_STEP_ROWS);
     *n_interior = t.v[0].size();
-    *ntiles = t.v[0].size() + t.v[1].size() + t.v[2].size() + t.v[3].size();
+    *ntiles = 0;
+    for (int q = 0; q < N_LAY; ++q) *ntiles += t.v[q].size();
     if (!out) return ZDA_OK;
     if (cap < *ntiles) return fail(ZDA_ERR_ARG, "out holds %zu tiles, the plan has %zu", cap, *ntiles);
     size_t p = 0;
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < N_LAY; ++q)
         for (const uint4 &u : t.v[q]) {
             out[4 * p] = u.x;
             out[4 * p + 1] = u.y;
@@ -2118,7 +2144,7 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
         b->h_prefix[i] = total;
         if (!b->two) total += b->fused ? tiles_fused(ab[i][0], b->tile_rows) : tiles_split(ab[i][0], b->tile_rows);
     }
-    unsigned n_lay[4] = {0, 0, 0, 0};
+    unsigned n_lay[N_LAY] = {};
     if (b->two) {
         // layer tiles with carried auxiliaries as the first zone's option says
         const bool flat = b->tile_rows == FLAT_TWO_ROWS;
@@ -2130,7 +2156,7 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
                            (unsigned)i, t, flat, carry);
         }
         std::vector<uint4> all;
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < N_LAY; ++q) {
             n_lay[q] = (unsigned)t.v[q].size();
             all.insert(all.end(), t.v[q].begin(), t.v[q].end());
         }
@@ -2173,7 +2199,7 @@ zda_status batch_loop(zda_batch *b, const std::vector<std::array<StepArgs, 2>> &
     auto two_pair = [&](int q, hipStream_t st) {
         BatchArgs x = ba[(q / 2) & 1];
         size_t off = 0;
-        for (int l = 0; l < 4; ++l) {
+        for (int l = 0; l < N_LAY; ++l) {
             x.tiles = b->tiles + off;
             launch_batch_two(x, n_lay[l], b->tile_rows, l, q, st);
             off += n_lay[l];

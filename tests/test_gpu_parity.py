@@ -237,7 +237,9 @@ def test_fused_launch_shapes_are_bitwise_identical(zda):
     tile and chunk shape (halo values are recomputed, not approximated), so
     the fused step and the two-step kernel give the same bits for every
     launch shape, whether the layer tiles keep step one's auxiliaries in
-    registers (the default) or pass them through the intermediate set."""
+    registers (the default; both 7-row r-layer bands of this zone take the
+    7-row r-layer-only tiles in the chunks without z-layer planes and 5-row
+    tiles in the others) or pass them through the intermediate set."""
     from paper_2501_07979_amd.workloads import Workload
     wl = Workload("determinism", r_in=360.0, nr=37, nphi=130, nz=41, n_fold=14, m=1, pml=(5, 6, 4, 7), k_src=9,
                   k_mon=30, design=(12, 17), k_sub=12, steps=120, omegas=(0.3,), omega_c=0.3, width=6.0)

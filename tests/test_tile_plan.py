@@ -129,8 +129,11 @@ PLAN_CARRY = 1 << 16
 def test_carry_plan_tiles(name, kchunk, tile_rows):
     """The plan of ZDA_OPT_LAYER_CARRY: every cell owned once; kind 1 tiles
     (r-layer rows, auxiliaries carried in registers) own at most 5 rows;
-    kind 2 tiles compute no r-layer row; the interior tiles are those of the
-    plain plan."""
+    kind 4 tiles (r-layer rows, r-layer recursions only) own at most 7 rows
+    and compute no z-layer plane, and a band holds them only where 7-row
+    tiles take fewer wavefront rows (10 per tile) than 5-row ones (8 per
+    tile); kind 2 tiles compute no r-layer row; the interior tiles are those
+    of the plain plan."""
     from paper_2501_07979_amd import zda
     z = ZONES[name]
     d = _desc(zda, **z)
@@ -144,17 +147,22 @@ def test_carry_plan_tiles(name, kchunk, tile_rows):
     for q, (bx, y, zz, kind) in enumerate(tiles):
         i0, rows = int(y & 0xFFFF), int(y >> 16)
         kb, ke = int(zz & 0xFFFF), int(zz >> 16)
-        assert (kind == 0) == (q < n_int) and kind in (0, 1, 2)
+        assert (kind == 0) == (q < n_int) and kind in (0, 1, 2, 4)
         cols = 56 if kind == 0 else 61
-        assert 1 <= rows <= (5 if kind == 1 else tile_rows) and kb < ke
+        assert 1 <= rows <= {1: 5, 4: 7}.get(int(kind), tile_rows) and kb < ke
         j0 = int(bx) * cols
         assert j0 < nphi
         own[kb:ke, i0:i0 + rows, j0:min(j0 + cols, nphi)] += 1
         r_lo, r_hi = max(i0 - 2, 0), min(i0 + rows, nr - 1)
         if kind == 2:
             assert pr0 <= r_lo and r_hi < nr - pr1, (i0, rows)
-        if kind == 1:
+        if kind in (1, 4):
             assert r_lo < pr0 or r_hi >= nr - pr1, (i0, rows)
+        if kind == 4:
+            k_lo, k_hi = max(kb - 2, 0), min(ke, nz - 1)
+            assert pz0 <= k_lo and k_hi < nz - pz1, (kb, ke)
+            h = pr0 + 2 if i0 < pr0 + 2 else nr - (nr - pr1 - 1)
+            assert -(-h // 7) * 10 < -(-h // 5) * 8, h
     assert own.min() == 1 and own.max() == 1
 
 
