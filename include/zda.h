@@ -321,6 +321,34 @@ zda_status zda_adjoint_grad(zda_zone *z, const float *dF_dE, int dF_on_device, f
 zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_device);
 zda_status zda_zone_write_field(zda_zone *z, int comp, const float *in, int in_on_device);
 
+/* Time-stepping memory of a zone held only while it steps, so that a lens
+ * of more zones than HBM holds with both buffer sets can run its zones in
+ * waves through the forward and the adjoint run of one design iteration
+ * (the paper steps every zone as an independent simulation, section
+ * "Zoned discrete axisymmetry").  zda_zone_release_fields waits for the
+ * zone's stream and gives back both field sets, the PML auxiliaries and
+ * the multi-step kernels' intermediate sets (or stops using the caller's
+ * buffer they were carved from); the zone keeps its permittivity, design,
+ * launch settings and monitors, including the last forward run's
+ * design-volume DFT, so zda_adjoint_grad can follow the next acquire.
+ * While released, runs (zone, batch, autotune, the entry point that
+ * allocates nothing), the adjoint and field reads and writes return
+ * ZDA_ERR_STATE.  zda_zone_acquire_fields takes that memory again with zero
+ * fields and auxiliaries (fills enqueued on the zone's stream): base NULL
+ * allocates it (ZDA_ERR_OOM, the zone staying released, if an allocation
+ * fails); otherwise it is carved from [base, base + bytes), device memory
+ * on the zone's device, 256-byte aligned, of at least the
+ * zda_zone_fields_bytes the zone reports (ZDA_ERR_ARG otherwise), which the
+ * caller owns and keeps valid and unused by anything else until the
+ * zone's release returns (one buffer can then serve the zones of the next
+ * wave without allocating).  Both calls are no-ops when the zone is
+ * already in that state.  A zone stepping in a caller's buffer cannot
+ * switch to the three-step kernel (ZDA_ERR_STATE from zda_zone_set_launch)
+ * until it is released. */
+zda_status zda_zone_release_fields(zda_zone *z);
+zda_status zda_zone_acquire_fields(zda_zone *z, void *base, size_t bytes);
+zda_status zda_zone_fields_bytes(zda_zone *z, size_t *bytes);
+
 /* Sizes and stability margin of a zone (the Courant bound of the Yee scheme,
  * section on the cylindrical solver). */
 typedef struct {

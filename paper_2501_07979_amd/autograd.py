@@ -77,3 +77,44 @@ class BatchFDTD(torch.autograd.Function):
 
 def batch_fdtd(rhos, batch, **run_kw):
     return BatchFDTD.apply(batch, run_kw, *rhos)
+
+
+class WaveFDTD(torch.autograd.Function):
+    """BatchFDTD for one wave of zones that hold their time-stepping memory
+    only while they step (zones of a lens larger than HBM with both buffer
+    sets): the forward acquires the zones' field memory (from the slices of
+    a caller's buffer in `bufs`, else allocated), runs and releases it; the
+    backward acquires it again for the batched adjoint run and releases it
+    after the overlaps.  The forward design-volume DFT stays in the zones in
+    between."""
+
+    @staticmethod
+    def _acquire(batch, bufs):
+        for z, b in zip(batch.zones, bufs if bufs is not None else [None] * len(batch.zones)):
+            z.acquire_fields(b)
+
+    @staticmethod
+    def forward(ctx, batch, run_kw, bufs, *rhos):
+        ctx.bufs = bufs
+        WaveFDTD._acquire(batch, bufs)
+        try:
+            planes = BatchFDTD.forward(ctx, batch, run_kw, *rhos)
+        finally:
+            for z in batch.zones:
+                z.release_fields()
+        return planes
+
+    @staticmethod
+    def backward(ctx, *grad_planes):
+        for z, s in zip(ctx.batch.zones, ctx.serials):
+            _check_fresh(z, s)
+        WaveFDTD._acquire(ctx.batch, ctx.bufs)
+        try:
+            return (None, *BatchFDTD.backward(ctx, *grad_planes))
+        finally:
+            for z in ctx.batch.zones:
+                z.release_fields()
+
+
+def wave_fdtd(rhos, batch, bufs=None, **run_kw):
+    return WaveFDTD.apply(batch, run_kw, bufs, *rhos)

@@ -266,6 +266,11 @@ struct zda_zone {
     uint4 *tiles2 = nullptr;
     size_t cap_tiles2 = 0;
     bool has_m = false;
+    // the time-stepping memory (field sets, auxiliaries, intermediate sets)
+    // is given back by zda_zone_release_fields until zda_zone_acquire_fields;
+    // has_second: the zone holds a second buffer set whenever it holds any;
+    // fields_external: that memory is carved from a caller's buffer
+    bool released = false, has_second = false, fields_external = false;
     TileCounts tc;
     int tiles_tr = 0, tiles_kc = 0, tiles_src = -1, k_src_last = -1, tiles_xcd = -1;
     RowCoef *rows = nullptr;
@@ -313,6 +318,70 @@ void dev_free(zda_zone *z, T *&p)
 {
     z->mem.put((void *)p);
     p = nullptr;
+}
+
+// the second intermediate set of the three-step kernel's layer auxiliaries
+zda_status alloc_m2(zda_zone *z)
+{
+    zda_status st = dev_alloc(z, &z->m2auxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi);
+    if (st == ZDA_OK) st = dev_alloc(z, &z->m2auxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
+    if (st != ZDA_OK) {
+        dev_free(z, z->m2auxR);
+        dev_free(z, z->m2auxZ);
+    }
+    return st;
+}
+
+// the time-stepping buffers of a zone: both field sets, the PML
+// auxiliaries and the intermediate sets, with their element counts
+template <class F>
+void for_each_stepping(zda_zone *z, F f)
+{
+    const size_t nR = (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi, nZ = (size_t)N_AUX_Z * z->dZ * z->plane;
+    for (int b = 0; b < (z->has_second ? 2 : 1); ++b) {
+        for (auto &p : z->F[b]) f(p, z->ncell);
+        f(z->auxR[b], nR);
+        f(z->auxZ[b], nZ);
+    }
+    if (z->has_m) {
+        f(z->mauxR, nR);
+        f(z->mauxZ, nZ);
+    }
+    if (z->three) {
+        f(z->m2auxR, nR);
+        f(z->m2auxZ, nZ);
+    }
+}
+
+// bytes of a stepping buffer carved from a caller's memory (256 B aligned)
+size_t carved_bytes(size_t n) { return (n * sizeof(float2) + 255) / 256 * 256; }
+
+// free the time-stepping memory (or drop the pointers into a caller's buffer)
+void free_stepping(zda_zone *z)
+{
+    if (z->fields_external) {
+        for (auto &set : z->F)
+            for (auto &f : set) f = nullptr;
+        z->auxR[0] = z->auxR[1] = z->auxZ[0] = z->auxZ[1] = nullptr;
+        z->mauxR = z->mauxZ = z->m2auxR = z->m2auxZ = nullptr;
+        z->fields_external = false;
+        return;
+    }
+    for (auto &set : z->F)
+        for (auto &f : set) dev_free(z, f);
+    for (int b = 0; b < 2; ++b) {
+        dev_free(z, z->auxR[b]);
+        dev_free(z, z->auxZ[b]);
+    }
+    dev_free(z, z->mauxR);
+    dev_free(z, z->mauxZ);
+    dev_free(z, z->m2auxR);
+    dev_free(z, z->m2auxZ);
+}
+
+zda_status released_error()
+{
+    return fail(ZDA_ERR_STATE, "the zone's fields are released (zda_zone_acquire_fields first)");
 }
 
 // wait for everything the zone has enqueued (its stream and the layer stream)
@@ -543,6 +612,7 @@ zda_status prepare_run(zda_zone *z, int m, int nsteps, int k_src, int P, const c
                        float2 *dft_plane, float2 *dft_vol, bool reset, hipStream_t s, StepArgs ab[2],
                        const RunBufs &rb)
 {
+    if (z->released) return released_error();
     // next to the axis the z components there are single-valued scalars; they
     // vanish (and the scheme holds) only when the seam phase is not 1
     if (z->d.axis && (z->d.n_fold > 0 ? m % z->d.n_fold == 0 : m == 0))
@@ -1466,6 +1536,7 @@ zda_status zda_zone_create(const zda_zone_desc *d, const float *eps, int eps_on_
             z->fused = false;
             z->tile_rows = 4;
         } else {
+            z->has_second = true;
             // intermediate auxiliaries of the two-step kernel (optional)
             zda_status s2 = dev_alloc(z, &z->mauxR, (size_t)N_AUX_R * d->nz * z->dR * d->nphi);
             if (s2 == ZDA_OK) s2 = dev_alloc(z, &z->mauxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
@@ -1596,6 +1667,7 @@ zda_status zda_fdtd_run(zda_zone *z, const zda_source *s, int nsteps, const doub
                         void *stream)
 {
     if (!z || !s) return fail(ZDA_ERR_ARG, "NULL zone or source");
+    if (z->released) return released_error();
     DeviceGuard g(z->device);
     hipStream_t hs = (hipStream_t)stream;
     z->stream = hs;
@@ -1652,6 +1724,7 @@ zda_status zda_fdtd_run_noalloc(zda_zone *z, const zda_source *s, int nsteps, co
                                 int dft_flags, void *stream)
 {
     if (!z || !s) return fail(ZDA_ERR_ARG, "NULL zone or source");
+    if (z->released) return released_error();
     if (dft_flags & ZDA_RUN_TIMING) return fail(ZDA_ERR_ARG, "ZDA_RUN_TIMING is not available without allocation");
     if (nsteps < 0 || K < 0 || K > ZDA_MAX_FREQ) return fail(ZDA_ERR_ARG, "bad nsteps or K");
     if (s->k_src < 1 || s->k_src >= z->d.nz) return fail(ZDA_ERR_ARG, "k_src must be in [1, nz)");
@@ -1886,6 +1959,7 @@ zda_status zda_adjoint_grad(zda_zone *z, const float *dF_dE, int dF_on_device, f
                             double adj_width, void *stream)
 {
     if (!z || !dF_dE || !grad_rho) return fail(ZDA_ERR_ARG, "NULL argument");
+    if (z->released) return released_error();
     DeviceGuard g(z->device);
     hipStream_t hs = (hipStream_t)stream;
     z->stream = hs;
@@ -1903,6 +1977,7 @@ zda_status zda_adjoint_grad(zda_zone *z, const float *dF_dE, int dF_on_device, f
 zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_device)
 {
     if (!z || !out || comp < 0 || comp > 5) return fail(ZDA_ERR_ARG, "bad argument");
+    if (z->released) return released_error();
     DeviceGuard g(z->device);
     HIP_TRY(hipMemcpyAsync(out, z->F[z->cur][comp], z->ncell * sizeof(float2),
                            out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, z->stream));
@@ -1913,6 +1988,7 @@ zda_status zda_zone_read_field(zda_zone *z, int comp, float *out, int out_on_dev
 zda_status zda_zone_write_field(zda_zone *z, int comp, const float *in, int in_on_device)
 {
     if (!z || !in || comp < 0 || comp > 5) return fail(ZDA_ERR_ARG, "bad argument");
+    if (z->released) return released_error();
     DeviceGuard g(z->device);
     hipStream_t s = z->stream;
     HIP_TRY(hipMemcpyAsync(z->F[z->cur][comp], in, z->ncell * sizeof(float2),
@@ -1922,6 +1998,66 @@ zda_status zda_zone_write_field(zda_zone *z, int comp, const float *in, int in_o
                       z->d.nphi, z->d.nz, z->d.pml_r_in, z->d.pml_r_out, (float)z->dt, s);
     HIP_TRY(hipGetLastError());
     if (!in_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return ZDA_OK;
+}
+
+zda_status zda_zone_release_fields(zda_zone *z)
+{
+    if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
+    if (z->released) return ZDA_OK;
+    DeviceGuard g(z->device);
+    HIP_TRY(zone_wait(z));   // nothing in flight may still use the memory (nor the caller's buffer)
+    free_stepping(z);
+    z->released = true;
+    z->has_m2 = false;
+    z->cur = 0;
+    z->n_done = 0;
+    return ZDA_OK;
+}
+
+zda_status zda_zone_fields_bytes(zda_zone *z, size_t *bytes)
+{
+    if (!z || !bytes) return fail(ZDA_ERR_ARG, "NULL argument");
+    size_t total = 0;
+    for_each_stepping(z, [&](float2 *&, size_t n) { total += carved_bytes(n); });
+    *bytes = total;
+    return ZDA_OK;
+}
+
+zda_status zda_zone_acquire_fields(zda_zone *z, void *base, size_t bytes)
+{
+    if (!z) return fail(ZDA_ERR_ARG, "NULL zone");
+    if (!z->released) return ZDA_OK;
+    DeviceGuard g(z->device);
+    zda_status st = ZDA_OK;
+    if (base) {
+        size_t need = 0;
+        zda_zone_fields_bytes(z, &need);
+        if (bytes < need) return fail(ZDA_ERR_ARG, "the buffer holds %zu bytes, the zone needs %zu", bytes, need);
+        if ((uintptr_t)base % 256 != 0) return fail(ZDA_ERR_ARG, "the buffer must be 256-byte aligned");
+        char *p = (char *)base;
+        for_each_stepping(z, [&](float2 *&q, size_t n) {
+            q = n ? (float2 *)p : nullptr;
+            p += carved_bytes(n);
+        });
+        z->fields_external = true;
+    } else {
+        for_each_stepping(z, [&](float2 *&q, size_t n) {
+            if (st == ZDA_OK) st = dev_alloc(z, &q, n);
+        });
+        if (st != ZDA_OK) {
+            free_stepping(z);
+            return st;
+        }
+    }
+    z->has_m2 = z->three;
+    z->released = false;
+    // zero fields and auxiliaries, as after a reset
+    hipStream_t s = z->stream;
+    for_each_stepping(z, [&](float2 *&q, size_t n) {
+        if (q) launch_fill(q, n, s);
+    });
+    HIP_TRY(hipGetLastError());
     return ZDA_OK;
 }
 
@@ -1937,24 +2073,22 @@ zda_status zda_zone_set_launch(zda_zone *z, int kchunk, int tile_rows)
     if (!split && !fused && !two)
         return fail(ZDA_ERR_ARG, "tile_rows must be 1, 2, 4, 8, 16, 32 (in place), 3, 7, 15, 33 (fused), 5, 13, "
                                  "34 (two-step) or 11 (three-step)");
-    if ((fused || two) && !z->auxR[1] && z->dR > 0) return fail(ZDA_ERR_STATE, "no second buffer set");
-    if ((fused || two) && !z->F[1][0]) return fail(ZDA_ERR_STATE, "no second buffer set");
+    if ((fused || two) && !z->has_second) return fail(ZDA_ERR_STATE, "no second buffer set");
     if (two && !z->has_m) return fail(ZDA_ERR_STATE, "no intermediate auxiliaries for the two-step kernel");
     if (two && (z->d.nr > 65535 || z->d.nz > 65535)) return fail(ZDA_ERR_ARG, "two-step tiles need nr, nz <= 65535");
     if (tile_rows == FLAT_FUSED_ROWS && z->d.nphi > FLAT_FUSED_MAX_PHI)
         return fail(ZDA_ERR_ARG, "the flat fused step needs nphi <= %d", FLAT_FUSED_MAX_PHI);
     if (tile_rows == FLAT_TWO_ROWS && z->d.nphi > FLAT_TWO_MAX_PHI)
         return fail(ZDA_ERR_ARG, "the flat two-step kernel needs nphi <= %d", FLAT_TWO_MAX_PHI);
-    if (three && !z->has_m2) {
-        // the second intermediate time level of the layer auxiliaries
+    if (three && !z->has_m2 && z->fields_external)
+        return fail(ZDA_ERR_STATE, "the zone steps in a caller's buffer: release it before selecting the three-step "
+                                   "kernel");
+    if (three && !z->has_m2 && !z->released) {
+        // the second intermediate time level of the layer auxiliaries (a
+        // released zone gets it with the rest of its memory)
         DeviceGuard g(z->device);
-        zda_status st = dev_alloc(z, &z->m2auxR, (size_t)N_AUX_R * z->d.nz * z->dR * z->d.nphi);
-        if (st == ZDA_OK) st = dev_alloc(z, &z->m2auxZ, (size_t)N_AUX_Z * z->dZ * z->plane);
-        if (st != ZDA_OK) {
-            dev_free(z, z->m2auxR);
-            dev_free(z, z->m2auxZ);
-            return st;
-        }
+        zda_status st = alloc_m2(z);
+        if (st != ZDA_OK) return st;
         z->has_m2 = true;
     }
     z->kchunk = kchunk;
@@ -2125,7 +2259,7 @@ struct zda_batch {
 
 namespace {
 
-bool zone_has_second_set(const zda_zone *z) { return z->F[1][0] && (z->dR == 0 || z->auxR[1]) && (z->dZ == 0 || z->auxZ[1]); }
+bool zone_has_second_set(const zda_zone *z) { return z->has_second; }
 bool zone_two_step_ok(const zda_zone *z)
 {
     return zone_has_second_set(z) && z->has_m && z->d.nr <= 65535 && z->d.nz <= 65535;
@@ -2362,6 +2496,8 @@ zda_status zda_batch_run(zda_batch *b, const zda_source *sources, int nsteps, co
 {
     if (!b || !sources) return fail(ZDA_ERR_ARG, "NULL batch or sources");
     if (dft_flags & ZDA_RUN_TIMING) return fail(ZDA_ERR_ARG, "per-kernel timing is not available for batches");
+    for (auto z : b->zones)
+        if (z->released) return released_error();
     DeviceGuard g(b->device);
     hipStream_t hs = (hipStream_t)stream;
     const size_t nz = b->zones.size();
@@ -2391,6 +2527,7 @@ zda_status zda_batch_adjoint_grad(zda_batch *b, const float *const *dF_dE, float
     const size_t nz = b->zones.size();
     int T = -1;
     for (auto z : b->zones) {
+        if (z->released) return released_error();
         if (!z->have_vol || z->last_K < 1) return fail(ZDA_ERR_STATE, "every zone needs a forward run with ZDA_DFT_VOLUME");
         if (T >= 0 && z->last_T != T) return fail(ZDA_ERR_STATE, "zones ran different step counts");
         T = z->last_T;
@@ -2419,6 +2556,8 @@ zda_status zda_batch_autotune(zda_batch *b, const zda_source *sources, int probe
                               void *stream, zda_tune_result *res)
 {
     if (!b || !sources || !res || probe_steps < 2) return fail(ZDA_ERR_ARG, "bad autotune arguments");
+    for (auto z : b->zones)
+        if (z->released) return released_error();
     DeviceGuard g(b->device);
     hipStream_t hs = (hipStream_t)stream;
     const size_t nz = b->zones.size();

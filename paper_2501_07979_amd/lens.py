@@ -2,11 +2,12 @@
 axisymmetry (ZDA)"): the first zone contains the axis and is continuously
 axisymmetric, the following ones are n-fold wedges with n growing with the
 radius (section "Results and Discussion").  Every zone is its own
-PML-terminated simulation; the zones are stepped together in one batch, and
+PML-terminated simulation; the zones are stepped together in batches (or, for
+a lens larger than HBM with both buffer sets, in waves of batches), and
 the objective is the focal-spot intensity of the whole lens: each zone's
 exit-plane field projected onto the common on-axis focal point, the zones'
 phasors summed coherently, F = sum_k |sum_zones a_k|^2.  Its gradient with
-respect to every zone's design density comes from one batched adjoint run.
+respect to every zone's design density comes from batched adjoint runs.
 """
 from __future__ import annotations
 
@@ -14,15 +15,24 @@ import numpy as np
 import torch
 
 from . import objective, zda
-from .autograd import batch_fdtd
+from .autograd import batch_fdtd, wave_fdtd
 
 
 class Lens:
     """Zones (Workload descriptions sharing the time step, source plane,
     pulse, frequencies and step count) of one lens; focal length from the
-    numerical aperture at the lens's outer radius."""
+    numerical aperture at the lens's outer radius.
 
-    def __init__(self, workloads, na=0.3, single_buffer=False):
+    waves=True: zones keep both buffer sets (so the batched two-step kernel
+    applies) but hold their time-stepping memory only while they step; the
+    forward and the adjoint run go through the zones in waves whose
+    time-stepping memory fits budget_bytes (default: 80 % of the HBM free
+    once every zone is created, less what a design iteration adds for every
+    zone: the forward and adjoint design-volume DFTs, the adjoint source and
+    the iteration's tensors), one batch per wave.  One buffer of the largest
+    wave's size is allocated once; each wave's zones step in slices of it."""
+
+    def __init__(self, workloads, na=0.3, single_buffer=False, waves=False, budget_bytes=None):
         self.workloads = list(workloads)
         w0 = self.workloads[0]
         for w in self.workloads[1:]:
@@ -31,25 +41,48 @@ class Lens:
                     raise ValueError("zones of one lens share %s (%r != %r)" % (f, getattr(w, f), getattr(w0, f)))
         self.radius = max(w.r_in + w.nr * w.dr for w in self.workloads)
         self.focal = objective.focal_length(self.radius, na)
+        if waves and single_buffer:
+            raise ValueError("waves keep both buffer sets")
         sb = 1 if single_buffer else 0
-        self.zones = [zda.Zone(zda.default_desc(single_buffer=sb, **w.desc_kwargs()), w.eps())
-                      for w in self.workloads]
+        self.waves = waves
+        self.arena = None
+        self.zones = []
+        for w in self.workloads:
+            z = zda.Zone(zda.default_desc(single_buffer=sb, **w.desc_kwargs()), w.eps())
+            if waves:
+                z.release_fields()
+            self.zones.append(z)
         # one batch per kernel family: narrow wedges and the continuous zone on
         # the flat-mapped two-step kernel, the others on the two-step kernel;
         # single-buffer zones (half the field memory, so that a lens larger
         # than half the HBM fits at once) all on the in-place kernels
         self.groups = []
-        if single_buffer:
+        if waves:
+            if budget_bytes is None:
+                torch.cuda.empty_cache()
+                budget_bytes = int(0.8 * torch.cuda.mem_get_info()[0]) - sum(iteration_bytes(w)
+                                                                            for w in self.workloads)
+            need = [z.fields_bytes() for z in self.zones]
+            plan = plan_waves(self.workloads, budget_bytes, sizes=need)
+            self.arena = torch.empty(max(sum(need[q] for q in idx) for _, idx in plan), dtype=torch.uint8,
+                                     device="cuda")
+            for fam, idx in plan:
+                b = zda.Batch([self.zones[q] for q in idx])
+                set_family(b, fam, [self.workloads[q] for q in idx])
+                offs = np.cumsum([0] + [need[q] for q in idx])
+                bufs = [self.arena[int(offs[p]):int(offs[p + 1])] for p in range(len(idx))]
+                self.groups.append((idx, b, bufs))
+        elif single_buffer:
             b = zda.Batch(self.zones)
             set_family(b, IN_PLACE, self.workloads)
-            self.groups.append((list(range(len(self.zones))), b))
+            self.groups.append((list(range(len(self.zones))), b, None))
         else:
             for narrow in (True, False):
                 idx = [q for q, w in enumerate(self.workloads) if is_narrow(w) == narrow]
                 if idx:
                     b = zda.Batch([self.zones[q] for q in idx])
                     set_family(b, FLAT if narrow else TWO_STEP, [self.workloads[q] for q in idx])
-                    self.groups.append((idx, b))
+                    self.groups.append((idx, b, None))
         self.weights = [objective.focal_weights(w, w.omegas, self.focal) for w in self.workloads]
         self.run_kw = dict(nsteps=w0.steps, omegas=w0.omegas, k_src=w0.k_src, omega_c=w0.omega_c, width=w0.width)
 
@@ -57,8 +90,11 @@ class Lens:
         """Focal phasors a_k of the whole lens for design densities rhos
         (one [k1-k0][nr][nphi] float32 CUDA tensor per zone)."""
         a = 0
-        for idx, b in self.groups:
-            planes = batch_fdtd([rhos[q] for q in idx], b, **self.run_kw)
+        for idx, b, bufs in self.groups:
+            if self.waves:
+                planes = wave_fdtd([rhos[q] for q in idx], b, bufs, **self.run_kw)
+            else:
+                planes = batch_fdtd([rhos[q] for q in idx], b, **self.run_kw)
             a = a + sum((p * self.weights[q]).sum(dim=(1, 2, 3)) for p, q in zip(planes, idx))
         return a
 
@@ -67,10 +103,11 @@ class Lens:
         return (a.abs() ** 2).sum(), a
 
     def close(self):
-        for _, b in self.groups:
+        for _, b, _ in self.groups:
             b.close()
         for z in self.zones:
             z.close()
+        self.arena = None
 
 
 # batch launch codes: the two-step kernel (13 rows) and, for narrow zones,
@@ -114,17 +151,29 @@ def zone_device_bytes(w, both_sets=True, max_freq=8):
     return cells * (48 * (2 if both_sets else 1) + 4) + aux + max_freq * 2 * plane * 8
 
 
-def plan_waves(workloads, budget_bytes, tile_rows=None):
+def iteration_bytes(w):
+    """Device memory a design iteration adds to a zone beyond its creation:
+    the forward and adjoint design-volume DFTs (K x 3 components x design
+    planes), the adjoint source pattern and the exit-plane tensors of the
+    iteration (K x 2 components each, a few of them), the design density and
+    its gradient, in bytes."""
+    K, plane = len(w.omegas), w.nr * w.nphi
+    nd = w.design[1] - w.design[0]
+    return 2 * K * 3 * nd * plane * 8 + 6 * K * 2 * plane * 8 + 2 * nd * plane * 4
+
+
+def plan_waves(workloads, budget_bytes, tile_rows=None, sizes=None):
     """Waves of zone indices [(launch code, [indices])]: zones of one kernel
     family (or all, if tile_rows fixes the launch), in their order, cut where
-    the next zone would take the wave past budget_bytes with both buffer sets;
-    narrow zones after the others."""
+    the next zone would take the wave past budget_bytes with both buffer sets
+    (zone_device_bytes, or sizes[q] bytes for zone q); narrow zones after the
+    others."""
     order = sorted(range(len(workloads)), key=lambda q: is_narrow(workloads[q]) if tile_rows is None else 0)
     waves, cur, used, fam = [], [], 0, None
     for q in order:
         w = workloads[q]
         f = tile_rows if tile_rows is not None else (FLAT if is_narrow(w) else TWO_STEP)
-        b = zone_device_bytes(w)
+        b = zone_device_bytes(w) if sizes is None else sizes[q]
         if cur and (used + b > budget_bytes or f != fam):
             waves.append((fam, cur))
             cur, used = [], 0

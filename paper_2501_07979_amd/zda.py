@@ -31,7 +31,9 @@ EXPORTS = ["zda_set_allocator", "zda_zone_desc_default", "zda_zone_create", "zda
            "zda_zone_set_design", "zda_zone_set_stream", "zda_zone_sync", "zda_fdtd_run", "zda_fdtd_run_noalloc",
            "zda_fdtd_run_fp64", "zda_dft_fields",
            "zda_adjoint_grad",
-           "zda_zone_read_field", "zda_zone_write_field", "zda_zone_get_info", "zda_zone_set_launch",
+           "zda_zone_read_field", "zda_zone_write_field", "zda_zone_release_fields", "zda_zone_acquire_fields",
+           "zda_zone_fields_bytes",
+           "zda_zone_get_info", "zda_zone_set_launch",
            "zda_zone_set_option",
            "zda_zone_last_timing", "zda_plan_two_step_tiles", "zda_batch_create", "zda_batch_destroy", "zda_batch_run",
            "zda_batch_adjoint_grad", "zda_batch_set_launch", "zda_batch_autotune",
@@ -116,6 +118,9 @@ def load():
     lib.zda_adjoint_grad.argtypes = [P, P, I, P, I, D, P]
     lib.zda_zone_read_field.argtypes = [P, I, P, I]
     lib.zda_zone_write_field.argtypes = [P, I, P, I]
+    lib.zda_zone_release_fields.argtypes = [P]
+    lib.zda_zone_acquire_fields.argtypes = [P, P, ctypes.c_size_t]
+    lib.zda_zone_fields_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.zda_zone_get_info.argtypes = [P, ctypes.POINTER(ZoneInfo)]
     lib.zda_zone_last_timing.argtypes = [P, ctypes.POINTER(Timing)]
     lib.zda_zone_set_launch.argtypes = [P, I, I]
@@ -284,6 +289,29 @@ class Zone:
 
     def set_launch(self, kchunk, tile_rows):
         _check(load().zda_zone_set_launch(self._h, int(kchunk), int(tile_rows)))
+
+    def release_fields(self):
+        """Give back the time-stepping memory (both field sets, PML
+        auxiliaries, intermediate sets); the zone keeps its permittivity,
+        design, launch settings and monitors (zda_zone_release_fields)."""
+        _check(load().zda_zone_release_fields(self._h))
+
+    def acquire_fields(self, buffer=None):
+        """Take the time-stepping memory again, zeroed on the zone's stream
+        (zda_zone_acquire_fields): allocated, or carved from `buffer` (a CUDA
+        tensor of at least fields_bytes() bytes, 256-byte aligned, that the
+        caller keeps and leaves alone until release_fields returns)."""
+        if buffer is None:
+            _check(load().zda_zone_acquire_fields(self._h, None, 0))
+        else:
+            nbytes = buffer.numel() * buffer.element_size()
+            _check(load().zda_zone_acquire_fields(self._h, ctypes.c_void_p(buffer.data_ptr()), nbytes))
+
+    def fields_bytes(self):
+        """Bytes of time-stepping memory the zone carves from a caller's buffer."""
+        n = ctypes.c_size_t()
+        _check(load().zda_zone_fields_bytes(self._h, ctypes.byref(n)))
+        return n.value
 
     @property
     def dt(self):

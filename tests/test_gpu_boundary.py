@@ -1,6 +1,7 @@
 """The C ABI's boundary semantics on the GPU: monitor component selection,
 the divergence watchdog, stream ordering of reads, host and device inputs,
-and zone memory from a caller's allocator (torch's caching allocator)."""
+zone memory from a caller's allocator (torch's caching allocator), and
+released time-stepping memory."""
 import ctypes
 
 import numpy as np
@@ -113,6 +114,58 @@ def test_run_on_a_side_stream(zda):
     z.sync()
     assert np.array_equal(got, ref)
     z.close()
+
+
+def test_released_fields(zda):
+    """A zone whose time-stepping memory is released refuses runs, the
+    adjoint and field access (ZDA_ERR_STATE) and holds less device memory;
+    it keeps its monitors (the last forward run's exit-plane DFT reads back
+    unchanged), and after acquiring the memory again its runs and adjoint
+    gradient equal those of a zone that never released it."""
+    wl = _small()
+    ref = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    _run(ref, wl, volume=True)
+    dF = (ref.dft(zda.MON_PLANE) * 0.01).contiguous()
+    g_ref = ref.adjoint_grad(dF).cpu().numpy()
+    p_ref = ref.dft(zda.MON_PLANE).cpu().numpy()
+    z = zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps())
+    _run(z, wl, volume=True)
+    full = z.info().device_bytes
+    z.release_fields()
+    z.release_fields()                       # a no-op when already released
+    assert z.info().device_bytes < 0.5 * full
+    assert np.array_equal(z.dft(zda.MON_PLANE).cpu().numpy(), p_ref)
+    for call in (lambda: _run(z, wl), lambda: z.read_field("Ez"), lambda: z.adjoint_grad(dF),
+                 lambda: z.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width,
+                               noalloc=True)):
+        with pytest.raises(zda.ZdaError) as e:
+            call()
+        assert e.value.status == zda.ZDA_ERR_STATE
+    z.acquire_fields()
+    z.acquire_fields()                       # a no-op when already held
+    assert z.info().device_bytes == full
+    assert not np.abs(z.read_field("Hz").cpu().numpy()).any()   # zeroed
+    # the forward state survived the release: the adjoint needs no new forward run
+    assert np.array_equal(z.adjoint_grad(dF).cpu().numpy(), g_ref)
+    _run(z, wl, volume=True)
+    assert np.array_equal(z.dft(zda.MON_PLANE).cpu().numpy(), p_ref)
+    # the same memory carved from a caller's buffer
+    import torch
+    z.release_fields()
+    need = z.fields_bytes()
+    buf = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    for bad in (buf[:need - 256], buf[8:8 + need]):        # too small; not 256-byte aligned
+        with pytest.raises(zda.ZdaError) as e:
+            z.acquire_fields(bad)
+        assert e.value.status == zda.ZDA_ERR_ARG
+    z.acquire_fields(buf[256:256 + need])
+    assert z.info().device_bytes < 0.5 * full             # the zone allocated nothing
+    assert np.array_equal(z.adjoint_grad(dF).cpu().numpy(), g_ref)
+    _run(z, wl)
+    assert np.array_equal(z.dft(zda.MON_PLANE).cpu().numpy(), p_ref)
+    z.release_fields()
+    z.close()
+    ref.close()
 
 
 def test_host_and_device_inputs_agree(zda):

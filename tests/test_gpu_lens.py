@@ -110,3 +110,33 @@ def test_lwir_zone_full_size_in_the_lens_launch(oracle_mod, zone):
         _say(w.name, c, "rel L2 %.2e" % e)
         assert e <= 1e-5, (c, e)
     g.close()
+
+
+def test_lens_in_waves_gives_the_same_bits():
+    """The lens run in waves (each zone holding its field memory only while
+    it steps, one zone per wave here) gives the same phasors and gradient
+    bits as the lens whose zones stay resident."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_07979_amd.lens import Lens
+    wls = _zones()
+    for w in wls:
+        w.steps = 600
+    out = []
+    for waves in (False, True):
+        lens = Lens(wls, waves=waves, budget_bytes=1 if waves else None)
+        _say("lens, waves", waves, "groups", len(lens.groups))
+        rhos = [torch.tensor(w.rho(), device="cuda", requires_grad=True) for w in wls]
+        F, a = lens.objective(rhos)
+        F.backward()
+        out.append((a.detach().cpu().numpy(), [r.grad.cpu().numpy() for r in rhos]))
+        if waves:
+            assert len(lens.groups) == len(wls)
+            assert all(z.info().device_bytes < 0.5 * zone_full for z, zone_full in zip(lens.zones, full_bytes))
+        else:
+            full_bytes = [z.info().device_bytes for z in lens.zones]
+        lens.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for g0, g1 in zip(out[0][1], out[1][1]):
+        assert np.array_equal(g0, g1)
