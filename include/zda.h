@@ -520,11 +520,12 @@ zda_status zda_batch_run(zda_batch *b, const zda_source *sources, int nsteps, co
 zda_status zda_batch_adjoint_grad(zda_batch *b, const float *const *dF_dE, float *const *grad_rho, void *stream);
 
 /* Launch shape shared by the batched kernels of the leap-frog (eq. 3-5;
- * tile_rows as in
- * zda_zone_set_launch) and per-zone z-chunk depth kchunk[nzones] (NULL keeps
- * each zone's; the flat two-step kernel, 34, wants chunks of 12 to 64 planes,
- * far deeper than the 2 that narrow zones keep for their default in-place
- * kernels).  Errors as for zda_zone_set_launch, for any zone. */
+ * tile_rows as in zda_zone_set_launch, except 11: the three-step kernel
+ * runs single zones only) and per-zone z-chunk depth kchunk[nzones] (NULL
+ * keeps each zone's; the flat two-step kernel, 34, wants chunks of 12 to 64
+ * planes, far deeper than the 2 that narrow zones keep for their default
+ * in-place kernels).  Errors as for zda_zone_set_launch, for any zone;
+ * ZDA_ERR_ARG for tile_rows 11. */
 zda_status zda_batch_set_launch(zda_batch *b, int tile_rows, const int *kchunk);
 
 /* Autotuner of the batched leap-frog (eq. 3-5): times short probe runs
