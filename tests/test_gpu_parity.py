@@ -267,6 +267,36 @@ def test_fused_launch_shapes_are_bitwise_identical(zda):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("pml", [(8, 8, 8, 8), (12, 12, 12, 12)])
+def test_rband_tilings_are_bitwise_identical(zda, pml):
+    """The r-layer bands of 10 and 9 rows (8-cell layers: carried tiles of 5
+    rows) and of 14 and 13 rows (12-cell layers: carried tiles of 7 rows
+    with the r-layer recursions only in the chunks without z-layer planes,
+    5 rows in the others): the same bits as the fused step and as the layer
+    tiles that pass their auxiliaries through the intermediate set."""
+    from paper_2501_07979_amd.workloads import Workload
+    wl = Workload("rband_determinism", r_in=480.0, nr=56, nphi=96, nz=48, n_fold=16, m=1, pml=pml, k_src=14,
+                  k_mon=32, design=(18, 22), k_sub=18, steps=90, omegas=(0.3,), omega_c=0.3, width=6.0)
+    rng = np.random.default_rng(44)
+    eps = (1.0 + 4.0 * rng.random((wl.nz, wl.nr, wl.nphi))).astype(np.float32)
+    kinds = set(int(k) for k in zda.plan_two_step_tiles(zda.default_desc(**wl.desc_kwargs()), 13, 9, k_src=wl.k_src,
+                                                         order=1 << 16)[0][:, 3])
+    assert kinds == ({0, 1, 2} if pml[0] == 8 else {0, 1, 2, 4}), kinds
+    outs = []
+    for kc, tr, carry in [(5, 3, 1), (9, 13, 1), (48, 13, 1), (4, 5, 1), (9, 13, 0)]:
+        _say("r-band determinism", pml, kc, tr, carry)
+        g = zda.Zone(zda.default_desc(**wl.desc_kwargs()), eps)
+        g.set_launch(kc, tr)
+        g.set_option(zda.OPT_LAYER_CARRY, carry)
+        g.run(wl.steps, wl.omegas, k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
+        outs.append([g.read_field(c).cpu().numpy() for c in ("Er", "Ephi", "Ez", "Hr", "Hphi", "Hz")] +
+                    [g.dft(zda.MON_PLANE).cpu().numpy()])
+        g.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("nphi", [11, 24])
 def test_narrow_zone_launch_shapes_are_bitwise_identical(zda, nphi):
     """A narrow wedge gives the same bits on the 13-row two-step kernel, the

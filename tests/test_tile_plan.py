@@ -15,6 +15,7 @@ ZONES = {
     "no_layers": dict(nr=29, nphi=64, nz=33, pml=(0, 0, 0, 0)),
     "axis_zone": dict(nr=45, nphi=1, nz=50, pml=(0, 6, 4, 7)),
     "thin": dict(nr=3, nphi=5, nz=4, pml=(1, 1, 1, 1)),
+    "layers_8": dict(nr=48, nphi=96, nz=40, pml=(8, 8, 8, 8)),
 }
 
 
