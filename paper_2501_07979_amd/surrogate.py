@@ -1,7 +1,7 @@
 """Design surrogate: a dilated convolutional network that maps a zone's
 design-layer pattern to its complex exit-plane DFT fields, so that inner
 design iterations can run on it; the FDTD (libzda) generates its training
-samples and stays the fallback and the judge, re-checking every k-th
+samples and stays the fallback and the arbiter, re-checking every k-th
 iterate (checked_loop).
 
 Every layer runs on the hand-written gfx950 kernels of libzsur.so (BF16 MFMA

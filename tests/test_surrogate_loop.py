@@ -1,5 +1,5 @@
 """Host logic of the surrogate-assisted design loop (CPU, no GPU): the FDTD
-re-check is the judge and the fallback.  With an analytic objective standing
+re-check is the arbiter and the fallback.  With an analytic objective standing
 in for the FDTD-adjoint evaluation: a surrogate whose gradient is right
 speeds the ascent; a corrupted surrogate (its weights scrambled: a gradient
 pointing away from the optimum, or non-finite values) has every block of its
