@@ -361,7 +361,7 @@ def adam_update(x, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def checked_loop(fdtd, sur, rho0, outer, inner, lr, stop=None, log=None):
-    """Surrogate-assisted ascent with the FDTD as fallback and judge.
+    """Surrogate-assisted ascent with the FDTD as fallback and arbiter.
 
     fdtd(rho) -> (F, dF/drho) is the plain FDTD-adjoint evaluation and
     sur(rho) -> dF/drho the surrogate's gradient.  Each outer step re-checks
