@@ -107,6 +107,7 @@ class Lens:
             b.close()
         for z in self.zones:
             z.close()
+        self.groups = []          # drops the slices of the wave buffer with it
         self.arena = None
 
 
