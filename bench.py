@@ -259,6 +259,48 @@ def batch_lens(steps, warmup, autotune=True):
     return cells, ms, tune
 
 
+def lens_iteration(T):
+    """One optimizer step of the 48-zone lens (2.89e9 cells) at T steps per
+    run: batched forward runs with the design-layer DFT, the lens focal
+    objective (all 48 zones' phasors summed), batched adjoint runs and the
+    overlaps, through torch.autograd; the zones hold their field memory (both
+    buffer sets, so the batched two-step kernel applies) only while they
+    step, in waves.  The second of two iterations is timed."""
+    import torch
+    from paper_2501_07979_amd import lens
+    from paper_2501_07979_amd.workloads import c4, c4_zone
+    torch.cuda.empty_cache()
+    full_steps = c4_zone(1).steps
+    wl_it = c4(steps=T)
+    cells = sum(w.cells for w in wl_it)
+    print("bench: lens forward + adjoint iteration (%d steps per run)" % T, file=sys.stderr, flush=True)
+    ln = lens.Lens(wl_it, waves=True)
+    n_waves = len(ln.groups)
+    rhos = [torch.tensor(w.rho(), device="cuda", requires_grad=True) for w in wl_it]
+    secs = []
+    for it in range(2):
+        for r in rhos:
+            r.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F, _ = ln.objective(rhos)
+        F.backward()
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+        print("bench: lens iteration %d: %.2f s" % (it, secs[-1]), file=sys.stderr, flush=True)
+    finite = all(bool(torch.isfinite(r.grad).all()) for r in rhos)
+    ln.close()
+    del ln, rhos
+    torch.cuda.empty_cache()
+    rate = 2 * cells * T / secs[1] / 1e9
+    return {"workload": "c4_batched_lens_48_zones", "cells": cells, "steps_per_run": T, "runs_per_iter": 2,
+            "s_per_iter": round(secs[1], 3), "s_first_iter": round(secs[0], 3), "gcell_updates_per_s": round(rate, 3),
+            "finite_gradient": finite,
+            "kernels": "batched two-step kernels in waves of zones (%d), each zone's field memory held only while "
+                       "it steps" % n_waves,
+            "s_per_iter_at_%d_steps" % full_steps: round(2 * cells * full_steps / (rate * 1e9), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,8 +313,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-assisted vs plain design comparison on the surrogate zone")
     ap.add_argument("--lens-iter-steps", type=int, default=None,
-                    help="with --workload lwir or c4: steps per run of the timed lens design iterations "
-                         "(0: none; default 2000 for lwir, 200 for c4)")
+                    help="steps per run of the timed lens design iterations (the 48-zone lens with the default "
+                         "workload and c4, the LWIR-shaped lens with lwir; 0: none; default 200, 2000 for lwir)")
     ap.add_argument("--launch", default=None, metavar="KCHUNK,TILE_ROWS",
                     help="launch shape of the timed zone (zda_zone_set_launch), e.g. 64,11 for the three-step "
                          "kernel; default: the zone's own")
@@ -280,7 +322,7 @@ def main():
                     help="also run a plain 4 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.lens_iter_steps is None:
-        args.lens_iter_steps = 200 if args.workload == "c4" else 2000
+        args.lens_iter_steps = 2000 if args.workload == "lwir" else 200
     if args.gpus != 1:
         print("bench.py: the benchmark runs on one GPU only; --gpus %d is not supported "
               "(a lens would shard its zones across GPUs, one zone per GPU; not built)" % args.gpus,
@@ -360,42 +402,7 @@ def main():
                                             keep_fields=False)
         gw = cells * args.steps / (ms_w / 1e3) / 1e9
         best_waves = gw > gc
-        fa = None
-        if args.lens_iter_steps > 0:
-            # one optimizer step of the whole lens: batched forward runs with
-            # the design-layer DFT, the lens focal objective (all 48 zones'
-            # phasors summed), batched adjoint runs and the overlaps; the
-            # zones hold their field memory (both buffer sets, so the batched
-            # two-step kernel applies) only while they step, in waves
-            from paper_2501_07979_amd.workloads import c4 as c4_lens
-            from paper_2501_07979_amd.workloads import c4_zone
-            T = args.lens_iter_steps
-            full_steps = c4_zone(1).steps
-            wl_it = c4_lens(steps=T)
-            print("bench: lens forward + adjoint iteration (%d steps per run)" % T, file=sys.stderr, flush=True)
-            ln = lens.Lens(wl_it, waves=True)
-            n_waves = len(ln.groups)
-            rhos = [torch.tensor(w.rho(), device="cuda", requires_grad=True) for w in wl_it]
-            secs = []
-            for it in range(2):
-                for r in rhos:
-                    r.grad = None
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                F, _ = ln.objective(rhos)
-                F.backward()
-                torch.cuda.synchronize()
-                secs.append(time.perf_counter() - t0)
-            finite = all(bool(torch.isfinite(r.grad).all()) for r in rhos)
-            ln.close()
-            del ln, rhos
-            torch.cuda.empty_cache()
-            rate = 2 * cells * T / secs[1] / 1e9
-            fa = {"steps_per_run": T, "runs_per_iter": 2, "s_per_iter": round(secs[1], 3),
-                  "s_first_iter": round(secs[0], 3), "gcell_updates_per_s": round(rate, 3), "finite_gradient": finite,
-                  "kernels": "batched two-step kernels in waves of zones (%d), each zone's field memory held "
-                             "only while it steps" % n_waves,
-                  "s_per_iter_at_%d_steps" % full_steps: round(2 * cells * full_steps / (rate * 1e9), 1)}
+        fa = lens_iteration(args.lens_iter_steps) if args.lens_iter_steps > 0 else None
         print(json.dumps({"metric": METRIC, "value": round(max(gc, gw), 4), "unit": "Gcell-updates/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": round((ms_w if best_waves else ms) / args.steps, 4),
@@ -537,6 +544,8 @@ def main():
     if not args.no_surrogate and args.workload == "c2":
         print("bench: surrogate-assisted vs plain design at equal efficiency", file=sys.stderr, flush=True)
         out["surrogate_design"] = surrogate_comparison()
+    if args.lens_iter_steps > 0 and args.workload == "c2":
+        out["lens_forward_adjoint_iteration"] = lens_iteration(args.lens_iter_steps)
     if not args.no_cpu_baseline:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, eps_host)
