@@ -380,9 +380,11 @@ typedef struct {
  * the two-step kernel needs), tile_rows = 11 the three-step kernel (three
  * time steps per launch, a block owns 11 rows x 56 phi cells, r-layer band
  * tiles 7 rows x 59 cells, tiles with z-layer planes only 11 x 59; the last
- * nsteps mod 3 steps of a run take the fused step; needs what the two-step
- * kernel needs, and allocates a second intermediate set of the layer
- * auxiliaries when first selected: ZDA_ERR_OOM if that fails).  Default: for zones of at most 16
+ * nsteps mod 3 steps of a run take the fused step; its layer tiles pass the
+ * auxiliaries of both intermediate time levels through device memory
+ * whatever ZDA_OPT_LAYER_CARRY says; needs what the two-step kernel needs,
+ * and allocates a second intermediate set of the layer auxiliaries when
+ * first selected: ZDA_ERR_OOM if that fails).  Default: for zones of at most 16
  * phi cells (and the continuous zone) the flat in-place kernels; for zones
  * of 17 to 32 phi cells the flat two-step kernel in 4-plane chunks (where
  * the two-step kernel fits); otherwise the two-step kernel with 13 rows
