@@ -270,16 +270,18 @@ def random_patterns(n, nr, nphi, seed, sigma=2.5, beta=6.0):
     return out
 
 
-def generate_samples(wl, patterns, zones_per_batch=8, log=None):
+def generate_samples(wl, patterns, zones_per_batch=32, log=None):
     """FDTD exit-plane fields of every pattern (extruded through the design
-    layer), run as batches of zones of the workload's geometry."""
+    layer), run as batches of zones of the workload's geometry on the batched
+    two-step kernel."""
     import torch
-    from . import zda
+    from . import lens, zda
     n = len(patterns)
     nd = wl.design[1] - wl.design[0]
     zb = min(zones_per_batch, n)
     zones = [zda.Zone(zda.default_desc(**wl.desc_kwargs()), wl.eps()) for _ in range(zb)]
     batch = zda.Batch(zones)
+    lens.set_family(batch, lens.FLAT if lens.is_narrow(wl) else lens.TWO_STEP, [wl] * zb)
     src = zda.preset_source(k_src=wl.k_src, omega_c=wl.omega_c, width=wl.width)
     out = np.empty((n, 4 * len(wl.omegas), wl.nr, wl.nphi), np.float32)
     for q0 in range(0, n, zb):
