@@ -104,6 +104,52 @@ __device__ __forceinline__ void tile_load(uint16_t (*S)[LDK], const uint16_t *__
     }
 }
 
+// The vector modes in two halves, so that the next k-tile's global loads are
+// in flight while the current tile's MFMAs run: fetch (global -> eight bf16
+// in a register) and put (register -> LDS), the same elements and zero
+// fill as tile_load.
+__device__ __forceinline__ uint4 tile_fetch(const uint16_t *__restrict__ P, long s_row, long s_k, int mode, int r0,
+                                            int R, int k0, int kend, int tid)
+{
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (mode == 1) {
+        const int gr = r0 + (tid >> 2), gk = k0 + (tid & 3) * 8;
+        if (gr < R) {
+            if (gk + 7 < kend) {
+                v = *reinterpret_cast<const uint4 *>(P + (long)gr * s_row + gk);
+            } else {
+                uint16_t t[8];
+                for (int e = 0; e < 8; ++e) t[e] = (gk + e < kend) ? P[(long)gr * s_row + gk + e] : (uint16_t)0;
+                __builtin_memcpy(&v, t, sizeof v);
+            }
+        }
+    } else {
+        const int gk = k0 + (tid >> 3), gr = r0 + (tid & 7) * 8;
+        if (gk < kend) {
+            if (gr + 7 < R) {
+                v = *reinterpret_cast<const uint4 *>(P + gr + (long)gk * s_k);
+            } else {
+                uint16_t t[8];
+                for (int e = 0; e < 8; ++e) t[e] = (gr + e < R) ? P[(long)(gr + e) + (long)gk * s_k] : (uint16_t)0;
+                __builtin_memcpy(&v, t, sizeof v);
+            }
+        }
+    }
+    return v;
+}
+
+__device__ __forceinline__ void tile_put(uint16_t (*S)[LDK], uint4 v, int mode, int tid)
+{
+    if (mode == 1) {
+        *reinterpret_cast<uint4 *>(&S[tid >> 2][(tid & 3) * 8]) = v;
+    } else {
+        uint16_t t[8];
+        __builtin_memcpy(t, &v, sizeof t);
+        const int kk = tid >> 3, rr = (tid & 7) * 8;
+        for (int e = 0; e < 8; ++e) S[rr + e][kk] = t[e];
+    }
+}
+
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const uint16_t *__restrict__ A, long sam,
                                                    long sak, const uint16_t *__restrict__ B, long sbk, long sbn,
                                                    float *C, long ldc, uint16_t *Cb, const float *bias, int act,
@@ -112,17 +158,37 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const ui
     __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN, z = blockIdx.z;
+    // the M tiles of one N column are consecutive blocks, so the B tile they
+    // share is read from HBM once and from the L2 by the others
+    const int gm = (M + TM - 1) / TM;
+    const int m0 = (int)(blockIdx.x % (unsigned)gm) * TM, n0 = (int)(blockIdx.x / (unsigned)gm) * TN, z = blockIdx.z;
     const int kper = ((K + split - 1) / split + TK - 1) / TK * TK;
     const int kbeg = z * kper, kend = min(K, kbeg + kper);
     const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
     floatx4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // both operands in a vector mode: the next k-tile is fetched into
+    // registers before the current one's MFMAs (same values, same order)
+    const bool pipe = amode != 0 && bmode != 0;
+    uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = ra;
+    if (pipe && kbeg < kend) {
+        ra = tile_fetch(A, sam, sak, amode, m0, M, kbeg, kend, tid);
+        rb = tile_fetch(B, sbn, sbk, bmode, n0, N, kbeg, kend, tid);
+    }
     for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        tile_load(As, A, sam, sak, amode, m0, M, k0, kend, tid);
-        tile_load(Bs, B, sbn, sbk, bmode, n0, N, k0, kend, tid);
+        if (pipe) {
+            tile_put(As, ra, amode, tid);
+            tile_put(Bs, rb, bmode, tid);
+        } else {
+            tile_load(As, A, sam, sak, amode, m0, M, k0, kend, tid);
+            tile_load(Bs, B, sbn, sbk, bmode, n0, N, k0, kend, tid);
+        }
         __syncthreads();
+        if (pipe && k0 + TK < kend) {
+            ra = tile_fetch(A, sam, sak, amode, m0, M, k0 + TK, kend, tid);
+            rb = tile_fetch(B, sbn, sbk, bmode, n0, N, k0 + TK, kend, tid);
+        }
         const int g8 = 8 * (lane >> 4), r16 = lane & 15;
         for (int i = 0; i < 2; ++i) {
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wm + i * 16 + r16][g8]);
@@ -329,7 +395,9 @@ zsur_status zsur_gemm(int M, int N, int K, const uint16_t *A, long sam, long sak
         return 0;
     };
     const int amode = mode(A, sam, sak), bmode = mode(B, sbn, sbk);
-    dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, split);
+    const long tiles = (long)((N + TN - 1) / TN) * ((M + TM - 1) / TM);
+    if (tiles > 0x7fffffffL || split > 65535) return fail(ZSUR_ERR_ARG, "zsur_gemm: too many tiles");
+    dim3 grid((unsigned)tiles, 1, split);
     hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, Cb, bias, act,
                        slope, split, work, amode, bmode);
     if (split > 1)
