@@ -1,5 +1,6 @@
 """Host logic of the lens helpers (no GPU): which zones count as narrow, the
-device-memory estimate, and the grouping of zones into waves."""
+device-memory estimate, the grouping of zones into waves and the memory a
+design iteration adds per zone."""
 import numpy as np
 
 from paper_2501_07979_amd import lens
@@ -30,6 +31,26 @@ def test_waves_respect_budget_family_and_cover_every_zone_once():
     waves = lens.plan_waves(ws, budget, tile_rows=32)
     assert [q for _, idx in waves for q in idx] == list(range(len(ws)))
     assert all(f == 32 for f, _ in waves)
+
+
+def test_waves_with_given_sizes_and_iteration_reserve():
+    """Waves planned on given per-zone sizes (the exact time-stepping bytes a
+    zone reports) cut on those sizes; the bytes a design iteration adds per
+    zone are the forward and adjoint design-volume DFTs, the adjoint source
+    and the iteration's tensors."""
+    ws = c4(12)
+    sizes = [1000 + 10 * q for q in range(len(ws))]
+    budget = 3500
+    waves = lens.plan_waves(ws, budget, sizes=sizes)
+    assert sorted(q for _, idx in waves for q in idx) == list(range(len(ws)))
+    for _, idx in waves:
+        assert len(idx) == 1 or sum(sizes[q] for q in idx) <= budget
+    assert [len(idx) for _, idx in waves] == [3, 3, 3, 3]
+    # a budget below every zone: one zone per wave
+    assert [len(idx) for _, idx in lens.plan_waves(ws, 1, sizes=sizes)] == [1] * len(ws)
+    w = ws[0]
+    K, plane, nd = len(w.omegas), w.nr * w.nphi, w.design[1] - w.design[0]
+    assert lens.iteration_bytes(w) == 2 * K * 3 * nd * plane * 8 + 6 * K * 2 * plane * 8 + 2 * nd * plane * 4
 
 
 def test_lwir_lens_geometry():
