@@ -498,6 +498,11 @@ def main():
             "cell_updates_per_launch": tm.e_cells * tm.steps_per_launch,
             "cells_per_launch": tm.e_cells, "steps_per_launch": tm.steps_per_launch,
             "avg_launch_ms": round(e_avg, 5)}
+    if traffic is not None:
+        # the counters' bytes (FETCH_SIZE + WRITE_SIZE, calibrated) over the
+        # same launch time: what the memory system moved
+        roof["traffic_achieved"] = round(traffic / (e_avg / 1e3) / 1e9, 1)
+        roof["traffic_frac"] = round(traffic / (e_avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     if min_bytes is not None:
         # the least HBM traffic of the launch: each field read and written
         # once per two steps; its rate against peak is what HBM delivers
