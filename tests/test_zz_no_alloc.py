@@ -42,11 +42,11 @@ def _rel(a, b):
 
 
 # (kchunk, tile_rows): None = the zone's default (two-step kernel), the fused
-# one-step kernel, the split pair
-SHAPES = [None, (12, 3), (7, 4)]
+# one-step kernel, the split pair, the three-step kernel
+SHAPES = [None, (12, 3), (7, 4), (9, 11)]
 
 
-@pytest.mark.parametrize("shape", SHAPES, ids=["default", "fused_r3", "split_r4"])
+@pytest.mark.parametrize("shape", SHAPES, ids=["default", "fused_r3", "split_r4", "three_r11"])
 def test_noalloc_matches_run_on_two_calls(zda, shape):
     calls = [_large(), _small()]          # the second call is smaller (zone, steps, frequencies)
     zones = []
